@@ -1,0 +1,169 @@
+/*
+ * ata.h -- C ABI of the MI355X (gfx950) AtA library.
+ *
+ * The library computes the symmetric Gram product C = A^T A of a rectangular
+ * matrix A with the AtA method of Arrigoni, Maggioli, Massini and Rodola,
+ * "Efficiently Parallelizable Strassen-Based Multiplication of a Matrix by
+ * its Transpose" (arXiv 2110.13042):
+ *   - Sec. 3.1, Eq. "submatA"/"Cij" and Alg. 1: split A into 2x2 blocks with
+ *     floor/ceil halves; the diagonal blocks C11 and C22 come from recursive
+ *     AtA calls, the off-diagonal block C21 from Strassen's seven-product
+ *     scheme applied to A^T B, and C12 = C21^T is never formed;
+ *   - Sec. 3.2: the cost is about 2/3 of Strassen's;
+ *   - Sec. 3.3: Strassen temporaries live in one preallocated workspace.
+ * Only the lower triangle of C is produced, in packed form (Sec. 4.3.1 packs
+ * the lower triangle of A^T A results; the element order is this library's).
+ *
+ * Conventions for every entry point:
+ *   - A is row-major: element (r, c) is A[r * lda + c], 0 <= r < m,
+ *     0 <= c < n, lda >= max(1, n).  A and C_packed are DEVICE pointers on
+ *     the handle's device; the caller owns them.
+ *   - Output: C_packed[i * (i + 1) / 2 + j] = sum_r A[r][i] * A[r][j] for
+ *     0 <= j <= i < n (row-major lower packed, n(n+1)/2 elements).  The
+ *     library overwrites C (alpha = 1, beta = 0; Sec. 3.1 drops beta because
+ *     C can be scaled beforehand).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All device work is enqueued on it; no entry point of the compute path
+ *     synchronises the host, except where stated.
+ *   - Errors are returned, never thrown.  Argument errors are detected before
+ *     anything is enqueued, and C is left untouched.  Device faults are
+ *     asynchronous and surface at a later call or at the caller's sync.
+ *   - A handle must not be used by two host threads at once.
+ */
+#ifndef ATA_H
+#define ATA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ata_ctx* ata_handle_t;
+
+typedef enum {
+    ATA_OK = 0,
+    ATA_ERR_INVALID_VALUE = 1,   /* bad argument: nothing enqueued            */
+    ATA_ERR_NOT_SUPPORTED = 2,   /* valid request this build cannot serve     */
+    ATA_ERR_OUT_OF_MEMORY = 3,   /* workspace above the limit or hipMalloc failed */
+    ATA_ERR_HIP = 4,             /* a HIP runtime call failed                 */
+    ATA_ERR_INTERNAL = 5
+} ata_status_t;
+
+typedef enum {
+    ATA_F64 = 0,          /* A: double, C: double; FP64 MFMA leaves            */
+    ATA_F32 = 1,          /* A: float,  C: float;  FP32 MFMA leaves            */
+    ATA_F32_BF16X3 = 2,   /* A: float,  C: float;  split-BF16 hi/lo operands,
+                             three BF16 MFMA products, FP32 accumulation       */
+    ATA_F32_FP8E4M3 = 3   /* A: float,  C: float;  e4m3 operands with one
+                             power-of-two scale per 128x128 block, FP32 acc.   */
+} ata_dtype_t;
+
+typedef enum {
+    /* Leaf cutoff b (Sec. 3.1 base case): an AtA call on w columns is a SYRK
+       leaf iff w <= b; a Strassen call on an n x k output is a GEMM leaf iff
+       max(n, k) <= b.  0 = the planner's choice (default). */
+    ATA_OPT_LEAF_CUTOFF = 0,
+    /* Maximum Strassen levels under one AtA node; -1 = the mode's default
+       (F64: unlimited, F32: 3, BF16X3: 2, FP8: 1). */
+    ATA_OPT_MAX_STRASSEN_DEPTH = 1,
+    /* Spread threshold tau on column norms for the FP32-family FP64 fallback:
+       an AtA node whose max/min squared column norm exceeds tau^2 runs its
+       diagonal leaves in FP64 and its off-diagonal block without Strassen.
+       <= 0 disables the check (default 4096). Ignored by ATA_F64. */
+    ATA_OPT_SPREAD_TAU = 2,
+    /* 1 = after each ata_gram, compute the FP64 Freivalds residual
+       ||C x - A^T (A x)|| / (||A||_F^2 ||x||), x in {-1,+1}^n (default 0). */
+    ATA_OPT_RESIDUAL = 3,
+    /* Upper bound in bytes on the workspace; 0 = no bound (default). */
+    ATA_OPT_WORKSPACE_LIMIT = 4,
+    /* Seed of the residual probe signs (SplitMix64 counter stream). */
+    ATA_OPT_RESIDUAL_SEED = 5
+} ata_option_t;
+
+/* Plan and run summary of the last ata_gram call on a handle. */
+typedef struct {
+    int64_t m, n, lda;
+    int32_t dtype;
+    int32_t strassen_levels;      /* deepest Strassen recursion in the plan    */
+    int64_t leaf_cutoff;          /* b used                                    */
+    int64_t ata_nodes;            /* AtA calls in the recursion (incl. leaves) */
+    int64_t syrk_leaves;
+    int64_t gemm_leaves;
+    int64_t strassen_nodes;
+    int64_t multiplications;      /* scalar multiplications of the plan
+                                     (leaf sizes at the ceil dimensions)       */
+    int64_t workspace_bytes;      /* device workspace the plan needs           */
+    int64_t kernel_launches;      /* launches per ata_gram call                */
+    int64_t flagged_nodes;        /* AtA nodes flagged for the FP64 fallback;
+                                     -1 if not evaluated (syncs the stream)   */
+    double residual;              /* Freivalds residual; -1 if not computed   */
+} ata_report_t;
+
+/* One leaf of a plan, as returned by ata_plan_query. */
+typedef struct {
+    int32_t kind;                 /* 0 = SYRK (diagonal), 1 = GEMM             */
+    int32_t depth;                /* Strassen level of the leaf (0 = none)     */
+    int64_t rows, cols, contraction;  /* output rows x cols, summed length     */
+    int64_t out_row0, out_col0;   /* position in C when written there, else -1 */
+} ata_leaf_t;
+
+/* Create a handle bound to the current HIP device.  Returns ATA_ERR_HIP when
+   no device is usable.  *out is set to NULL on failure. */
+ata_status_t ata_create(ata_handle_t* out);
+
+/* Destroy a handle and free its device memory.  No work that uses the handle
+   may still be in flight.  NULL is accepted (no-op). */
+ata_status_t ata_destroy(ata_handle_t h);
+
+/* C_packed = lower(A^T A) (Alg. 1 AtA with the handle's options).
+   m = 0 zero-fills C; n = 0 is a no-op.  A and C must not overlap. */
+ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n,
+                      int64_t lda, ata_dtype_t dtype, void* C_packed,
+                      void* stream);
+
+/* batch independent Gram products, C_packed[i] = lower(A[i]^T A[i]), of
+   uneven shapes, in one persistent launch on `stream`.  The host arrays are
+   read during the call only.  Any invalid member fails the whole call with
+   nothing enqueued; the first bad index is in the report's `m` field as
+   -(index + 1). */
+ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch,
+                              const void* const* A, const int64_t* m,
+                              const int64_t* n, const int64_t* lda,
+                              ata_dtype_t dtype, void* const* C_packed,
+                              void* stream);
+
+/* Freivalds probe of a given product (the check ATA_OPT_RESIDUAL runs after
+   ata_gram): *result = ||C x - A^T (A x)||_2 / (||A||_F^2 ||x||_2) with
+   x_j = +1 if the top bit of SplitMix64 output j of stream `seed` is 0, else
+   -1; computed in FP64 on the device.  A is m x n (lda), C_packed the packed
+   lower triangle of an n x n symmetric matrix, both device pointers of the
+   dtype's element type (double for ATA_F64, float otherwise).  Blocks until
+   the result is on the host (synchronises `stream`). */
+ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n,
+                          int64_t lda, ata_dtype_t dtype, const void* C_packed,
+                          uint64_t seed, double* result, void* stream);
+
+/* Set an option (see ata_option_t); takes effect at the next call. */
+ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value);
+
+/* Copy the last call's report.  When the last call computed a residual or a
+   fallback flag count, this synchronises the stream of that call first. */
+ata_status_t ata_get_report(ata_handle_t h, ata_report_t* out);
+
+/* Host-only planning query: no device needed, no handle.  Fills *info (may be
+   NULL) and up to `cap` leaves; *n_leaves receives the total leaf count.
+   leaf_cutoff <= 0 and max_depth < 0 select the defaults. */
+ata_status_t ata_plan_query(int64_t m, int64_t n, ata_dtype_t dtype,
+                            int64_t leaf_cutoff, int32_t max_depth,
+                            ata_report_t* info, ata_leaf_t* leaves, int64_t cap,
+                            int64_t* n_leaves);
+
+/* Static description of a status code. */
+const char* ata_status_string(ata_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATA_H */

@@ -1,0 +1,233 @@
+"""ctypes binding of ``libata.so`` (argument marshalling only).
+
+The functions named like the C entry points (``ata_create``, ``ata_gram``,
+``ata_gram_batched``, ``ata_destroy``, ``ata_set_option``, ``ata_get_report``,
+``ata_plan_query``) take plain integers for device pointers and streams and
+return what the C call returns, raising ``AtaError`` on a non-OK status.
+``gram`` is the torch convenience wrapper: it allocates the packed output
+tensor on the input's device and calls ``ata_gram`` on the current stream.
+
+There is no fallback: if the library is missing, or no GPU is present, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libata.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ata.h")
+
+F64, F32, F32_BF16X3, F32_FP8E4M3 = 0, 1, 2, 3
+DTYPE_NAMES = {"f64": F64, "f32": F32, "bf16x3": F32_BF16X3, "fp8": F32_FP8E4M3}
+
+OPT_LEAF_CUTOFF, OPT_MAX_STRASSEN_DEPTH, OPT_SPREAD_TAU = 0, 1, 2
+OPT_RESIDUAL, OPT_WORKSPACE_LIMIT, OPT_RESIDUAL_SEED = 3, 4, 5
+
+STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
+          3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
+
+
+class AtaError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("strassen_levels", ctypes.c_int32),
+                ("leaf_cutoff", ctypes.c_int64), ("ata_nodes", ctypes.c_int64),
+                ("syrk_leaves", ctypes.c_int64), ("gemm_leaves", ctypes.c_int64),
+                ("strassen_nodes", ctypes.c_int64), ("multiplications", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("kernel_launches", ctypes.c_int64),
+                ("flagged_nodes", ctypes.c_int64), ("residual", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Leaf(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("contraction", ctypes.c_int64), ("out_row0", ctypes.c_int64),
+                ("out_col0", ctypes.c_int64)]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libata.so (raises if it was not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    L.ata_create.argtypes = [ctypes.POINTER(vp)]
+    L.ata_destroy.argtypes = [vp]
+    L.ata_gram.argtypes = [vp, vp, i64, i64, i64, st, vp, vp]
+    L.ata_gram_batched.argtypes = [vp, i64, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                   ctypes.POINTER(i64), ctypes.POINTER(i64), st,
+                                   ctypes.POINTER(vp), vp]
+    L.ata_set_option.argtypes = [vp, st, ctypes.c_double]
+    L.ata_get_report.argtypes = [vp, ctypes.POINTER(Report)]
+    L.ata_plan_query.argtypes = [i64, i64, st, i64, i32, ctypes.POINTER(Report),
+                                 ctypes.POINTER(Leaf), i64, ctypes.POINTER(i64)]
+    L.ata_residual.argtypes = [vp, vp, i64, i64, i64, st, vp, ctypes.c_uint64,
+                               ctypes.POINTER(ctypes.c_double), vp]
+    L.ata_status_string.argtypes = [st]
+    L.ata_status_string.restype = ctypes.c_char_p
+    for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_batched", "ata_set_option",
+                 "ata_get_report", "ata_plan_query", "ata_residual"):
+        getattr(L, name).restype = st
+    _LIB = L
+    return L
+
+
+def header_symbols() -> list:
+    """Entry points declared in include/ata.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|ata_status_t)\s+(ata_\w+)\s*\(", text, re.M)))
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise AtaError(status, where)
+
+
+# ----------------------------------------------------------- C-ABI mirrors
+def ata_create() -> int:
+    h = ctypes.c_void_p()
+    _check(lib().ata_create(ctypes.byref(h)), "ata_create")
+    return h.value
+
+
+def ata_destroy(h: int) -> None:
+    _check(lib().ata_destroy(h), "ata_destroy")
+
+
+def ata_gram(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, stream: int = 0) -> None:
+    _check(lib().ata_gram(h, A, m, n, lda, dtype, C, stream), "ata_gram")
+
+
+def ata_gram_batched(h: int, A_ptrs, ms, ns, ldas, dtype: int, C_ptrs, stream: int = 0) -> None:
+    b = len(A_ptrs)
+    arr_p = ctypes.c_void_p * b
+    arr_i = ctypes.c_int64 * b
+    _check(lib().ata_gram_batched(h, b, arr_p(*A_ptrs), arr_i(*ms), arr_i(*ns), arr_i(*ldas), dtype,
+                                  arr_p(*C_ptrs), stream), "ata_gram_batched")
+
+
+def ata_set_option(h: int, key: int, value: float) -> None:
+    _check(lib().ata_set_option(h, key, float(value)), "ata_set_option")
+
+
+def ata_get_report(h: int) -> dict:
+    r = Report()
+    _check(lib().ata_get_report(h, ctypes.byref(r)), "ata_get_report")
+    return r.as_dict()
+
+
+def ata_plan_query(m: int, n: int, dtype: int, leaf_cutoff: int = 0, max_depth: int = -1):
+    """(report dict, list of leaf dicts) of the plan; host only."""
+    info = Report()
+    count = ctypes.c_int64()
+    _check(lib().ata_plan_query(m, n, dtype, leaf_cutoff, max_depth, ctypes.byref(info), None, 0,
+                                ctypes.byref(count)), "ata_plan_query")
+    leaves = (Leaf * max(count.value, 1))()
+    _check(lib().ata_plan_query(m, n, dtype, leaf_cutoff, max_depth, None, leaves, count.value,
+                                ctypes.byref(count)), "ata_plan_query")
+    out = [{k: getattr(leaves[i], k) for k, _ in Leaf._fields_} for i in range(count.value)]
+    return info.as_dict(), out
+
+
+def ata_residual(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, seed: int,
+                 stream: int = 0) -> float:
+    r = ctypes.c_double()
+    _check(lib().ata_residual(h, A, m, n, lda, dtype, C, seed, ctypes.byref(r), stream),
+           "ata_residual")
+    return r.value
+
+
+def status_string(s: int) -> str:
+    return lib().ata_status_string(s).decode()
+
+
+# ------------------------------------------------------------ torch wrapper
+class Handle:
+    """Owns one ata handle; options are set by keyword."""
+
+    def __init__(self, **options):
+        self.h = ata_create()
+        for k, v in options.items():
+            self.set(k, v)
+
+    def set(self, name: str, value) -> None:
+        key = {"leaf_cutoff": OPT_LEAF_CUTOFF, "max_depth": OPT_MAX_STRASSEN_DEPTH,
+               "spread_tau": OPT_SPREAD_TAU, "residual": OPT_RESIDUAL,
+               "workspace_limit": OPT_WORKSPACE_LIMIT, "residual_seed": OPT_RESIDUAL_SEED}[name]
+        ata_set_option(self.h, key, value)
+
+    def report(self) -> dict:
+        return ata_get_report(self.h)
+
+    def close(self) -> None:
+        if self.h:
+            ata_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _mode_of(A, dtype):
+    import torch
+    if dtype is None:
+        return F64 if A.dtype == torch.float64 else F32
+    return DTYPE_NAMES[dtype] if isinstance(dtype, str) else int(dtype)
+
+
+_DEFAULT = {}
+
+
+def default_handle(device_index: int) -> Handle:
+    """One long-lived handle per device (keeps its plan cache and workspace)."""
+    if device_index not in _DEFAULT:
+        _DEFAULT[device_index] = Handle()
+    return _DEFAULT[device_index]
+
+
+def gram(A, dtype=None, handle: Handle | None = None, out=None):
+    """Packed lower triangle of A^T A for a 2-D CUDA tensor A (row-major rows)."""
+    import torch
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D tensor on a GPU")
+    mode = _mode_of(A, dtype)
+    want = torch.float64 if mode == F64 else torch.float32
+    if A.dtype != want:
+        raise TypeError(f"mode {mode} needs a {want} input")
+    m, n = A.shape
+    if n > 0 and m > 1 and A.stride(1) != 1:
+        raise ValueError("A's rows must be contiguous (stride(1) == 1)")
+    lda = A.stride(0) if m > 1 else max(n, 1)
+    lda = max(lda, n, 1)
+    if out is None:
+        out = torch.empty(n * (n + 1) // 2, dtype=want, device=A.device)
+    h = handle or default_handle(A.device.index or 0)
+    stream = torch.cuda.current_stream(A.device).cuda_stream
+    ata_gram(h.h, A.data_ptr(), m, n, lda, mode, out.data_ptr(), stream)
+    return out

@@ -1,0 +1,363 @@
+// Memory-bound kernels of the AtA plan: Strassen pre-sums and combines
+// (the block additions of Sec. 3.1 / 3.2, done as fused streaming passes
+// instead of one ?axpy per block pair), column norms and spread flags for the
+// FP64 fallback, and the FP64 Freivalds residual probe.
+#include "kernels_common.hpp"
+#include "launch.hpp"
+
+namespace ata {
+
+namespace {
+
+constexpr int EW_THREADS = 256;
+
+// --------------------------------------------------------------- pre-sums
+// Work item = one row r and four consecutive columns c..c+3 of the m2 x n2
+// sums.  Reads the four quadrant values of the parent operand (zero outside
+// its physical extent and outside the quadrant's real size) and writes the
+// five sums, including the zero padding of the ceil-sized buffers.
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* tasks, int ntasks,
+                                                            int64_t items, const T* A, T* arena,
+                                                            const uint8_t* flags) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= items) return;
+    const PresumDesc& d = tasks[find_task(tasks, ntasks, x)];
+    if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    const int64_t e = x - d.elem_begin;
+    const int64_t groups = (d.n2 + 3) >> 2;
+    const int64_t r = e / groups, c0 = (e - r * groups) << 2;
+    const T* V = (d.V.base == BASE_A ? A : arena) + d.V.off;
+    const int64_t ld = d.V.ld, pr = d.V.prows, pc = d.V.pcols;
+    const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
+    const int64_t plane = m2 * n2;
+    T* out = arena + d.out_off + r * n2;
+    auto get = [&](int qr, int qc, int64_t c) -> T {
+        const int64_t rr = qr ? m1 + r : r, cc = qc ? n1 + c : c;
+        const bool in = r < (qr ? m2 : m1) && c < (qc ? n2 : n1) && rr < pr && cc < pc;
+        return in ? V[rr * ld + cc] : T(0);
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t c = c0 + q;
+        if (c >= n2) break;
+        const T a11 = get(0, 0, c), a12 = get(0, 1, c), a21 = get(1, 0, c), a22 = get(1, 1, c);
+        if (d.side == 0) {
+            out[0 * plane + c] = a11 + a22;   // S1 = X11 + X22
+            out[1 * plane + c] = a12 + a22;   // S2 = X12 + X22
+            out[2 * plane + c] = a11 + a21;   // S3 = X11 + X21
+            out[3 * plane + c] = a12 - a11;   // S4 = X12 - X11
+            out[4 * plane + c] = a21 - a22;   // S5 = X21 - X22
+        } else {
+            out[0 * plane + c] = a11 + a22;   // T1 = Y11 + Y22
+            out[1 * plane + c] = a12 - a22;   // T2 = Y12 - Y22
+            out[2 * plane + c] = a21 - a11;   // T3 = Y21 - Y11
+            out[3 * plane + c] = a11 + a12;   // T4 = Y11 + Y12
+            out[4 * plane + c] = a21 + a22;   // T5 = Y21 + Y22
+        }
+    }
+}
+
+// ---------------------------------------------------------------- combine
+// Work item = one row i and four columns j..j+3 of the n2 x k2 products.
+// C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4,
+// C22 = M1 - M2 + M3 + M6, each summed left to right; only the leading part
+// of a product reaches a floor-sized quadrant.
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* tasks, int ntasks,
+                                                             int64_t items, T* C, T* arena,
+                                                             const uint8_t* flags) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= items) return;
+    const CombineDesc& d = tasks[find_task(tasks, ntasks, x)];
+    if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    const int64_t e = x - d.elem_begin;
+    const int64_t groups = (d.k2 + 3) >> 2;
+    const int64_t i = e / groups, j0 = (e - i * groups) << 2;
+    const int64_t n1 = d.n1, k1 = d.k1, k2 = d.k2, plane = d.n2 * d.k2;
+    const T* M = arena + d.m_off + i * k2;
+    auto put = [&](int64_t ii, int64_t jj, T v) {
+        if (d.out_kind == OUT_PACKED)
+            C[packed_index(d.out_row0 + ii, d.out_col0 + jj)] = v;
+        else
+            arena[d.out_off + ii * d.out_ld + jj] = v;
+    };
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t j = j0 + q;
+        if (j >= k2) break;
+        const T m1 = M[j], m2 = M[plane + j], m3 = M[2 * plane + j], m4 = M[3 * plane + j];
+        const T m5 = M[4 * plane + j], m6 = M[5 * plane + j], m7 = M[6 * plane + j];
+        if (i < n1) {
+            if (j < k1) put(i, j, ((m1 + m4) - m5) + m7);
+            put(i, k1 + j, m3 + m5);
+        }
+        if (j < k1) put(n1 + i, j, m2 + m4);
+        put(n1 + i, k1 + j, ((m1 - m2) + m3) + m6);
+    }
+}
+
+// ------------------------------------------------------------ column norms
+constexpr int64_t NORM_ROWS = 1024;
+
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void colnorm_partial(const T* A, int64_t m, int64_t n,
+                                                              int64_t lda, double* partial) {
+    const int64_t j = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (j >= n) return;
+    const int64_t r0 = chunk * NORM_ROWS, r1 = r0 + NORM_ROWS < m ? r0 + NORM_ROWS : m;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double a = (double)A[r * lda + j];
+        s += a * a;
+    }
+    partial[chunk * n + j] = s;
+}
+
+__global__ __launch_bounds__(EW_THREADS) void sum_partials(const double* partial, int64_t nchunks,
+                                                           int64_t n, double* out) {
+    const int64_t j = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int64_t c = 0; c < nchunks; ++c) s += partial[c * n + j];
+    out[j] = s;
+}
+
+// spread flag per AtA node: max/min of the nonzero squared norms > tau^2
+__global__ __launch_bounds__(EW_THREADS) void flags_kernel(const double* nu, const NodeDesc* nodes,
+                                                           double tau2, uint8_t* flags) {
+    __shared__ double smax[EW_THREADS], smin[EW_THREADS];
+    __shared__ int scnt[EW_THREADS];
+    const NodeDesc nd = nodes[blockIdx.x];
+    double mx = 0.0, mn = 0.0;
+    int cnt = 0;
+    for (int64_t j = nd.c0 + threadIdx.x; j < nd.c0 + nd.w; j += EW_THREADS) {
+        const double v = nu[j];
+        if (v > 0.0) {
+            mx = cnt ? fmax(mx, v) : v;
+            mn = cnt ? fmin(mn, v) : v;
+            ++cnt;
+        }
+    }
+    smax[threadIdx.x] = mx;
+    smin[threadIdx.x] = mn;
+    scnt[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = EW_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const int o = threadIdx.x + s;
+            if (scnt[o]) {
+                if (scnt[threadIdx.x]) {
+                    smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[o]);
+                    smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[o]);
+                } else {
+                    smax[threadIdx.x] = smax[o];
+                    smin[threadIdx.x] = smin[o];
+                }
+                scnt[threadIdx.x] += scnt[o];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double spread = scnt[0] >= 2 ? smax[0] / smin[0] : 1.0;
+        flags[blockIdx.x] = spread > tau2 ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------- Freivalds residual
+__device__ __forceinline__ double probe_sign(uint64_t seed, int64_t j) {
+    // SplitMix64 output at counter j: state = seed + (j + 1) * gamma, then mix
+    uint64_t z = seed + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    return (z >> 63) ? -1.0 : 1.0;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// y[r] = sum_j A[r][j] x_j : one wave per row, lanes stride over j
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void res_ax(const T* A, int64_t m, int64_t n, int64_t lda,
+                                                     uint64_t seed, double* y) {
+    const int64_t r = (int64_t)blockIdx.x * (EW_THREADS / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= m) return;
+    double s = 0.0;
+    for (int64_t j = lane; j < n; j += 64) s += (double)A[r * lda + j] * probe_sign(seed, j);
+    s = wave_sum(s);
+    if (lane == 0) y[r] = s;
+}
+
+// zpart[chunk][j] = sum_{r in chunk} A[r][j] y[r];  fpart[chunk][j] = sum a^2
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void res_aty(const T* A, int64_t m, int64_t n, int64_t lda,
+                                                      const double* y, double* zpart, double* fpart) {
+    const int64_t j = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int64_t chunk = blockIdx.y;
+    if (j >= n) return;
+    const int64_t r0 = chunk * NORM_ROWS, r1 = r0 + NORM_ROWS < m ? r0 + NORM_ROWS : m;
+    double s = 0.0, f = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+        const double a = (double)A[r * lda + j];
+        s += a * y[r];
+        f += a * a;
+    }
+    zpart[chunk * n + j] = s;
+    fpart[chunk * n + j] = f;
+}
+
+// wrow[i] = sum_{j <= i} C[i][j] x_j : one wave per packed row
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void res_crow(const T* Cp, int64_t n, uint64_t seed, double* wrow) {
+    const int64_t i = (int64_t)blockIdx.x * (EW_THREADS / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= n) return;
+    const T* row = Cp + i * (i + 1) / 2;
+    double s = 0.0;
+    for (int64_t j = lane; j <= i; j += 64) s += (double)row[j] * probe_sign(seed, j);
+    s = wave_sum(s);
+    if (lane == 0) wrow[i] = s;
+}
+
+// wpart[band][j] = sum_{i in band, i > j} C[i][j] x_i  (the strictly-upper part of C x)
+constexpr int64_t BAND = 256;
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void res_ccol(const T* Cp, int64_t n, uint64_t seed, double* wpart) {
+    const int64_t j = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int64_t band = blockIdx.y;
+    if (j >= n) return;
+    const int64_t i0 = band * BAND, i1 = i0 + BAND < n ? i0 + BAND : n;
+    double s = 0.0;
+    for (int64_t i = (i0 > j + 1 ? i0 : j + 1); i < i1; ++i)
+        s += (double)Cp[i * (i + 1) / 2 + j] * probe_sign(seed, i);
+    wpart[band * n + j] = s;
+}
+
+// one block: residual = ||wrow + wcol - z|| / (||A||_F^2 sqrt(n))
+__global__ __launch_bounds__(EW_THREADS) void res_final(const double* wrow, const double* wcol,
+                                                        const double* z, const double* fro,
+                                                        int64_t n, double* out) {
+    __shared__ double s1[EW_THREADS], s2[EW_THREADS];
+    double a = 0.0, f = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += EW_THREADS) {
+        const double d = wrow[j] + wcol[j] - z[j];
+        a += d * d;
+        f += fro[j];
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = f;
+    __syncthreads();
+    for (int s = EW_THREADS / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            s1[threadIdx.x] += s1[threadIdx.x + s];
+            s2[threadIdx.x] += s2[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double denom = s2[0] * sqrt((double)n);
+        *out = denom > 0.0 ? sqrt(s1[0]) / denom : 0.0;
+    }
+}
+
+unsigned blocks_for(int64_t items) { return (unsigned)((items + EW_THREADS - 1) / EW_THREADS); }
+
+}  // namespace
+
+hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, int64_t items,
+                         const void* A, void* arena, const uint8_t* flags, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(presum_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+                           d_tasks, ntasks, items, static_cast<const double*>(A),
+                           static_cast<double*>(arena), flags);
+    else
+        hipLaunchKernelGGL(presum_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+                           d_tasks, ntasks, items, static_cast<const float*>(A),
+                           static_cast<float*>(arena), flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
+                          void* C, void* arena, const uint8_t* flags, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(combine_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+                           d_tasks, ntasks, items, static_cast<double*>(C),
+                           static_cast<double*>(arena), flags);
+    else
+        hipLaunchKernelGGL(combine_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+                           d_tasks, ntasks, items, static_cast<float*>(C),
+                           static_cast<float*>(arena), flags);
+    return hipGetLastError();
+}
+
+int64_t colnorm_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / NORM_ROWS; }
+
+hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
+                           int64_t nchunks, double* nu, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(colnorm_partial<float>, dim3(blocks_for(n), (unsigned)nchunks),
+                       dim3(EW_THREADS), 0, stream, A, m, n, lda, partial);
+    hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), dim3(EW_THREADS), 0, stream, partial,
+                       nchunks, n, nu);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags(const double* nu, const NodeDesc* d_nodes, int nnodes, double tau2,
+                        uint8_t* flags, hipStream_t stream) {
+    if (nnodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(flags_kernel, dim3(nnodes), dim3(EW_THREADS), 0, stream, nu, d_nodes, tau2, flags);
+    return hipGetLastError();
+}
+
+int64_t residual_work_elems(int64_t m, int64_t n) {
+    const int64_t chunks = colnorm_chunks(m), bands = (n + BAND - 1) / BAND;
+    // y | zpart | fpart | z | fro | wrow | wpart | wcol
+    return m + 2 * chunks * n + 2 * n + n + bands * n + n;
+}
+
+hipError_t launch_residual(int32_t mode, const void* A, int64_t m, int64_t n, int64_t lda,
+                           const void* C, uint64_t seed, double* work, double* out,
+                           hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t chunks = colnorm_chunks(m), bands = (n + BAND - 1) / BAND;
+    double* y = work;
+    double* zpart = y + m;
+    double* fpart = zpart + chunks * n;
+    double* z = fpart + chunks * n;
+    double* fro = z + n;
+    double* wrow = fro + n;
+    double* wpart = wrow + n;
+    double* wcol = wpart + bands * n;
+    const dim3 blk(EW_THREADS);
+    const unsigned rows_blocks = (unsigned)((m + 3) / 4), crow_blocks = (unsigned)((n + 3) / 4);
+    if (mode == MODE_F64) {
+        const double* a = static_cast<const double*>(A);
+        const double* c = static_cast<const double*>(C);
+        if (m > 0) hipLaunchKernelGGL(res_ax<double>, dim3(rows_blocks), blk, 0, stream, a, m, n, lda, seed, y);
+        hipLaunchKernelGGL(res_aty<double>, dim3(blocks_for(n), (unsigned)chunks), blk, 0, stream, a, m, n, lda, y, zpart, fpart);
+        hipLaunchKernelGGL(res_crow<double>, dim3(crow_blocks), blk, 0, stream, c, n, seed, wrow);
+        hipLaunchKernelGGL(res_ccol<double>, dim3(blocks_for(n), (unsigned)bands), blk, 0, stream, c, n, seed, wpart);
+    } else {
+        const float* a = static_cast<const float*>(A);
+        const float* c = static_cast<const float*>(C);
+        if (m > 0) hipLaunchKernelGGL(res_ax<float>, dim3(rows_blocks), blk, 0, stream, a, m, n, lda, seed, y);
+        hipLaunchKernelGGL(res_aty<float>, dim3(blocks_for(n), (unsigned)chunks), blk, 0, stream, a, m, n, lda, y, zpart, fpart);
+        hipLaunchKernelGGL(res_crow<float>, dim3(crow_blocks), blk, 0, stream, c, n, seed, wrow);
+        hipLaunchKernelGGL(res_ccol<float>, dim3(blocks_for(n), (unsigned)bands), blk, 0, stream, c, n, seed, wpart);
+    }
+    hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), blk, 0, stream, zpart, chunks, n, z);
+    hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), blk, 0, stream, fpart, chunks, n, fro);
+    hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), blk, 0, stream, wpart, bands, n, wcol);
+    hipLaunchKernelGGL(res_final, dim3(1), blk, 0, stream, wrow, wcol, z, fro, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace ata

@@ -1,0 +1,53 @@
+// Device-side helpers shared by the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace ata {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int LEAF_THREADS = 256;
+
+// Row-major lower packed index of (i, j), j <= i.
+__device__ __forceinline__ int64_t packed_index(int64_t i, int64_t j) { return i * (i + 1) / 2 + j; }
+
+// Consecutive workgroup ids go round-robin to the 8 XCDs.  Remap so that, in
+// every window of 8 * chunk ids, XCD x works on the consecutive tile range
+// [x * chunk, (x + 1) * chunk) of that window: tiles that share operand
+// panels then share one XCD's L2.  The last partial window keeps identity.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total, int64_t chunk) {
+    const int64_t win = 8 * chunk;
+    const int64_t full = (total / win) * win;
+    if (bid >= full) return bid;
+    const int64_t w0 = (bid / win) * win;
+    const int64_t r = bid - w0;
+    return w0 + (r % 8) * chunk + r / 8;
+}
+
+// Lower-triangular tile (ti >= tj) of a linear index q.
+__device__ __forceinline__ void tri_tile(int64_t q, int& ti, int& tj) {
+    int64_t i = (int64_t)((__builtin_sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > q) --i;
+    while ((i + 1) * (i + 2) / 2 <= q) ++i;
+    ti = (int)i;
+    tj = (int)(q - i * (i + 1) / 2);
+}
+
+template <class D>
+__device__ __forceinline__ int find_task(const D* tasks, int ntasks, int64_t x) {
+    // largest t with tasks[t].begin <= x (begin fields ascending)
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tasks[mid].elem_begin <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace ata

@@ -1,0 +1,241 @@
+// Planner: AtA recursion (Alg. 1, rows kept) -> flattened launch phases.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <stdexcept>
+
+namespace ata {
+
+int64_t default_leaf_cutoff(int32_t mode, int64_t m, int64_t n) {
+    (void)m;
+    switch (mode) {
+        case MODE_F64: return n <= 2048 ? 256 : 512;
+        case MODE_F32: return 1024;
+        case MODE_BF16X3: return 2048;
+        default: return 2048;
+    }
+}
+
+int32_t default_max_depth(int32_t mode) {
+    switch (mode) {
+        case MODE_F64: return 64;
+        case MODE_F32: return 3;
+        case MODE_BF16X3: return 2;
+        default: return 1;
+    }
+}
+
+int64_t Plan::launches() const {
+    int64_t l = (int64_t)presum.size() + (leaves.empty() ? 0 : 1) + (int64_t)combine.size();
+    if (fallback) l += 2;  // column norms + flags
+    return l;
+}
+
+namespace {
+
+int64_t clamp64(int64_t v, int64_t lo, int64_t hi) { return std::max(lo, std::min(hi, v)); }
+
+// Sub-block of v starting at (r0, c0) whose real extent is real_r x real_c
+// and whose logical (zero-padded) extent is log_r x log_c.
+View sub(const View& v, int64_t r0, int64_t real_r, int64_t log_r, int64_t c0,
+         int64_t real_c, int64_t log_c) {
+    View s = v;
+    s.off = v.off + r0 * v.ld + c0;
+    s.prows = clamp64(std::min(v.prows, r0 + real_r) - r0, 0, real_r);
+    s.pcols = clamp64(std::min(v.pcols, c0 + real_c) - c0, 0, real_c);
+    s.rows = log_r;
+    s.cols = log_c;
+    return s;
+}
+
+View arena_view(int64_t off, int64_t rows, int64_t cols) {
+    View v{};
+    v.base = BASE_ARENA;
+    v.off = off;
+    v.ld = cols;
+    v.rows = v.prows = rows;
+    v.cols = v.pcols = cols;
+    return v;
+}
+
+struct Target {
+    int32_t kind;
+    int64_t off, ld;      // dense
+    int64_t row0, col0;   // packed
+};
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Builder {
+    Plan& p;
+    int64_t b;
+    int32_t maxd;
+    bool fb;
+    bool counting = true;   // false while planning a fallback alternative
+
+    explicit Builder(Plan& plan) : p(plan), b(plan.b), maxd(plan.max_depth), fb(plan.fallback) {}
+
+    int64_t alloc(int64_t elems) {
+        int64_t off = p.arena_elems;
+        // keep every buffer 256-byte aligned for vector loads
+        int64_t align = 256 / p.elem_bytes();
+        p.arena_elems += cdiv(elems, align) * align;
+        return off;
+    }
+
+    View a_cols(int64_t c0, int64_t w) const {
+        View v{};
+        v.base = BASE_A;
+        v.off = c0;
+        v.ld = p.lda;
+        v.rows = v.prows = p.m;
+        v.cols = v.pcols = w;
+        return v;
+    }
+
+    void add_leaf(int32_t kind, const View& X, const View& Y, const Target& t, int depth,
+                  int32_t pred_node, int32_t pred_value, int32_t fb_node) {
+        LeafDesc L{};
+        L.kind = kind;
+        L.out_kind = t.kind;
+        L.X = X;
+        L.Y = Y;
+        L.rows = X.cols;
+        L.cols = Y.cols;
+        L.K = std::min(X.prows, Y.prows);
+        L.tiles_m = (int32_t)cdiv(L.rows, TILE_M);
+        L.tiles_n = (int32_t)cdiv(L.cols, TILE_N);
+        L.tiles = kind == LEAF_SYRK ? (int64_t)L.tiles_m * (L.tiles_m + 1) / 2
+                                    : (int64_t)L.tiles_m * L.tiles_n;
+        L.out_off = t.off;
+        L.out_ld = t.ld;
+        L.out_row0 = t.row0;
+        L.out_col0 = t.col0;
+        L.pred_node = pred_node;
+        L.pred_value = pred_value;
+        L.fb_node = fb_node;
+        L.depth = depth;
+        if (counting) {
+            if (kind == LEAF_SYRK) {
+                ++p.stats.syrk_leaves;
+                p.stats.mults += X.rows * X.cols * (X.cols + 1) / 2;
+            } else {
+                ++p.stats.gemm_leaves;
+                p.stats.mults += X.rows * X.cols * Y.cols;
+            }
+        }
+        p.leaves.push_back(L);
+    }
+
+    // Levels a Strassen call on (mm, n, k) would recurse (ignores predicates).
+    int levels(int64_t mm, int64_t n, int64_t k, int depth) const {
+        if (std::max(n, k) <= b || std::min(mm, std::min(n, k)) <= 1 || depth >= maxd) return 0;
+        return 1 + levels(mm - mm / 2, n - n / 2, k - k / 2, depth + 1);
+    }
+
+    void ata(int64_t c0, int64_t w) {
+        const int32_t node = (int32_t)p.nodes.size();
+        p.nodes.push_back(NodeDesc{c0, w});
+        ++p.stats.ata_nodes;
+        if (w <= b || p.m <= 1 || w <= 1) {
+            Target t{OUT_PACKED, 0, 0, c0, c0};
+            View X = a_cols(c0, w);
+            add_leaf(LEAF_SYRK, X, X, t, 0, -1, 0, fb ? node : -1);
+            return;
+        }
+        const int64_t n1 = w / 2, n2 = w - n1;
+        ata(c0, n1);
+        ata(c0 + n1, n2);
+        const View X = a_cols(c0 + n1, n2), Y = a_cols(c0, n1);
+        const Target t{OUT_PACKED, 0, 0, c0 + n1, c0};
+        if (fb && levels(p.m, n2, n1, 0) > 0) {
+            // flagged node: plain product, no Strassen (predicated on the device)
+            counting = false;
+            add_leaf(LEAF_GEMM, X, Y, t, 0, node, 1, -1);
+            counting = true;
+            strassen(X, Y, t, 0, node, 0);
+        } else {
+            strassen(X, Y, t, 0, -1, 0);
+        }
+    }
+
+    // C_target = X^T Y.  Returns the height of this node (0 = leaf).
+    int strassen(const View& X, const View& Y, const Target& t, int depth, int32_t pn, int32_t pv) {
+        const int64_t mm = X.rows, n = X.cols, k = Y.cols;
+        if (std::max(n, k) <= b || std::min(mm, std::min(n, k)) <= 1 || depth >= maxd) {
+            add_leaf(LEAF_GEMM, X, Y, t, depth, pn, pv, -1);
+            return 0;
+        }
+        if (counting) ++p.stats.strassen_nodes;
+        const int64_t m1 = mm / 2, m2 = mm - m1, n1 = n / 2, n2 = n - n1, k1 = k / 2, k2 = k - k1;
+        const int64_t S = alloc(5 * m2 * n2), T = alloc(5 * m2 * k2), M = alloc(7 * n2 * k2);
+        if ((int)p.presum.size() <= depth) p.presum.resize(depth + 1);
+        PresumDesc ps{};
+        ps.V = X; ps.m1 = m1; ps.m2 = m2; ps.n1 = n1; ps.n2 = n2; ps.out_off = S;
+        ps.elems = m2 * cdiv(n2, 4); ps.side = 0; ps.pred_node = pn; ps.pred_value = pv;
+        p.presum[depth].push_back(ps);
+        PresumDesc pt = ps;
+        pt.V = Y; pt.n1 = k1; pt.n2 = k2; pt.out_off = T; pt.elems = m2 * cdiv(k2, 4); pt.side = 1;
+        p.presum[depth].push_back(pt);
+
+        const View X11 = sub(X, 0, m1, m2, 0, n1, n2), X12 = sub(X, 0, m1, m2, n1, n2, n2);
+        const View X21 = sub(X, m1, m2, m2, 0, n1, n2), X22 = sub(X, m1, m2, m2, n1, n2, n2);
+        const View Y11 = sub(Y, 0, m1, m2, 0, k1, k2), Y22 = sub(Y, m1, m2, m2, k1, k2, k2);
+        (void)X12; (void)X21;
+        auto Sv = [&](int i) { return arena_view(S + (i - 1) * m2 * n2, m2, n2); };
+        auto Tv = [&](int i) { return arena_view(T + (i - 1) * m2 * k2, m2, k2); };
+        auto Mt = [&](int i) { return Target{OUT_DENSE, M + (i - 1) * n2 * k2, k2, 0, 0}; };
+        int h = 0;
+        h = std::max(h, strassen(Sv(1), Tv(1), Mt(1), depth + 1, pn, pv));  // M1 = S1^T T1
+        h = std::max(h, strassen(Sv(2), Y11, Mt(2), depth + 1, pn, pv));    // M2 = S2^T Y11
+        h = std::max(h, strassen(X11, Tv(2), Mt(3), depth + 1, pn, pv));    // M3 = X11^T T2
+        h = std::max(h, strassen(X22, Tv(3), Mt(4), depth + 1, pn, pv));    // M4 = X22^T T3
+        h = std::max(h, strassen(Sv(3), Y22, Mt(5), depth + 1, pn, pv));    // M5 = S3^T Y22
+        h = std::max(h, strassen(Sv(4), Tv(4), Mt(6), depth + 1, pn, pv));  // M6 = S4^T T4
+        h = std::max(h, strassen(Sv(5), Tv(5), Mt(7), depth + 1, pn, pv));  // M7 = S5^T T5
+        const int height = h + 1;
+        if ((int)p.combine.size() < height) p.combine.resize(height);
+        CombineDesc c{};
+        c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
+        c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
+        c.elems = n2 * cdiv(k2, 4); c.pred_node = pn; c.pred_value = pv;
+        p.combine[height - 1].push_back(c);
+        if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
+        return height;
+    }
+};
+
+}  // namespace
+
+Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt) {
+    if (mode < MODE_F64 || mode > MODE_FP8) throw std::invalid_argument("mode");
+    if (m < 0 || n < 0 || lda < std::max<int64_t>(1, n)) throw std::invalid_argument("sizes");
+    Plan p;
+    p.mode = mode;
+    p.m = m;
+    p.n = n;
+    p.lda = lda;
+    p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, n);
+    p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode);
+    p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
+    if (n == 0) return p;
+    Builder bld(p);
+    bld.ata(0, n);
+    // LPT: longest contraction first (stable, so ties keep tree order)
+    std::stable_sort(p.leaves.begin(), p.leaves.end(),
+                     [](const LeafDesc& a, const LeafDesc& c) { return a.K > c.K; });
+    int64_t t = 0;
+    for (auto& L : p.leaves) { L.tile_begin = t; t += L.tiles; }
+    p.total_tiles = t;
+    for (auto& lvl : p.presum) {
+        int64_t e = 0;
+        for (auto& d : lvl) { d.elem_begin = e; e += d.elems; }
+    }
+    for (auto& lvl : p.combine) {
+        int64_t e = 0;
+        for (auto& d : lvl) { d.elem_begin = e; e += d.elems; }
+    }
+    return p;
+}
+
+}  // namespace ata

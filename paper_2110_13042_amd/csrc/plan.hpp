@@ -1,0 +1,132 @@
+// Plan of one Gram product: the AtA recursion tree flattened into launch
+// phases, plus the plain-old-data task descriptors the kernels read.
+//
+// The recursion is Alg. 1 (Sec. 3.1) in its rows-kept form: an AtA node on
+// the column range [c0, c0 + w) is a SYRK leaf when w <= b; otherwise it
+// splits w into n1 = floor(w/2), n2 = ceil(w/2) (Eq. "submatA"), recurses on
+// both column halves for the diagonal blocks C11 and C22 and hands the
+// off-diagonal block C21 = A[:, c0+n1:]^T A[:, c0:c0+n1] (Eq. "Cij") to a
+// Strassen node.  A Strassen node computing C = X^T Y splits m, n and k
+// floor/ceil, forms five sums of X blocks and five of Y blocks at the ceil
+// dimensions (operands one row or column short act as if padded with zeros,
+// Sec. 3.1's simulated padding), multiplies seven pairs and combines the
+// products into the four quadrants (Strassen's scheme, Sec. 3.2).
+//
+// The GPU runs every level's pre-sums in one launch (top-down), every leaf
+// product of the whole tree in one grouped launch, then every level's
+// combines in one launch (bottom-up).  All temporaries sit in one arena
+// (Sec. 3.3's preallocated workspace).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ata {
+
+enum Mode : int32_t { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2, MODE_FP8 = 3 };
+
+// Base buffers a view can point into.
+enum Base : int32_t { BASE_A = 0, BASE_ARENA = 1 };
+
+// Element (r, c) of the rows x cols logical operand is
+// base[off + r * ld + c] when r < prows and c < pcols, and 0 otherwise.
+struct View {
+    int32_t base;
+    int32_t pad_;
+    int64_t off, ld;
+    int64_t rows, cols;       // logical
+    int64_t prows, pcols;     // physical extent (<= logical)
+};
+
+enum LeafKind : int32_t { LEAF_SYRK = 0, LEAF_GEMM = 1 };
+enum OutKind : int32_t { OUT_PACKED = 0, OUT_DENSE = 1 };
+
+// One leaf product out = X^T Y (SYRK: X == Y, lower triangle only).
+struct LeafDesc {
+    int32_t kind;             // LeafKind
+    int32_t out_kind;         // OutKind
+    int32_t tiles_m, tiles_n; // output tile grid (SYRK: tiles_m == tiles_n)
+    int64_t tile_begin;       // first global tile index of this task
+    int64_t tiles;            // tiles of this task
+    int64_t K;                // contraction length (rows)
+    View X, Y;
+    int64_t rows, cols;       // logical output (rows = X.cols, cols = Y.cols)
+    int64_t out_off, out_ld;  // OUT_DENSE: arena element offset and row stride
+    int64_t out_row0, out_col0;  // OUT_PACKED: position in C
+    int32_t pred_node;        // run only when flags[pred_node] == pred_value (-1: always)
+    int32_t pred_value;
+    int32_t fb_node;          // SYRK leaves: FP64 path when flags[fb_node] != 0 (-1: never)
+    int32_t depth;            // Strassen level of the leaf (0 = directly in C)
+};
+
+// Five Strassen pre-sums of one operand (X side: S1..S5, Y side: T1..T5).
+struct PresumDesc {
+    View V;                   // the parent operand (m x n logical)
+    int64_t m1, m2, n1, n2;
+    int64_t out_off;          // arena: five m2 x n2 buffers, row stride n2
+    int64_t elem_begin;       // first global work item (groups of 4 columns)
+    int64_t elems;
+    int32_t side;             // 0 = X (S sums), 1 = Y (T sums)
+    int32_t pred_node, pred_value;
+    int32_t pad_;
+};
+
+// Strassen combine: seven n2 x k2 products into the four quadrants.
+struct CombineDesc {
+    int64_t m_off;            // arena: seven n2 x k2 buffers, row stride k2
+    int64_t n1, n2, k1, k2;
+    int32_t out_kind;
+    int32_t pred_node;
+    int64_t out_off, out_ld;      // OUT_DENSE target (parent's product buffer)
+    int64_t out_row0, out_col0;   // OUT_PACKED target (C21 block of C)
+    int64_t elem_begin, elems;
+    int32_t pred_value;
+    int32_t pad_;
+};
+
+// AtA node for the spread flags: columns [c0, c0 + w).
+struct NodeDesc {
+    int64_t c0, w;
+};
+
+struct PlanOptions {
+    int64_t leaf_cutoff = 0;       // 0: default for the mode
+    int32_t max_depth = -1;        // -1: default for the mode
+    double spread_tau = 4096.0;    // <= 0: no fallback
+};
+
+struct PlanStats {
+    int64_t ata_nodes = 0, syrk_leaves = 0, gemm_leaves = 0, strassen_nodes = 0;
+    int64_t mults = 0;
+    int32_t max_levels = 0;
+};
+
+struct Plan {
+    int32_t mode = MODE_F32;
+    int64_t m = 0, n = 0, lda = 0;
+    int64_t b = 0;
+    int32_t max_depth = 0;
+    bool fallback = false;
+    std::vector<std::vector<PresumDesc>> presum;    // [level-1] top-down
+    std::vector<LeafDesc> leaves;                   // LPT order (longest first)
+    std::vector<std::vector<CombineDesc>> combine;  // [height-1] bottom-up
+    std::vector<NodeDesc> nodes;                    // AtA nodes (flags)
+    int64_t arena_elems = 0;                        // in the mode's sum/product type
+    int64_t total_tiles = 0;
+    PlanStats stats;
+    int64_t elem_bytes() const { return mode == MODE_F64 ? 8 : 4; }
+    int64_t launches() const;
+};
+
+int64_t default_leaf_cutoff(int32_t mode, int64_t m, int64_t n);
+int32_t default_max_depth(int32_t mode);
+
+// Builds the plan (host only).  Throws std::invalid_argument on bad sizes.
+Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);
+
+// Tile sizes of the leaf kernels (shared with the device code).
+constexpr int TILE_M = 128;
+constexpr int TILE_N = 128;
+
+}  // namespace ata

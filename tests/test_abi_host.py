@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI: the library loads, exports what the header
+declares, plans like the oracle's recursion, and rejects bad arguments before
+touching a device (CPU only)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import recursive
+from paper_2110_13042_amd import ata
+
+
+def test_library_exports_every_declared_symbol():
+    syms = ata.header_symbols()
+    assert {"ata_create", "ata_gram", "ata_gram_batched", "ata_destroy"} <= set(syms)
+    lib = ata.lib()
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_status_strings():
+    for code, name in ata.STATUS.items():
+        assert ata.status_string(code) == name
+
+
+@pytest.mark.parametrize("m,n,b,depth", [(1024, 1024, 256, -1), (8192, 8192, 1024, 3),
+                                         (8192, 8192, 512, 3), (262144, 4096, 1024, 3),
+                                         (300, 257, 16, 2), (1000, 999, 100, 4), (50, 37, 5, 64)])
+def test_plan_matches_oracle_recursion(m, n, b, depth):
+    dtype = ata.F64 if depth == 64 or depth == -1 else ata.F32
+    info, leaves = ata.ata_plan_query(m, n, dtype, b, depth)
+    d = 64 if depth == -1 else depth
+    c = recursive.count(m, n, b, split_m=False, max_strassen_depth=d)
+    assert info["multiplications"] == c.mults
+    assert info["syrk_leaves"] == c.syrk_leaves
+    assert info["gemm_leaves"] == c.gemm_leaves
+    assert info["strassen_nodes"] == c.strassen_nodes
+    assert info["ata_nodes"] == c.ata_nodes
+    assert len(leaves) == c.syrk_leaves + c.gemm_leaves
+    # leaves written straight into C tile the lower triangle exactly once
+    # (Strassen products land in the workspace, their roots cover the rest)
+    cover = np.zeros((n, n), dtype=np.int32) if n <= 1200 else None
+    if cover is not None:
+        for L in leaves:
+            if L["out_row0"] < 0:
+                continue
+            r0, c0, R, Cn = L["out_row0"], L["out_col0"], L["rows"], L["cols"]
+            blk = cover[r0:r0 + R, c0:c0 + Cn]
+            blk += np.tril(np.ones((R, Cn), np.int32)) if L["kind"] == 0 else 1
+        for (x0, y0, _, nn, kk, levels, _) in c.strassen_roots:
+            if levels > 0:
+                cover[x0:x0 + nn, y0:y0 + kk] += 1
+        assert np.array_equal(cover, np.tril(np.ones((n, n), np.int32)))
+
+
+def test_plan_mult_count_pin():
+    info, _ = ata.ata_plan_query(1024, 1024, ata.F64, 256, -1)
+    assert info["multiplications"] == 503840768
+    assert info["strassen_levels"] == 1
+
+
+def test_plan_query_rejects_bad_arguments():
+    with pytest.raises(ata.AtaError):
+        ata.ata_plan_query(-1, 5, ata.F64)
+    with pytest.raises(ata.AtaError):
+        ata.ata_plan_query(5, 5, 9)
+
+
+def test_gram_argument_errors_need_no_device():
+    L = ata.lib()
+    # NULL handle, negative sizes, lda < n: rejected synchronously
+    assert L.ata_gram(None, None, 4, 4, 4, 1, None, None) == 1
+    assert L.ata_set_option(None, 0, 1.0) == 1
+    assert L.ata_get_report(None, None) == 1
+    assert L.ata_destroy(None) == 0
+    assert L.ata_gram_batched(None, 0, None, None, None, None, 1, None, None) == 1
+    h = ctypes.c_void_p()
+    assert L.ata_create(None) == 1
