@@ -1,0 +1,215 @@
+"""Benchmark of the AtA Gram product on one MI355X.
+
+One step = one ata_gram call: every phase of the plan (column norms and
+spread flags, Strassen pre-sums, all leaf products, combines) on a
+synthetic input already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode f32|f64|bf16x3|fp8]
+                    [--workload NAME] [--no-cpu-baseline]
+
+The effective rate is m n (n+1) / t (the paper's effective-GFLOPs measure
+with r = 1, in rectangular form).  The roofline object covers the dominant
+kernel, the grouped leaf-product launch: its algorithmic flops are twice the
+plan's multiplications and its duration is measured with HIP events on the
+stream it runs on (the library's profiling option).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0, "fp8": 5033.2}
+MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "fp8": 3}
+DEFAULT_WORKLOAD = {"f64": "square_f64_1024", "f32": "square_f32_8192",
+                    "bf16x3": "square_f32_8192", "fp8": "square_f32_8192"}
+LEAF_KERNEL_FILES = ["paper_2110_13042_amd/csrc/leaf.hip", "paper_2110_13042_amd/csrc/kernels_common.hpp"]
+
+
+def leaf_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in LEAF_KERNEL_FILES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(mode: str, workload: str):
+    """HBM bytes per leaf launch from the committed counter summary, or None.
+
+    The summary records FETCH_SIZE and WRITE_SIZE of the leaf kernel, the
+    calibration factor from a plain copy of known size, and the hash of the
+    kernel sources it was taken on; a different hash means the kernel has
+    changed since, and the figure no longer applies.
+    """
+    path = os.path.join(ROOT, "profiles", f"leaf_{workload}_{mode}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("leaf_source_sha256_16") != leaf_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(A: np.ndarray, samples: int):
+    """The plain FP64 oracle on a bounded sample: `samples` full columns of C."""
+    from oracle import plain
+    from paper_2110_13042_amd import workloads
+    m, n = A.shape
+    S = workloads.sampled_columns(n, min(samples, n), seed=1234)
+    threads = plain.threads_used(0)
+    t0 = time.perf_counter()
+    cols = plain.gram_cols(A, S)
+    dt = time.perf_counter() - t0
+    flops = 2.0 * m * n * len(S)
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(S)} of {n} full columns of C (plain FP64 oracle, same A), "
+                      f"{dt:.2f} s; full-problem time extrapolates to "
+                      f"{dt * (n + 1) / (2 * len(S)):.1f} s"}, S, cols
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="f32", choices=sorted(MODES))
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--leaf-cutoff", type=int, default=0)
+    ap.add_argument("--max-depth", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-samples", type=int, default=512)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the "
+              "multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2110_13042_amd import ata, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    mode = args.mode
+    wl = args.workload or DEFAULT_WORKLOAD[mode]
+    w = workloads.WORKLOADS[wl]
+    print(f"[bench] generating {wl} ({w.description})", file=sys.stderr, flush=True)
+    A_np = workloads.make(wl)
+    if mode != "f64" and A_np.dtype != np.float32:
+        A_np = A_np.astype(np.float32)
+    m, n = A_np.shape
+    tdt = torch.float64 if mode == "f64" else torch.float32
+    A = torch.from_numpy(A_np).to(dev, tdt)
+    C = torch.empty(n * (n + 1) // 2, dtype=tdt, device=dev)
+    h = ata.Handle()
+    if args.leaf_cutoff:
+        h.set("leaf_cutoff", args.leaf_cutoff)
+    if args.max_depth >= 0:
+        h.set("max_depth", args.max_depth)
+    stream = torch.cuda.current_stream(dev)
+    sp = stream.cuda_stream
+    lda = A.stride(0)
+
+    def step():
+        ata.ata_gram(h.h, A.data_ptr(), m, n, lda, MODES[mode], C.data_ptr(), sp)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    # timed region: K steps, phase events recorded on the same stream
+    h.set("profile", 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = h.report()
+    h.set("profile", 0)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    eff = m * n * (n + 1) / (ms_per_step * 1e-3) / 1e12
+    calls = max(rep["profiled_calls"], 1)
+    leaf_ms = rep["phase_ms"][2] / calls
+    leaf_flops = 2.0 * rep["multiplications"]
+    achieved = leaf_flops / (leaf_ms * 1e-3) / 1e12 if leaf_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[mode]
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step, phases(ms/call) "
+          f"{[round(x / calls, 4) for x in rep['phase_ms']]}", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 3 x copy of 1 GiB", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "effective TFLOP/s m*n*(n+1)/t (AtA Gram product C = A^T A, packed lower)",
+        "value": round(eff, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": mode,
+        "data": "synthetic",
+        "config": {"workload": wl, "m": m, "n": n, "mode": mode,
+                   "leaf_cutoff": rep["leaf_cutoff"], "strassen_levels": rep["strassen_levels"],
+                   "multiplications": rep["multiplications"],
+                   "mult_ratio_vs_syrk": round(rep["multiplications"] / (m * n * (n + 1) / 2), 4),
+                   "launches_per_step": rep["kernel_launches"],
+                   "workspace_bytes": rep["workspace_bytes"],
+                   "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
+                       ["norms_flags", "presum", "leaves", "combine", "residual"], rep["phase_ms"])},
+                   "frac_of_dtype_peak_effective": round(eff / peak, 4)},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": traffic_from_profiles(mode, wl),
+                     "kernel": "leaf_kernel (all SYRK/GEMM leaf products, one grouped launch)",
+                     "algorithmic_flops_per_launch": leaf_flops,
+                     "avg_launch_ms": round(leaf_ms, 4)},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline on a column sample", file=sys.stderr, flush=True)
+        base, S, cols = cpu_baseline(A_np, args.cpu_samples)
+        out["cpu_baseline"] = base
+        Cp = C.double().cpu().numpy()
+        ii = np.arange(n)[:, None]
+        jj = np.asarray(S)[None, :]
+        r, c = np.maximum(ii, jj), np.minimum(ii, jj)
+        got = Cp[r * (r + 1) // 2 + c]
+        out["config"]["rel_error_sampled_columns"] = float(np.linalg.norm(got - cols) / np.linalg.norm(cols))
+    print(json.dumps(out), flush=True)
+    h.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -78,7 +78,11 @@ typedef enum {
     /* Upper bound in bytes on the workspace; 0 = no bound (default). */
     ATA_OPT_WORKSPACE_LIMIT = 4,
     /* Seed of the residual probe signs (SplitMix64 counter stream). */
-    ATA_OPT_RESIDUAL_SEED = 5
+    ATA_OPT_RESIDUAL_SEED = 5,
+    /* 1 = record HIP events on the call's stream around each launch phase of
+       every ata_gram call; ata_get_report then synchronises and returns the
+       summed phase times since the option was last set (default 0). */
+    ATA_OPT_PROFILE = 6
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */
@@ -98,6 +102,9 @@ typedef struct {
     int64_t flagged_nodes;        /* AtA nodes flagged for the FP64 fallback;
                                      -1 if not evaluated (syncs the stream)   */
     double residual;              /* Freivalds residual; -1 if not computed   */
+    int64_t profiled_calls;       /* calls timed since ATA_OPT_PROFILE was set */
+    double phase_ms[5];           /* summed ms: column norms + flags, pre-sums,
+                                     leaf products, combines, residual        */
 } ata_report_t;
 
 /* One leaf of a plan, as returned by ata_plan_query. */

@@ -24,7 +24,7 @@ F64, F32, F32_BF16X3, F32_FP8E4M3 = 0, 1, 2, 3
 DTYPE_NAMES = {"f64": F64, "f32": F32, "bf16x3": F32_BF16X3, "fp8": F32_FP8E4M3}
 
 OPT_LEAF_CUTOFF, OPT_MAX_STRASSEN_DEPTH, OPT_SPREAD_TAU = 0, 1, 2
-OPT_RESIDUAL, OPT_WORKSPACE_LIMIT, OPT_RESIDUAL_SEED = 3, 4, 5
+OPT_RESIDUAL, OPT_WORKSPACE_LIMIT, OPT_RESIDUAL_SEED, OPT_PROFILE = 3, 4, 5, 6
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -43,10 +43,13 @@ class Report(ctypes.Structure):
                 ("syrk_leaves", ctypes.c_int64), ("gemm_leaves", ctypes.c_int64),
                 ("strassen_nodes", ctypes.c_int64), ("multiplications", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("kernel_launches", ctypes.c_int64),
-                ("flagged_nodes", ctypes.c_int64), ("residual", ctypes.c_double)]
+                ("flagged_nodes", ctypes.c_int64), ("residual", ctypes.c_double),
+                ("profiled_calls", ctypes.c_int64), ("phase_ms", ctypes.c_double * 5)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["phase_ms"] = list(self.phase_ms)
+        return d
 
 
 class Leaf(ctypes.Structure):
@@ -170,7 +173,8 @@ class Handle:
     def set(self, name: str, value) -> None:
         key = {"leaf_cutoff": OPT_LEAF_CUTOFF, "max_depth": OPT_MAX_STRASSEN_DEPTH,
                "spread_tau": OPT_SPREAD_TAU, "residual": OPT_RESIDUAL,
-               "workspace_limit": OPT_WORKSPACE_LIMIT, "residual_seed": OPT_RESIDUAL_SEED}[name]
+               "workspace_limit": OPT_WORKSPACE_LIMIT, "residual_seed": OPT_RESIDUAL_SEED,
+               "profile": OPT_PROFILE}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

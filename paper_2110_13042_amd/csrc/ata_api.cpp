@@ -64,11 +64,42 @@ struct ata_ctx {
     double* last_residual = nullptr;
     int64_t last_nodes = 0;
     ata_report_t report{};
+    // phase profiling: six events per profiled call, summed at report time
+    bool profile = false;
+    std::vector<hipEvent_t> events;   // pool, grows on demand
+    size_t events_used = 0;
+    int64_t profiled_calls = 0;
+    double phase_ms[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
 
 ata_status_t hip_status(hipError_t e) { return e == hipSuccess ? ATA_OK : ATA_ERR_HIP; }
+
+constexpr int EVENTS_PER_CALL = 6;
+
+// Sum the elapsed times of all recorded calls (waits for them) and reset.
+hipError_t drain_events(ata_ctx* h) {
+    for (size_t base = 0; base + EVENTS_PER_CALL <= h->events_used; base += EVENTS_PER_CALL) {
+        hipError_t e = hipEventSynchronize(h->events[base + EVENTS_PER_CALL - 1]);
+        if (e != hipSuccess) return e;
+        for (int ph = 0; ph < 5; ++ph) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, h->events[base + ph], h->events[base + ph + 1]);
+            if (e != hipSuccess) return e;
+            h->phase_ms[ph] += ms;
+        }
+        ++h->profiled_calls;
+    }
+    h->events_used = 0;
+    return hipSuccess;
+}
+
+void clear_events(ata_ctx* h) {
+    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    h->events.clear();
+    h->events_used = 0;
+}
 
 ata_status_t ensure(void*& ptr, size_t& cap, size_t bytes) {
     if (bytes <= cap) return ATA_OK;
@@ -187,6 +218,8 @@ ata_status_t ata_destroy(ata_handle_t h) {
     if (!h) return ATA_OK;
     (void)hipSetDevice(h->device);
     h->plans.clear();
+    (void)hipDeviceSynchronize();
+    clear_events(h);
     if (h->arena) (void)hipFree(h->arena);
     if (h->aux) (void)hipFree(h->aux);
     delete h;
@@ -216,6 +249,12 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             return ATA_OK;
         case ATA_OPT_RESIDUAL_SEED:
             h->seed = (uint64_t)value;
+            return ATA_OK;
+        case ATA_OPT_PROFILE:
+            if (h->events_used) (void)drain_events(h);
+            h->profile = value != 0.0;
+            h->profiled_calls = 0;
+            for (double& x : h->phase_ms) x = 0.0;
             return ATA_OK;
     }
     return ATA_ERR_INVALID_VALUE;
@@ -318,26 +357,49 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     double* res_work = reinterpret_cast<double*>(aux + ax.res_work_off);
     double* res = reinterpret_cast<double*>(aux + ax.res_off);
     hipError_t e = hipSuccess;
+    hipEvent_t* ev = nullptr;
+    if (h->profile) {
+        if (h->events_used + EVENTS_PER_CALL > 4096) {
+            e = drain_events(h);
+            if (e != hipSuccess) return ATA_ERR_HIP;
+        }
+        while (h->events.size() < h->events_used + EVENTS_PER_CALL) {
+            hipEvent_t x;
+            if (hipEventCreate(&x) != hipSuccess) return ATA_ERR_HIP;
+            h->events.push_back(x);
+        }
+        ev = h->events.data() + h->events_used;
+        h->events_used += EVENTS_PER_CALL;
+    }
+    auto mark = [&](int i) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
+    };
+    mark(0);
     if (p.fallback) {
         e = launch_colnorms(static_cast<const float*>(A), m, n, lda, partial, colnorm_chunks(m), nu, st);
         if (e == hipSuccess)
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
+    mark(1);
     for (size_t l = 0; e == hipSuccess && l < p.presum.size(); ++l) {
         const auto& lv = p.presum[l];
         e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
                           A, h->arena, flags, st);
     }
+    mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
                           flags, h->chunk, st);
+    mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
         e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
                            C_packed, h->arena, flags, st);
     }
+    mark(4);
     if (e == hipSuccess && h->residual)
         e = launch_residual(mode, A, m, n, lda, C_packed, h->seed, res_work, res, st);
+    mark(5);
     if (e != hipSuccess) return ATA_ERR_HIP;
 
     fill_report(h->report, p);
@@ -385,6 +447,11 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
 
 ata_status_t ata_get_report(ata_handle_t h, ata_report_t* out) {
     if (!h || !out) return ATA_ERR_INVALID_VALUE;
+    if (h->events_used) {
+        if (hipSetDevice(h->device) != hipSuccess || drain_events(h) != hipSuccess) return ATA_ERR_HIP;
+    }
+    h->report.profiled_calls = h->profiled_calls;
+    for (int i = 0; i < 5; ++i) h->report.phase_ms[i] = h->phase_ms[i];
     if (h->pending_flags || h->pending_residual) {
         if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
         if (hipStreamSynchronize(h->last_stream) != hipSuccess) return ATA_ERR_HIP;
