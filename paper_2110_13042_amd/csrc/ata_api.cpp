@@ -36,7 +36,9 @@ struct DevicePlan {
     Plan plan;
     void* d_buf = nullptr;
     LeafDesc* d_leaves = nullptr;
+    LeafDesc* d_fb_leaves = nullptr;
     std::vector<PresumDesc*> d_presum;
+    PackDesc* d_pack = nullptr;
     std::vector<CombineDesc*> d_combine;
     NodeDesc* d_nodes = nullptr;
     ~DevicePlan() { if (d_buf) (void)hipFree(d_buf); }
@@ -123,6 +125,8 @@ ata_status_t upload_plan(DevicePlan& dp) {
     for (auto& l : p.presum) bytes += align256(l.size() * sizeof(PresumDesc));
     for (auto& l : p.combine) bytes += align256(l.size() * sizeof(CombineDesc));
     bytes += align256(p.nodes.size() * sizeof(NodeDesc));
+    bytes += align256(p.pack.size() * sizeof(PackDesc));
+    bytes += align256(p.fb_leaves.size() * sizeof(LeafDesc));
     if (bytes == 0) return ATA_OK;
     std::vector<unsigned char> host(bytes, 0);
     if (hipMalloc(&dp.d_buf, bytes) != hipSuccess) {
@@ -140,6 +144,8 @@ ata_status_t upload_plan(DevicePlan& dp) {
     for (auto& l : p.presum) dp.d_presum.push_back(static_cast<PresumDesc*>(put(l.data(), l.size() * sizeof(PresumDesc))));
     for (auto& l : p.combine) dp.d_combine.push_back(static_cast<CombineDesc*>(put(l.data(), l.size() * sizeof(CombineDesc))));
     dp.d_nodes = static_cast<NodeDesc*>(put(p.nodes.data(), p.nodes.size() * sizeof(NodeDesc)));
+    dp.d_pack = static_cast<PackDesc*>(put(p.pack.data(), p.pack.size() * sizeof(PackDesc)));
+    dp.d_fb_leaves = static_cast<LeafDesc*>(put(p.fb_leaves.data(), p.fb_leaves.size() * sizeof(LeafDesc)));
     return hip_status(hipMemcpy(dp.d_buf, host.data(), bytes, hipMemcpyHostToDevice));
 }
 
@@ -265,7 +271,7 @@ ata_status_t ata_plan_query(int64_t m, int64_t n, ata_dtype_t dtype, int64_t lea
                             int64_t cap, int64_t* n_leaves) {
     if (!valid_dtype(dtype) || m < 0 || n < 0 || cap < 0 || (cap > 0 && !leaves))
         return ATA_ERR_INVALID_VALUE;
-    if (dtype == ATA_F32_BF16X3 || dtype == ATA_F32_FP8E4M3) return ATA_ERR_NOT_SUPPORTED;
+    if (dtype == ATA_F32_FP8E4M3) return ATA_ERR_NOT_SUPPORTED;
     PlanOptions o;
     o.leaf_cutoff = leaf_cutoff > 0 ? leaf_cutoff : 0;
     o.max_depth = max_depth;
@@ -298,7 +304,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         return ATA_ERR_INVALID_VALUE;
     if (n > 0 && !C_packed) return ATA_ERR_INVALID_VALUE;
     if (n > 0 && m > 0 && !A) return ATA_ERR_INVALID_VALUE;
-    if (dtype == ATA_F32_BF16X3 || dtype == ATA_F32_FP8E4M3) return ATA_ERR_NOT_SUPPORTED;
+    if (dtype == ATA_F32_FP8E4M3) return ATA_ERR_NOT_SUPPORTED;
     const size_t es = dtype == ATA_F64 ? 8 : 4;
     if (n > 0 && m > 0) {
         const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (size_t)((m - 1) * lda + n) * es;
@@ -386,10 +392,16 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
                           A, h->arena, flags, st);
     }
+    if (e == hipSuccess && !p.pack.empty())
+        e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
+                        A, h->arena, flags, st);
     mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
                           flags, h->chunk, st);
+    if (e == hipSuccess && !p.fb_leaves.empty())
+        e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
+                                   h->arena, flags, h->chunk, st);
     mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];

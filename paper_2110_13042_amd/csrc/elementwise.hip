@@ -16,6 +16,30 @@ constexpr int EW_THREADS = 256;
 // sums.  Reads the four quadrant values of the parent operand (zero outside
 // its physical extent and outside the quadrant's real size) and writes the
 // five sums, including the zero padding of the ceil-sized buffers.
+template <class T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { struct type { double x, y, z, w; }; };
+
+template <class T>
+__device__ __forceinline__ typename Vec4<T>::type ld4(const T* p) {
+    if constexpr (sizeof(T) == 4) {
+        return *reinterpret_cast<const float4*>(p);
+    } else {
+        const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+        return {a.x, a.y, b.x, b.y};
+    }
+}
+template <class T>
+__device__ __forceinline__ void st4(T* p, const typename Vec4<T>::type& v) {
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = v;
+    } else {
+        reinterpret_cast<double2*>(p)[0] = make_double2(v.x, v.y);
+        reinterpret_cast<double2*>(p)[1] = make_double2(v.z, v.w);
+    }
+}
+#define V4OP(a, op, b) {a.x op b.x, a.y op b.y, a.z op b.z, a.w op b.w}
+
 template <class T>
 __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* tasks, int ntasks,
                                                             int64_t items, const T* A, T* arena,
@@ -32,6 +56,29 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
     const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
     const int64_t plane = m2 * n2;
     T* out = arena + d.out_off + r * n2;
+    // fast path: four full columns in every quadrant, 16-byte aligned rows
+    const bool inside = r < m1 && m1 + r < pr && c0 + 4 <= n1 && n1 + c0 + 4 <= pc;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(V) | (uintptr_t)(ld * sizeof(T)) |
+                           (uintptr_t)(n1 * sizeof(T)) | (uintptr_t)(n2 * sizeof(T))) & 15) == 0;
+    if (inside && aligned) {
+        typedef typename Vec4<T>::type V4;
+        const V4 a11 = ld4(V + r * ld + c0), a12 = ld4(V + r * ld + n1 + c0);
+        const V4 a21 = ld4(V + (m1 + r) * ld + c0), a22 = ld4(V + (m1 + r) * ld + n1 + c0);
+        if (d.side == 0) {
+            st4(out + 0 * plane + c0, V4 V4OP(a11, +, a22));   // S1 = X11 + X22
+            st4(out + 1 * plane + c0, V4 V4OP(a12, +, a22));   // S2 = X12 + X22
+            st4(out + 2 * plane + c0, V4 V4OP(a11, +, a21));   // S3 = X11 + X21
+            st4(out + 3 * plane + c0, V4 V4OP(a12, -, a11));   // S4 = X12 - X11
+            st4(out + 4 * plane + c0, V4 V4OP(a21, -, a22));   // S5 = X21 - X22
+        } else {
+            st4(out + 0 * plane + c0, V4 V4OP(a11, +, a22));   // T1 = Y11 + Y22
+            st4(out + 1 * plane + c0, V4 V4OP(a12, -, a22));   // T2 = Y12 - Y22
+            st4(out + 2 * plane + c0, V4 V4OP(a21, -, a11));   // T3 = Y21 - Y11
+            st4(out + 3 * plane + c0, V4 V4OP(a11, +, a12));   // T4 = Y11 + Y12
+            st4(out + 4 * plane + c0, V4 V4OP(a21, +, a22));   // T5 = Y21 + Y22
+        }
+        return;
+    }
     auto get = [&](int qr, int qc, int64_t c) -> T {
         const int64_t rr = qr ? m1 + r : r, cc = qc ? n1 + c : c;
         const bool in = r < (qr ? m2 : m1) && c < (qc ? n2 : n1) && rr < pr && cc < pc;
@@ -43,19 +90,58 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
         if (c >= n2) break;
         const T a11 = get(0, 0, c), a12 = get(0, 1, c), a21 = get(1, 0, c), a22 = get(1, 1, c);
         if (d.side == 0) {
-            out[0 * plane + c] = a11 + a22;   // S1 = X11 + X22
-            out[1 * plane + c] = a12 + a22;   // S2 = X12 + X22
-            out[2 * plane + c] = a11 + a21;   // S3 = X11 + X21
-            out[3 * plane + c] = a12 - a11;   // S4 = X12 - X11
-            out[4 * plane + c] = a21 - a22;   // S5 = X21 - X22
+            out[0 * plane + c] = a11 + a22;
+            out[1 * plane + c] = a12 + a22;
+            out[2 * plane + c] = a11 + a21;
+            out[3 * plane + c] = a12 - a11;
+            out[4 * plane + c] = a21 - a22;
         } else {
-            out[0 * plane + c] = a11 + a22;   // T1 = Y11 + Y22
-            out[1 * plane + c] = a12 - a22;   // T2 = Y12 - Y22
-            out[2 * plane + c] = a21 - a11;   // T3 = Y21 - Y11
-            out[3 * plane + c] = a11 + a12;   // T4 = Y11 + Y12
-            out[4 * plane + c] = a21 + a22;   // T5 = Y21 + Y22
+            out[0 * plane + c] = a11 + a22;
+            out[1 * plane + c] = a12 - a22;
+            out[2 * plane + c] = a21 - a11;
+            out[3 * plane + c] = a11 + a12;
+            out[4 * plane + c] = a21 + a22;
         }
     }
+}
+
+// ------------------------------------------------------ split-BF16 packing
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+    const v2bf p = {(__bf16)a, (__bf16)b};          // round to nearest even
+    return __builtin_bit_cast(uint32_t, p);
+}
+
+// Work item = one 16-byte chunk (row-group g, column c): rows 8g..8g+7 of
+// column c split into hi = bf16(a) and lo = bf16(a - hi).
+__global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks, int ntasks,
+                                                          int64_t items, const float* A,
+                                                          float* arena, const uint8_t* flags) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= items) return;
+    const PackDesc& d = tasks[find_task(tasks, ntasks, x)];
+    if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    const int64_t e = x - d.elem_begin;
+    const int64_t g = e / d.cols, c = e - g * d.cols;
+    const float* src = (d.src.base == BASE_A ? A : arena) + d.src.off;
+    float v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t r = 8 * g + q;
+        v[q] = (r < d.src.prows && c < d.src.pcols) ? src[r * d.src.ld + c] : 0.f;
+    }
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        hi[q] = pk_bf16(v[2 * q], v[2 * q + 1]);
+        const float h0 = __builtin_bit_cast(float, hi[q] << 16);
+        const float h1 = __builtin_bit_cast(float, hi[q] & 0xFFFF0000u);
+        lo[q] = pk_bf16(v[2 * q] - h0, v[2 * q + 1] - h1);
+    }
+    uint4* H = reinterpret_cast<uint4*>(arena + d.dst) + g * d.cols + c;
+    uint4* L = reinterpret_cast<uint4*>(arena + d.dst + d.lo_delta) + g * d.cols + c;
+    *H = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    *L = make_uint4(lo[0], lo[1], lo[2], lo[3]);
 }
 
 // ---------------------------------------------------------------- combine
@@ -76,12 +162,39 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
     const int64_t i = e / groups, j0 = (e - i * groups) << 2;
     const int64_t n1 = d.n1, k1 = d.k1, k2 = d.k2, plane = d.n2 * d.k2;
     const T* M = arena + d.m_off + i * k2;
-    auto put = [&](int64_t ii, int64_t jj, T v) {
-        if (d.out_kind == OUT_PACKED)
-            C[packed_index(d.out_row0 + ii, d.out_col0 + jj)] = v;
-        else
-            arena[d.out_off + ii * d.out_ld + jj] = v;
+    auto dst = [&](int64_t ii, int64_t jj) -> T* {
+        return d.out_kind == OUT_PACKED ? C + packed_index(d.out_row0 + ii, d.out_col0 + jj)
+                                        : arena + d.out_off + ii * d.out_ld + jj;
     };
+    if (i < n1 && j0 + 4 <= k1 && (k2 & 3) == 0) {
+        typedef typename Vec4<T>::type V4;
+        const V4 m1 = ld4(M + j0), m2 = ld4(M + plane + j0), m3 = ld4(M + 2 * plane + j0);
+        const V4 m4 = ld4(M + 3 * plane + j0), m5 = ld4(M + 4 * plane + j0);
+        const V4 m6 = ld4(M + 5 * plane + j0), m7 = ld4(M + 6 * plane + j0);
+        const V4 t14 = V4OP(m1, +, m4);
+        const V4 t145 = V4OP(t14, -, m5);
+        const V4 c11 = V4OP(t145, +, m7);
+        const V4 c12 = V4OP(m3, +, m5);
+        const V4 c21 = V4OP(m2, +, m4);
+        const V4 t12 = V4OP(m1, -, m2);
+        const V4 t123 = V4OP(t12, +, m3);
+        const V4 c22 = V4OP(t123, +, m6);
+        T* p11 = dst(i, j0);
+        T* p12 = dst(i, k1 + j0);
+        T* p21 = dst(n1 + i, j0);
+        T* p22 = dst(n1 + i, k1 + j0);
+        const V4* vs[4] = {&c11, &c12, &c21, &c22};
+        T* ps[4] = {p11, p12, p21, p22};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if ((reinterpret_cast<uintptr_t>(ps[q]) & 15) == 0) {
+                st4(ps[q], *vs[q]);
+            } else {
+                ps[q][0] = vs[q]->x; ps[q][1] = vs[q]->y; ps[q][2] = vs[q]->z; ps[q][3] = vs[q]->w;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int64_t j = j0 + q;
@@ -89,30 +202,51 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
         const T m1 = M[j], m2 = M[plane + j], m3 = M[2 * plane + j], m4 = M[3 * plane + j];
         const T m5 = M[4 * plane + j], m6 = M[5 * plane + j], m7 = M[6 * plane + j];
         if (i < n1) {
-            if (j < k1) put(i, j, ((m1 + m4) - m5) + m7);
-            put(i, k1 + j, m3 + m5);
+            if (j < k1) *dst(i, j) = ((m1 + m4) - m5) + m7;
+            *dst(i, k1 + j) = m3 + m5;
         }
-        if (j < k1) put(n1 + i, j, m2 + m4);
-        put(n1 + i, k1 + j, ((m1 - m2) + m3) + m6);
+        if (j < k1) *dst(n1 + i, j) = m2 + m4;
+        *dst(n1 + i, k1 + j) = ((m1 - m2) + m3) + m6;
     }
 }
 
 // ------------------------------------------------------------ column norms
-constexpr int64_t NORM_ROWS = 1024;
+constexpr int64_t NORM_ROWS = 256;
 
+// partial[chunk][j] = sum of a_rj^2 over the chunk's rows, four columns per
+// thread (16-byte loads when the rows allow it), rows in ascending order.
 template <class T>
 __global__ __launch_bounds__(EW_THREADS) void colnorm_partial(const T* A, int64_t m, int64_t n,
                                                               int64_t lda, double* partial) {
-    const int64_t j = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    const int64_t j0 = ((int64_t)blockIdx.x * EW_THREADS + threadIdx.x) * 4;
     const int64_t chunk = blockIdx.y;
-    if (j >= n) return;
+    if (j0 >= n) return;
     const int64_t r0 = chunk * NORM_ROWS, r1 = r0 + NORM_ROWS < m ? r0 + NORM_ROWS : m;
-    double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) {
-        const double a = (double)A[r * lda + j];
-        s += a * a;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    const bool vec = sizeof(T) == 4 && j0 + 4 <= n &&
+                     ((reinterpret_cast<uintptr_t>(A) | (uintptr_t)(lda * sizeof(T))) & 15) == 0;
+    if (vec) {
+        for (int64_t r = r0; r < r1; ++r) {
+            const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(A) + r * lda + j0);
+            s0 += (double)a.x * (double)a.x;
+            s1 += (double)a.y * (double)a.y;
+            s2 += (double)a.z * (double)a.z;
+            s3 += (double)a.w * (double)a.w;
+        }
+    } else {
+        for (int64_t r = r0; r < r1; ++r) {
+            const T* row = A + r * lda + j0;
+            if (j0 < n) { const double a = (double)row[0]; s0 += a * a; }
+            if (j0 + 1 < n) { const double a = (double)row[1]; s1 += a * a; }
+            if (j0 + 2 < n) { const double a = (double)row[2]; s2 += a * a; }
+            if (j0 + 3 < n) { const double a = (double)row[3]; s3 += a * a; }
+        }
     }
-    partial[chunk * n + j] = s;
+    double* p = partial + chunk * n + j0;
+    p[0] = s0;
+    if (j0 + 1 < n) p[1] = s1;
+    if (j0 + 2 < n) p[2] = s2;
+    if (j0 + 3 < n) p[3] = s3;
 }
 
 __global__ __launch_bounds__(EW_THREADS) void sum_partials(const double* partial, int64_t nchunks,
@@ -284,6 +418,14 @@ hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, in
     return hipGetLastError();
 }
 
+hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const void* A,
+                       void* arena, const uint8_t* flags, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream, d_tasks,
+                       ntasks, items, static_cast<const float*>(A), static_cast<float*>(arena), flags);
+    return hipGetLastError();
+}
+
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
                           void* C, void* arena, const uint8_t* flags, hipStream_t stream) {
     if (items <= 0) return hipSuccess;
@@ -303,7 +445,7 @@ int64_t colnorm_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / NO
 hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
                            int64_t nchunks, double* nu, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(colnorm_partial<float>, dim3(blocks_for(n), (unsigned)nchunks),
+    hipLaunchKernelGGL(colnorm_partial<float>, dim3(blocks_for((n + 3) / 4), (unsigned)nchunks),
                        dim3(EW_THREADS), 0, stream, A, m, n, lda, partial);
     hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), dim3(EW_THREADS), 0, stream, partial,
                        nchunks, n, nu);

@@ -13,9 +13,19 @@ hipError_t launch_leaves(int32_t mode, const LeafDesc* d_tasks, int ntasks, int6
                          const void* A, void* C, void* arena, const uint8_t* flags, int chunk,
                          hipStream_t stream);
 
+// FP64 fallback of flagged SYRK leaves (FP32 inputs and output); the tasks
+// are the plan's fallback-capable SYRK leaves, unflagged ones exit at once.
+hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t ntiles, const void* A,
+                                  void* C, void* arena, const uint8_t* flags, int chunk,
+                                  hipStream_t stream);
+
 // One Strassen level of pre-sums (S1..S5 / T1..T5 for every node of the level).
 hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, int64_t items,
                          const void* A, void* arena, const uint8_t* flags, hipStream_t stream);
+
+// Split-BF16 packing of the leaf operands (one launch for the whole plan).
+hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const void* A,
+                       void* arena, const uint8_t* flags, hipStream_t stream);
 
 // One height of Strassen combines (seven products -> four quadrants).
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,

@@ -15,6 +15,14 @@
 //     j; result register v of lane l -> (i = 8(v/4) + 4(l/32) + v%4, j = l%32)
 //   v_mfma_f64_16x16x4f64:  A lane l -> (i = l%16, k = l/16), B likewise;
 //     result register v of lane l -> (i = 4v + l/16, j = l%16)
+//   v_mfma_f32_32x32x16_bf16: A lane l element e -> (i = l%32, k = 8(l/32) + e),
+//     B likewise; result layout as v_mfma_f32_32x32x2f32
+//
+// Split-BF16 (three products): each FP32 operand element a is split (by the
+// packing pass) into hi = bf16_RNE(a) and lo = bf16_RNE(a - hi) (a - hi is
+// exact in FP32); the tile accumulates Xh^T Yh + Xh^T Yl + Xl^T Yh in FP32.
+// The BF16 MFMA wants each lane's eight consecutive k values of one row i
+// together, so the slab is stored i-major in LDS ([i][k], k contiguous).
 #include "kernels_common.hpp"
 #include "launch.hpp"
 
@@ -30,6 +38,17 @@ constexpr int LD64 = TILE_M + PAD64;
 constexpr size_t LDS32_BYTES = 2 * 2 * BK * LD32 * sizeof(float);
 constexpr size_t LDS64_BYTES = 2 * 2 * BK * LD64 * sizeof(double);
 constexpr size_t LEAF_LDS_BYTES = LDS64_BYTES > LDS32_BYTES ? LDS64_BYTES : LDS32_BYTES;
+constexpr int BKB = 32;         // rows of A per K step, split-BF16 path
+constexpr int LDB = 40;         // bf16 per LDS row: 32 k values + 8 pad (80-byte stride)
+constexpr size_t LDSB_BYTES = 2 * 4 * TILE_M * LDB * 2;   // 2 stages x {Xh, Xl, Yh, Yl}
+// Kernel variant of the FP64 fallback: FP32 inputs, FP64 MFMA, FP32 output.
+constexpr int MODE_FALLBACK = 100;
+constexpr size_t lds_bytes(int mode) {
+    return mode == MODE_BF16X3 ? LDSB_BYTES : mode == MODE_F32 ? LDS32_BYTES : LDS64_BYTES;
+}
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
 struct LeafArgs {
     const LeafDesc* tasks;
@@ -173,6 +192,108 @@ __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, in
             }
 }
 
+// ------------------------------------------------------------ split-BF16 x3
+// Operands come pre-split and packed (see Packed): each 16-byte chunk is the
+// eight consecutive k values of one column, so a slab load is a plain
+// 16-byte load per chunk and an LDS store at [column][k]; no conversion work
+// is left in the K loop.  Loads go through buffer resources bounded by the
+// packed array, so reads past its end return zero instead of faulting.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const float* arena, const Packed& P, bool lo) {
+    const float* b = arena + P.off + (lo ? P.lo_delta : 0);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(b), (short)0,
+                                             (int)(uint32_t)((P.end - P.off) * 4), 0x00020000);
+}
+
+__device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, int tj,
+                            float* C, float* arena, unsigned char* smem) {
+    unsigned short* lds = reinterpret_cast<unsigned short*>(smem);
+    // stage s, array a (0 = Xh, 1 = Xl, 2 = Yh, 3 = Yl): TILE_M rows of LDB bf16
+    auto arr = [&](int s, int a) { return lds + (s * 4 + a) * TILE_M * LDB; };
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    const int c = t & 127, side = t >> 7;          // chunk column; 0 = X, 1 = Y (wave-uniform)
+    const Packed& P = side ? d.PY : d.PX;
+    const __amdgpu_buffer_rsrc_t rh = packed_rsrc(arena_in, P, false), rl = packed_rsrc(arena_in, P, true);
+    const uint32_t colb = (uint32_t)(((side ? tj : ti) * TILE_M + c) * 16);
+    const uint32_t gsb = (uint32_t)(P.gstride * 4);
+    const int64_t K = d.K;
+    const int64_t nk = (K + BKB - 1) / BKB;
+
+    v16f acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    v4u rh4[4], rl4[4];
+    auto gload = [&](int64_t kt) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int64_t grow = kt * 4 + g;
+            if (grow * 8 < K) {
+                const uint32_t off = (uint32_t)grow * gsb + colb;
+                rh4[g] = __builtin_amdgcn_raw_buffer_load_b128(rh, (int)off, 0, 0);
+                rl4[g] = __builtin_amdgcn_raw_buffer_load_b128(rl, (int)off, 0, 0);
+            } else {
+                rh4[g] = v4u{0u, 0u, 0u, 0u};
+                rl4[g] = v4u{0u, 0u, 0u, 0u};
+            }
+        }
+    };
+    auto sstore = [&](int s) {
+        unsigned short* hi = arr(s, 2 * side) + c * LDB;
+        unsigned short* lo = arr(s, 2 * side + 1) + c * LDB;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            *reinterpret_cast<v4u*>(hi + 8 * g) = rh4[g];
+            *reinterpret_cast<v4u*>(lo + 8 * g) = rl4[g];
+        }
+    };
+
+    if (nk > 0) {
+        gload(0);
+        sstore(0);
+    }
+    __syncthreads();
+    const int io = lane & 31, ko = 8 * (lane >> 5);
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        if (kt + 1 < nk) gload(kt + 1);
+        const unsigned short* xh = arr(cur, 0) + (wm * 64 + io) * LDB + ko;
+        const unsigned short* xl = arr(cur, 1) + (wm * 64 + io) * LDB + ko;
+        const unsigned short* yh = arr(cur, 2) + (wn * 64 + io) * LDB + ko;
+        const unsigned short* yl = arr(cur, 3) + (wn * 64 + io) * LDB + ko;
+#pragma unroll
+        for (int ks = 0; ks < BKB / 16; ++ks) {
+            v8bf ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                ah[s2] = *reinterpret_cast<const v8bf*>(xh + s2 * 32 * LDB + ks * 16);
+                al[s2] = *reinterpret_cast<const v8bf*>(xl + s2 * 32 * LDB + ks * 16);
+                bh[s2] = *reinterpret_cast<const v8bf*>(yh + s2 * 32 * LDB + ks * 16);
+                bl[s2] = *reinterpret_cast<const v8bf*>(yl + s2 * 32 * LDB + ks * 16);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+                }
+        }
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int v = 0; v < 16; ++v) {
+                const int r = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int cc = wn * 64 + b * 32 + (lane & 31);
+                store_elem<float>(d, ti, tj, r, cc, acc[a][b][v], C, arena);
+            }
+}
+
 // ---------------------------------------------------------------- FP64 MFMA
 // InT = double (FP64 mode) or float (FP64 fallback of the FP32 family: the
 // inputs are promoted exactly, the result is rounded to OutT on store).
@@ -277,7 +398,7 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, int ti
 
 template <int MODE>
 __global__ __launch_bounds__(LEAF_THREADS) void leaf_kernel(LeafArgs args) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[MODE == MODE_F64 || MODE == MODE_F32 ? LEAF_LDS_BYTES : LDS32_BYTES];
+    __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
     const int64_t bid = xcd_remap(blockIdx.x, args.ntiles, args.chunk);
     const LeafDesc& d = args.tasks[find_leaf(args.tasks, args.ntasks, bid)];
     if (d.pred_node >= 0 && (int32_t)args.flags[d.pred_node] != d.pred_value) return;
@@ -289,19 +410,27 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_kernel(LeafArgs args) {
         ti = (int)(q / d.tiles_n);
         tj = (int)(q % d.tiles_n);
     }
+    // SYRK leaves under the spread check run in exactly one of the two
+    // launches: the FP64 fallback kernel when their node is flagged, the
+    // mode's own kernel otherwise.
+    const bool flagged = d.fb_node >= 0 && args.flags[d.fb_node];
     if constexpr (MODE == MODE_F64) {
         tile_f64<double, double>(d, view_ptr<double>(d.X, args.A, args.arena),
                                  view_ptr<double>(d.Y, args.A, args.arena), ti, tj,
                                  static_cast<double*>(args.C), static_cast<double*>(args.arena), smem);
+    } else if constexpr (MODE == MODE_FALLBACK) {
+        if (!flagged) return;
+        tile_f64<float, float>(d, view_ptr<float>(d.X, args.A, args.arena),
+                               view_ptr<float>(d.Y, args.A, args.arena), ti, tj,
+                               static_cast<float*>(args.C), static_cast<float*>(args.arena), smem);
+    } else if constexpr (MODE == MODE_BF16X3) {
+        if (flagged) return;
+        tile_bf16x3(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
+                    static_cast<float*>(args.arena), smem);
     } else {
-        const float* Xp = view_ptr<float>(d.X, args.A, args.arena);
-        const float* Yp = view_ptr<float>(d.Y, args.A, args.arena);
-        if (d.fb_node >= 0 && args.flags[d.fb_node]) {
-            tile_f64<float, float>(d, Xp, Yp, ti, tj, static_cast<float*>(args.C),
-                                   static_cast<float*>(args.arena), smem);
-        } else {
-            tile_f32(d, Xp, Yp, ti, tj, static_cast<float*>(args.C), static_cast<float*>(args.arena), smem);
-        }
+        if (flagged) return;
+        tile_f32(d, view_ptr<float>(d.X, args.A, args.arena), view_ptr<float>(d.Y, args.A, args.arena),
+                 ti, tj, static_cast<float*>(args.C), static_cast<float*>(args.arena), smem);
     }
 }
 
@@ -316,8 +445,18 @@ hipError_t launch_leaves(int32_t mode, const LeafDesc* d_tasks, int ntasks, int6
     switch (mode) {
         case MODE_F64: hipLaunchKernelGGL(leaf_kernel<MODE_F64>, grid, block, 0, stream, a); break;
         case MODE_F32: hipLaunchKernelGGL(leaf_kernel<MODE_F32>, grid, block, 0, stream, a); break;
+        case MODE_BF16X3: hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3>, grid, block, 0, stream, a); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t ntiles, const void* A,
+                                  void* C, void* arena, const uint8_t* flags, int chunk,
+                                  hipStream_t stream) {
+    if (ntiles <= 0) return hipSuccess;
+    LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags};
+    hipLaunchKernelGGL(leaf_kernel<MODE_FALLBACK>, dim3((unsigned)ntiles), dim3(LEAF_THREADS), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -2,7 +2,9 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <map>
 #include <stdexcept>
+#include <tuple>
 
 namespace ata {
 
@@ -25,8 +27,17 @@ int32_t default_max_depth(int32_t mode) {
     }
 }
 
+int64_t Plan::alloc(int64_t elems) {
+    const int64_t off = arena_elems;
+    const int64_t align = 256 / elem_bytes();
+    arena_elems += (elems + align - 1) / align * align;
+    return off;
+}
+
 int64_t Plan::launches() const {
     int64_t l = (int64_t)presum.size() + (leaves.empty() ? 0 : 1) + (int64_t)combine.size();
+    if (!pack.empty()) l += 1;
+    if (!fb_leaves.empty()) l += 1;
     if (fallback) l += 2;  // column norms + flags
     return l;
 }
@@ -75,13 +86,7 @@ struct Builder {
 
     explicit Builder(Plan& plan) : p(plan), b(plan.b), maxd(plan.max_depth), fb(plan.fallback) {}
 
-    int64_t alloc(int64_t elems) {
-        int64_t off = p.arena_elems;
-        // keep every buffer 256-byte aligned for vector loads
-        int64_t align = 256 / p.elem_bytes();
-        p.arena_elems += cdiv(elems, align) * align;
-        return off;
-    }
+    int64_t alloc(int64_t elems) { return p.alloc(elems); }
 
     View a_cols(int64_t c0, int64_t w) const {
         View v{};
@@ -205,6 +210,75 @@ struct Builder {
     }
 };
 
+// Split-BF16: give every leaf operand a packed hi/lo copy.  Views of A whose
+// first row is a multiple of 8 share one packing of the whole of A (rows past
+// the leaf's contraction length are masked by the kernel chunk-wise, which is
+// exact when that length is a multiple of 8 or reaches the end of A); every
+// other view is packed on its own, once per distinct view.
+void assign_packed(Plan& p) {
+    int64_t a_off = -1, a_groups = 0;
+    auto packed_a = [&]() {
+        if (a_off < 0) {
+            a_groups = std::max<int64_t>(1, cdiv(p.m, 8));
+            a_off = p.alloc(a_groups * p.n * 8);
+            PackDesc d{};
+            d.src.base = BASE_A;
+            d.src.off = 0;
+            d.src.ld = p.lda;
+            d.src.rows = d.src.prows = p.m;
+            d.src.cols = d.src.pcols = p.n;
+            d.dst = a_off;
+            d.lo_delta = a_groups * p.n * 4;
+            d.groups = a_groups;
+            d.cols = p.n;
+            d.elems = a_groups * p.n;
+            d.pred_node = -1;
+            p.pack.push_back(d);
+        }
+        return a_off;
+    };
+    std::map<std::tuple<int32_t, int64_t, int64_t, int64_t, int64_t, int64_t>, Packed> memo;
+    auto ref = [&](const View& V, int64_t K, int32_t pn, int32_t pv) {
+        Packed P{};
+        const int64_t r0 = V.base == BASE_A ? V.off / p.lda : 0, c0 = V.base == BASE_A ? V.off % p.lda : 0;
+        if (V.base == BASE_A && r0 % 8 == 0 && V.pcols == V.cols && (K % 8 == 0 || r0 + K == p.m)) {
+            const int64_t base = packed_a();
+            P.off = base + (r0 / 8) * p.n * 4 + c0 * 4;
+            P.lo_delta = a_groups * p.n * 4;
+            P.gstride = p.n * 4;
+            P.end = base + a_groups * p.n * 4;
+            return P;
+        }
+        const auto key = std::make_tuple(V.base, V.off, V.ld, V.prows, V.pcols, V.cols);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        const int64_t groups = std::max<int64_t>(1, cdiv(V.prows, 8));
+        const int64_t off = p.alloc(groups * V.cols * 8);
+        PackDesc d{};
+        d.src = V;
+        d.dst = off;
+        d.lo_delta = groups * V.cols * 4;
+        d.groups = groups;
+        d.cols = V.cols;
+        d.elems = groups * V.cols;
+        d.pred_node = pn;
+        d.pred_value = pv;
+        p.pack.push_back(d);
+        P.off = off;
+        P.lo_delta = groups * V.cols * 4;
+        P.gstride = V.cols * 4;
+        P.end = off + groups * V.cols * 4;
+        memo.emplace(key, P);
+        return P;
+    };
+    for (auto& L : p.leaves) {
+        L.PX = ref(L.X, L.K, L.pred_node, L.pred_value);
+        L.PY = L.kind == LEAF_SYRK ? L.PX : ref(L.Y, L.K, L.pred_node, L.pred_value);
+    }
+    int64_t e = 0;
+    for (auto& d : p.pack) { d.elem_begin = e; e += d.elems; }
+}
+
 }  // namespace
 
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt) {
@@ -221,12 +295,22 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     if (n == 0) return p;
     Builder bld(p);
     bld.ata(0, n);
+    if (mode == MODE_BF16X3 && m > 0) assign_packed(p);
     // LPT: longest contraction first (stable, so ties keep tree order)
     std::stable_sort(p.leaves.begin(), p.leaves.end(),
                      [](const LeafDesc& a, const LeafDesc& c) { return a.K > c.K; });
     int64_t t = 0;
     for (auto& L : p.leaves) { L.tile_begin = t; t += L.tiles; }
     p.total_tiles = t;
+    t = 0;
+    for (const auto& L : p.leaves) {
+        if (L.fb_node >= 0) {
+            p.fb_leaves.push_back(L);
+            p.fb_leaves.back().tile_begin = t;
+            t += L.tiles;
+        }
+    }
+    p.fb_tiles = t;
     for (auto& lvl : p.presum) {
         int64_t e = 0;
         for (auto& d : lvl) { d.elem_begin = e; e += d.elems; }

@@ -39,6 +39,18 @@ struct View {
     int64_t prows, pcols;     // physical extent (<= logical)
 };
 
+// A leaf operand repacked for the BF16 MFMAs: hi and lo bf16 arrays of
+// `groups` row-groups x `cols` columns of 16-byte chunks; chunk (g, c) holds
+// rows 8g..8g+7 of column c (zero beyond the source's physical extent), so a
+// chunk is exactly the eight consecutive k values one MFMA lane consumes.
+// Offsets and strides are in floats (4 bytes) of the arena.
+struct Packed {
+    int64_t off;        // chunk (0, 0) of this operand in the hi array
+    int64_t lo_delta;   // hi array -> lo array
+    int64_t gstride;    // one row-group (= total columns of the array * 4)
+    int64_t end;        // end of the hi array (bounds every load)
+};
+
 enum LeafKind : int32_t { LEAF_SYRK = 0, LEAF_GEMM = 1 };
 enum OutKind : int32_t { OUT_PACKED = 0, OUT_DENSE = 1 };
 
@@ -58,6 +70,18 @@ struct LeafDesc {
     int32_t pred_value;
     int32_t fb_node;          // SYRK leaves: FP64 path when flags[fb_node] != 0 (-1: never)
     int32_t depth;            // Strassen level of the leaf (0 = directly in C)
+    Packed PX, PY;            // split-BF16 mode: packed operands
+};
+
+// Split one FP32 operand view into the packed hi/lo layout (one work item per
+// 16-byte chunk).
+struct PackDesc {
+    View src;
+    int64_t dst;              // arena float offset of the hi array
+    int64_t lo_delta;
+    int64_t groups, cols;
+    int64_t elem_begin, elems;
+    int32_t pred_node, pred_value;
 };
 
 // Five Strassen pre-sums of one operand (X side: S1..S5, Y side: T1..T5).
@@ -109,13 +133,17 @@ struct Plan {
     int32_t max_depth = 0;
     bool fallback = false;
     std::vector<std::vector<PresumDesc>> presum;    // [level-1] top-down
+    std::vector<PackDesc> pack;                     // split-BF16 operand packing
     std::vector<LeafDesc> leaves;                   // LPT order (longest first)
+    std::vector<LeafDesc> fb_leaves;                // SYRK leaves under the spread check
     std::vector<std::vector<CombineDesc>> combine;  // [height-1] bottom-up
     std::vector<NodeDesc> nodes;                    // AtA nodes (flags)
     int64_t arena_elems = 0;                        // in the mode's sum/product type
     int64_t total_tiles = 0;
+    int64_t fb_tiles = 0;
     PlanStats stats;
     int64_t elem_bytes() const { return mode == MODE_F64 ? 8 : 4; }
+    int64_t alloc(int64_t elems);                   // 256-byte aligned arena carve
     int64_t launches() const;
 };
 

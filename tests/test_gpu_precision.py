@@ -1,0 +1,75 @@
+"""Reduced-precision modes (split-BF16 x3, block-scaled FP8) against the oracle.
+
+Two references: the plain FP64 oracle (the normwise error the mode reaches)
+and the CPU emulation of the mode's operand transform with FP64 products
+(pins the split / quantisation itself: the GPU may differ from it only by
+FP32 accumulation order)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import emulate, plain
+from paper_2110_13042_amd import ata, workloads
+from gpu_helpers import device, full_error, packed_columns, run_gram
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def h():
+    device()
+    hd = ata.Handle(spread_tau=0)
+    yield hd
+    hd.close()
+
+
+def test_bf16x3_small_integers_bit_exact(h):
+    rng = np.random.default_rng(51)
+    for (m, n, b, depth) in [(300, 513, 64, 2), (1000, 777, 100, 1), (64, 1500, 128, 2), (5, 3, 64, 0)]:
+        _say("case: bf16x3 int", m, n, b, depth)
+        A = rng.integers(-2, 3, (m, n)).astype(np.float32)
+        h.set("leaf_cutoff", b)
+        h.set("max_depth", depth)
+        Cp = run_gram(A, ata.F32_BF16X3, h)
+        assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth)
+
+
+@pytest.mark.parametrize("depth", [0, 1, 2])
+def test_bf16x3_matches_emulation(h, depth):
+    rng = np.random.default_rng(52 + depth)
+    m, n, b = 1536, 1100, 256
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    h.set("leaf_cutoff", b)
+    h.set("max_depth", depth)
+    _say("case: bf16x3 emulation depth", depth)
+    Cp = run_gram(A, ata.F32_BF16X3, h)
+    emul = emulate.ata_emulated(A, "bf16x3", b, max_strassen_depth=depth)
+    exact = plain.gram_packed(A)
+    d_emul = full_error(Cp, emul)
+    e_exact = full_error(Cp, exact)
+    _say("  vs emulation", d_emul, " vs FP64 oracle", e_exact, " emulation vs oracle",
+         full_error(emul, exact))
+    assert d_emul <= 1e-6
+    assert e_exact <= 2e-5
+
+
+def test_precision_forms_16384_sampled(h):
+    """16384 x 16384 N(0,1): FP32 and split-BF16 within 2e-5 on 256 sampled columns."""
+    _say("case: normal_f32_16384 full size")
+    A = workloads.make("normal_f32_16384")
+    S = workloads.sampled_columns(16384, 256, seed=4, after_rows=16384, after_cols=16384)
+    ref = plain.gram_cols(A, S)
+    h.set("leaf_cutoff", 0)
+    h.set("max_depth", -1)
+    for mode, tol in [(ata.F32, 2e-5), (ata.F32_BF16X3, 2e-5)]:
+        Cp = run_gram(A, mode, h)
+        got = packed_columns(Cp, 16384, S)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        _say("  mode", mode, "e_S", err, h.report()["strassen_levels"])
+        assert err <= tol
