@@ -84,15 +84,88 @@ def cpu_baseline(A: np.ndarray, samples: int):
                       f"{dt * (n + 1) / (2 * len(S)):.1f} s"}, S, cols
 
 
+def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
+    """Time one mode on the resident input; returns (result dict, C tensor)."""
+    m, n = A_np.shape
+    tdt = torch.float64 if mode == "f64" else torch.float32
+    A = torch.from_numpy(A_np).to(dev, tdt)
+    C = torch.empty(n * (n + 1) // 2, dtype=tdt, device=dev)
+    h = ata.Handle()
+    if args.leaf_cutoff:
+        h.set("leaf_cutoff", args.leaf_cutoff)
+    if args.max_depth >= 0:
+        h.set("max_depth", args.max_depth)
+    if args.leaf_tile:
+        h.set("leaf_tile", args.leaf_tile)
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    lda = A.stride(0)
+
+    def step():
+        ata.ata_gram(h.h, A.data_ptr(), m, n, lda, MODES[mode], C.data_ptr(), sp)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] {mode}: warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    # timed region: K steps; the library records phase events on the same stream
+    h.set("profile", 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = h.report()
+    h.set("profile", 0)
+    h.close()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    eff = m * n * (n + 1) / (ms_per_step * 1e-3) / 1e12
+    calls = max(rep["profiled_calls"], 1)
+    leaf_ms = rep["phase_ms"][2] / calls
+    leaf_flops = 2.0 * rep["multiplications"]
+    achieved = leaf_flops / (leaf_ms * 1e-3) / 1e12 if leaf_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[mode]
+    print(f"[bench] {mode}: {args.steps} steps, {ms_per_step:.3f} ms/step, phases(ms/step) "
+          f"{[round(x / calls, 4) for x in rep['phase_ms']]}", file=sys.stderr, flush=True)
+    res = {
+        "value": round(eff, 3), "ms_per_step": round(ms_per_step, 4), "dtype": mode,
+        "frac_of_dtype_peak_effective": round(eff / peak, 4),
+        "plan": {"leaf_cutoff": rep["leaf_cutoff"], "strassen_levels": rep["strassen_levels"],
+                 "multiplications": rep["multiplications"],
+                 "mult_ratio_vs_syrk": round(rep["multiplications"] / (m * n * (n + 1) / 2), 4),
+                 "launches_per_step": rep["kernel_launches"], "workspace_bytes": rep["workspace_bytes"]},
+        "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
+            ["norms_flags", "presum_pack", "leaves", "combine", "residual"], rep["phase_ms"])},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": traffic_from_profiles(mode, wl),
+                     "kernel": "leaf_kernel (every SYRK/GEMM leaf product of the plan, one grouped launch)",
+                     "algorithmic_flops_per_launch": leaf_flops,
+                     "avg_launch_ms": round(leaf_ms, 4)},
+    }
+    return res, C
+
+
+def sampled_error(C, n: int, S, cols) -> float:
+    Cp = C.double().cpu().numpy()
+    ii = np.arange(n)[:, None]
+    jj = np.asarray(S)[None, :]
+    r, c = np.maximum(ii, jj), np.minimum(ii, jj)
+    got = Cp[r * (r + 1) // 2 + c]
+    return float(np.linalg.norm(got - cols) / np.linalg.norm(cols))
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="f32", choices=sorted(MODES))
-    ap.add_argument("--workload", default=None)
+    ap.add_argument("--mode", default="bf16x3,f32",
+                    help="comma list; the first is the headline, the rest are reported beside it")
+    ap.add_argument("--workload", default="square_f32_8192")
     ap.add_argument("--leaf-cutoff", type=int, default=0)
     ap.add_argument("--max-depth", type=int, default=-1)
+    ap.add_argument("--leaf-tile", type=int, default=0, help="split-BF16 leaf tile: 0 = 128x128, 1 = 256x128, 2 = 256x256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -111,53 +184,21 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
-    mode = args.mode
-    wl = args.workload or DEFAULT_WORKLOAD[mode]
+    modes = [x.strip() for x in args.mode.split(",") if x.strip()]
+    for md in modes:
+        if md not in MODES:
+            print(f"unknown mode {md}", file=sys.stderr)
+            return 2
+    wl = args.workload
     w = workloads.WORKLOADS[wl]
     print(f"[bench] generating {wl} ({w.description})", file=sys.stderr, flush=True)
     A_np = workloads.make(wl)
-    if mode != "f64" and A_np.dtype != np.float32:
+    if "f64" not in modes and A_np.dtype != np.float32:
         A_np = A_np.astype(np.float32)
     m, n = A_np.shape
-    tdt = torch.float64 if mode == "f64" else torch.float32
-    A = torch.from_numpy(A_np).to(dev, tdt)
-    C = torch.empty(n * (n + 1) // 2, dtype=tdt, device=dev)
-    h = ata.Handle()
-    if args.leaf_cutoff:
-        h.set("leaf_cutoff", args.leaf_cutoff)
-    if args.max_depth >= 0:
-        h.set("max_depth", args.max_depth)
-    stream = torch.cuda.current_stream(dev)
-    sp = stream.cuda_stream
-    lda = A.stride(0)
-
-    def step():
-        ata.ata_gram(h.h, A.data_ptr(), m, n, lda, MODES[mode], C.data_ptr(), sp)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-    # timed region: K steps, phase events recorded on the same stream
-    h.set("profile", 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    rep = h.report()
-    h.set("profile", 0)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    eff = m * n * (n + 1) / (ms_per_step * 1e-3) / 1e12
-    calls = max(rep["profiled_calls"], 1)
-    leaf_ms = rep["phase_ms"][2] / calls
-    leaf_flops = 2.0 * rep["multiplications"]
-    achieved = leaf_flops / (leaf_ms * 1e-3) / 1e12 if leaf_ms > 0 else 0.0
-    peak = PEAK_TFLOPS[mode]
-    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step, phases(ms/call) "
-          f"{[round(x / calls, 4) for x in rep['phase_ms']]}", file=sys.stderr, flush=True)
-
+    results, outs = {}, {}
+    for md in modes:
+        results[md], outs[md] = run_mode(ata, torch, dev, A_np, md, args, wl)
     if args.copy_calibration:
         # a plain copy of known size: 1 GiB read + 1 GiB written per launch
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -166,48 +207,29 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print("[bench] copy calibration: 3 x copy of 1 GiB", file=sys.stderr, flush=True)
-
-    out = {
-        "metric": "effective TFLOP/s m*n*(n+1)/t (AtA Gram product C = A^T A, packed lower)",
-        "value": round(eff, 3),
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": mode,
-        "data": "synthetic",
-        "config": {"workload": wl, "m": m, "n": n, "mode": mode,
-                   "leaf_cutoff": rep["leaf_cutoff"], "strassen_levels": rep["strassen_levels"],
-                   "multiplications": rep["multiplications"],
-                   "mult_ratio_vs_syrk": round(rep["multiplications"] / (m * n * (n + 1) / 2), 4),
-                   "launches_per_step": rep["kernel_launches"],
-                   "workspace_bytes": rep["workspace_bytes"],
-                   "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
-                       ["norms_flags", "presum", "leaves", "combine", "residual"], rep["phase_ms"])},
-                   "frac_of_dtype_peak_effective": round(eff / peak, 4)},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": traffic_from_profiles(mode, wl),
-                     "kernel": "leaf_kernel (all SYRK/GEMM leaf products, one grouped launch)",
-                     "algorithmic_flops_per_launch": leaf_flops,
-                     "avg_launch_ms": round(leaf_ms, 4)},
-    }
+    base = None
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline on a column sample", file=sys.stderr, flush=True)
         base, S, cols = cpu_baseline(A_np, args.cpu_samples)
+        for md in modes:
+            results[md]["rel_error_sampled_columns"] = sampled_error(outs[md], n, S, cols)
+    head = results[modes[0]]
+    out = {
+        "metric": "effective TFLOP/s m*n*(n+1)/t of C = A^T A (AtA, packed lower); "
+                  "split-BF16 x3 vs FP32, each at <= 2e-5 relative error",
+        "value": head["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": modes[0], "data": "synthetic",
+        "config": {"workload": wl, "m": m, "n": n, "description": w.description,
+                   "plan": head["plan"], "phase_ms_per_step": head["phase_ms_per_step"],
+                   "frac_of_dtype_peak_effective": head["frac_of_dtype_peak_effective"],
+                   "rel_error_sampled_columns": head.get("rel_error_sampled_columns")},
+        "roofline": head["roofline"],
+        "side_by_side": {md: results[md] for md in modes[1:]},
+    }
+    if base is not None:
         out["cpu_baseline"] = base
-        Cp = C.double().cpu().numpy()
-        ii = np.arange(n)[:, None]
-        jj = np.asarray(S)[None, :]
-        r, c = np.maximum(ii, jj), np.minimum(ii, jj)
-        got = Cp[r * (r + 1) // 2 + c]
-        out["config"]["rel_error_sampled_columns"] = float(np.linalg.norm(got - cols) / np.linalg.norm(cols))
     print(json.dumps(out), flush=True)
-    h.close()
     return 0
 
 

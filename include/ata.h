@@ -82,7 +82,10 @@ typedef enum {
     /* 1 = record HIP events on the call's stream around each launch phase of
        every ata_gram call; ata_get_report then synchronises and returns the
        summed phase times since the option was last set (default 0). */
-    ATA_OPT_PROFILE = 6
+    ATA_OPT_PROFILE = 6,
+    /* Output tile of the split-BF16 leaf kernel: 0 = 128 x 128 (default),
+       1 = 256 x 128, 2 = 256 x 256.  Other dtypes ignore it. */
+    ATA_OPT_LEAF_TILE = 7
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

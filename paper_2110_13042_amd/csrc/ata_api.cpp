@@ -25,9 +25,10 @@ struct PlanKey {
     int64_t m, n, lda, b;
     int32_t depth;
     bool fb;
+    int32_t tile_cfg;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb) <
-               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb);
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg) <
+               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg);
     }
 };
 
@@ -162,7 +163,7 @@ AuxLayout aux_layout(const Plan& p, bool residual) {
     a.flags_off = off;
     off += align256(std::max<size_t>(p.nodes.size(), 1));
     a.part_off = off;
-    off += align256(sizeof(double) * (size_t)(p.fallback ? colnorm_chunks(p.m) * p.n : 0));
+    off += align256(sizeof(double) * (size_t)(p.fallback ? colnorm_chunks(p.m, p.n) * p.n : 0));
     a.nu_off = off;
     off += align256(sizeof(double) * (size_t)(p.fallback ? p.n : 0));
     a.res_work_off = off;
@@ -256,6 +257,10 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
         case ATA_OPT_RESIDUAL_SEED:
             h->seed = (uint64_t)value;
             return ATA_OK;
+        case ATA_OPT_LEAF_TILE:
+            if (value != 0 && value != 1 && value != 2) return ATA_ERR_INVALID_VALUE;
+            h->popt.tile_cfg = (int32_t)value;
+            return ATA_OK;
         case ATA_OPT_PROFILE:
             if (h->events_used) (void)drain_events(h);
             h->profile = value != 0.0;
@@ -326,7 +331,8 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     const int64_t b = h->popt.leaf_cutoff > 0 ? h->popt.leaf_cutoff : default_leaf_cutoff(mode, m, n);
     const int32_t depth = h->popt.max_depth >= 0 ? h->popt.max_depth : default_max_depth(mode);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
-    const PlanKey key{mode, m, n, lda, b, depth, fb};
+    const int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
+    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -334,6 +340,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         o.leaf_cutoff = b;
         o.max_depth = depth;
         o.spread_tau = fb ? h->popt.spread_tau : 0.0;
+        o.tile_cfg = tile_cfg;
         try {
             dp->plan = make_plan(mode, m, n, lda, o);
         } catch (const std::invalid_argument&) {
@@ -382,7 +389,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     };
     mark(0);
     if (p.fallback) {
-        e = launch_colnorms(static_cast<const float*>(A), m, n, lda, partial, colnorm_chunks(m), nu, st);
+        e = launch_colnorms(static_cast<const float*>(A), m, n, lda, partial, colnorm_chunks(m, n), nu, st);
         if (e == hipSuccess)
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
@@ -397,7 +404,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
                         A, h->arena, flags, st);
     mark(2);
     if (e == hipSuccess)
-        e = launch_leaves(mode, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
+        e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
                           flags, h->chunk, st);
     if (e == hipSuccess && !p.fb_leaves.empty())
         e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,

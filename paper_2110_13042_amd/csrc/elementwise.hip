@@ -16,6 +16,64 @@ constexpr int EW_THREADS = 256;
 // sums.  Reads the four quadrant values of the parent operand (zero outside
 // its physical extent and outside the quadrant's real size) and writes the
 // five sums, including the zero padding of the ceil-sized buffers.
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+    const v2bf p = {(__bf16)a, (__bf16)b};          // round to nearest even
+    return __builtin_bit_cast(uint32_t, p);
+}
+
+// Split eight consecutive k values into packed hi and lo chunks.
+__device__ __forceinline__ void split8(const float* v, uint4& hi, uint4& lo) {
+    uint32_t h[4], l[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = pk_bf16(v[2 * q], v[2 * q + 1]);
+        const float h0 = __builtin_bit_cast(float, h[q] << 16);
+        const float h1 = __builtin_bit_cast(float, h[q] & 0xFFFF0000u);
+        l[q] = pk_bf16(v[2 * q] - h0, v[2 * q + 1] - h1);
+    }
+    hi = make_uint4(h[0], h[1], h[2], h[3]);
+    lo = make_uint4(l[0], l[1], l[2], l[3]);
+}
+
+// Pre-sums of a node whose products are all leaves, written straight into the
+// split-BF16 packed layout.  Work item = one chunk (row-group g, column c):
+// eight rows of the four quadrant values, the five sums formed in FP32, then
+// split.
+__device__ void presum_packed(const PresumDesc& d, int64_t e, const float* A, float* arena) {
+    const int64_t g = e / d.n2, c = e - g * d.n2;
+    const float* V = (d.V.base == BASE_A ? A : arena) + d.V.off;
+    const int64_t ld = d.V.ld, pr = d.V.prows, pc = d.V.pcols;
+    const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
+    float sum[5][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int64_t r = 8 * g + q;
+        auto get = [&](int qr, int qc) -> float {
+            const int64_t rr = qr ? m1 + r : r, cc = qc ? n1 + c : c;
+            const bool in = r < (qr ? m2 : m1) && c < (qc ? n2 : n1) && rr < pr && cc < pc;
+            return in ? V[rr * ld + cc] : 0.f;
+        };
+        const float a11 = get(0, 0), a12 = get(0, 1), a21 = get(1, 0), a22 = get(1, 1);
+        if (d.side == 0) {
+            sum[0][q] = a11 + a22; sum[1][q] = a12 + a22; sum[2][q] = a11 + a21;
+            sum[3][q] = a12 - a11; sum[4][q] = a21 - a22;
+        } else {
+            sum[0][q] = a11 + a22; sum[1][q] = a12 - a22; sum[2][q] = a21 - a11;
+            sum[3][q] = a11 + a12; sum[4][q] = a21 + a22;
+        }
+    }
+    const int64_t groups = (m2 + 7) / 8, each = groups * n2 * 8, lo_delta = groups * n2 * 4;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        uint4 hi, lo;
+        split8(sum[i], hi, lo);
+        float* base = arena + d.out_off + i * each;
+        reinterpret_cast<uint4*>(base)[g * n2 + c] = hi;
+        reinterpret_cast<uint4*>(base + lo_delta)[g * n2 + c] = lo;
+    }
+}
+
 template <class T> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { struct type { double x, y, z, w; }; };
@@ -49,6 +107,12 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
     const PresumDesc& d = tasks[find_task(tasks, ntasks, x)];
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
     const int64_t e = x - d.elem_begin;
+    if constexpr (sizeof(T) == 4) {
+        if (d.packed_out) {
+            presum_packed(d, e, A, arena);
+            return;
+        }
+    }
     const int64_t groups = (d.n2 + 3) >> 2;
     const int64_t r = e / groups, c0 = (e - r * groups) << 2;
     const T* V = (d.V.base == BASE_A ? A : arena) + d.V.off;
@@ -106,11 +170,6 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
 }
 
 // ------------------------------------------------------ split-BF16 packing
-__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
-    typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
-    const v2bf p = {(__bf16)a, (__bf16)b};          // round to nearest even
-    return __builtin_bit_cast(uint32_t, p);
-}
 
 // Work item = one 16-byte chunk (row-group g, column c): rows 8g..8g+7 of
 // column c split into hi = bf16(a) and lo = bf16(a - hi).
@@ -130,18 +189,10 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
         const int64_t r = 8 * g + q;
         v[q] = (r < d.src.prows && c < d.src.pcols) ? src[r * d.src.ld + c] : 0.f;
     }
-    uint32_t hi[4], lo[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        hi[q] = pk_bf16(v[2 * q], v[2 * q + 1]);
-        const float h0 = __builtin_bit_cast(float, hi[q] << 16);
-        const float h1 = __builtin_bit_cast(float, hi[q] & 0xFFFF0000u);
-        lo[q] = pk_bf16(v[2 * q] - h0, v[2 * q + 1] - h1);
-    }
-    uint4* H = reinterpret_cast<uint4*>(arena + d.dst) + g * d.cols + c;
-    uint4* L = reinterpret_cast<uint4*>(arena + d.dst + d.lo_delta) + g * d.cols + c;
-    *H = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-    *L = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    uint4 hi, lo;
+    split8(v, hi, lo);
+    reinterpret_cast<uint4*>(arena + d.dst)[g * d.cols + c] = hi;
+    reinterpret_cast<uint4*>(arena + d.dst + d.lo_delta)[g * d.cols + c] = lo;
 }
 
 // ---------------------------------------------------------------- combine
@@ -211,17 +262,25 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
 }
 
 // ------------------------------------------------------------ column norms
-constexpr int64_t NORM_ROWS = 256;
+constexpr int64_t NORM_ROWS = 256;   // residual passes
+
+// Rows per chunk of the column-norm pass: enough chunks that (n / 4) x chunks
+// threads fill the GPU (about 2^19), at least 16 rows, at most 4096.
+int64_t norm_rows(int64_t m, int64_t n) {
+    int64_t r = (m * (n > 0 ? n : 1)) >> 21;
+    r = r < 16 ? 16 : (r > 4096 ? 4096 : r);
+    return r;
+}
 
 // partial[chunk][j] = sum of a_rj^2 over the chunk's rows, four columns per
 // thread (16-byte loads when the rows allow it), rows in ascending order.
 template <class T>
 __global__ __launch_bounds__(EW_THREADS) void colnorm_partial(const T* A, int64_t m, int64_t n,
-                                                              int64_t lda, double* partial) {
+                                                              int64_t lda, int64_t rows, double* partial) {
     const int64_t j0 = ((int64_t)blockIdx.x * EW_THREADS + threadIdx.x) * 4;
     const int64_t chunk = blockIdx.y;
     if (j0 >= n) return;
-    const int64_t r0 = chunk * NORM_ROWS, r1 = r0 + NORM_ROWS < m ? r0 + NORM_ROWS : m;
+    const int64_t r0 = chunk * rows, r1 = r0 + rows < m ? r0 + rows : m;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     const bool vec = sizeof(T) == 4 && j0 + 4 <= n &&
                      ((reinterpret_cast<uintptr_t>(A) | (uintptr_t)(lda * sizeof(T))) & 15) == 0;
@@ -440,13 +499,17 @@ hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, 
     return hipGetLastError();
 }
 
-int64_t colnorm_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / NORM_ROWS; }
+int64_t colnorm_chunks(int64_t m, int64_t n) {
+    const int64_t r = norm_rows(m, n);
+    return m <= 0 ? 1 : (m + r - 1) / r;
+}
+int64_t residual_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / NORM_ROWS; }
 
 hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
                            int64_t nchunks, double* nu, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(colnorm_partial<float>, dim3(blocks_for((n + 3) / 4), (unsigned)nchunks),
-                       dim3(EW_THREADS), 0, stream, A, m, n, lda, partial);
+                       dim3(EW_THREADS), 0, stream, A, m, n, lda, norm_rows(m, n), partial);
     hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), dim3(EW_THREADS), 0, stream, partial,
                        nchunks, n, nu);
     return hipGetLastError();
@@ -460,7 +523,7 @@ hipError_t launch_flags(const double* nu, const NodeDesc* d_nodes, int nnodes, d
 }
 
 int64_t residual_work_elems(int64_t m, int64_t n) {
-    const int64_t chunks = colnorm_chunks(m), bands = (n + BAND - 1) / BAND;
+    const int64_t chunks = residual_chunks(m), bands = (n + BAND - 1) / BAND;
     // y | zpart | fpart | z | fro | wrow | wpart | wcol
     return m + 2 * chunks * n + 2 * n + n + bands * n + n;
 }
@@ -469,7 +532,7 @@ hipError_t launch_residual(int32_t mode, const void* A, int64_t m, int64_t n, in
                            const void* C, uint64_t seed, double* work, double* out,
                            hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    const int64_t chunks = colnorm_chunks(m), bands = (n + BAND - 1) / BAND;
+    const int64_t chunks = residual_chunks(m), bands = (n + BAND - 1) / BAND;
     double* y = work;
     double* zpart = y + m;
     double* fpart = zpart + chunks * n;

@@ -30,15 +30,6 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t total, int64_t
     return w0 + (r % 8) * chunk + r / 8;
 }
 
-// Lower-triangular tile (ti >= tj) of a linear index q.
-__device__ __forceinline__ void tri_tile(int64_t q, int& ti, int& tj) {
-    int64_t i = (int64_t)((__builtin_sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
-    while (i * (i + 1) / 2 > q) --i;
-    while ((i + 1) * (i + 2) / 2 <= q) ++i;
-    ti = (int)i;
-    tj = (int)(q - i * (i + 1) / 2);
-}
-
 template <class D>
 __device__ __forceinline__ int find_task(const D* tasks, int ntasks, int64_t x) {
     // largest t with tasks[t].begin <= x (begin fields ascending)

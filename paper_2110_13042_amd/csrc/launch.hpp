@@ -9,9 +9,11 @@
 namespace ata {
 
 // All leaf products of a plan (one grouped launch, one workgroup per tile).
-hipError_t launch_leaves(int32_t mode, const LeafDesc* d_tasks, int ntasks, int64_t ntiles,
-                         const void* A, void* C, void* arena, const uint8_t* flags, int chunk,
-                         hipStream_t stream);
+// tile_cfg selects the output tile of the split-BF16 kernel (0: 128 x 128,
+// 1: 256 x 128); the other modes have one tile shape.
+hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
+                         int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
+                         int chunk, hipStream_t stream);
 
 // FP64 fallback of flagged SYRK leaves (FP32 inputs and output); the tasks
 // are the plan's fallback-capable SYRK leaves, unflagged ones exit at once.
@@ -35,7 +37,7 @@ hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, 
 // partial[chunk][j] over row chunks, then nu[j] = sum over chunks in order.
 hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
                            int64_t nchunks, double* nu, hipStream_t stream);
-int64_t colnorm_chunks(int64_t m);
+int64_t colnorm_chunks(int64_t m, int64_t n);
 
 // flags[i] = spread of nu over node i's columns > tau^2 (1/0); count in *count.
 hipError_t launch_flags(const double* nu, const NodeDesc* d_nodes, int nnodes, double tau2,

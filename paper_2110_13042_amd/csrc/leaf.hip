@@ -40,12 +40,18 @@ constexpr size_t LDS64_BYTES = 2 * 2 * BK * LD64 * sizeof(double);
 constexpr size_t LEAF_LDS_BYTES = LDS64_BYTES > LDS32_BYTES ? LDS64_BYTES : LDS32_BYTES;
 constexpr int BKB = 32;         // rows of A per K step, split-BF16 path
 constexpr int LDB = 40;         // bf16 per LDS row: 32 k values + 8 pad (80-byte stride)
-constexpr size_t LDSB_BYTES = 2 * 4 * TILE_M * LDB * 2;   // 2 stages x {Xh, Xl, Yh, Yl}
 // Kernel variant of the FP64 fallback: FP32 inputs, FP64 MFMA, FP32 output.
 constexpr int MODE_FALLBACK = 100;
+// Split-BF16 with the 256 x 128 and 256 x 256 tiles.
+constexpr int MODE_BF16X3_LARGE = 101;
+constexpr int MODE_BF16X3_HUGE = 102;
 constexpr size_t lds_bytes(int mode) {
-    return mode == MODE_BF16X3 ? LDSB_BYTES : mode == MODE_F32 ? LDS32_BYTES : LDS64_BYTES;
+    return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 40 * 2
+           : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 40 * 2
+           : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
+           : mode == MODE_F32 ? LDS32_BYTES : LDS64_BYTES;
 }
+constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE ? 512 : LEAF_THREADS; }
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
@@ -103,6 +109,35 @@ __device__ __forceinline__ double2 load2d(const double* p, int64_t ld, int64_t r
     return v;
 }
 
+// Tile coordinates of the q-th tile of a leaf.  SYRK: lower-triangular rows,
+// row ti holding min(rho (ti + 1), tiles_n) tiles.  GEMM: bands of TILE_BAND
+// tile rows, column by column inside a band.
+template <int RHO>
+__device__ __forceinline__ void leaf_tile(const LeafDesc& d, int64_t q, int& ti, int& tj) {
+    const int64_t tn = d.tiles_n;
+    if (d.kind == LEAF_SYRK) {
+        const int64_t L = tn / RHO;
+        const int64_t full = RHO * L * (L + 1) / 2;
+        if (q < full) {
+            int64_t i = (int64_t)((__builtin_sqrt(8.0 * (double)q / RHO + 1.0) - 1.0) * 0.5);
+            while (i > 0 && RHO * i * (i + 1) / 2 > q) --i;
+            while (RHO * (i + 1) * (i + 2) / 2 <= q) ++i;
+            ti = (int)i;
+            tj = (int)(q - RHO * i * (i + 1) / 2);
+        } else {
+            const int64_t r = q - full;
+            ti = (int)(L + r / tn);
+            tj = (int)(r % tn);
+        }
+    } else {
+        const int64_t band = q / (TILE_BAND * tn);
+        const int64_t rows = d.tiles_m - band * TILE_BAND < TILE_BAND ? d.tiles_m - band * TILE_BAND : TILE_BAND;
+        const int64_t local = q - band * TILE_BAND * tn;
+        ti = (int)(band * TILE_BAND + local % rows);
+        tj = (int)(local / rows);
+    }
+}
+
 template <class T>
 __device__ __forceinline__ const T* view_ptr(const View& v, const void* A, const void* arena) {
     return (v.base == BASE_A ? static_cast<const T*>(A) : static_cast<const T*>(arena)) + v.off;
@@ -114,10 +149,10 @@ __device__ __forceinline__ bool vec_ok(const T* p, int64_t ld, int width) {
 }
 
 // Store one accumulator element of tile (ti, tj) at tile-local (r, c).
-template <class OutT>
+template <class OutT, int TM = TILE_M, int TN = TILE_N>
 __device__ __forceinline__ void store_elem(const LeafDesc& d, int ti, int tj, int r, int c,
                                            OutT v, OutT* C, OutT* arena) {
-    const int64_t gi = (int64_t)ti * TILE_M + r, gj = (int64_t)tj * TILE_N + c;
+    const int64_t gi = (int64_t)ti * TM + r, gj = (int64_t)tj * TN + c;
     if (gi >= d.rows || gj >= d.cols) return;
     if (d.kind == LEAF_SYRK && gj > gi) return;
     if (d.out_kind == OUT_PACKED)
@@ -206,48 +241,138 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const float* arena
                                              (int)(uint32_t)((P.end - P.off) * 4), 0x00020000);
 }
 
+// Split-BF16 tile engine.  WAVES_M x WAVES_N waves; each wave owns BMB x BNB
+// blocks of 32 x 32, so the output tile is TM x TN with TM = WAVES_M * BMB * 32
+// and TN = WAVES_N * BNB * 32.  The K loop runs over slabs of 8 * GROUPS rows
+// (GROUPS / 2 MFMA steps of 16 k); LDS holds two slabs.  With two steps per
+// slab, operand fragments are double-buffered in registers (the second step's
+// fragments are read while the first step's MFMAs run).  Scheduling barriers
+// keep the compiler from merging these phases.
+template <int WAVES_M_, int WAVES_N_, int BMB_, int BNB_, int GROUPS_>
+struct BfCfg {
+    static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, BMB = BMB_, BNB = BNB_;
+    static constexpr int GROUPS = GROUPS_;
+    static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
+    static constexpr int TM = WAVES_M * BMB * 32;
+    static constexpr int TN = WAVES_N * BNB * 32;
+    static constexpr int LDR = 8 * GROUPS + 8;                  // bf16 per LDS row (k values + pad)
+    static constexpr int STAGE = (2 * TM + 2 * TN) * LDR;      // bf16 elements per slab
+    static constexpr size_t LDS = 2 * STAGE * 2;               // bytes, two slabs
+    static constexpr int PAIRS = GROUPS * (TM + TN) / THREADS;  // (hi, lo) chunk pairs per thread
+};
+using BfSmall = BfCfg<2, 2, 2, 2, 4>;   // 128 x 128, 4 waves, 80 KB LDS (two workgroups per CU)
+using BfLarge = BfCfg<2, 2, 4, 2, 4>;   // 256 x 128, 4 waves, 120 KB LDS
+using BfHuge = BfCfg<2, 4, 4, 2, 2>;    // 256 x 256, 8 waves, 16-row slabs, 80 KB LDS
+
+template <class CFG>
 __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, int tj,
                             float* C, float* arena, unsigned char* smem) {
+    constexpr int TM = CFG::TM, TN = CFG::TN, STAGE = CFG::STAGE, LDR = CFG::LDR;
+    constexpr int BMB = CFG::BMB, BNB = CFG::BNB, G = CFG::GROUPS, NT = CFG::THREADS;
     unsigned short* lds = reinterpret_cast<unsigned short*>(smem);
-    // stage s, array a (0 = Xh, 1 = Xl, 2 = Yh, 3 = Yl): TILE_M rows of LDB bf16
-    auto arr = [&](int s, int a) { return lds + (s * 4 + a) * TILE_M * LDB; };
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
-    const int c = t & 127, side = t >> 7;          // chunk column; 0 = X, 1 = Y (wave-uniform)
-    const Packed& P = side ? d.PY : d.PX;
-    const __amdgpu_buffer_rsrc_t rh = packed_rsrc(arena_in, P, false), rl = packed_rsrc(arena_in, P, true);
-    const uint32_t colb = (uint32_t)(((side ? tj : ti) * TILE_M + c) * 16);
-    const uint32_t gsb = (uint32_t)(P.gstride * 4);
+    // slab s: Xh[TM][LDR], Xl[TM][LDR], Yh[TN][LDR], Yl[TN][LDR]
+    auto xh_ = [&](int s) { return lds + s * STAGE; };
+    auto xl_ = [&](int s) { return lds + s * STAGE + TM * LDR; };
+    auto yh_ = [&](int s) { return lds + s * STAGE + 2 * TM * LDR; };
+    auto yl_ = [&](int s) { return lds + s * STAGE + 2 * TM * LDR + TN * LDR; };
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w / CFG::WAVES_N, wn = w % CFG::WAVES_N;
+    const __amdgpu_buffer_rsrc_t rx[2] = {packed_rsrc(arena_in, d.PX, false), packed_rsrc(arena_in, d.PX, true)};
+    const __amdgpu_buffer_rsrc_t ry[2] = {packed_rsrc(arena_in, d.PY, false), packed_rsrc(arena_in, d.PY, true)};
+    const uint32_t xgs = (uint32_t)(d.PX.gstride * 4), ygs = (uint32_t)(d.PY.gstride * 4);
     const int64_t K = d.K;
-    const int64_t nk = (K + BKB - 1) / BKB;
+    const int64_t nk = (K + 8 * G - 1) / (8 * G);
 
-    v16f acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+    v16f acc[BMB][BNB];
+#pragma unroll
+    for (int a = 0; a < BMB; ++a)
+#pragma unroll
+        for (int b = 0; b < BNB; ++b)
+#pragma unroll
             for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
 
-    v4u rh4[4], rl4[4];
+    // loader: pair index tr = t + NT i; X pairs [0, G TM) then Y pairs [0, G TN),
+    // pair (g, col) = row-group g of the slab, tile column col
+    v4u st_hi[CFG::PAIRS], st_lo[CFG::PAIRS];
+    const v4u zero = {0u, 0u, 0u, 0u};
+    // the operand and row-group of pair i are the same for the whole wave;
+    // derive them from the wave index so they are provably uniform (scalar
+    // buffer descriptors, no per-lane selection)
+    const int wave_base = __builtin_amdgcn_readfirstlane(t & ~63);
+    auto pair_of = [&](int i, bool& isx, int& g, int& col) {
+        const int trw = wave_base + NT * i;                 // first pair of this wave
+        isx = trw < G * TM;
+        const int trw2 = isx ? trw : trw - G * TM;
+        const int cols = isx ? TM : TN;
+        g = trw2 / cols;
+        col = trw2 - g * cols + lane;
+    };
     auto gload = [&](int64_t kt) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int64_t grow = kt * 4 + g;
+        for (int i = 0; i < CFG::PAIRS; ++i) {
+            bool isx;
+            int g, col;
+            pair_of(i, isx, g, col);
+            const int64_t grow = kt * G + g;
+            const uint32_t off = (uint32_t)grow * (isx ? xgs : ygs) +
+                                 (uint32_t)(((isx ? ti * TM : tj * TN) + col) * 16);
             if (grow * 8 < K) {
-                const uint32_t off = (uint32_t)grow * gsb + colb;
-                rh4[g] = __builtin_amdgcn_raw_buffer_load_b128(rh, (int)off, 0, 0);
-                rl4[g] = __builtin_amdgcn_raw_buffer_load_b128(rl, (int)off, 0, 0);
+                st_hi[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx[0] : ry[0], (int)off, 0, 0);
+                st_lo[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx[1] : ry[1], (int)off, 0, 0);
             } else {
-                rh4[g] = v4u{0u, 0u, 0u, 0u};
-                rl4[g] = v4u{0u, 0u, 0u, 0u};
+                st_hi[i] = zero;
+                st_lo[i] = zero;
             }
         }
     };
     auto sstore = [&](int s) {
-        unsigned short* hi = arr(s, 2 * side) + c * LDB;
-        unsigned short* lo = arr(s, 2 * side + 1) + c * LDB;
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            *reinterpret_cast<v4u*>(hi + 8 * g) = rh4[g];
-            *reinterpret_cast<v4u*>(lo + 8 * g) = rl4[g];
+        for (int i = 0; i < CFG::PAIRS; ++i) {
+            bool isx;
+            int g, col;
+            pair_of(i, isx, g, col);
+            unsigned short* h = (isx ? xh_(s) : yh_(s)) + col * LDR + 8 * g;
+            unsigned short* l = (isx ? xl_(s) : yl_(s)) + col * LDR + 8 * g;
+            *reinterpret_cast<v4u*>(h) = st_hi[i];
+            *reinterpret_cast<v4u*>(l) = st_lo[i];
         }
+    };
+
+    const int io = lane & 31, ko = 8 * (lane >> 5);
+    constexpr int NB = G / 2 >= 2 ? 2 : 1;                 // fragment buffers
+    v8bf fah[NB][BMB], fal[NB][BMB], fbh[NB][BNB], fbl[NB][BNB];
+    auto read_frags = [&](int buf, int s, int ks) {
+        const unsigned short* ah = xh_(s) + (wm * BMB * 32 + io) * LDR + ko + ks * 16;
+        const unsigned short* al = xl_(s) + (wm * BMB * 32 + io) * LDR + ko + ks * 16;
+        const unsigned short* bh = yh_(s) + (wn * BNB * 32 + io) * LDR + ko + ks * 16;
+        const unsigned short* bl = yl_(s) + (wn * BNB * 32 + io) * LDR + ko + ks * 16;
+#pragma unroll
+        for (int a = 0; a < BMB; ++a) {
+            fah[buf][a] = *reinterpret_cast<const v8bf*>(ah + a * 32 * LDR);
+            fal[buf][a] = *reinterpret_cast<const v8bf*>(al + a * 32 * LDR);
+        }
+#pragma unroll
+        for (int b = 0; b < BNB; ++b) {
+            fbh[buf][b] = *reinterpret_cast<const v8bf*>(bh + b * 32 * LDR);
+            fbl[buf][b] = *reinterpret_cast<const v8bf*>(bl + b * 32 * LDR);
+        }
+    };
+    auto mfmas = [&](int buf) {
+#pragma unroll
+        for (int a = 0; a < BMB; ++a)
+#pragma unroll
+            for (int b = 0; b < BNB; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[buf][a], fbh[buf][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < BMB; ++a)
+#pragma unroll
+            for (int b = 0; b < BNB; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[buf][a], fbl[buf][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < BMB; ++a)
+#pragma unroll
+            for (int b = 0; b < BNB; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[buf][a], fbh[buf][b], acc[a][b], 0, 0, 0);
     };
 
     if (nk > 0) {
@@ -255,42 +380,43 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
         sstore(0);
     }
     __syncthreads();
-    const int io = lane & 31, ko = 8 * (lane >> 5);
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int cur = (int)(kt & 1);
-        if (kt + 1 < nk) gload(kt + 1);
-        const unsigned short* xh = arr(cur, 0) + (wm * 64 + io) * LDB + ko;
-        const unsigned short* xl = arr(cur, 1) + (wm * 64 + io) * LDB + ko;
-        const unsigned short* yh = arr(cur, 2) + (wn * 64 + io) * LDB + ko;
-        const unsigned short* yl = arr(cur, 3) + (wn * 64 + io) * LDB + ko;
-#pragma unroll
-        for (int ks = 0; ks < BKB / 16; ++ks) {
-            v8bf ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-            for (int s2 = 0; s2 < 2; ++s2) {
-                ah[s2] = *reinterpret_cast<const v8bf*>(xh + s2 * 32 * LDB + ks * 16);
-                al[s2] = *reinterpret_cast<const v8bf*>(xl + s2 * 32 * LDB + ks * 16);
-                bh[s2] = *reinterpret_cast<const v8bf*>(yh + s2 * 32 * LDB + ks * 16);
-                bl[s2] = *reinterpret_cast<const v8bf*>(yl + s2 * 32 * LDB + ks * 16);
-            }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-                }
+    if constexpr (NB == 2) {
+        if (nk > 0) read_frags(0, 0, 0);
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int cur = (int)(kt & 1);
+            const bool more = kt + 1 < nk;
+            if (more) gload(kt + 1);
+            read_frags(1, cur, 1);                 // second 16-k step of this slab
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(0);                              // first step
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) sstore(cur ^ 1);             // next slab into the other LDS buffer
+            __builtin_amdgcn_sched_barrier(0);
+            mfmas(1);
+            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
+            if (more) read_frags(0, cur ^ 1, 0);
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
-        __syncthreads();
+    } else {
+        for (int64_t kt = 0; kt < nk; ++kt) {
+            const int cur = (int)(kt & 1);
+            const bool more = kt + 1 < nk;
+            if (more) gload(kt + 1);
+            read_frags(0, cur, 0);
+            mfmas(0);
+            if (more) sstore(cur ^ 1);
+            __syncthreads();
+        }
     }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int a = 0; a < BMB; ++a)
+#pragma unroll
+        for (int b = 0; b < BNB; ++b)
+#pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int r = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int cc = wn * 64 + b * 32 + (lane & 31);
-                store_elem<float>(d, ti, tj, r, cc, acc[a][b][v], C, arena);
+                const int r = wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int cc = wn * BNB * 32 + b * 32 + (lane & 31);
+                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena);
             }
 }
 
@@ -397,19 +523,14 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, int ti
 }
 
 template <int MODE>
-__global__ __launch_bounds__(LEAF_THREADS) void leaf_kernel(LeafArgs args) {
+__global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel(LeafArgs args) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
     const int64_t bid = xcd_remap(blockIdx.x, args.ntiles, args.chunk);
     const LeafDesc& d = args.tasks[find_leaf(args.tasks, args.ntasks, bid)];
     if (d.pred_node >= 0 && (int32_t)args.flags[d.pred_node] != d.pred_value) return;
     const int64_t q = bid - d.tile_begin;
     int ti, tj;
-    if (d.kind == LEAF_SYRK) {
-        tri_tile(q, ti, tj);
-    } else {
-        ti = (int)(q / d.tiles_n);
-        tj = (int)(q % d.tiles_n);
-    }
+    leaf_tile<MODE == MODE_BF16X3_LARGE ? 2 : 1>(d, q, ti, tj);
     // SYRK leaves under the spread check run in exactly one of the two
     // launches: the FP64 fallback kernel when their node is flagged, the
     // mode's own kernel otherwise.
@@ -425,8 +546,16 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_kernel(LeafArgs args) {
                                static_cast<float*>(args.C), static_cast<float*>(args.arena), smem);
     } else if constexpr (MODE == MODE_BF16X3) {
         if (flagged) return;
-        tile_bf16x3(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
-                    static_cast<float*>(args.arena), smem);
+        tile_bf16x3<BfSmall>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
+                             static_cast<float*>(args.arena), smem);
+    } else if constexpr (MODE == MODE_BF16X3_LARGE) {
+        if (flagged) return;
+        tile_bf16x3<BfLarge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
+                             static_cast<float*>(args.arena), smem);
+    } else if constexpr (MODE == MODE_BF16X3_HUGE) {
+        if (flagged) return;
+        tile_bf16x3<BfHuge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
+                            static_cast<float*>(args.arena), smem);
     } else {
         if (flagged) return;
         tile_f32(d, view_ptr<float>(d.X, args.A, args.arena), view_ptr<float>(d.Y, args.A, args.arena),
@@ -436,12 +565,20 @@ __global__ __launch_bounds__(LEAF_THREADS) void leaf_kernel(LeafArgs args) {
 
 }  // namespace
 
-hipError_t launch_leaves(int32_t mode, const LeafDesc* d_tasks, int ntasks, int64_t ntiles,
-                         const void* A, void* C, void* arena, const uint8_t* flags, int chunk,
-                         hipStream_t stream) {
+hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
+                         int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
+                         int chunk, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
     LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags};
     dim3 grid((unsigned)ntiles), block(LEAF_THREADS);
+    if (mode == MODE_BF16X3 && tile_cfg == 1) {
+        hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3_LARGE>, grid, block, 0, stream, a);
+        return hipGetLastError();
+    }
+    if (mode == MODE_BF16X3 && tile_cfg == 2) {
+        hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3_HUGE>, grid, dim3(512), 0, stream, a);
+        return hipGetLastError();
+    }
     switch (mode) {
         case MODE_F64: hipLaunchKernelGGL(leaf_kernel<MODE_F64>, grid, block, 0, stream, a); break;
         case MODE_F32: hipLaunchKernelGGL(leaf_kernel<MODE_F32>, grid, block, 0, stream, a); break;

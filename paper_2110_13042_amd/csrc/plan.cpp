@@ -27,6 +27,12 @@ int32_t default_max_depth(int32_t mode) {
     }
 }
 
+int64_t syrk_tiles(int64_t tm, int64_t tn, int64_t rho) {
+    const int64_t L = tn / rho;   // rows 0..L-1 are not clipped by tn
+    if (tm <= L) return rho * tm * (tm + 1) / 2;
+    return rho * L * (L + 1) / 2 + (tm - L) * tn;
+}
+
 int64_t Plan::alloc(int64_t elems) {
     const int64_t off = arena_elems;
     const int64_t align = 256 / elem_bytes();
@@ -108,9 +114,10 @@ struct Builder {
         L.rows = X.cols;
         L.cols = Y.cols;
         L.K = std::min(X.prows, Y.prows);
-        L.tiles_m = (int32_t)cdiv(L.rows, TILE_M);
-        L.tiles_n = (int32_t)cdiv(L.cols, TILE_N);
-        L.tiles = kind == LEAF_SYRK ? (int64_t)L.tiles_m * (L.tiles_m + 1) / 2
+        const int tmz = tile_m_for(p.mode, p.tile_cfg), tnz = tile_n_for(p.mode, p.tile_cfg);
+        L.tiles_m = (int32_t)cdiv(L.rows, tmz);
+        L.tiles_n = (int32_t)cdiv(L.cols, tnz);
+        L.tiles = kind == LEAF_SYRK ? syrk_tiles(L.tiles_m, L.tiles_n, tmz / tnz)
                                     : (int64_t)L.tiles_m * L.tiles_n;
         L.out_off = t.off;
         L.out_ld = t.ld;
@@ -173,22 +180,40 @@ struct Builder {
         }
         if (counting) ++p.stats.strassen_nodes;
         const int64_t m1 = mm / 2, m2 = mm - m1, n1 = n / 2, n2 = n - n1, k1 = k / 2, k2 = k - k1;
-        const int64_t S = alloc(5 * m2 * n2), T = alloc(5 * m2 * k2), M = alloc(7 * n2 * k2);
+        // split-BF16: when all seven products are leaves, the sums are only
+        // ever leaf operands, so the pre-sum writes them split and packed
+        const bool children_leaf = std::max(n2, k2) <= b || std::min(m2, std::min(n2, k2)) <= 1 ||
+                                   depth + 1 >= maxd;
+        const bool packed = p.mode == MODE_BF16X3 && children_leaf;
+        const int64_t groups = cdiv(m2, 8);
+        const int64_t s_each = packed ? groups * n2 * 8 : m2 * n2;
+        const int64_t t_each = packed ? groups * k2 * 8 : m2 * k2;
+        const int64_t S = alloc(5 * s_each), T = alloc(5 * t_each), M = alloc(7 * n2 * k2);
         if ((int)p.presum.size() <= depth) p.presum.resize(depth + 1);
         PresumDesc ps{};
         ps.V = X; ps.m1 = m1; ps.m2 = m2; ps.n1 = n1; ps.n2 = n2; ps.out_off = S;
-        ps.elems = m2 * cdiv(n2, 4); ps.side = 0; ps.pred_node = pn; ps.pred_value = pv;
+        ps.elems = packed ? groups * n2 : m2 * cdiv(n2, 4);
+        ps.side = 0; ps.pred_node = pn; ps.pred_value = pv; ps.packed_out = packed ? 1 : 0;
         p.presum[depth].push_back(ps);
         PresumDesc pt = ps;
-        pt.V = Y; pt.n1 = k1; pt.n2 = k2; pt.out_off = T; pt.elems = m2 * cdiv(k2, 4); pt.side = 1;
+        pt.V = Y; pt.n1 = k1; pt.n2 = k2; pt.out_off = T; pt.side = 1;
+        pt.elems = packed ? groups * k2 : m2 * cdiv(k2, 4);
         p.presum[depth].push_back(pt);
 
         const View X11 = sub(X, 0, m1, m2, 0, n1, n2), X12 = sub(X, 0, m1, m2, n1, n2, n2);
         const View X21 = sub(X, m1, m2, m2, 0, n1, n2), X22 = sub(X, m1, m2, m2, n1, n2, n2);
         const View Y11 = sub(Y, 0, m1, m2, 0, k1, k2), Y22 = sub(Y, m1, m2, m2, k1, k2, k2);
         (void)X12; (void)X21;
-        auto Sv = [&](int i) { return arena_view(S + (i - 1) * m2 * n2, m2, n2); };
-        auto Tv = [&](int i) { return arena_view(T + (i - 1) * m2 * k2, m2, k2); };
+        auto Sv = [&](int i) {
+            View v = arena_view(S + (i - 1) * s_each, m2, n2);
+            if (packed) v.base = BASE_PACKED;
+            return v;
+        };
+        auto Tv = [&](int i) {
+            View v = arena_view(T + (i - 1) * t_each, m2, k2);
+            if (packed) v.base = BASE_PACKED;
+            return v;
+        };
         auto Mt = [&](int i) { return Target{OUT_DENSE, M + (i - 1) * n2 * k2, k2, 0, 0}; };
         int h = 0;
         h = std::max(h, strassen(Sv(1), Tv(1), Mt(1), depth + 1, pn, pv));  // M1 = S1^T T1
@@ -240,6 +265,14 @@ void assign_packed(Plan& p) {
     std::map<std::tuple<int32_t, int64_t, int64_t, int64_t, int64_t, int64_t>, Packed> memo;
     auto ref = [&](const View& V, int64_t K, int32_t pn, int32_t pv) {
         Packed P{};
+        if (V.base == BASE_PACKED) {
+            const int64_t groups = std::max<int64_t>(1, cdiv(V.prows, 8));
+            P.off = V.off;
+            P.lo_delta = groups * V.cols * 4;
+            P.gstride = V.cols * 4;
+            P.end = V.off + groups * V.cols * 4;
+            return P;
+        }
         const int64_t r0 = V.base == BASE_A ? V.off / p.lda : 0, c0 = V.base == BASE_A ? V.off % p.lda : 0;
         if (V.base == BASE_A && r0 % 8 == 0 && V.pcols == V.cols && (K % 8 == 0 || r0 + K == p.m)) {
             const int64_t base = packed_a();
@@ -292,6 +325,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, n);
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode);
     p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
+    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : 0;
     if (n == 0) return p;
     Builder bld(p);
     bld.ata(0, n);
@@ -305,9 +339,14 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     t = 0;
     for (const auto& L : p.leaves) {
         if (L.fb_node >= 0) {
-            p.fb_leaves.push_back(L);
-            p.fb_leaves.back().tile_begin = t;
-            t += L.tiles;
+            // the FP64 fallback kernel works on TILE_M x TILE_N tiles
+            LeafDesc F = L;
+            F.tiles_m = (int32_t)cdiv(F.rows, TILE_M);
+            F.tiles_n = (int32_t)cdiv(F.cols, TILE_N);
+            F.tiles = syrk_tiles(F.tiles_m, F.tiles_n, TILE_M / TILE_N);
+            F.tile_begin = t;
+            t += F.tiles;
+            p.fb_leaves.push_back(F);
         }
     }
     p.fb_tiles = t;

@@ -27,7 +27,9 @@ namespace ata {
 enum Mode : int32_t { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2, MODE_FP8 = 3 };
 
 // Base buffers a view can point into.
-enum Base : int32_t { BASE_A = 0, BASE_ARENA = 1 };
+// BASE_PACKED: a split-BF16 operand that a pre-sum wrote directly in the
+// packed hi/lo layout (see Packed) at arena offset `off`, `rows` x `cols`.
+enum Base : int32_t { BASE_A = 0, BASE_ARENA = 1, BASE_PACKED = 2 };
 
 // Element (r, c) of the rows x cols logical operand is
 // base[off + r * ld + c] when r < prows and c < pcols, and 0 otherwise.
@@ -93,7 +95,8 @@ struct PresumDesc {
     int64_t elems;
     int32_t side;             // 0 = X (S sums), 1 = Y (T sums)
     int32_t pred_node, pred_value;
-    int32_t pad_;
+    int32_t packed_out;       // 1: write the five sums split and packed (work item = one
+                              // 16-byte chunk; sum i at out_off + i * ceil(m2/8) * n2 * 8)
 };
 
 // Strassen combine: seven n2 x k2 products into the four quadrants.
@@ -117,6 +120,7 @@ struct NodeDesc {
 struct PlanOptions {
     int64_t leaf_cutoff = 0;       // 0: default for the mode
     int32_t max_depth = -1;        // -1: default for the mode
+    int32_t tile_cfg = 0;          // split-BF16 leaf tile: 0 = 128 x 128, 1 = 256 x 128, 2 = 256 x 256
     double spread_tau = 4096.0;    // <= 0: no fallback
 };
 
@@ -131,6 +135,7 @@ struct Plan {
     int64_t m = 0, n = 0, lda = 0;
     int64_t b = 0;
     int32_t max_depth = 0;
+    int32_t tile_cfg = 0;
     bool fallback = false;
     std::vector<std::vector<PresumDesc>> presum;    // [level-1] top-down
     std::vector<PackDesc> pack;                     // split-BF16 operand packing
@@ -153,8 +158,21 @@ int32_t default_max_depth(int32_t mode);
 // Builds the plan (host only).  Throws std::invalid_argument on bad sizes.
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);
 
-// Tile sizes of the leaf kernels (shared with the device code).
+// Output tile of the leaf kernels (shared with the device code): 128 x 128
+// for FP64/FP32 (and the FP64 fallback), 256 x 128 for split-BF16.  A SYRK
+// leaf tiles its lower triangle with tile rows of TM and tile columns of TN:
+// tile row ti holds the tiles tj < min(rho (ti + 1), tiles_n), rho = TM / TN.
 constexpr int TILE_M = 128;
 constexpr int TILE_N = 128;
+constexpr int tile_m_for(int32_t mode, int32_t tile_cfg) {
+    return mode == MODE_BF16X3 && tile_cfg >= 1 ? 256 : 128;
+}
+constexpr int tile_n_for(int32_t mode, int32_t tile_cfg) {
+    return mode == MODE_BF16X3 && tile_cfg == 2 ? 256 : 128;
+}
+// GEMM tiles are ordered in bands of this many tile rows, column by column
+// inside a band, so consecutive tiles share operand panels.
+constexpr int TILE_BAND = 4;
+int64_t syrk_tiles(int64_t tm, int64_t tn, int64_t rho);
 
 }  // namespace ata

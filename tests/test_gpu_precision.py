@@ -29,10 +29,13 @@ def h():
     hd.close()
 
 
-def test_bf16x3_small_integers_bit_exact(h):
+@pytest.mark.parametrize("tile", [0, 1, 2])
+def test_bf16x3_small_integers_bit_exact(h, tile):
     rng = np.random.default_rng(51)
-    for (m, n, b, depth) in [(300, 513, 64, 2), (1000, 777, 100, 1), (64, 1500, 128, 2), (5, 3, 64, 0)]:
-        _say("case: bf16x3 int", m, n, b, depth)
+    h.set("leaf_tile", tile)
+    for (m, n, b, depth) in [(300, 513, 64, 2), (1000, 777, 100, 1), (64, 1500, 128, 2), (5, 3, 64, 0),
+                             (77, 300, 300, 0)]:
+        _say("case: bf16x3 int", m, n, b, depth, "tile", tile)
         A = rng.integers(-2, 3, (m, n)).astype(np.float32)
         h.set("leaf_cutoff", b)
         h.set("max_depth", depth)
@@ -40,14 +43,15 @@ def test_bf16x3_small_integers_bit_exact(h):
         assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth)
 
 
-@pytest.mark.parametrize("depth", [0, 1, 2])
-def test_bf16x3_matches_emulation(h, depth):
+@pytest.mark.parametrize("depth,tile", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (0, 2), (2, 2)])
+def test_bf16x3_matches_emulation(h, depth, tile):
     rng = np.random.default_rng(52 + depth)
     m, n, b = 1536, 1100, 256
     A = rng.standard_normal((m, n)).astype(np.float32)
     h.set("leaf_cutoff", b)
     h.set("max_depth", depth)
-    _say("case: bf16x3 emulation depth", depth)
+    h.set("leaf_tile", tile)
+    _say("case: bf16x3 emulation depth", depth, "tile", tile)
     Cp = run_gram(A, ata.F32_BF16X3, h)
     emul = emulate.ata_emulated(A, "bf16x3", b, max_strassen_depth=depth)
     exact = plain.gram_packed(A)
@@ -67,6 +71,7 @@ def test_precision_forms_16384_sampled(h):
     ref = plain.gram_cols(A, S)
     h.set("leaf_cutoff", 0)
     h.set("max_depth", -1)
+    h.set("leaf_tile", 0)
     for mode, tol in [(ata.F32, 2e-5), (ata.F32_BF16X3, 2e-5)]:
         Cp = run_gram(A, mode, h)
         got = packed_columns(Cp, 16384, S)
