@@ -85,7 +85,11 @@ typedef enum {
     ATA_OPT_PROFILE = 6,
     /* Output tile of the split-BF16 leaf kernel: 0 = 128 x 128 (default),
        1 = 256 x 128, 2 = 256 x 256.  Other dtypes ignore it. */
-    ATA_OPT_LEAF_TILE = 7
+    ATA_OPT_LEAF_TILE = 7,
+    /* ata_gram_batched: 1 = capture the batch's launch sequence once per
+       shape signature in a hipGraph and replay it (default); 0 = enqueue the
+       launches directly on the caller's stream. */
+    ATA_OPT_BATCH_GRAPH = 8
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */
@@ -133,10 +137,18 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n,
                       void* stream);
 
 /* batch independent Gram products, C_packed[i] = lower(A[i]^T A[i]), of
-   uneven shapes, in one persistent launch on `stream`.  The host arrays are
-   read during the call only.  Any invalid member fails the whole call with
-   nothing enqueued; the first bad index is in the report's `m` field as
-   -(index + 1). */
+   uneven shapes.  Every problem's plan is merged into one: each phase is a
+   single launch for the whole batch, and all leaf products of all problems
+   run in one persistent launch whose workgroups pull tiles (longest
+   contraction first) from a queue.  The first call for a shape signature
+   (the m, n, lda of every member plus the handle's options) builds the plan
+   and captures the launch sequence in a hipGraph; later calls replay it on an
+   internal stream ordered after `stream` by events (the caller's stream
+   waits for the replay).  The host arrays are read during the call only; when
+   the pointers differ from the previous call of the same signature, the call
+   first waits for that call's replay to finish.  Any invalid member fails the
+   whole call with nothing enqueued; the first bad index is in the report's
+   `m` field as -(index + 1).  No residual is computed for batches. */
 ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch,
                               const void* const* A, const int64_t* m,
                               const int64_t* n, const int64_t* lda,

@@ -25,7 +25,7 @@ DTYPE_NAMES = {"f64": F64, "f32": F32, "bf16x3": F32_BF16X3, "fp8": F32_FP8E4M3}
 
 OPT_LEAF_CUTOFF, OPT_MAX_STRASSEN_DEPTH, OPT_SPREAD_TAU = 0, 1, 2
 OPT_RESIDUAL, OPT_WORKSPACE_LIMIT, OPT_RESIDUAL_SEED, OPT_PROFILE = 3, 4, 5, 6
-OPT_LEAF_TILE = 7
+OPT_LEAF_TILE, OPT_BATCH_GRAPH = 7, 8
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -175,7 +175,8 @@ class Handle:
         key = {"leaf_cutoff": OPT_LEAF_CUTOFF, "max_depth": OPT_MAX_STRASSEN_DEPTH,
                "spread_tau": OPT_SPREAD_TAU, "residual": OPT_RESIDUAL,
                "workspace_limit": OPT_WORKSPACE_LIMIT, "residual_seed": OPT_RESIDUAL_SEED,
-               "profile": OPT_PROFILE, "leaf_tile": OPT_LEAF_TILE}[name]
+               "profile": OPT_PROFILE, "leaf_tile": OPT_LEAF_TILE,
+               "batch_graph": OPT_BATCH_GRAPH}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:
@@ -214,6 +215,30 @@ def default_handle(device_index: int) -> Handle:
     if device_index not in _DEFAULT:
         _DEFAULT[device_index] = Handle()
     return _DEFAULT[device_index]
+
+
+def gram_batched(As, dtype=None, handle: Handle | None = None, outs=None):
+    """Packed lower triangles of A_i^T A_i for a list of 2-D CUDA tensors (one call)."""
+    import torch
+    if not As:
+        return []
+    mode = _mode_of(As[0], dtype)
+    want = torch.float64 if mode == F64 else torch.float32
+    ms, ns, ldas, aps, cps, res = [], [], [], [], [], []
+    for i, A in enumerate(As):
+        if A.dim() != 2 or not A.is_cuda or A.dtype != want:
+            raise ValueError(f"member {i}: need a 2-D {want} tensor on a GPU")
+        m, n = A.shape
+        if n > 0 and m > 1 and A.stride(1) != 1:
+            raise ValueError(f"member {i}: rows must be contiguous")
+        lda = max(A.stride(0) if m > 1 else n, n, 1)
+        C = outs[i] if outs is not None else torch.empty(n * (n + 1) // 2, dtype=want, device=A.device)
+        ms.append(m); ns.append(n); ldas.append(lda); aps.append(A.data_ptr()); cps.append(C.data_ptr())
+        res.append(C)
+    h = handle or default_handle(As[0].device.index or 0)
+    stream = torch.cuda.current_stream(As[0].device).cuda_stream
+    ata_gram_batched(h.h, aps, ms, ns, ldas, mode, cps, stream)
+    return res
 
 
 def gram(A, dtype=None, handle: Handle | None = None, out=None):

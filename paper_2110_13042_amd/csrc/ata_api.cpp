@@ -40,12 +40,56 @@ struct DevicePlan {
     LeafDesc* d_fb_leaves = nullptr;
     std::vector<PresumDesc*> d_presum;
     PackDesc* d_pack = nullptr;
+    Pack8Desc* d_pack8 = nullptr;
     std::vector<CombineDesc*> d_combine;
     NodeDesc* d_nodes = nullptr;
     ~DevicePlan() { if (d_buf) (void)hipFree(d_buf); }
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BatchKey {
+    int32_t mode;
+    int64_t b;
+    int32_t depth;
+    bool fb;
+    int32_t tile_cfg;
+    std::vector<int64_t> shapes;   // m, n, lda per problem
+    bool operator<(const BatchKey& o) const {
+        return std::tie(mode, b, depth, fb, tile_cfg, shapes) <
+               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.shapes);
+    }
+};
+
+// A merged batch plan with its own device buffers and captured graph.
+struct BatchEntry {
+    std::unique_ptr<DevicePlan> dp;
+    std::vector<ColDesc> col1, col2;
+    ColDesc* d_col1 = nullptr;
+    ColDesc* d_col2 = nullptr;
+    void* aux = nullptr;               // ptr arrays | counter | flags | partials | nu
+    size_t aux_bytes = 0;
+    const void** d_A = nullptr;
+    void** d_C = nullptr;
+    unsigned long long* d_counter = nullptr;
+    uint8_t* d_flags = nullptr;
+    double* d_partial = nullptr;
+    double* d_nu = nullptr;
+    void** pinned = nullptr;           // A pointers then C pointers (page-locked)
+    int64_t nprob = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t arena_gen = 0;            // arena generation the graph was captured with
+    hipEvent_t done = nullptr;
+    bool launched = false;
+    ~BatchEntry() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (done) (void)hipEventDestroy(done);
+        if (pinned) (void)hipHostFree(pinned);
+        if (aux) (void)hipFree(aux);
+    }
+};
 
 }  // namespace
 
@@ -67,6 +111,12 @@ struct ata_ctx {
     double* last_residual = nullptr;
     int64_t last_nodes = 0;
     ata_report_t report{};
+    // batches: merged plans, captured graphs, internal capture stream
+    std::map<BatchKey, std::unique_ptr<BatchEntry>> batches;
+    hipStream_t batch_stream = nullptr;
+    hipEvent_t batch_in = nullptr;
+    bool batch_graph = true;
+    uint64_t arena_gen = 0;
     // phase profiling: six events per profiled call, summed at report time
     bool profile = false;
     std::vector<hipEvent_t> events;   // pool, grows on demand
@@ -128,6 +178,7 @@ ata_status_t upload_plan(DevicePlan& dp) {
     bytes += align256(p.nodes.size() * sizeof(NodeDesc));
     bytes += align256(p.pack.size() * sizeof(PackDesc));
     bytes += align256(p.fb_leaves.size() * sizeof(LeafDesc));
+    bytes += align256(p.pack8.size() * sizeof(Pack8Desc));
     if (bytes == 0) return ATA_OK;
     std::vector<unsigned char> host(bytes, 0);
     if (hipMalloc(&dp.d_buf, bytes) != hipSuccess) {
@@ -147,6 +198,7 @@ ata_status_t upload_plan(DevicePlan& dp) {
     dp.d_nodes = static_cast<NodeDesc*>(put(p.nodes.data(), p.nodes.size() * sizeof(NodeDesc)));
     dp.d_pack = static_cast<PackDesc*>(put(p.pack.data(), p.pack.size() * sizeof(PackDesc)));
     dp.d_fb_leaves = static_cast<LeafDesc*>(put(p.fb_leaves.data(), p.fb_leaves.size() * sizeof(LeafDesc)));
+    dp.d_pack8 = static_cast<Pack8Desc*>(put(p.pack8.data(), p.pack8.size() * sizeof(Pack8Desc)));
     return hip_status(hipMemcpy(dp.d_buf, host.data(), bytes, hipMemcpyHostToDevice));
 }
 
@@ -224,8 +276,11 @@ ata_status_t ata_create(ata_handle_t* out) {
 ata_status_t ata_destroy(ata_handle_t h) {
     if (!h) return ATA_OK;
     (void)hipSetDevice(h->device);
-    h->plans.clear();
     (void)hipDeviceSynchronize();
+    h->batches.clear();
+    h->plans.clear();
+    if (h->batch_stream) (void)hipStreamDestroy(h->batch_stream);
+    if (h->batch_in) (void)hipEventDestroy(h->batch_in);
     clear_events(h);
     if (h->arena) (void)hipFree(h->arena);
     if (h->aux) (void)hipFree(h->aux);
@@ -261,6 +316,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             if (value != 0 && value != 1 && value != 2) return ATA_ERR_INVALID_VALUE;
             h->popt.tile_cfg = (int32_t)value;
             return ATA_OK;
+        case ATA_OPT_BATCH_GRAPH:
+            h->batch_graph = value != 0.0;
+            return ATA_OK;
         case ATA_OPT_PROFILE:
             if (h->events_used) (void)drain_events(h);
             h->profile = value != 0.0;
@@ -276,7 +334,6 @@ ata_status_t ata_plan_query(int64_t m, int64_t n, ata_dtype_t dtype, int64_t lea
                             int64_t cap, int64_t* n_leaves) {
     if (!valid_dtype(dtype) || m < 0 || n < 0 || cap < 0 || (cap > 0 && !leaves))
         return ATA_ERR_INVALID_VALUE;
-    if (dtype == ATA_F32_FP8E4M3) return ATA_ERR_NOT_SUPPORTED;
     PlanOptions o;
     o.leaf_cutoff = leaf_cutoff > 0 ? leaf_cutoff : 0;
     o.max_depth = max_depth;
@@ -309,7 +366,6 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         return ATA_ERR_INVALID_VALUE;
     if (n > 0 && !C_packed) return ATA_ERR_INVALID_VALUE;
     if (n > 0 && m > 0 && !A) return ATA_ERR_INVALID_VALUE;
-    if (dtype == ATA_F32_FP8E4M3) return ATA_ERR_NOT_SUPPORTED;
     const size_t es = dtype == ATA_F64 ? 8 : 4;
     if (n > 0 && m > 0) {
         const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (size_t)((m - 1) * lda + n) * es;
@@ -357,8 +413,10 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     const AuxLayout ax = aux_layout(p, h->residual);
     const size_t arena_bytes = (size_t)p.arena_elems * (size_t)p.elem_bytes();
     if (h->ws_limit > 0 && (int64_t)(arena_bytes + ax.total) > h->ws_limit) return ATA_ERR_OUT_OF_MEMORY;
+    const size_t old_cap = h->arena_cap;
     ata_status_t s = ensure(h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
     if (s != ATA_OK) return s;
+    if (h->arena_cap != old_cap) ++h->arena_gen;
     s = ensure(h->aux, h->aux_cap, ax.total);
     if (s != ATA_OK) return s;
 
@@ -402,6 +460,9 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     if (e == hipSuccess && !p.pack.empty())
         e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
                         A, h->arena, flags, st);
+    if (e == hipSuccess && !p.pack8.empty())
+        e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems,
+                          A, h->arena, flags, st);
     mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
@@ -455,13 +516,247 @@ ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n, i
     return e == hipSuccess ? ATA_OK : ATA_ERR_HIP;
 }
 
+namespace {
+
+// Enqueue every phase of a merged batch plan on `st` (also used for capture).
+hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st) {
+    const Plan& p = be.dp->plan;
+    DevicePlan& dp = *be.dp;
+    const int32_t mode = p.mode;
+    hipError_t e = hipMemcpyAsync(be.d_A, be.pinned, sizeof(void*) * 2 * (size_t)be.nprob,
+                                  hipMemcpyHostToDevice, st);
+    const int64_t slots = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
+    BatchPtrs bp{be.d_A, be.d_C, be.d_counter, slots};
+    BatchPtrs bq{be.d_A, be.d_C, nullptr, 0};
+    if (e == hipSuccess && p.fallback) {
+        const ColDesc& l1 = be.col1.back();
+        const ColDesc& l2 = be.col2.back();
+        e = launch_colnorms_batched(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
+                                    (int)be.col2.size(), l2.elem_begin + l2.elems, be.d_A, be.d_partial,
+                                    be.d_nu, st);
+        if (e == hipSuccess)
+            e = launch_flags(be.d_nu, dp.d_nodes, (int)p.nodes.size(),
+                             h->popt.spread_tau * h->popt.spread_tau, be.d_flags, st);
+    }
+    for (size_t l = 0; e == hipSuccess && l < p.presum.size(); ++l) {
+        const auto& lv = p.presum[l];
+        if (!lv.empty())
+            e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
+                              nullptr, h->arena, be.d_flags, st, &bq);
+    }
+    if (e == hipSuccess && !p.pack.empty())
+        e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
+                        nullptr, h->arena, be.d_flags, st, &bq);
+    if (e == hipSuccess && !p.pack8.empty())
+        e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems,
+                          nullptr, h->arena, be.d_flags, st, &bq);
+    if (e == hipSuccess)
+        e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, nullptr,
+                          nullptr, h->arena, be.d_flags, h->chunk, st, &bp);
+    if (e == hipSuccess && !p.fb_leaves.empty())
+        e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, nullptr, nullptr,
+                                   h->arena, be.d_flags, h->chunk, st, &bq);
+    for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
+        const auto& lv = p.combine[l];
+        if (!lv.empty())
+            e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
+                               nullptr, h->arena, be.d_flags, st, &bq);
+    }
+    return e;
+}
+
+}  // namespace
+
 ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* A,
                               const int64_t* m, const int64_t* n, const int64_t* lda,
                               ata_dtype_t dtype, void* const* C_packed, void* stream) {
-    (void)stream;
     if (!h || batch <= 0 || !A || !m || !n || !lda || !C_packed || !valid_dtype(dtype))
         return ATA_ERR_INVALID_VALUE;
-    return ATA_ERR_NOT_SUPPORTED;
+    const size_t es = dtype == ATA_F64 ? 8 : 4;
+    for (int64_t i = 0; i < batch; ++i) {
+        bool bad = m[i] < 0 || n[i] < 0 || lda[i] < std::max<int64_t>(1, n[i]) ||
+                   (n[i] > 0 && !C_packed[i]) || (n[i] > 0 && m[i] > 0 && !A[i]);
+        if (!bad && n[i] > 0 && m[i] > 0) {
+            const uintptr_t a0 = (uintptr_t)A[i], a1 = a0 + (size_t)((m[i] - 1) * lda[i] + n[i]) * es;
+            const uintptr_t c0 = (uintptr_t)C_packed[i], c1 = c0 + (size_t)(n[i] * (n[i] + 1) / 2) * es;
+            bad = a0 < c1 && c0 < a1;
+        }
+        if (bad) {
+            h->report = ata_report_t{};
+            h->report.m = -(i + 1);
+            h->report.flagged_nodes = -1;
+            h->report.residual = -1.0;
+            return ATA_ERR_INVALID_VALUE;
+        }
+    }
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    const int32_t mode = (int32_t)dtype;
+    const int32_t depth = h->popt.max_depth >= 0 ? h->popt.max_depth : default_max_depth(mode);
+    const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0;
+    const int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
+    BatchKey key{mode, h->popt.leaf_cutoff, depth, fb, tile_cfg, {}};
+    key.shapes.reserve(3 * (size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) {
+        key.shapes.push_back(m[i]);
+        key.shapes.push_back(n[i]);
+        key.shapes.push_back(lda[i]);
+    }
+    auto it = h->batches.find(key);
+    if (it == h->batches.end()) {
+        auto be = std::make_unique<BatchEntry>();
+        be->nprob = batch;
+        std::vector<Plan> parts;
+        parts.reserve((size_t)batch);
+        try {
+            for (int64_t i = 0; i < batch; ++i) {
+                PlanOptions o;
+                o.leaf_cutoff = h->popt.leaf_cutoff > 0 ? h->popt.leaf_cutoff : default_leaf_cutoff(mode, m[i], n[i]);
+                o.max_depth = depth;
+                o.spread_tau = fb ? h->popt.spread_tau : 0.0;
+                o.tile_cfg = tile_cfg;
+                parts.push_back(make_plan(mode, m[i], n[i], lda[i], o));
+            }
+            be->dp = std::make_unique<DevicePlan>();
+            be->dp->plan = merge_plans(parts);
+        } catch (const std::invalid_argument&) {
+            return ATA_ERR_INVALID_VALUE;
+        } catch (const std::exception&) {
+            return ATA_ERR_INTERNAL;
+        }
+        const Plan& mp = be->dp->plan;
+        ata_status_t st0 = upload_plan(*be->dp);
+        if (st0 != ATA_OK) return st0;
+        // column-norm tasks (every problem, so the merged norm array is complete)
+        int64_t part_off = 0, nu_off = 0;
+        if (mp.fallback) {
+            int64_t e1 = 0, e2 = 0;
+            for (int64_t i = 0; i < batch; ++i) {
+                ColDesc d{};
+                d.m = m[i];
+                d.n = n[i];
+                d.lda = lda[i];
+                d.rows = colnorm_rows(m[i], n[i]);
+                d.nchunks = colnorm_chunks(m[i], n[i]);
+                d.part_off = part_off;
+                d.nu_off = nu_off;
+                d.prob = (int32_t)i;
+                part_off += d.nchunks * n[i];
+                nu_off += n[i];
+                if (n[i] == 0) continue;
+                ColDesc d1 = d, d2 = d;
+                d1.elems = d.nchunks * ((n[i] + 3) / 4);
+                d1.elem_begin = e1;
+                e1 += d1.elems;
+                d2.elems = n[i];
+                d2.elem_begin = e2;
+                e2 += d2.elems;
+                be->col1.push_back(d1);
+                be->col2.push_back(d2);
+            }
+            if (be->col1.empty()) {
+                // no columns anywhere: nothing for the norm passes
+                ColDesc z{};
+                be->col1.push_back(z);
+                be->col2.push_back(z);
+            }
+        }
+        // auxiliary device buffer owned by the batch entry
+        const size_t ptr_b = align256(sizeof(void*) * 2 * (size_t)batch);
+        const size_t cnt_b = 256;
+        const size_t flg_b = align256(std::max<size_t>(mp.nodes.size(), 1));
+        const size_t par_b = align256(sizeof(double) * (size_t)std::max<int64_t>(part_off, 1));
+        const size_t nu_b = align256(sizeof(double) * (size_t)std::max<int64_t>(nu_off, 1));
+        const size_t c1_b = align256(sizeof(ColDesc) * be->col1.size());
+        const size_t c2_b = align256(sizeof(ColDesc) * be->col2.size());
+        be->aux_bytes = ptr_b + cnt_b + flg_b + par_b + nu_b + c1_b + c2_b;
+        if (hipMalloc(&be->aux, be->aux_bytes) != hipSuccess) {
+            be->aux = nullptr;
+            return ATA_ERR_OUT_OF_MEMORY;
+        }
+        unsigned char* a = static_cast<unsigned char*>(be->aux);
+        be->d_A = reinterpret_cast<const void**>(a);
+        be->d_C = reinterpret_cast<void**>(a) + batch;
+        be->d_counter = reinterpret_cast<unsigned long long*>(a + ptr_b);
+        be->d_flags = a + ptr_b + cnt_b;
+        be->d_partial = reinterpret_cast<double*>(a + ptr_b + cnt_b + flg_b);
+        be->d_nu = reinterpret_cast<double*>(a + ptr_b + cnt_b + flg_b + par_b);
+        be->d_col1 = reinterpret_cast<ColDesc*>(a + ptr_b + cnt_b + flg_b + par_b + nu_b);
+        be->d_col2 = reinterpret_cast<ColDesc*>(a + ptr_b + cnt_b + flg_b + par_b + nu_b + c1_b);
+        if (!be->col1.empty()) {
+            if (hipMemcpy(be->d_col1, be->col1.data(), sizeof(ColDesc) * be->col1.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(be->d_col2, be->col2.data(), sizeof(ColDesc) * be->col2.size(), hipMemcpyHostToDevice) != hipSuccess)
+                return ATA_ERR_HIP;
+        }
+        if (hipHostMalloc(reinterpret_cast<void**>(&be->pinned), sizeof(void*) * 2 * (size_t)batch, 0) != hipSuccess) {
+            be->pinned = nullptr;
+            return ATA_ERR_OUT_OF_MEMORY;
+        }
+        if (hipEventCreateWithFlags(&be->done, hipEventDisableTiming) != hipSuccess) return ATA_ERR_HIP;
+        it = h->batches.emplace(key, std::move(be)).first;
+    }
+    BatchEntry& be = *it->second;
+    const Plan& mp = be.dp->plan;
+    const size_t arena_bytes = (size_t)mp.arena_elems * (size_t)mp.elem_bytes();
+    if (h->ws_limit > 0 && (int64_t)(arena_bytes + be.aux_bytes) > h->ws_limit) return ATA_ERR_OUT_OF_MEMORY;
+    const size_t old_cap = h->arena_cap;
+    ata_status_t s = ensure(h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
+    if (s != ATA_OK) return s;
+    if (h->arena_cap != old_cap) ++h->arena_gen;
+    // stage the pointers; a previous replay may still be copying them
+    bool changed = !be.launched;
+    for (int64_t i = 0; i < batch && !changed; ++i)
+        changed = be.pinned[i] != A[i] || be.pinned[batch + i] != C_packed[i];
+    if (changed) {
+        if (be.launched && hipEventSynchronize(be.done) != hipSuccess) return ATA_ERR_HIP;
+        for (int64_t i = 0; i < batch; ++i) {
+            be.pinned[i] = const_cast<void*>(A[i]);
+            be.pinned[batch + i] = C_packed[i];
+        }
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (!h->batch_graph) {
+        e = enqueue_batch(h, be, st);
+        if (e == hipSuccess) e = hipEventRecord(be.done, st);
+    } else {
+        if (!h->batch_stream) {
+            if (hipStreamCreateWithFlags(&h->batch_stream, hipStreamNonBlocking) != hipSuccess) return ATA_ERR_HIP;
+            if (hipEventCreateWithFlags(&h->batch_in, hipEventDisableTiming) != hipSuccess) return ATA_ERR_HIP;
+        }
+        if (!be.exec || be.arena_gen != h->arena_gen) {
+            if (be.exec) {
+                if (be.launched && hipEventSynchronize(be.done) != hipSuccess) return ATA_ERR_HIP;
+                (void)hipGraphExecDestroy(be.exec);
+                (void)hipGraphDestroy(be.graph);
+                be.exec = nullptr;
+                be.graph = nullptr;
+            }
+            (void)leaf_blocks_per_cu(mode, mp.tile_cfg);   // occupancy query outside the capture
+            e = hipStreamBeginCapture(h->batch_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t e1 = enqueue_batch(h, be, h->batch_stream);
+                e = hipStreamEndCapture(h->batch_stream, &be.graph);
+                if (e1 != hipSuccess) e = e1;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&be.exec, be.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return ATA_ERR_HIP;
+            be.arena_gen = h->arena_gen;
+        }
+        e = hipEventRecord(h->batch_in, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->batch_stream, h->batch_in, 0);
+        if (e == hipSuccess) e = hipGraphLaunch(be.exec, h->batch_stream);
+        if (e == hipSuccess) e = hipEventRecord(be.done, h->batch_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, be.done, 0);
+    }
+    if (e != hipSuccess) return ATA_ERR_HIP;
+    be.launched = true;
+    fill_report(h->report, mp);
+    h->report.m = 0;
+    h->report.n = 0;
+    h->report.lda = 0;
+    h->pending_flags = false;
+    h->pending_residual = false;
+    return ATA_OK;
 }
 
 ata_status_t ata_get_report(ata_handle_t h, ata_report_t* out) {

@@ -100,12 +100,13 @@ __device__ __forceinline__ void st4(T* p, const typename Vec4<T>::type& v) {
 
 template <class T>
 __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* tasks, int ntasks,
-                                                            int64_t items, const T* A, T* arena,
-                                                            const uint8_t* flags) {
+                                                            int64_t items, const T* A0, T* arena,
+                                                            const uint8_t* flags, const void* const* Aptrs) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
     const PresumDesc& d = tasks[find_task(tasks, ntasks, x)];
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    const T* A = Aptrs ? static_cast<const T*>(Aptrs[d.prob]) : A0;
     const int64_t e = x - d.elem_begin;
     if constexpr (sizeof(T) == 4) {
         if (d.packed_out) {
@@ -174,12 +175,14 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
 // Work item = one 16-byte chunk (row-group g, column c): rows 8g..8g+7 of
 // column c split into hi = bf16(a) and lo = bf16(a - hi).
 __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks, int ntasks,
-                                                          int64_t items, const float* A,
-                                                          float* arena, const uint8_t* flags) {
+                                                          int64_t items, const float* A0,
+                                                          float* arena, const uint8_t* flags,
+                                                          const void* const* Aptrs) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
     const PackDesc& d = tasks[find_task(tasks, ntasks, x)];
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    const float* A = Aptrs ? static_cast<const float*>(Aptrs[d.prob]) : A0;
     const int64_t e = x - d.elem_begin;
     const int64_t g = e / d.cols, c = e - g * d.cols;
     const float* src = (d.src.base == BASE_A ? A : arena) + d.src.off;
@@ -195,6 +198,61 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
     reinterpret_cast<uint4*>(arena + d.dst + d.lo_delta)[g * d.cols + c] = lo;
 }
 
+// ------------------------------------------------------------ FP8 quantising
+// One workgroup per 128 x 128 block of an operand view: block amax, the
+// power-of-two exponent e (smallest e with amax <= 448 * 2^e; 448 = 0.875 * 2^9,
+// so with amax = f 2^E, f in [0.5, 1): e = E - 9 if f <= 0.875 else E - 8,
+// exact), then q = e4m3_RNE(a * 2^-e) packed in 16-row chunks.
+__global__ __launch_bounds__(EW_THREADS) void quant8_kernel(const Pack8Desc* tasks, int ntasks,
+                                                            const float* A0, float* arena,
+                                                            const uint8_t* flags,
+                                                            const void* const* Aptrs) {
+    __shared__ float wmax[EW_THREADS / 64];
+    const int64_t x = blockIdx.x;
+    const Pack8Desc& d = tasks[find_task(tasks, ntasks, x)];
+    if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    const float* A = Aptrs ? static_cast<const float*>(Aptrs[d.prob]) : A0;
+    const int64_t blk = x - d.elem_begin;
+    const int64_t nbc = d.cols_p / 128;
+    const int64_t bi = blk / nbc, bj = blk - bi * nbc;
+    const float* src = (d.src.base == BASE_A ? A : arena) + d.src.off;
+    const int t = threadIdx.x, c = t & 127, h = t >> 7;
+    const int64_t col = bj * 128 + c, row0 = bi * 128 + h * 64;
+    float v[64];
+    float amax = 0.f;
+#pragma unroll
+    for (int q = 0; q < 64; ++q) {
+        const int64_t r = row0 + q;
+        v[q] = (r < d.src.prows && col < d.src.pcols) ? src[r * d.src.ld + col] : 0.f;
+        amax = fmaxf(amax, fabsf(v[q]));
+    }
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    if ((t & 63) == 0) wmax[t >> 6] = amax;
+    __syncthreads();
+    amax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    int e = 0;
+    if (amax > 0.f) {
+        int E;
+        const float f = frexpf(amax, &E);
+        e = f <= 0.875f ? E - 9 : E - 8;
+    }
+    if (t == 0) reinterpret_cast<int*>(arena + d.scales)[blk] = e;
+    unsigned char* data = reinterpret_cast<unsigned char*>(arena + d.dst);
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        uint32_t wds[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float* p4 = v + ch * 16 + q * 4;
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(p4[0], -e), ldexpf(p4[1], -e), 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(p4[2], -e), ldexpf(p4[3], -e), w, true);
+            wds[q] = (uint32_t)w;
+        }
+        const int64_t g = row0 / 16 + ch;
+        reinterpret_cast<uint4*>(data)[g * d.cols_p + col] = make_uint4(wds[0], wds[1], wds[2], wds[3]);
+    }
+}
+
 // ---------------------------------------------------------------- combine
 // Work item = one row i and four columns j..j+3 of the n2 x k2 products.
 // C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4,
@@ -202,12 +260,13 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
 // of a product reaches a floor-sized quadrant.
 template <class T>
 __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* tasks, int ntasks,
-                                                             int64_t items, T* C, T* arena,
-                                                             const uint8_t* flags) {
+                                                             int64_t items, T* C0, T* arena,
+                                                             const uint8_t* flags, void* const* Cptrs) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
     const CombineDesc& d = tasks[find_task(tasks, ntasks, x)];
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    T* C = Cptrs ? static_cast<T*>(Cptrs[d.prob]) : C0;
     const int64_t e = x - d.elem_begin;
     const int64_t groups = (d.k2 + 3) >> 2;
     const int64_t i = e / groups, j0 = (e - i * groups) << 2;
@@ -306,6 +365,44 @@ __global__ __launch_bounds__(EW_THREADS) void colnorm_partial(const T* A, int64_
     if (j0 + 1 < n) p[1] = s1;
     if (j0 + 2 < n) p[2] = s2;
     if (j0 + 3 < n) p[3] = s3;
+}
+
+// Batched column norms: pass 1 item = (chunk, four columns) of one problem.
+__global__ __launch_bounds__(EW_THREADS) void colnorm_batched(const ColDesc* tasks, int ntasks,
+                                                              int64_t items, const void* const* Aptrs,
+                                                              double* partial) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= items) return;
+    const ColDesc& d = tasks[find_task(tasks, ntasks, x)];
+    const float* A = static_cast<const float*>(Aptrs[d.prob]);
+    const int64_t e = x - d.elem_begin;
+    const int64_t groups = (d.n + 3) / 4;
+    const int64_t chunk = e / groups, j0 = (e - chunk * groups) * 4;
+    const int64_t r0 = chunk * d.rows, r1 = r0 + d.rows < d.m ? r0 + d.rows : d.m;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = r0; r < r1; ++r) {
+        const float* row = A + r * d.lda + j0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (j0 + q < d.n) { const double a = (double)row[q]; s[q] += a * a; }
+    }
+    double* p = partial + d.part_off + chunk * d.n + j0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (j0 + q < d.n) p[q] = s[q];
+}
+
+// Batched column norms: pass 2 item = one column of one problem.
+__global__ __launch_bounds__(EW_THREADS) void colsum_batched(const ColDesc* tasks, int ntasks,
+                                                             int64_t items, const double* partial,
+                                                             double* nu) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= items) return;
+    const ColDesc& d = tasks[find_task(tasks, ntasks, x)];
+    const int64_t j = x - d.elem_begin;
+    double s = 0.0;
+    for (int64_t c = 0; c < d.nchunks; ++c) s += partial[d.part_off + c * d.n + j];
+    nu[d.nu_off + j] = s;
 }
 
 __global__ __launch_bounds__(EW_THREADS) void sum_partials(const double* partial, int64_t nchunks,
@@ -464,38 +561,52 @@ unsigned blocks_for(int64_t items) { return (unsigned)((items + EW_THREADS - 1) 
 }  // namespace
 
 hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, int64_t items,
-                         const void* A, void* arena, const uint8_t* flags, hipStream_t stream) {
+                         const void* A, void* arena, const uint8_t* flags, hipStream_t stream,
+                         const BatchPtrs* bp) {
     if (items <= 0) return hipSuccess;
+    const void* const* Ap = bp ? bp->A : nullptr;
     if (mode == MODE_F64)
         hipLaunchKernelGGL(presum_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<const double*>(A),
-                           static_cast<double*>(arena), flags);
+                           static_cast<double*>(arena), flags, Ap);
     else
         hipLaunchKernelGGL(presum_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<const float*>(A),
-                           static_cast<float*>(arena), flags);
+                           static_cast<float*>(arena), flags, Ap);
     return hipGetLastError();
 }
 
 hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const void* A,
-                       void* arena, const uint8_t* flags, hipStream_t stream) {
+                       void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp) {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream, d_tasks,
-                       ntasks, items, static_cast<const float*>(A), static_cast<float*>(arena), flags);
+                       ntasks, items, static_cast<const float*>(A), static_cast<float*>(arena), flags,
+                       bp ? bp->A : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, const void* A,
+                         void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(quant8_kernel, dim3((unsigned)blocks), dim3(EW_THREADS), 0, stream, d_tasks,
+                       ntasks, static_cast<const float*>(A), static_cast<float*>(arena), flags,
+                       bp ? bp->A : nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
-                          void* C, void* arena, const uint8_t* flags, hipStream_t stream) {
+                          void* C, void* arena, const uint8_t* flags, hipStream_t stream,
+                          const BatchPtrs* bp) {
     if (items <= 0) return hipSuccess;
+    void* const* Cp = bp ? bp->C : nullptr;
     if (mode == MODE_F64)
         hipLaunchKernelGGL(combine_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<double*>(C),
-                           static_cast<double*>(arena), flags);
+                           static_cast<double*>(arena), flags, Cp);
     else
         hipLaunchKernelGGL(combine_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<float*>(C),
-                           static_cast<float*>(arena), flags);
+                           static_cast<float*>(arena), flags, Cp);
     return hipGetLastError();
 }
 
@@ -503,6 +614,7 @@ int64_t colnorm_chunks(int64_t m, int64_t n) {
     const int64_t r = norm_rows(m, n);
     return m <= 0 ? 1 : (m + r - 1) / r;
 }
+int64_t colnorm_rows(int64_t m, int64_t n) { return norm_rows(m, n); }
 int64_t residual_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / NORM_ROWS; }
 
 hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
@@ -512,6 +624,19 @@ hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, do
                        dim3(EW_THREADS), 0, stream, A, m, n, lda, norm_rows(m, n), partial);
     hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), dim3(EW_THREADS), 0, stream, partial,
                        nchunks, n, nu);
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorms_batched(const ColDesc* d_pass1, int n1, int64_t items1,
+                                   const ColDesc* d_pass2, int n2, int64_t items2,
+                                   const void* const* Aptrs, double* partial, double* nu,
+                                   hipStream_t stream) {
+    if (items1 > 0)
+        hipLaunchKernelGGL(colnorm_batched, dim3(blocks_for(items1)), dim3(EW_THREADS), 0, stream,
+                           d_pass1, n1, items1, Aptrs, partial);
+    if (items2 > 0)
+        hipLaunchKernelGGL(colsum_batched, dim3(blocks_for(items2)), dim3(EW_THREADS), 0, stream,
+                           d_pass2, n2, items2, partial, nu);
     return hipGetLastError();
 }
 

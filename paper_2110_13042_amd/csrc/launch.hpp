@@ -8,36 +8,64 @@
 
 namespace ata {
 
+// Device arrays of a batch: A and C pointer of problem i at A[i], C[i]; the
+// persistent leaf launch's queue head and grid size.
+struct BatchPtrs {
+    const void* const* A;
+    void* const* C;
+    unsigned long long* counter;   // null: one workgroup per tile
+    int64_t persistent_blocks;
+};
+
+// Resident leaf workgroups per CU for the mode's kernel (occupancy query).
+int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg);
+
 // All leaf products of a plan (one grouped launch, one workgroup per tile).
 // tile_cfg selects the output tile of the split-BF16 kernel (0: 128 x 128,
 // 1: 256 x 128); the other modes have one tile shape.
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
-                         int chunk, hipStream_t stream);
+                         int chunk, hipStream_t stream, const BatchPtrs* bp = nullptr);
 
 // FP64 fallback of flagged SYRK leaves (FP32 inputs and output); the tasks
 // are the plan's fallback-capable SYRK leaves, unflagged ones exit at once.
 hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t ntiles, const void* A,
                                   void* C, void* arena, const uint8_t* flags, int chunk,
-                                  hipStream_t stream);
+                                  hipStream_t stream, const BatchPtrs* bp = nullptr);
 
 // One Strassen level of pre-sums (S1..S5 / T1..T5 for every node of the level).
 hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, int64_t items,
-                         const void* A, void* arena, const uint8_t* flags, hipStream_t stream);
+                         const void* A, void* arena, const uint8_t* flags, hipStream_t stream,
+                         const BatchPtrs* bp = nullptr);
 
 // Split-BF16 packing of the leaf operands (one launch for the whole plan).
 hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const void* A,
-                       void* arena, const uint8_t* flags, hipStream_t stream);
+                       void* arena, const uint8_t* flags, hipStream_t stream,
+                       const BatchPtrs* bp = nullptr);
+
+// FP8 quantisation of the leaf operands (one workgroup per 128 x 128 block).
+hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, const void* A,
+                         void* arena, const uint8_t* flags, hipStream_t stream,
+                         const BatchPtrs* bp = nullptr);
 
 // One height of Strassen combines (seven products -> four quadrants).
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
-                          void* C, void* arena, const uint8_t* flags, hipStream_t stream);
+                          void* C, void* arena, const uint8_t* flags, hipStream_t stream,
+                          const BatchPtrs* bp = nullptr);
+
+// Column norms of every problem of a batch (pass 1 over row chunks, pass 2
+// sums the chunks of each column in order).
+hipError_t launch_colnorms_batched(const ColDesc* d_pass1, int n1, int64_t items1,
+                                   const ColDesc* d_pass2, int n2, int64_t items2,
+                                   const void* const* Aptrs, double* partial, double* nu,
+                                   hipStream_t stream);
 
 // Squared column norms (FP64) of a float matrix, deterministic two-pass sum:
 // partial[chunk][j] over row chunks, then nu[j] = sum over chunks in order.
 hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
                            int64_t nchunks, double* nu, hipStream_t stream);
 int64_t colnorm_chunks(int64_t m, int64_t n);
+int64_t colnorm_rows(int64_t m, int64_t n);
 
 // flags[i] = spread of nu over node i's columns > tau^2 (1/0); count in *count.
 hipError_t launch_flags(const double* nu, const NodeDesc* d_nodes, int nnodes, double tau2,

@@ -49,7 +49,7 @@ constexpr size_t lds_bytes(int mode) {
     return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
-           : mode == MODE_F32 ? LDS32_BYTES : LDS64_BYTES;
+           : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
 constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE ? 512 : LEAF_THREADS; }
 
@@ -65,6 +65,9 @@ struct LeafArgs {
     void* C;
     void* arena;
     const uint8_t* flags;
+    const void* const* Aptrs;     // batches: A and C of problem d.prob (else A, C)
+    void* const* Cptrs;
+    unsigned long long* counter;  // persistent mode: tile queue head (else null)
 };
 
 __device__ __forceinline__ int find_leaf(const LeafDesc* t, int n, int64_t x) {
@@ -420,6 +423,112 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
             }
 }
 
+// ------------------------------------------------------------ FP8 e4m3
+// 128 x 128 tile, four waves (2 x 2), each 64 x 64 = 4 x 4 blocks of 16 x 16
+// on v_mfma_scale_f32_16x16x128_f8f6f4.  A slab is 128 rows, i.e. exactly one
+// 128-row scale block of each operand, and a tile column range is one
+// 128-column scale block, so both E8M0 scales (127 + e) are uniform per slab.
+// MFMA lane layout: lane l holds row/column l%16 and k = 32(l/16) .. +31; the
+// result register v of lane l is (i = 4(l/16) + v, j = l%16).
+typedef int v8i __attribute__((ext_vector_type(8)));
+constexpr int LD8 = 144;                         // bytes per LDS row: 128 k + 16 pad
+constexpr size_t LDS8_BYTES = 2 * 2 * 128 * LD8;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t q8_rsrc(const float* arena, const Packed8& Q) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(arena + Q.off), (short)0,
+                                             (int)(uint32_t)((Q.end - Q.off) * 4), 0x00020000);
+}
+
+__device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int tj,
+                         float* C, float* arena, unsigned char* smem) {
+    auto xq_ = [&](int s) { return smem + s * 2 * 128 * LD8; };
+    auto yq_ = [&](int s) { return smem + s * 2 * 128 * LD8 + 128 * LD8; };
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    const __amdgpu_buffer_rsrc_t rx = q8_rsrc(arena_in, d.QX), ry = q8_rsrc(arena_in, d.QY);
+    const int* sx = reinterpret_cast<const int*>(arena_in + d.QX.scales);
+    const int* sy = reinterpret_cast<const int*>(arena_in + d.QY.scales);
+    const int64_t sxs = d.QX.cols_p / 128, sys = d.QY.cols_p / 128;
+    const int64_t K = d.K;
+    const int64_t nk = (K + 127) / 128;
+    const int wave_base = __builtin_amdgcn_readfirstlane(t & ~63);
+
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.f;
+
+    // chunks: X [0, 1024) then Y [0, 1024); chunk (g, col): rows 16g..16g+15 of the slab
+    v4u st[8];
+    auto gload = [&](int64_t kt) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int trw = wave_base + 256 * i;
+            const bool isx = trw < 1024;
+            const int trw2 = isx ? trw : trw - 1024;
+            const int g = trw2 >> 7, col = (trw2 & 127) + lane;
+            const int64_t cp = isx ? d.QX.cols_p : d.QY.cols_p;
+            const uint32_t off = (uint32_t)(((kt * 8 + g) * cp + (isx ? ti : tj) * 128 + col) * 16);
+            st[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx : ry, (int)off, 0, 0);
+        }
+    };
+    auto sstore = [&](int s) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int trw = wave_base + 256 * i;
+            const bool isx = trw < 1024;
+            const int trw2 = isx ? trw : trw - 1024;
+            const int g = trw2 >> 7, col = (trw2 & 127) + lane;
+            *reinterpret_cast<v4u*>((isx ? xq_(s) : yq_(s)) + col * LD8 + 16 * g) = st[i];
+        }
+    };
+
+    if (nk > 0) {
+        gload(0);
+        sstore(0);
+    }
+    __syncthreads();
+    const int io = lane & 15, ko = 32 * (lane >> 4);
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int cur = (int)(kt & 1);
+        if (kt + 1 < nk) gload(kt + 1);
+        const int sa = 127 + sx[kt * sxs + ti], sb = 127 + sy[kt * sys + tj];
+        v8i fa[4], fb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const unsigned char* p = xq_(cur) + (wm * 64 + a * 16 + io) * LD8 + ko;
+            const v4u lo = *reinterpret_cast<const v4u*>(p), hi = *reinterpret_cast<const v4u*>(p + 16);
+            fa[a] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const unsigned char* p = yq_(cur) + (wn * 64 + b * 16 + io) * LD8 + ko;
+            const v4u lo = *reinterpret_cast<const v4u*>(p), hi = *reinterpret_cast<const v4u*>(p + 16);
+            fb[b] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[a], fb[b], acc[a][b],
+                                                                             0, 0, 0, sa, 0, sb);
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wm * 64 + a * 16 + 4 * (lane >> 4) + v;
+                const int c = wn * 64 + b * 16 + (lane & 15);
+                store_elem<float>(d, ti, tj, r, c, acc[a][b][v], C, arena);
+            }
+}
+
 // ---------------------------------------------------------------- FP64 MFMA
 // InT = double (FP64 mode) or float (FP64 fallback of the FP32 family: the
 // inputs are promoted exactly, the result is rounded to OutT on store).
@@ -523,10 +632,10 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, int ti
 }
 
 template <int MODE>
-__global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel(LeafArgs args) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
-    const int64_t bid = xcd_remap(blockIdx.x, args.ntiles, args.chunk);
+__device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsigned char* smem) {
     const LeafDesc& d = args.tasks[find_leaf(args.tasks, args.ntasks, bid)];
+    const void* Aptr = args.Aptrs ? args.Aptrs[d.prob] : args.A;
+    void* Cptr = args.Cptrs ? args.Cptrs[d.prob] : args.C;
     if (d.pred_node >= 0 && (int32_t)args.flags[d.pred_node] != d.pred_value) return;
     const int64_t q = bid - d.tile_begin;
     int ti, tj;
@@ -536,41 +645,76 @@ __global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel(LeafArgs args) 
     // mode's own kernel otherwise.
     const bool flagged = d.fb_node >= 0 && args.flags[d.fb_node];
     if constexpr (MODE == MODE_F64) {
-        tile_f64<double, double>(d, view_ptr<double>(d.X, args.A, args.arena),
-                                 view_ptr<double>(d.Y, args.A, args.arena), ti, tj,
-                                 static_cast<double*>(args.C), static_cast<double*>(args.arena), smem);
+        tile_f64<double, double>(d, view_ptr<double>(d.X, Aptr, args.arena),
+                                 view_ptr<double>(d.Y, Aptr, args.arena), ti, tj,
+                                 static_cast<double*>(Cptr), static_cast<double*>(args.arena), smem);
     } else if constexpr (MODE == MODE_FALLBACK) {
         if (!flagged) return;
-        tile_f64<float, float>(d, view_ptr<float>(d.X, args.A, args.arena),
-                               view_ptr<float>(d.Y, args.A, args.arena), ti, tj,
-                               static_cast<float*>(args.C), static_cast<float*>(args.arena), smem);
+        tile_f64<float, float>(d, view_ptr<float>(d.X, Aptr, args.arena),
+                               view_ptr<float>(d.Y, Aptr, args.arena), ti, tj,
+                               static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem);
     } else if constexpr (MODE == MODE_BF16X3) {
         if (flagged) return;
-        tile_bf16x3<BfSmall>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
+        tile_bf16x3<BfSmall>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
                              static_cast<float*>(args.arena), smem);
     } else if constexpr (MODE == MODE_BF16X3_LARGE) {
         if (flagged) return;
-        tile_bf16x3<BfLarge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
+        tile_bf16x3<BfLarge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
                              static_cast<float*>(args.arena), smem);
+    } else if constexpr (MODE == MODE_FP8) {
+        if (flagged) return;
+        tile_fp8(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                 static_cast<float*>(args.arena), smem);
     } else if constexpr (MODE == MODE_BF16X3_HUGE) {
         if (flagged) return;
-        tile_bf16x3<BfHuge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(args.C),
+        tile_bf16x3<BfHuge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
                             static_cast<float*>(args.arena), smem);
     } else {
         if (flagged) return;
-        tile_f32(d, view_ptr<float>(d.X, args.A, args.arena), view_ptr<float>(d.Y, args.A, args.arena),
-                 ti, tj, static_cast<float*>(args.C), static_cast<float*>(args.arena), smem);
+        tile_f32(d, view_ptr<float>(d.X, Aptr, args.arena), view_ptr<float>(d.Y, Aptr, args.arena),
+                 ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem);
     }
 }
+
+template <int MODE>
+__global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel(LeafArgs args) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
+    if (!args.counter) {
+        run_tile<MODE>(args, xcd_remap(blockIdx.x, args.ntiles, args.chunk), smem);
+        return;
+    }
+    // persistent: pull tiles (longest contraction first) until the queue is empty
+    __shared__ int64_t next;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int64_t)atomicAdd(args.counter, 1ull);
+        __syncthreads();
+        const int64_t tile = next;
+        __syncthreads();
+        if (tile >= args.ntiles) break;
+        run_tile<MODE>(args, tile, smem);
+    }
+}
+
+__global__ void zero_counter(unsigned long long* c) { *c = 0ull; }
 
 }  // namespace
 
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
-                         int chunk, hipStream_t stream) {
+                         int chunk, hipStream_t stream, const BatchPtrs* bp) {
     if (ntiles <= 0) return hipSuccess;
-    LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags};
+    LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr};
     dim3 grid((unsigned)ntiles), block(LEAF_THREADS);
+    if (bp) {
+        a.Aptrs = bp->A;
+        a.Cptrs = bp->C;
+        if (bp->counter) {
+            a.counter = bp->counter;
+            hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, stream, bp->counter);
+            const int64_t g = ntiles < bp->persistent_blocks ? ntiles : bp->persistent_blocks;
+            grid = dim3((unsigned)g);
+        }
+    }
     if (mode == MODE_BF16X3 && tile_cfg == 1) {
         hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3_LARGE>, grid, block, 0, stream, a);
         return hipGetLastError();
@@ -583,6 +727,7 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
         case MODE_F64: hipLaunchKernelGGL(leaf_kernel<MODE_F64>, grid, block, 0, stream, a); break;
         case MODE_F32: hipLaunchKernelGGL(leaf_kernel<MODE_F32>, grid, block, 0, stream, a); break;
         case MODE_BF16X3: hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3>, grid, block, 0, stream, a); break;
+        case MODE_FP8: hipLaunchKernelGGL(leaf_kernel<MODE_FP8>, grid, block, 0, stream, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -590,11 +735,34 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
 
 hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t ntiles, const void* A,
                                   void* C, void* arena, const uint8_t* flags, int chunk,
-                                  hipStream_t stream) {
+                                  hipStream_t stream, const BatchPtrs* bp) {
     if (ntiles <= 0) return hipSuccess;
-    LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags};
+    LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags,
+               bp ? bp->A : nullptr, bp ? bp->C : nullptr, nullptr};
     hipLaunchKernelGGL(leaf_kernel<MODE_FALLBACK>, dim3((unsigned)ntiles), dim3(LEAF_THREADS), 0, stream, a);
     return hipGetLastError();
+}
+
+}  // namespace ata
+
+namespace ata {
+
+int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    if (mode == MODE_BF16X3 && tile_cfg == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_BF16X3_LARGE>, LEAF_THREADS, 0);
+    else if (mode == MODE_BF16X3 && tile_cfg == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_BF16X3_HUGE>, 512, 0);
+    else if (mode == MODE_BF16X3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_BF16X3>, LEAF_THREADS, 0);
+    else if (mode == MODE_FP8)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_FP8>, LEAF_THREADS, 0);
+    else if (mode == MODE_F32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_F32>, LEAF_THREADS, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_F64>, LEAF_THREADS, 0);
+    return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 }  // namespace ata

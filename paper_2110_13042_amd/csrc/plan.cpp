@@ -43,6 +43,7 @@ int64_t Plan::alloc(int64_t elems) {
 int64_t Plan::launches() const {
     int64_t l = (int64_t)presum.size() + (leaves.empty() ? 0 : 1) + (int64_t)combine.size();
     if (!pack.empty()) l += 1;
+    if (!pack8.empty()) l += 1;
     if (!fb_leaves.empty()) l += 1;
     if (fallback) l += 2;  // column norms + flags
     return l;
@@ -312,6 +313,42 @@ void assign_packed(Plan& p) {
     for (auto& d : p.pack) { d.elem_begin = e; e += d.elems; }
 }
 
+// FP8: every distinct leaf operand view is quantised on its own (blocks
+// aligned to the view's first row and column).
+void assign_quant(Plan& p) {
+    std::map<std::tuple<int32_t, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t>, Packed8> memo;
+    auto ref = [&](const View& V, int32_t pn, int32_t pv) {
+        const auto key = std::make_tuple(V.base, V.off, V.ld, V.prows, V.pcols, V.rows, V.cols);
+        auto it = memo.find(key);
+        if (it != memo.end()) return it->second;
+        const int64_t rows_p = std::max<int64_t>(128, cdiv(V.prows, 128) * 128);
+        const int64_t cols_p = std::max<int64_t>(128, cdiv(V.cols, 128) * 128);
+        Pack8Desc d{};
+        d.src = V;
+        d.dst = p.alloc(rows_p * cols_p / 4);
+        d.scales = p.alloc((rows_p / 128) * (cols_p / 128));
+        d.rows_p = rows_p;
+        d.cols_p = cols_p;
+        d.elems = (rows_p / 128) * (cols_p / 128);
+        d.pred_node = pn;
+        d.pred_value = pv;
+        p.pack8.push_back(d);
+        Packed8 Q{};
+        Q.off = d.dst;
+        Q.scales = d.scales;
+        Q.cols_p = cols_p;
+        Q.end = d.dst + rows_p * cols_p / 4;
+        memo.emplace(key, Q);
+        return Q;
+    };
+    for (auto& L : p.leaves) {
+        L.QX = ref(L.X, L.pred_node, L.pred_value);
+        L.QY = L.kind == LEAF_SYRK ? L.QX : ref(L.Y, L.pred_node, L.pred_value);
+    }
+    int64_t e = 0;
+    for (auto& d : p.pack8) { d.elem_begin = e; e += d.elems; }
+}
+
 }  // namespace
 
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt) {
@@ -330,6 +367,12 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     Builder bld(p);
     bld.ata(0, n);
     if (mode == MODE_BF16X3 && m > 0) assign_packed(p);
+    if (mode == MODE_FP8 && m > 0) assign_quant(p);
+    finalize_plan(p);
+    return p;
+}
+
+void finalize_plan(Plan& p) {
     // LPT: longest contraction first (stable, so ties keep tree order)
     std::stable_sort(p.leaves.begin(), p.leaves.end(),
                      [](const LeafDesc& a, const LeafDesc& c) { return a.K > c.K; });
@@ -337,6 +380,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     for (auto& L : p.leaves) { L.tile_begin = t; t += L.tiles; }
     p.total_tiles = t;
     t = 0;
+    p.fb_leaves.clear();
     for (const auto& L : p.leaves) {
         if (L.fb_node >= 0) {
             // the FP64 fallback kernel works on TILE_M x TILE_N tiles
@@ -358,7 +402,104 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
         int64_t e = 0;
         for (auto& d : lvl) { d.elem_begin = e; e += d.elems; }
     }
-    return p;
+    int64_t e = 0;
+    for (auto& d : p.pack) { d.elem_begin = e; e += d.elems; }
+    e = 0;
+    for (auto& d : p.pack8) { d.elem_begin = e; e += d.elems; }
 }
+
+namespace {
+
+void shift_view(View& v, int64_t ab) {
+    if (v.base != BASE_A) v.off += ab;
+}
+
+}  // namespace
+
+Plan merge_plans(std::vector<Plan>& parts) {
+    Plan out;
+    if (parts.empty()) return out;
+    out.mode = parts[0].mode;
+    out.nprob = (int32_t)parts.size();
+    out.tile_cfg = parts[0].tile_cfg;
+    out.max_depth = 0;
+    int64_t node_base = 0;
+    for (size_t q = 0; q < parts.size(); ++q) {
+        Plan& p = parts[q];
+        const int32_t prob = (int32_t)q;
+        const int64_t ab = out.arena_elems;
+        const int32_t nb = (int32_t)node_base;
+        auto pn = [&](int32_t x) { return x >= 0 ? x + nb : x; };
+        out.fallback = out.fallback || p.fallback;
+        out.b = std::max(out.b, p.b);
+        out.max_depth = std::max(out.max_depth, p.max_depth);
+        for (auto L : p.leaves) {
+            shift_view(L.X, ab);
+            shift_view(L.Y, ab);
+            if (L.out_kind == OUT_DENSE) L.out_off += ab;
+            L.PX.off += ab; L.PX.end += ab; L.PY.off += ab; L.PY.end += ab;
+            L.QX.off += ab; L.QX.scales += ab; L.QX.end += ab;
+            L.QY.off += ab; L.QY.scales += ab; L.QY.end += ab;
+            L.pred_node = pn(L.pred_node);
+            L.fb_node = pn(L.fb_node);
+            L.prob = prob;
+            out.leaves.push_back(L);
+        }
+        if (out.presum.size() < p.presum.size()) out.presum.resize(p.presum.size());
+        for (size_t l = 0; l < p.presum.size(); ++l)
+            for (auto d : p.presum[l]) {
+                shift_view(d.V, ab);
+                d.out_off += ab;
+                d.pred_node = pn(d.pred_node);
+                d.prob = prob;
+                out.presum[l].push_back(d);
+            }
+        if (out.combine.size() < p.combine.size()) out.combine.resize(p.combine.size());
+        for (size_t l = 0; l < p.combine.size(); ++l)
+            for (auto d : p.combine[l]) {
+                d.m_off += ab;
+                if (d.out_kind == OUT_DENSE) d.out_off += ab;
+                d.pred_node = pn(d.pred_node);
+                d.prob = prob;
+                out.combine[l].push_back(d);
+            }
+        for (auto d : p.pack) {
+            shift_view(d.src, ab);
+            d.dst += ab;
+            d.pred_node = pn(d.pred_node);
+            d.prob = prob;
+            out.pack.push_back(d);
+        }
+        for (auto d : p.pack8) {
+            shift_view(d.src, ab);
+            d.dst += ab;
+            d.scales += ab;
+            d.pred_node = pn(d.pred_node);
+            d.prob = prob;
+            out.pack8.push_back(d);
+        }
+        out.arena_elems += p.arena_elems;
+        node_base += (int64_t)p.nodes.size();
+        out.stats.ata_nodes += p.stats.ata_nodes;
+        out.stats.syrk_leaves += p.stats.syrk_leaves;
+        out.stats.gemm_leaves += p.stats.gemm_leaves;
+        out.stats.strassen_nodes += p.stats.strassen_nodes;
+        out.stats.mults += p.stats.mults;
+        out.stats.max_levels = std::max(out.stats.max_levels, p.stats.max_levels);
+    }
+    // nodes: columns of each problem are offset by the problem's first norm
+    // index, so one flags launch covers the batch
+    int64_t nu_base = 0;
+    for (auto& p : parts) {
+        for (auto nd : p.nodes) {
+            nd.c0 += nu_base;
+            out.nodes.push_back(nd);
+        }
+        nu_base += p.n;
+    }
+    finalize_plan(out);
+    return out;
+}
+
 
 }  // namespace ata

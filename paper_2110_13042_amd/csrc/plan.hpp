@@ -53,6 +53,18 @@ struct Packed {
     int64_t end;        // end of the hi array (bounds every load)
 };
 
+// A leaf operand quantised for the FP8 MFMA: e4m3 bytes in 16-byte chunks of
+// 16 consecutive rows of one column, chunk (g, c) at byte (g * cols_p + c) * 16;
+// rows and columns padded with zeros to multiples of 128.  Block (bi, bj) of
+// 128 x 128 elements has the scale 2^e, e = scales[bi * (cols_p / 128) + bj]
+// (int32).  Offsets in floats of the arena.
+struct Packed8 {
+    int64_t off;        // data array
+    int64_t scales;     // int32 exponents
+    int64_t cols_p;     // padded columns
+    int64_t end;        // end of the data array (bounds every load)
+};
+
 enum LeafKind : int32_t { LEAF_SYRK = 0, LEAF_GEMM = 1 };
 enum OutKind : int32_t { OUT_PACKED = 0, OUT_DENSE = 1 };
 
@@ -73,6 +85,20 @@ struct LeafDesc {
     int32_t fb_node;          // SYRK leaves: FP64 path when flags[fb_node] != 0 (-1: never)
     int32_t depth;            // Strassen level of the leaf (0 = directly in C)
     Packed PX, PY;            // split-BF16 mode: packed operands
+    Packed8 QX, QY;           // FP8 mode: quantised operands
+    int32_t prob;             // problem of a batch (selects its A and C)
+    int32_t pad_;
+};
+
+// Quantise one FP32 operand view to block-scaled e4m3 (one work item per
+// 128 x 128 block).
+struct Pack8Desc {
+    View src;
+    int64_t dst, scales;
+    int64_t rows_p, cols_p;
+    int64_t elem_begin, elems;
+    int32_t pred_node, pred_value;
+    int32_t prob, pad_;
 };
 
 // Split one FP32 operand view into the packed hi/lo layout (one work item per
@@ -84,6 +110,7 @@ struct PackDesc {
     int64_t groups, cols;
     int64_t elem_begin, elems;
     int32_t pred_node, pred_value;
+    int32_t prob, pad_;
 };
 
 // Five Strassen pre-sums of one operand (X side: S1..S5, Y side: T1..T5).
@@ -97,6 +124,7 @@ struct PresumDesc {
     int32_t pred_node, pred_value;
     int32_t packed_out;       // 1: write the five sums split and packed (work item = one
                               // 16-byte chunk; sum i at out_off + i * ceil(m2/8) * n2 * 8)
+    int32_t prob, pad_;
 };
 
 // Strassen combine: seven n2 x k2 products into the four quadrants.
@@ -109,7 +137,17 @@ struct CombineDesc {
     int64_t out_row0, out_col0;   // OUT_PACKED target (C21 block of C)
     int64_t elem_begin, elems;
     int32_t pred_value;
-    int32_t pad_;
+    int32_t prob;
+};
+
+// Column norms of one problem of a batch: pass 1 work item = (row chunk,
+// group of four columns); pass 2 work item = one column.
+struct ColDesc {
+    int64_t m, n, lda, rows;      // rows per chunk
+    int64_t nchunks;
+    int64_t part_off, nu_off;     // doubles in the partial and norm arrays
+    int64_t elem_begin, elems;
+    int32_t prob, pad_;
 };
 
 // AtA node for the spread flags: columns [c0, c0 + w).
@@ -132,6 +170,7 @@ struct PlanStats {
 
 struct Plan {
     int32_t mode = MODE_F32;
+    int32_t nprob = 1;
     int64_t m = 0, n = 0, lda = 0;
     int64_t b = 0;
     int32_t max_depth = 0;
@@ -139,6 +178,7 @@ struct Plan {
     bool fallback = false;
     std::vector<std::vector<PresumDesc>> presum;    // [level-1] top-down
     std::vector<PackDesc> pack;                     // split-BF16 operand packing
+    std::vector<Pack8Desc> pack8;                   // FP8 operand quantisation
     std::vector<LeafDesc> leaves;                   // LPT order (longest first)
     std::vector<LeafDesc> fb_leaves;                // SYRK leaves under the spread check
     std::vector<std::vector<CombineDesc>> combine;  // [height-1] bottom-up
@@ -157,6 +197,15 @@ int32_t default_max_depth(int32_t mode);
 
 // Builds the plan (host only).  Throws std::invalid_argument on bad sizes.
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);
+
+// Orders the leaves (longest contraction first) and fills the tile and
+// work-item prefix sums of every phase.
+void finalize_plan(Plan& p);
+
+// One plan for a batch of independent problems: every problem's phases are
+// merged (arena offsets, node indices and problem indices shifted) so that
+// each phase is one launch for the whole batch.
+Plan merge_plans(std::vector<Plan>& parts);
 
 // Output tile of the leaf kernels (shared with the device code): 128 x 128
 // for FP64/FP32 (and the FP64 fallback), 256 x 128 for split-BF16.  A SYRK
