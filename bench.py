@@ -5,7 +5,11 @@ spread flags, Strassen pre-sums, all leaf products, combines) on a
 synthetic input already resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode f32|f64|bf16x3|fp8]
-                    [--workload NAME] [--no-cpu-baseline]
+                    [--workload NAME] [--no-cpu-baseline] [--autotune]
+
+With --workload batch_512_uneven_f32 one step is one ata_gram_batched call
+over all 512 problems (one captured graph replay); the same problems issued
+as 512 separate ata_gram calls are timed beside it.
 
 The effective rate is m n (n+1) / t (the paper's effective-GFLOPs measure
 with r = 1, in rectangular form).  The roofline object covers the dominant
@@ -30,6 +34,7 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0, "fp8": 5033.2}
 MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "fp8": 3}
+TUNE_TABLE = os.path.join(ROOT, "paper_2110_13042_amd", "tune_table.json")
 DEFAULT_WORKLOAD = {"f64": "square_f64_1024", "f32": "square_f32_8192",
                     "bf16x3": "square_f32_8192", "fp8": "square_f32_8192"}
 LEAF_KERNEL_FILES = ["paper_2110_13042_amd/csrc/leaf.hip", "paper_2110_13042_amd/csrc/kernels_common.hpp"]
@@ -90,15 +95,17 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
     tdt = torch.float64 if mode == "f64" else torch.float32
     A = torch.from_numpy(A_np).to(dev, tdt)
     C = torch.empty(n * (n + 1) // 2, dtype=tdt, device=dev)
-    h = ata.Handle()
-    if args.leaf_cutoff:
-        h.set("leaf_cutoff", args.leaf_cutoff)
-    if args.max_depth >= 0:
-        h.set("max_depth", args.max_depth)
-    if args.leaf_tile:
-        h.set("leaf_tile", args.leaf_tile)
+    h = make_handle(ata, args)
     sp = torch.cuda.current_stream(dev).cuda_stream
     lda = A.stride(0)
+    tuned = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        tuned = h.autotune(A, MODES[mode])
+        print(f"[bench] {mode}: autotune {tuned} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+        if args.tune_save:
+            h.tune_save(args.tune_save)
 
     def step():
         ata.ata_gram(h.h, A.data_ptr(), m, n, lda, MODES[mode], C.data_ptr(), sp)
@@ -133,7 +140,8 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
         "plan": {"leaf_cutoff": rep["leaf_cutoff"], "strassen_levels": rep["strassen_levels"],
                  "multiplications": rep["multiplications"],
                  "mult_ratio_vs_syrk": round(rep["multiplications"] / (m * n * (n + 1) / 2), 4),
-                 "launches_per_step": rep["kernel_launches"], "workspace_bytes": rep["workspace_bytes"]},
+                 "launches_per_step": rep["kernel_launches"], "workspace_bytes": rep["workspace_bytes"],
+                 "leaf_tile": args.leaf_tile if not tuned else tuned["leaf_tile"]},
         "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
             ["norms_flags", "presum_pack", "leaves", "combine", "residual"], rep["phase_ms"])},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
@@ -144,6 +152,147 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
                      "avg_launch_ms": round(leaf_ms, 4)},
     }
     return res, C
+
+
+def make_handle(ata, args):
+    h = ata.Handle()
+    if not args.no_tune_table and os.path.exists(args.tune_table):
+        h.tune_load(args.tune_table)
+    if args.leaf_cutoff:
+        h.set("leaf_cutoff", args.leaf_cutoff)
+    if args.max_depth >= 0:
+        h.set("max_depth", args.max_depth)
+    if args.leaf_tile:
+        h.set("leaf_tile", args.leaf_tile)
+    return h
+
+
+def run_batched(ata, torch, dev, mats, mode: str, args):
+    """Time one mode on the batch: graph replays, then eager profiled calls
+    (leaf-kernel duration), then the same problems as separate calls."""
+    tdt = torch.float32
+    As = [torch.from_numpy(M).to(dev, tdt) for M in mats]
+    Cs = [torch.empty(M.shape[1] * (M.shape[1] + 1) // 2, dtype=tdt, device=dev) for M in mats]
+    ms = [M.shape[0] for M in mats]
+    ns = [M.shape[1] for M in mats]
+    arrs = ata.batch_arrays([A.data_ptr() for A in As], ms, ns, [max(n, 1) for n in ns],
+                            [C.data_ptr() for C in Cs])
+    work = float(sum(m * n * (n + 1) for m, n in zip(ms, ns)))
+    sp = torch.cuda.current_stream(dev).cuda_stream
+    h = make_handle(ata, args)
+    dt = MODES[mode]
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    h.set("batch_graph", 1)
+    ms_graph = timed(lambda: ata.ata_gram_batched(h.h, *arrs[:4], dt, arrs[4], sp), args.steps)
+    rep = h.report()
+    print(f"[bench] {mode}: batch graph {ms_graph:.3f} ms/step", file=sys.stderr, flush=True)
+    h.set("batch_graph", 0)
+    h.set("profile", 1)
+    ms_eager = timed(lambda: ata.ata_gram_batched(h.h, *arrs[:4], dt, arrs[4], sp), args.steps)
+    prof = h.report()
+    h.set("profile", 0)
+    print(f"[bench] {mode}: batch eager {ms_eager:.3f} ms/step", file=sys.stderr, flush=True)
+
+    def separate():
+        for i in range(len(As)):
+            ata.ata_gram(h.h, As[i].data_ptr(), ms[i], ns[i], max(ns[i], 1), dt, Cs[i].data_ptr(), sp)
+
+    ms_sep = timed(separate, max(1, args.steps // 4))
+    print(f"[bench] {mode}: 512 separate calls {ms_sep:.3f} ms/step", file=sys.stderr, flush=True)
+    h.close()
+    calls = max(prof["profiled_calls"], 1)
+    leaf_ms = prof["phase_ms"][2] / calls
+    leaf_flops = 2.0 * prof["multiplications"]
+    achieved = leaf_flops / (leaf_ms * 1e-3) / 1e12 if leaf_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[mode]
+    res = {
+        "value": round(work / (ms_graph * 1e-3) / 1e12, 3), "ms_per_step": round(ms_graph, 4),
+        "dtype": mode,
+        "eager_batched": {"ms_per_step": round(ms_eager, 4),
+                          "value": round(work / (ms_eager * 1e-3) / 1e12, 3)},
+        "separate_calls": {"ms_per_step": round(ms_sep, 4),
+                           "value": round(work / (ms_sep * 1e-3) / 1e12, 3)},
+        "plan": {"problems": len(As), "multiplications": rep["multiplications"],
+                 "leaves": rep["syrk_leaves"] + rep["gemm_leaves"],
+                 "strassen_nodes": rep["strassen_nodes"], "launches_per_step": rep["kernel_launches"],
+                 "workspace_bytes": rep["workspace_bytes"]},
+        "phase_ms_per_step_eager": {k: round(v / calls, 4) for k, v in zip(
+            ["norms_flags", "presum_pack", "leaves", "combine", "residual"], prof["phase_ms"])},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "leaf_kernel (persistent, every leaf of the 512 merged plans)",
+                     "algorithmic_flops_per_launch": leaf_flops, "avg_launch_ms": round(leaf_ms, 4),
+                     "timed_on": "eager batched calls (same merged plan, events on the caller's stream)"},
+    }
+    return res, Cs
+
+
+def cpu_baseline_batch(mats, budget_flops: float):
+    """The plain FP64 oracle on the leading problems of the batch, up to the budget."""
+    from oracle import plain
+    threads = plain.threads_used(0)
+    k, work = 0, 0.0
+    while k < len(mats) and work < budget_flops:
+        m, n = mats[k].shape
+        work += m * n * (n + 1)
+        k += 1
+    t0 = time.perf_counter()
+    refs = [plain.gram_packed(mats[i]) for i in range(k)]
+    dt = time.perf_counter() - t0
+    return {"value": work / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {k} of {len(mats)} problems, full packed C each (plain FP64 oracle), "
+                      f"{dt:.2f} s"}, refs
+
+
+def main_batch(args, torch, ata, workloads, dev, modes) -> int:
+    wl = args.workload
+    w = workloads.WORKLOADS[wl]
+    print(f"[bench] generating {wl} ({w.description})", file=sys.stderr, flush=True)
+    mats = workloads.batch(seed=w.seed)
+    results, outs = {}, {}
+    for md in modes:
+        if md == "f64":
+            print("the batched workload is FP32", file=sys.stderr)
+            return 2
+        results[md], outs[md] = run_batched(ata, torch, dev, mats, md, args)
+    base = None
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline on the leading problems", file=sys.stderr, flush=True)
+        base, refs = cpu_baseline_batch(mats, 3e11)
+        for md in modes:
+            errs = []
+            for i, ref in enumerate(refs):
+                got = outs[md][i].double().cpu().numpy()
+                errs.append(float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)))
+            results[md]["rel_error_max_over_sample"] = max(errs)
+    head = results[modes[0]]
+    out = {
+        "metric": "effective TFLOP/s sum_i m_i*n_i*(n_i+1)/t of C_i = A_i^T A_i over a batch (AtA, "
+                  "packed lower, one batched call)",
+        "value": head["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": modes[0], "data": "synthetic",
+        "config": {"workload": wl, "description": w.description, "plan": head["plan"],
+                   "eager_batched": head["eager_batched"], "separate_calls": head["separate_calls"],
+                   "phase_ms_per_step_eager": head["phase_ms_per_step_eager"],
+                   "rel_error_max_over_sample": head.get("rel_error_max_over_sample")},
+        "roofline": head["roofline"],
+        "side_by_side": {md: results[md] for md in modes[1:]},
+    }
+    if base is not None:
+        out["cpu_baseline"] = base
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def sampled_error(C, n: int, S, cols) -> float:
@@ -168,6 +317,11 @@ def main() -> int:
     ap.add_argument("--leaf-tile", type=int, default=0, help="split-BF16 leaf tile: 0 = 128x128, 1 = 256x128, 2 = 256x256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=512)
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune leaf cutoff / depth / tile for the workload before the warmup (untimed)")
+    ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table loaded into the handle")
+    ap.add_argument("--no-tune-table", action="store_true")
+    ap.add_argument("--tune-save", default="", help="with --autotune: merge the choices into this table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
@@ -190,6 +344,11 @@ def main() -> int:
             print(f"unknown mode {md}", file=sys.stderr)
             return 2
     wl = args.workload
+    if wl not in workloads.WORKLOADS:
+        print(f"unknown workload {wl}", file=sys.stderr)
+        return 2
+    if workloads.WORKLOADS[wl].kind == "batch":
+        return main_batch(args, torch, ata, workloads, dev, modes)
     w = workloads.WORKLOADS[wl]
     print(f"[bench] generating {wl} ({w.description})", file=sys.stderr, flush=True)
     A_np = workloads.make(wl)

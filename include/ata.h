@@ -166,6 +166,33 @@ ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n,
                           int64_t lda, ata_dtype_t dtype, const void* C_packed,
                           uint64_t seed, double* result, void* stream);
 
+/* One autotuned plan choice. */
+typedef struct {
+    int64_t leaf_cutoff;
+    int32_t max_depth;
+    int32_t leaf_tile;
+    double ms;                    /* measured time of one ata_gram call */
+} ata_tune_entry_t;
+
+/* Autotuner: times ata_gram on (A, C_packed) -- device buffers of the given
+   shape, contents are overwritten -- for every candidate leaf cutoff
+   (powers of two from 128 up to the first at or above n), Strassen depth cap
+   (0 up to the dtype's default) and, for ATA_F32_BF16X3, leaf tile, keeps
+   the fastest in the handle's table under (dtype, shape bucket) and returns
+   it in *best (may be NULL).  Buckets are half-octaves of m and of n.
+   ata_gram and ata_gram_batched use the table whenever the leaf cutoff and
+   depth options are left at their defaults (0 and -1).  Synchronises
+   `stream`. */
+ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n,
+                          int64_t lda, ata_dtype_t dtype, void* C_packed,
+                          void* stream, ata_tune_entry_t* best);
+
+/* Save / load the handle's tune table as JSON (one object per entry with the
+   device architecture, dtype, buckets and choice).  Loading merges entries of
+   the current architecture and skips others. */
+ata_status_t ata_tune_save(ata_handle_t h, const char* path);
+ata_status_t ata_tune_load(ata_handle_t h, const char* path);
+
 /* Set an option (see ata_option_t); takes effect at the next call. */
 ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value);
 

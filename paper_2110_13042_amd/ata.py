@@ -53,6 +53,11 @@ class Report(ctypes.Structure):
         return d
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("leaf_cutoff", ctypes.c_int64), ("max_depth", ctypes.c_int32),
+                ("leaf_tile", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
 class Leaf(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
@@ -84,10 +89,14 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(Leaf), i64, ctypes.POINTER(i64)]
     L.ata_residual.argtypes = [vp, vp, i64, i64, i64, st, vp, ctypes.c_uint64,
                                ctypes.POINTER(ctypes.c_double), vp]
+    L.ata_autotune.argtypes = [vp, vp, i64, i64, i64, st, vp, vp, ctypes.POINTER(TuneEntry)]
+    L.ata_tune_save.argtypes = [vp, ctypes.c_char_p]
+    L.ata_tune_load.argtypes = [vp, ctypes.c_char_p]
     L.ata_status_string.argtypes = [st]
     L.ata_status_string.restype = ctypes.c_char_p
     for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_batched", "ata_set_option",
-                 "ata_get_report", "ata_plan_query", "ata_residual"):
+                 "ata_get_report", "ata_plan_query", "ata_residual", "ata_autotune",
+                 "ata_tune_save", "ata_tune_load"):
         getattr(L, name).restype = st
     _LIB = L
     return L
@@ -119,12 +128,20 @@ def ata_gram(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, strea
     _check(lib().ata_gram(h, A, m, n, lda, dtype, C, stream), "ata_gram")
 
 
-def ata_gram_batched(h: int, A_ptrs, ms, ns, ldas, dtype: int, C_ptrs, stream: int = 0) -> None:
+def batch_arrays(A_ptrs, ms, ns, ldas, C_ptrs):
+    """ctypes arrays for ata_gram_batched, built once and reusable across calls."""
     b = len(A_ptrs)
     arr_p = ctypes.c_void_p * b
     arr_i = ctypes.c_int64 * b
-    _check(lib().ata_gram_batched(h, b, arr_p(*A_ptrs), arr_i(*ms), arr_i(*ns), arr_i(*ldas), dtype,
-                                  arr_p(*C_ptrs), stream), "ata_gram_batched")
+    return arr_p(*A_ptrs), arr_i(*ms), arr_i(*ns), arr_i(*ldas), arr_p(*C_ptrs)
+
+
+def ata_gram_batched(h: int, A_ptrs, ms, ns, ldas, dtype: int, C_ptrs, stream: int = 0) -> None:
+    arrs = (A_ptrs, ms, ns, ldas, C_ptrs)
+    if not isinstance(A_ptrs, ctypes.Array):
+        arrs = batch_arrays(A_ptrs, ms, ns, ldas, C_ptrs)
+    _check(lib().ata_gram_batched(h, len(arrs[0]), arrs[0], arrs[1], arrs[2], arrs[3], dtype, arrs[4],
+                                  stream), "ata_gram_batched")
 
 
 def ata_set_option(h: int, key: int, value: float) -> None:
@@ -158,6 +175,20 @@ def ata_residual(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, s
     return r.value
 
 
+def ata_autotune(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, stream: int = 0) -> dict:
+    e = TuneEntry()
+    _check(lib().ata_autotune(h, A, m, n, lda, dtype, C, stream, ctypes.byref(e)), "ata_autotune")
+    return {k: getattr(e, k) for k, _ in TuneEntry._fields_}
+
+
+def ata_tune_save(h: int, path: str) -> None:
+    _check(lib().ata_tune_save(h, path.encode()), "ata_tune_save")
+
+
+def ata_tune_load(h: int, path: str) -> None:
+    _check(lib().ata_tune_load(h, path.encode()), "ata_tune_load")
+
+
 def status_string(s: int) -> str:
     return lib().ata_status_string(s).decode()
 
@@ -181,6 +212,22 @@ class Handle:
 
     def report(self) -> dict:
         return ata_get_report(self.h)
+
+    def autotune(self, A, dtype=None) -> dict:
+        """Tune the plan for A's shape bucket (A's contents are only read)."""
+        import torch
+        mode = _mode_of(A, dtype)
+        m, n = A.shape
+        lda = max(A.stride(0) if m > 1 else n, n, 1)
+        C = torch.empty(n * (n + 1) // 2, dtype=A.dtype, device=A.device)
+        stream = torch.cuda.current_stream(A.device).cuda_stream
+        return ata_autotune(self.h, A.data_ptr(), m, n, lda, mode, C.data_ptr(), stream)
+
+    def tune_save(self, path: str) -> None:
+        ata_tune_save(self.h, path)
+
+    def tune_load(self, path: str) -> None:
+        ata_tune_load(self.h, path)
 
     def close(self) -> None:
         if self.h:

@@ -5,7 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <map>
 #include <memory>
 #include <new>
@@ -47,6 +52,15 @@ struct DevicePlan {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Autotune table key: dtype and half-octave buckets of m and n.
+struct TuneKey {
+    int32_t mode;
+    int32_t mb, nb;
+    bool operator<(const TuneKey& o) const { return std::tie(mode, mb, nb) < std::tie(o.mode, o.mb, o.nb); }
+};
+
+int32_t bucket(int64_t x) { return x <= 1 ? 0 : (int32_t)std::lround(2.0 * std::log2((double)x)); }
 
 struct BatchKey {
     int32_t mode;
@@ -111,6 +125,9 @@ struct ata_ctx {
     double* last_residual = nullptr;
     int64_t last_nodes = 0;
     ata_report_t report{};
+    // autotuned choices and the device architecture they were measured on
+    std::map<TuneKey, ata_tune_entry_t> tune;
+    std::string arch;
     // batches: merged plans, captured graphs, internal capture stream
     std::map<BatchKey, std::unique_ptr<BatchEntry>> batches;
     hipStream_t batch_stream = nullptr;
@@ -204,6 +221,25 @@ ata_status_t upload_plan(DevicePlan& dp) {
 
 bool valid_dtype(int d) { return d >= ATA_F64 && d <= ATA_F32_FP8E4M3; }
 
+// Leaf cutoff, depth cap and tile of one problem: explicit options win, then
+// the autotune table, then the planner's defaults.
+void choose(const ata_ctx* h, int32_t mode, int64_t m, int64_t n, int64_t& b, int32_t& depth,
+            int32_t& tile) {
+    b = h->popt.leaf_cutoff;
+    depth = h->popt.max_depth;
+    tile = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
+    if (b <= 0 && depth < 0) {
+        auto it = h->tune.find(TuneKey{mode, bucket(m), bucket(n)});
+        if (it != h->tune.end()) {
+            b = it->second.leaf_cutoff;
+            depth = it->second.max_depth;
+            if (mode == MODE_BF16X3) tile = it->second.leaf_tile;
+        }
+    }
+    if (b <= 0) b = default_leaf_cutoff(mode, m, n);
+    if (depth < 0) depth = default_max_depth(mode);
+}
+
 // Bytes of auxiliary device memory one call needs (flags, norms, residual).
 struct AuxLayout {
     size_t flags_off = 0, part_off = 0, nu_off = 0, res_work_off = 0, res_off = 0, total = 0;
@@ -269,6 +305,8 @@ ata_status_t ata_create(ata_handle_t* out) {
     ata_ctx* h = new (std::nothrow) ata_ctx;
     if (!h) return ATA_ERR_OUT_OF_MEMORY;
     h->device = dev;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) h->arch = prop.gcnArchName;
     *out = h;
     return ATA_OK;
 }
@@ -360,6 +398,25 @@ ata_status_t ata_plan_query(int64_t m, int64_t n, ata_dtype_t dtype, int64_t lea
     return ATA_OK;
 }
 
+namespace {
+
+// Six profiling events for one call (null when profiling is off).
+ata_status_t take_events(ata_ctx* h, hipEvent_t*& ev) {
+    ev = nullptr;
+    if (!h->profile) return ATA_OK;
+    if (h->events_used + EVENTS_PER_CALL > 4096 && drain_events(h) != hipSuccess) return ATA_ERR_HIP;
+    while (h->events.size() < h->events_used + EVENTS_PER_CALL) {
+        hipEvent_t x;
+        if (hipEventCreate(&x) != hipSuccess) return ATA_ERR_HIP;
+        h->events.push_back(x);
+    }
+    ev = h->events.data() + h->events_used;
+    h->events_used += EVENTS_PER_CALL;
+    return ATA_OK;
+}
+
+}  // namespace
+
 ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
                       ata_dtype_t dtype, void* C_packed, void* stream) {
     if (!h || !valid_dtype(dtype) || m < 0 || n < 0 || lda < std::max<int64_t>(1, n))
@@ -384,10 +441,10 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     }
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
     const int32_t mode = (int32_t)dtype;
-    const int64_t b = h->popt.leaf_cutoff > 0 ? h->popt.leaf_cutoff : default_leaf_cutoff(mode, m, n);
-    const int32_t depth = h->popt.max_depth >= 0 ? h->popt.max_depth : default_max_depth(mode);
+    int64_t b;
+    int32_t depth, tile_cfg;
+    choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
-    const int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
     const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
@@ -429,19 +486,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     double* res = reinterpret_cast<double*>(aux + ax.res_off);
     hipError_t e = hipSuccess;
     hipEvent_t* ev = nullptr;
-    if (h->profile) {
-        if (h->events_used + EVENTS_PER_CALL > 4096) {
-            e = drain_events(h);
-            if (e != hipSuccess) return ATA_ERR_HIP;
-        }
-        while (h->events.size() < h->events_used + EVENTS_PER_CALL) {
-            hipEvent_t x;
-            if (hipEventCreate(&x) != hipSuccess) return ATA_ERR_HIP;
-            h->events.push_back(x);
-        }
-        ev = h->events.data() + h->events_used;
-        h->events_used += EVENTS_PER_CALL;
-    }
+    if (take_events(h, ev) != ATA_OK) return ATA_ERR_HIP;
     auto mark = [&](int i) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
     };
@@ -519,12 +564,17 @@ ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n, i
 namespace {
 
 // Enqueue every phase of a merged batch plan on `st` (also used for capture).
-hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st) {
+// `ev`: six phase events of an eager profiled call, or null.
+hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t* ev = nullptr) {
     const Plan& p = be.dp->plan;
     DevicePlan& dp = *be.dp;
     const int32_t mode = p.mode;
-    hipError_t e = hipMemcpyAsync(be.d_A, be.pinned, sizeof(void*) * 2 * (size_t)be.nprob,
-                                  hipMemcpyHostToDevice, st);
+    hipError_t e = hipSuccess;
+    auto mark = [&](int i) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    e = hipMemcpyAsync(be.d_A, be.pinned, sizeof(void*) * 2 * (size_t)be.nprob, hipMemcpyHostToDevice, st);
     const int64_t slots = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
     BatchPtrs bp{be.d_A, be.d_C, be.d_counter, slots};
     BatchPtrs bq{be.d_A, be.d_C, nullptr, 0};
@@ -538,6 +588,7 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st) {
             e = launch_flags(be.d_nu, dp.d_nodes, (int)p.nodes.size(),
                              h->popt.spread_tau * h->popt.spread_tau, be.d_flags, st);
     }
+    mark(1);
     for (size_t l = 0; e == hipSuccess && l < p.presum.size(); ++l) {
         const auto& lv = p.presum[l];
         if (!lv.empty())
@@ -550,18 +601,22 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st) {
     if (e == hipSuccess && !p.pack8.empty())
         e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems,
                           nullptr, h->arena, be.d_flags, st, &bq);
+    mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, nullptr,
                           nullptr, h->arena, be.d_flags, h->chunk, st, &bp);
     if (e == hipSuccess && !p.fb_leaves.empty())
         e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, nullptr, nullptr,
                                    h->arena, be.d_flags, h->chunk, st, &bq);
+    mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
         if (!lv.empty())
             e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
                                nullptr, h->arena, be.d_flags, st, &bq);
     }
+    mark(4);
+    mark(5);
     return e;
 }
 
@@ -591,15 +646,21 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     }
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
     const int32_t mode = (int32_t)dtype;
-    const int32_t depth = h->popt.max_depth >= 0 ? h->popt.max_depth : default_max_depth(mode);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0;
+    // the batch runs one leaf kernel, so one tile shape: the handle's
     const int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
-    BatchKey key{mode, h->popt.leaf_cutoff, depth, fb, tile_cfg, {}};
-    key.shapes.reserve(3 * (size_t)batch);
+    std::vector<int64_t> bs((size_t)batch);
+    std::vector<int32_t> ds((size_t)batch);
+    BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, {}};
+    key.shapes.reserve(5 * (size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
+        int32_t tile_i;
+        choose(h, mode, m[i], n[i], bs[(size_t)i], ds[(size_t)i], tile_i);
         key.shapes.push_back(m[i]);
         key.shapes.push_back(n[i]);
         key.shapes.push_back(lda[i]);
+        key.shapes.push_back(bs[(size_t)i]);
+        key.shapes.push_back(ds[(size_t)i]);
     }
     auto it = h->batches.find(key);
     if (it == h->batches.end()) {
@@ -610,8 +671,8 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
         try {
             for (int64_t i = 0; i < batch; ++i) {
                 PlanOptions o;
-                o.leaf_cutoff = h->popt.leaf_cutoff > 0 ? h->popt.leaf_cutoff : default_leaf_cutoff(mode, m[i], n[i]);
-                o.max_depth = depth;
+                o.leaf_cutoff = bs[(size_t)i];
+                o.max_depth = ds[(size_t)i];
                 o.spread_tau = fb ? h->popt.spread_tau : 0.0;
                 o.tile_cfg = tile_cfg;
                 parts.push_back(make_plan(mode, m[i], n[i], lda[i], o));
@@ -716,7 +777,9 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
     if (!h->batch_graph) {
-        e = enqueue_batch(h, be, st);
+        hipEvent_t* ev = nullptr;
+        if (take_events(h, ev) != ATA_OK) return ATA_ERR_HIP;
+        e = enqueue_batch(h, be, st, ev);
         if (e == hipSuccess) e = hipEventRecord(be.done, st);
     } else {
         if (!h->batch_stream) {
@@ -756,6 +819,123 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     h->report.lda = 0;
     h->pending_flags = false;
     h->pending_residual = false;
+    return ATA_OK;
+}
+
+ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
+                          ata_dtype_t dtype, void* C_packed, void* stream, ata_tune_entry_t* best) {
+    if (!h || !valid_dtype(dtype) || m <= 0 || n <= 0 || lda < n || !A || !C_packed)
+        return ATA_ERR_INVALID_VALUE;
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    const int32_t mode = (int32_t)dtype;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const PlanOptions saved = h->popt;
+    const bool saved_profile = h->profile;
+    h->profile = false;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return ATA_ERR_HIP;
+    ata_tune_entry_t top{0, 0, 0, 1e30};
+    std::vector<int64_t> cutoffs;
+    for (int64_t b = 128; ; b *= 2) {
+        cutoffs.push_back(b);
+        if (b >= n) break;
+    }
+    const int32_t dmax = std::min<int32_t>(default_max_depth(mode), 3);
+    const int ntiles = mode == MODE_BF16X3 ? 3 : 1;
+    ata_status_t rs = ATA_OK;
+    for (int64_t b : cutoffs) {
+        for (int32_t d = 0; d <= dmax; ++d) {
+            if (b >= n && d > 0) break;            // a single leaf: depth does not matter
+            for (int tl = 0; tl < ntiles; ++tl) {
+                h->popt.leaf_cutoff = b;
+                h->popt.max_depth = d;
+                h->popt.tile_cfg = tl;
+                // skip depth caps the recursion cannot reach
+                Plan probe;
+                try {
+                    PlanOptions o;
+                    o.leaf_cutoff = b;
+                    o.max_depth = d;
+                    o.spread_tau = 0.0;
+                    probe = make_plan(mode, m, n, lda, o);
+                } catch (const std::exception&) {
+                    continue;
+                }
+                if (d > 0 && probe.stats.max_levels < d) continue;
+                rs = ata_gram(h, A, m, n, lda, dtype, C_packed, stream);   // warm-up (plans, arena)
+                if (rs != ATA_OK) break;
+                const int reps = 3;
+                if (hipEventRecord(e0, st) != hipSuccess) { rs = ATA_ERR_HIP; break; }
+                for (int r = 0; r < reps && rs == ATA_OK; ++r) rs = ata_gram(h, A, m, n, lda, dtype, C_packed, stream);
+                if (rs != ATA_OK) break;
+                float ms = 0.f;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rs = ATA_ERR_HIP; break; }
+                const double per = ms / reps;
+                if (per < top.ms) top = ata_tune_entry_t{b, d, tl, per};
+            }
+            if (rs != ATA_OK) break;
+        }
+        if (rs != ATA_OK) break;
+    }
+    h->popt = saved;
+    h->profile = saved_profile;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs != ATA_OK) return rs;
+    h->tune[TuneKey{mode, bucket(m), bucket(n)}] = top;
+    if (best) *best = top;
+    return ATA_OK;
+}
+
+ata_status_t ata_tune_save(ata_handle_t h, const char* path) {
+    if (!h || !path) return ATA_ERR_INVALID_VALUE;
+    std::ofstream f(path);
+    if (!f) return ATA_ERR_INVALID_VALUE;
+    f << "[\n";
+    size_t i = 0;
+    for (const auto& kv : h->tune) {
+        f << "  {\"arch\": \"" << h->arch << "\", \"dtype\": " << kv.first.mode << ", \"m_bucket\": "
+          << kv.first.mb << ", \"n_bucket\": " << kv.first.nb << ", \"leaf_cutoff\": " << kv.second.leaf_cutoff
+          << ", \"max_depth\": " << kv.second.max_depth << ", \"leaf_tile\": " << kv.second.leaf_tile
+          << ", \"ms\": " << kv.second.ms << "}" << (++i < h->tune.size() ? "," : "") << "\n";
+    }
+    f << "]\n";
+    return f ? ATA_OK : ATA_ERR_INTERNAL;
+}
+
+ata_status_t ata_tune_load(ata_handle_t h, const char* path) {
+    if (!h || !path) return ATA_ERR_INVALID_VALUE;
+    std::ifstream f(path);
+    if (!f) return ATA_ERR_INVALID_VALUE;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string text = ss.str();
+    auto num = [&](const std::string& obj, const char* key, double& out) {
+        const std::string k = std::string("\"") + key + "\":";
+        const size_t p = obj.find(k);
+        if (p == std::string::npos) return false;
+        out = std::strtod(obj.c_str() + p + k.size(), nullptr);
+        return true;
+    };
+    size_t pos = 0;
+    while ((pos = text.find('{', pos)) != std::string::npos) {
+        const size_t end = text.find('}', pos);
+        if (end == std::string::npos) break;
+        const std::string obj = text.substr(pos, end - pos + 1);
+        pos = end + 1;
+        const size_t a = obj.find("\"arch\": \"");
+        if (a == std::string::npos) continue;
+        const size_t a0 = a + 9, a1 = obj.find('"', a0);
+        if (obj.substr(a0, a1 - a0) != h->arch) continue;
+        double dt, mb, nb, b, d, tl, ms;
+        if (!num(obj, "dtype", dt) || !num(obj, "m_bucket", mb) || !num(obj, "n_bucket", nb) ||
+            !num(obj, "leaf_cutoff", b) || !num(obj, "max_depth", d) || !num(obj, "leaf_tile", tl) ||
+            !num(obj, "ms", ms))
+            continue;
+        h->tune[TuneKey{(int32_t)dt, (int32_t)mb, (int32_t)nb}] =
+            ata_tune_entry_t{(int64_t)b, (int32_t)d, (int32_t)tl, ms};
+    }
     return ATA_OK;
 }
 
