@@ -180,6 +180,7 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
     work = float(sum(m * n * (n + 1) for m, n in zip(ms, ns)))
     sp = torch.cuda.current_stream(dev).cuda_stream
     h = make_handle(ata, args)
+    h.set("batch_persistent", args.batch_persistent)
     dt = MODES[mode]
 
     def timed(fn, steps):
@@ -223,6 +224,7 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
         "separate_calls": {"ms_per_step": round(ms_sep, 4),
                            "value": round(work / (ms_sep * 1e-3) / 1e12, 3)},
         "plan": {"problems": len(As), "multiplications": rep["multiplications"],
+                 "leaf_launch": "persistent" if args.batch_persistent else "one workgroup per tile",
                  "leaves": rep["syrk_leaves"] + rep["gemm_leaves"],
                  "strassen_nodes": rep["strassen_nodes"], "launches_per_step": rep["kernel_launches"],
                  "workspace_bytes": rep["workspace_bytes"]},
@@ -322,6 +324,8 @@ def main() -> int:
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table loaded into the handle")
     ap.add_argument("--no-tune-table", action="store_true")
     ap.add_argument("--tune-save", default="", help="with --autotune: merge the choices into this table")
+    ap.add_argument("--batch-persistent", type=int, default=0,
+                    help="batched leaf launch: 1 = persistent grid with per-XCD queues, 0 = one workgroup per tile")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

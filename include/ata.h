@@ -89,7 +89,13 @@ typedef enum {
     /* ata_gram_batched: 1 = capture the batch's launch sequence once per
        shape signature in a hipGraph and replay it (default); 0 = enqueue the
        launches directly on the caller's stream. */
-    ATA_OPT_BATCH_GRAPH = 8
+    ATA_OPT_BATCH_GRAPH = 8,
+    /* Batched leaf products: 0 = one workgroup per tile in longest-first,
+       XCD-grouped order, scheduled by the hardware dispatcher (default: the
+       faster of the two on MI355X, since the persistent loop raises the
+       kernels' register use); 1 = a persistent grid (resident workgroups
+       only) pulling tiles from per-XCD queues.  Results are identical. */
+    ATA_OPT_BATCH_PERSISTENT = 9
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

@@ -48,6 +48,8 @@ struct DevicePlan {
     Pack8Desc* d_pack8 = nullptr;
     std::vector<CombineDesc*> d_combine;
     NodeDesc* d_nodes = nullptr;
+    ColDesc* d_col1 = nullptr;
+    ColDesc* d_col2 = nullptr;
     ~DevicePlan() { if (d_buf) (void)hipFree(d_buf); }
 };
 
@@ -86,6 +88,7 @@ struct BatchEntry {
     const void** d_A = nullptr;
     void** d_C = nullptr;
     unsigned long long* d_counter = nullptr;
+    bool graph_persistent = false;     // leaf launch form the graph was captured with
     uint8_t* d_flags = nullptr;
     double* d_partial = nullptr;
     double* d_nu = nullptr;
@@ -133,6 +136,7 @@ struct ata_ctx {
     hipStream_t batch_stream = nullptr;
     hipEvent_t batch_in = nullptr;
     bool batch_graph = true;
+    bool batch_persistent = false;
     uint64_t arena_gen = 0;
     // phase profiling: six events per profiled call, summed at report time
     bool profile = false;
@@ -196,6 +200,8 @@ ata_status_t upload_plan(DevicePlan& dp) {
     bytes += align256(p.pack.size() * sizeof(PackDesc));
     bytes += align256(p.fb_leaves.size() * sizeof(LeafDesc));
     bytes += align256(p.pack8.size() * sizeof(Pack8Desc));
+    bytes += align256(p.col1.size() * sizeof(ColDesc));
+    bytes += align256(p.col2.size() * sizeof(ColDesc));
     if (bytes == 0) return ATA_OK;
     std::vector<unsigned char> host(bytes, 0);
     if (hipMalloc(&dp.d_buf, bytes) != hipSuccess) {
@@ -216,6 +222,8 @@ ata_status_t upload_plan(DevicePlan& dp) {
     dp.d_pack = static_cast<PackDesc*>(put(p.pack.data(), p.pack.size() * sizeof(PackDesc)));
     dp.d_fb_leaves = static_cast<LeafDesc*>(put(p.fb_leaves.data(), p.fb_leaves.size() * sizeof(LeafDesc)));
     dp.d_pack8 = static_cast<Pack8Desc*>(put(p.pack8.data(), p.pack8.size() * sizeof(Pack8Desc)));
+    dp.d_col1 = static_cast<ColDesc*>(put(p.col1.data(), p.col1.size() * sizeof(ColDesc)));
+    dp.d_col2 = static_cast<ColDesc*>(put(p.col2.data(), p.col2.size() * sizeof(ColDesc)));
     return hip_status(hipMemcpy(dp.d_buf, host.data(), bytes, hipMemcpyHostToDevice));
 }
 
@@ -251,7 +259,7 @@ AuxLayout aux_layout(const Plan& p, bool residual) {
     a.flags_off = off;
     off += align256(std::max<size_t>(p.nodes.size(), 1));
     a.part_off = off;
-    off += align256(sizeof(double) * (size_t)(p.fallback ? colnorm_chunks(p.m, p.n) * p.n : 0));
+    off += align256(sizeof(double) * (size_t)(p.fallback ? p.col_partial : 0));
     a.nu_off = off;
     off += align256(sizeof(double) * (size_t)(p.fallback ? p.n : 0));
     a.res_work_off = off;
@@ -356,6 +364,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             return ATA_OK;
         case ATA_OPT_BATCH_GRAPH:
             h->batch_graph = value != 0.0;
+            return ATA_OK;
+        case ATA_OPT_BATCH_PERSISTENT:
+            h->batch_persistent = value != 0.0;
             return ATA_OK;
         case ATA_OPT_PROFILE:
             if (h->events_used) (void)drain_events(h);
@@ -492,7 +503,9 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     };
     mark(0);
     if (p.fallback) {
-        e = launch_colnorms(static_cast<const float*>(A), m, n, lda, partial, colnorm_chunks(m, n), nu, st);
+        e = launch_colnorms(dp.d_col1, (int)p.col1.size(), p.col1.back().elem_begin + p.col1.back().elems,
+                            dp.d_col2, (int)p.col2.size(), p.col2.back().elem_begin + p.col2.back().elems,
+                            static_cast<const float*>(A), nullptr, partial, nu, st);
         if (e == hipSuccess)
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
@@ -576,14 +589,14 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
     mark(0);
     e = hipMemcpyAsync(be.d_A, be.pinned, sizeof(void*) * 2 * (size_t)be.nprob, hipMemcpyHostToDevice, st);
     const int64_t slots = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
-    BatchPtrs bp{be.d_A, be.d_C, be.d_counter, slots};
+    BatchPtrs bp{be.d_A, be.d_C, h->batch_persistent ? be.d_counter : nullptr, slots};
     BatchPtrs bq{be.d_A, be.d_C, nullptr, 0};
     if (e == hipSuccess && p.fallback) {
         const ColDesc& l1 = be.col1.back();
         const ColDesc& l2 = be.col2.back();
-        e = launch_colnorms_batched(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
-                                    (int)be.col2.size(), l2.elem_begin + l2.elems, be.d_A, be.d_partial,
-                                    be.d_nu, st);
+        e = launch_colnorms(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
+                            (int)be.col2.size(), l2.elem_begin + l2.elems, nullptr, be.d_A, be.d_partial,
+                            be.d_nu, st);
         if (e == hipSuccess)
             e = launch_flags(be.d_nu, dp.d_nodes, (int)p.nodes.size(),
                              h->popt.spread_tau * h->popt.spread_tau, be.d_flags, st);
@@ -690,36 +703,8 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
         // column-norm tasks (every problem, so the merged norm array is complete)
         int64_t part_off = 0, nu_off = 0;
         if (mp.fallback) {
-            int64_t e1 = 0, e2 = 0;
-            for (int64_t i = 0; i < batch; ++i) {
-                ColDesc d{};
-                d.m = m[i];
-                d.n = n[i];
-                d.lda = lda[i];
-                d.rows = colnorm_rows(m[i], n[i]);
-                d.nchunks = colnorm_chunks(m[i], n[i]);
-                d.part_off = part_off;
-                d.nu_off = nu_off;
-                d.prob = (int32_t)i;
-                part_off += d.nchunks * n[i];
-                nu_off += n[i];
-                if (n[i] == 0) continue;
-                ColDesc d1 = d, d2 = d;
-                d1.elems = d.nchunks * ((n[i] + 3) / 4);
-                d1.elem_begin = e1;
-                e1 += d1.elems;
-                d2.elems = n[i];
-                d2.elem_begin = e2;
-                e2 += d2.elems;
-                be->col1.push_back(d1);
-                be->col2.push_back(d2);
-            }
-            if (be->col1.empty()) {
-                // no columns anywhere: nothing for the norm passes
-                ColDesc z{};
-                be->col1.push_back(z);
-                be->col2.push_back(z);
-            }
+            build_colnorm_tasks(m, n, lda, batch, be->col1, be->col2, &part_off);
+            for (int64_t i = 0; i < batch; ++i) nu_off += n[i];
         }
         // auxiliary device buffer owned by the batch entry
         const size_t ptr_b = align256(sizeof(void*) * 2 * (size_t)batch);
@@ -786,7 +771,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
             if (hipStreamCreateWithFlags(&h->batch_stream, hipStreamNonBlocking) != hipSuccess) return ATA_ERR_HIP;
             if (hipEventCreateWithFlags(&h->batch_in, hipEventDisableTiming) != hipSuccess) return ATA_ERR_HIP;
         }
-        if (!be.exec || be.arena_gen != h->arena_gen) {
+        if (!be.exec || be.arena_gen != h->arena_gen || be.graph_persistent != h->batch_persistent) {
             if (be.exec) {
                 if (be.launched && hipEventSynchronize(be.done) != hipSuccess) return ATA_ERR_HIP;
                 (void)hipGraphExecDestroy(be.exec);
@@ -804,6 +789,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
             if (e == hipSuccess) e = hipGraphInstantiate(&be.exec, be.graph, nullptr, nullptr, 0);
             if (e != hipSuccess) return ATA_ERR_HIP;
             be.arena_gen = h->arena_gen;
+            be.graph_persistent = h->batch_persistent;
         }
         e = hipEventRecord(h->batch_in, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(h->batch_stream, h->batch_in, 0);

@@ -10,6 +10,7 @@ namespace ata {
 namespace {
 
 constexpr int EW_THREADS = 256;
+static_assert(EW_THREADS == ITEM_BLOCK, "one workgroup per aligned item block");
 
 // --------------------------------------------------------------- pre-sums
 // Work item = one row r and four consecutive columns c..c+3 of the m2 x n2
@@ -41,7 +42,7 @@ __device__ __forceinline__ void split8(const float* v, uint4& hi, uint4& lo) {
 // eight rows of the four quadrant values, the five sums formed in FP32, then
 // split.
 __device__ void presum_packed(const PresumDesc& d, int64_t e, const float* A, float* arena) {
-    const int64_t g = e / d.n2, c = e - g * d.n2;
+    const int64_t g = udiv(e, d.n2), c = e - g * d.n2;
     const float* V = (d.V.base == BASE_A ? A : arena) + d.V.off;
     const int64_t ld = d.V.ld, pr = d.V.prows, pc = d.V.pcols;
     const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
@@ -104,10 +105,11 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
                                                             const uint8_t* flags, const void* const* Aptrs) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const PresumDesc& d = tasks[find_task(tasks, ntasks, x)];
+    const PresumDesc& d = tasks[block_task(tasks, ntasks)];
+    const int64_t e = x - d.elem_begin;
+    if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
     const T* A = Aptrs ? static_cast<const T*>(Aptrs[d.prob]) : A0;
-    const int64_t e = x - d.elem_begin;
     if constexpr (sizeof(T) == 4) {
         if (d.packed_out) {
             presum_packed(d, e, A, arena);
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
         }
     }
     const int64_t groups = (d.n2 + 3) >> 2;
-    const int64_t r = e / groups, c0 = (e - r * groups) << 2;
+    const int64_t r = udiv(e, groups), c0 = (e - r * groups) << 2;
     const T* V = (d.V.base == BASE_A ? A : arena) + d.V.off;
     const int64_t ld = d.V.ld, pr = d.V.prows, pc = d.V.pcols;
     const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
@@ -180,11 +182,12 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
                                                           const void* const* Aptrs) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const PackDesc& d = tasks[find_task(tasks, ntasks, x)];
+    const PackDesc& d = tasks[block_task(tasks, ntasks)];
+    const int64_t e = x - d.elem_begin;
+    if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
     const float* A = Aptrs ? static_cast<const float*>(Aptrs[d.prob]) : A0;
-    const int64_t e = x - d.elem_begin;
-    const int64_t g = e / d.cols, c = e - g * d.cols;
+    const int64_t g = udiv(e, d.cols), c = e - g * d.cols;
     const float* src = (d.src.base == BASE_A ? A : arena) + d.src.off;
     float v[8];
 #pragma unroll
@@ -264,12 +267,13 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
                                                              const uint8_t* flags, void* const* Cptrs) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const CombineDesc& d = tasks[find_task(tasks, ntasks, x)];
+    const CombineDesc& d = tasks[block_task(tasks, ntasks)];
+    const int64_t e = x - d.elem_begin;
+    if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
     T* C = Cptrs ? static_cast<T*>(Cptrs[d.prob]) : C0;
-    const int64_t e = x - d.elem_begin;
     const int64_t groups = (d.k2 + 3) >> 2;
-    const int64_t i = e / groups, j0 = (e - i * groups) << 2;
+    const int64_t i = udiv(e, groups), j0 = (e - i * groups) << 2;
     const int64_t n1 = d.n1, k1 = d.k1, k2 = d.k2, plane = d.n2 * d.k2;
     const T* M = arena + d.m_off + i * k2;
     auto dst = [&](int64_t ii, int64_t jj) -> T* {
@@ -323,85 +327,107 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
 // ------------------------------------------------------------ column norms
 constexpr int64_t NORM_ROWS = 256;   // residual passes
 
-// Rows per chunk of the column-norm pass: enough chunks that (n / 4) x chunks
-// threads fill the GPU (about 2^19), at least 16 rows, at most 4096.
-int64_t norm_rows(int64_t m, int64_t n) {
-    int64_t r = (m * (n > 0 ? n : 1)) >> 21;
-    r = r < 16 ? 16 : (r > 4096 ? 4096 : r);
-    return r;
-}
-
-// partial[chunk][j] = sum of a_rj^2 over the chunk's rows, four columns per
-// thread (16-byte loads when the rows allow it), rows in ascending order.
-template <class T>
-__global__ __launch_bounds__(EW_THREADS) void colnorm_partial(const T* A, int64_t m, int64_t n,
-                                                              int64_t lda, int64_t rows, double* partial) {
-    const int64_t j0 = ((int64_t)blockIdx.x * EW_THREADS + threadIdx.x) * 4;
-    const int64_t chunk = blockIdx.y;
-    if (j0 >= n) return;
-    const int64_t r0 = chunk * rows, r1 = r0 + rows < m ? r0 + rows : m;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    const bool vec = sizeof(T) == 4 && j0 + 4 <= n &&
-                     ((reinterpret_cast<uintptr_t>(A) | (uintptr_t)(lda * sizeof(T))) & 15) == 0;
+// Sum of squares of rows [r0, r1) of four columns starting at p (row stride
+// ld floats), each column summed in ascending row order.  `vec`: 16-byte
+// aligned rows and all four columns present; else `cols` columns, scalar.
+__device__ __forceinline__ void sumsq4(const float* p, int64_t ld, int64_t r0, int64_t r1, bool vec,
+                                       int cols, double s[4]) {
+    int64_t r = r0;
     if (vec) {
-        for (int64_t r = r0; r < r1; ++r) {
-            const float4 a = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(A) + r * lda + j0);
-            s0 += (double)a.x * (double)a.x;
-            s1 += (double)a.y * (double)a.y;
-            s2 += (double)a.z * (double)a.z;
-            s3 += (double)a.w * (double)a.w;
+        constexpr int U = 8;
+        for (; r + U <= r1; r += U) {
+            float4 a[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) a[q] = *reinterpret_cast<const float4*>(p + (r + q) * ld);
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                s[0] += (double)a[q].x * (double)a[q].x;
+                s[1] += (double)a[q].y * (double)a[q].y;
+                s[2] += (double)a[q].z * (double)a[q].z;
+                s[3] += (double)a[q].w * (double)a[q].w;
+            }
         }
-    } else {
-        for (int64_t r = r0; r < r1; ++r) {
-            const T* row = A + r * lda + j0;
-            if (j0 < n) { const double a = (double)row[0]; s0 += a * a; }
-            if (j0 + 1 < n) { const double a = (double)row[1]; s1 += a * a; }
-            if (j0 + 2 < n) { const double a = (double)row[2]; s2 += a * a; }
-            if (j0 + 3 < n) { const double a = (double)row[3]; s3 += a * a; }
+        for (; r < r1; ++r) {
+            const float4 a = *reinterpret_cast<const float4*>(p + r * ld);
+            s[0] += (double)a.x * (double)a.x;
+            s[1] += (double)a.y * (double)a.y;
+            s[2] += (double)a.z * (double)a.z;
+            s[3] += (double)a.w * (double)a.w;
         }
+        return;
     }
-    double* p = partial + chunk * n + j0;
-    p[0] = s0;
-    if (j0 + 1 < n) p[1] = s1;
-    if (j0 + 2 < n) p[2] = s2;
-    if (j0 + 3 < n) p[3] = s3;
-}
-
-// Batched column norms: pass 1 item = (chunk, four columns) of one problem.
-__global__ __launch_bounds__(EW_THREADS) void colnorm_batched(const ColDesc* tasks, int ntasks,
-                                                              int64_t items, const void* const* Aptrs,
-                                                              double* partial) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
-    if (x >= items) return;
-    const ColDesc& d = tasks[find_task(tasks, ntasks, x)];
-    const float* A = static_cast<const float*>(Aptrs[d.prob]);
-    const int64_t e = x - d.elem_begin;
-    const int64_t groups = (d.n + 3) / 4;
-    const int64_t chunk = e / groups, j0 = (e - chunk * groups) * 4;
-    const int64_t r0 = chunk * d.rows, r1 = r0 + d.rows < d.m ? r0 + d.rows : d.m;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t r = r0; r < r1; ++r) {
-        const float* row = A + r * d.lda + j0;
+    for (; r < r1; ++r) {
+        const float* row = p + r * ld;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            if (j0 + q < d.n) { const double a = (double)row[q]; s[q] += a * a; }
+            if (q < cols) { const double a = (double)row[q]; s[q] += a * a; }
     }
-    double* p = partial + d.part_off + chunk * d.n + j0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        if (j0 + q < d.n) p[q] = s[q];
 }
 
-// Batched column norms: pass 2 item = one column of one problem.
-__global__ __launch_bounds__(EW_THREADS) void colsum_batched(const ColDesc* tasks, int ntasks,
-                                                             int64_t items, const double* partial,
-                                                             double* nu) {
+// Column norms, pass 1: a workgroup covers 256 columns (four per lane) of one
+// row chunk; its four waves take consecutive quarters of the chunk's rows and
+// their sums are added in wave order through LDS (deterministic).
+// partial[part_off + chunk * n + j] = sum of a_rj^2 over the chunk's rows.
+__global__ __launch_bounds__(EW_THREADS) void colnorm_pass1(const ColDesc* tasks, int ntasks,
+                                                            int64_t items, const float* A0,
+                                                            const void* const* Aptrs, double* partial) {
+    __shared__ double red[3][64][4];
+    const int64_t x0 = (int64_t)blockIdx.x * EW_THREADS;
+    if (x0 >= items) return;
+    const ColDesc& d = tasks[block_task(tasks, ntasks)];
+    const int64_t blk = (x0 - d.elem_begin) / EW_THREADS;      // workgroup-uniform
+    if (x0 - d.elem_begin >= d.elems) return;
+    const float* A = Aptrs ? static_cast<const float*>(Aptrs[d.prob]) : A0;
+    const int64_t xblocks = (d.n + 255) / 256;
+    const int64_t chunk = blk / xblocks, xb = blk - chunk * xblocks;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t j0 = xb * 256 + lane * 4;
+    const int64_t q = d.rows / 4;
+    const int64_t rb = chunk * d.rows + wave * q;
+    const int64_t r0 = rb < d.m ? rb : d.m, r1 = rb + q < d.m ? rb + q : d.m;
+    const int cols = j0 >= d.n ? 0 : (d.n - j0 < 4 ? (int)(d.n - j0) : 4);
+    const bool vec = cols == 4 && ((reinterpret_cast<uintptr_t>(A) | (uintptr_t)(d.lda * 4)) & 15) == 0;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (cols > 0) sumsq4(A + j0, d.lda, r0, r1, vec, cols, s);
+    if (wave > 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) red[wave - 1][lane][c] = s[c];
+    }
+    __syncthreads();
+    if (wave == 0 && cols > 0) {
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[c] += red[w][lane][c];
+        double* p = partial + d.part_off + chunk * d.n + j0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < cols) p[c] = s[c];
+    }
+}
+
+// Column norms, pass 2: item = one column of one problem; the chunks are
+// summed in order (eight loads in flight).
+__global__ __launch_bounds__(EW_THREADS) void colnorm_pass2(const ColDesc* tasks, int ntasks,
+                                                            int64_t items, const double* partial,
+                                                            double* nu) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const ColDesc& d = tasks[find_task(tasks, ntasks, x)];
+    const ColDesc& d = tasks[block_task(tasks, ntasks)];
     const int64_t j = x - d.elem_begin;
+    if (j >= d.elems) return;
+    const double* p = partial + d.part_off + j;
+    const int64_t n = d.n, nc = d.nchunks;
     double s = 0.0;
-    for (int64_t c = 0; c < d.nchunks; ++c) s += partial[d.part_off + c * d.n + j];
+    int64_t c = 0;
+    for (; c + 8 <= nc; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(c + u) * n];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < nc; ++c) s += p[c * n];
     nu[d.nu_off + j] = s;
 }
 
@@ -610,32 +636,16 @@ hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, 
     return hipGetLastError();
 }
 
-int64_t colnorm_chunks(int64_t m, int64_t n) {
-    const int64_t r = norm_rows(m, n);
-    return m <= 0 ? 1 : (m + r - 1) / r;
-}
-int64_t colnorm_rows(int64_t m, int64_t n) { return norm_rows(m, n); }
 int64_t residual_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / NORM_ROWS; }
 
-hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
-                           int64_t nchunks, double* nu, hipStream_t stream) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(colnorm_partial<float>, dim3(blocks_for((n + 3) / 4), (unsigned)nchunks),
-                       dim3(EW_THREADS), 0, stream, A, m, n, lda, norm_rows(m, n), partial);
-    hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), dim3(EW_THREADS), 0, stream, partial,
-                       nchunks, n, nu);
-    return hipGetLastError();
-}
-
-hipError_t launch_colnorms_batched(const ColDesc* d_pass1, int n1, int64_t items1,
-                                   const ColDesc* d_pass2, int n2, int64_t items2,
-                                   const void* const* Aptrs, double* partial, double* nu,
-                                   hipStream_t stream) {
+hipError_t launch_colnorms(const ColDesc* d_pass1, int n1, int64_t items1, const ColDesc* d_pass2,
+                           int n2, int64_t items2, const float* A, const void* const* Aptrs,
+                           double* partial, double* nu, hipStream_t stream) {
     if (items1 > 0)
-        hipLaunchKernelGGL(colnorm_batched, dim3(blocks_for(items1)), dim3(EW_THREADS), 0, stream,
-                           d_pass1, n1, items1, Aptrs, partial);
+        hipLaunchKernelGGL(colnorm_pass1, dim3(blocks_for(items1)), dim3(EW_THREADS), 0, stream,
+                           d_pass1, n1, items1, A, Aptrs, partial);
     if (items2 > 0)
-        hipLaunchKernelGGL(colsum_batched, dim3(blocks_for(items2)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(colnorm_pass2, dim3(blocks_for(items2)), dim3(EW_THREADS), 0, stream,
                            d_pass2, n2, items2, partial, nu);
     return hipGetLastError();
 }

@@ -41,4 +41,18 @@ __device__ __forceinline__ int find_task(const D* tasks, int ntasks, int64_t x) 
     return lo;
 }
 
+// Task of the calling workgroup in a streaming launch whose tasks begin at
+// multiples of ITEM_BLOCK items: the lookup is the same for every lane, so it
+// runs once per wave on the scalar unit instead of once per thread.
+template <class D>
+__device__ __forceinline__ int block_task(const D* tasks, int ntasks) {
+    return find_task(tasks, ntasks, (int64_t)blockIdx.x * ITEM_BLOCK);
+}
+
+// a / b for 0 <= a, 0 < b; 32-bit division when both operands fit.
+__device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {
+    if (((uint64_t)a | (uint64_t)b) >> 32 == 0) return (int64_t)((uint32_t)a / (uint32_t)b);
+    return a / b;
+}
+
 }  // namespace ata

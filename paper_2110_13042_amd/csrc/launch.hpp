@@ -13,11 +13,11 @@ namespace ata {
 struct BatchPtrs {
     const void* const* A;
     void* const* C;
-    unsigned long long* counter;   // null: one workgroup per tile
+    unsigned long long* counter;   // eight queue heads; null: one workgroup per tile
     int64_t persistent_blocks;
 };
 
-// Resident leaf workgroups per CU for the mode's kernel (occupancy query).
+// Resident workgroups per CU of the mode's persistent leaf kernel (occupancy query).
 int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg);
 
 // All leaf products of a plan (one grouped launch, one workgroup per tile).
@@ -53,19 +53,12 @@ hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, 
                           void* C, void* arena, const uint8_t* flags, hipStream_t stream,
                           const BatchPtrs* bp = nullptr);
 
-// Column norms of every problem of a batch (pass 1 over row chunks, pass 2
-// sums the chunks of each column in order).
-hipError_t launch_colnorms_batched(const ColDesc* d_pass1, int n1, int64_t items1,
-                                   const ColDesc* d_pass2, int n2, int64_t items2,
-                                   const void* const* Aptrs, double* partial, double* nu,
-                                   hipStream_t stream);
-
-// Squared column norms (FP64) of a float matrix, deterministic two-pass sum:
-// partial[chunk][j] over row chunks, then nu[j] = sum over chunks in order.
-hipError_t launch_colnorms(const float* A, int64_t m, int64_t n, int64_t lda, double* partial,
-                           int64_t nchunks, double* nu, hipStream_t stream);
-int64_t colnorm_chunks(int64_t m, int64_t n);
-int64_t colnorm_rows(int64_t m, int64_t n);
+// Squared column norms (FP64) of every problem of the task lists (pass 1
+// over row chunks into `partial`, pass 2 sums each column's chunks in order
+// into `nu`).  A: the matrix when Aptrs is null, else Aptrs[prob].
+hipError_t launch_colnorms(const ColDesc* d_pass1, int n1, int64_t items1, const ColDesc* d_pass2,
+                           int n2, int64_t items2, const float* A, const void* const* Aptrs,
+                           double* partial, double* nu, hipStream_t stream);
 
 // flags[i] = spread of nu over node i's columns > tau^2 (1/0); count in *count.
 hipError_t launch_flags(const double* nu, const NodeDesc* d_nodes, int nnodes, double tau2,

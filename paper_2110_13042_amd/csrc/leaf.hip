@@ -67,7 +67,7 @@ struct LeafArgs {
     const uint8_t* flags;
     const void* const* Aptrs;     // batches: A and C of problem d.prob (else A, C)
     void* const* Cptrs;
-    unsigned long long* counter;  // persistent mode: tile queue head (else null)
+    unsigned long long* counter;  // persistent mode: eight tile queue heads (else null)
 };
 
 __device__ __forceinline__ int find_leaf(const LeafDesc* t, int n, int64_t x) {
@@ -676,26 +676,48 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
     }
 }
 
+// One workgroup per tile (XCD-aware order).
 template <int MODE>
 __global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel(LeafArgs args) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
-    if (!args.counter) {
-        run_tile<MODE>(args, xcd_remap(blockIdx.x, args.ntiles, args.chunk), smem);
-        return;
-    }
-    // persistent: pull tiles (longest contraction first) until the queue is empty
+    run_tile<MODE>(args, xcd_remap(blockIdx.x, args.ntiles, args.chunk), smem);
+}
+
+// Persistent form (its own kernel, so that the queue logic does not change
+// the register allocation of the one-tile-per-workgroup form): eight tile
+// queues, one per XCD (workgroup ids go round-robin to the XCDs).  Queue q
+// owns the chunk-sized runs q, q + 8, q + 16, ... of the longest-first tile
+// order, so the tiles one XCD runs share operand panels in its L2.  A
+// workgroup drains its own XCD's queue, then the others; a queue's tile index
+// grows with its ticket, so the first ticket past the end means the queue is
+// empty for good.
+template <int MODE>
+__global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel_persistent(LeafArgs args) {
+    __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
     __shared__ int64_t next;
-    for (;;) {
-        if (threadIdx.x == 0) next = (int64_t)atomicAdd(args.counter, 1ull);
+    const uint32_t chunk = (uint32_t)args.chunk;
+    const int home = (int)(blockIdx.x & 7);
+    for (int probe = 0; probe < 8;) {
+        const int q = (home + probe) & 7;
+        if (threadIdx.x == 0) {
+            const uint64_t k = atomicAdd(args.counter + q, 1ull);
+            const uint64_t run = k / chunk;
+            next = (int64_t)((run * 8 + (uint64_t)q) * chunk + (k - run * chunk));
+        }
         __syncthreads();
         const int64_t tile = next;
         __syncthreads();
-        if (tile >= args.ntiles) break;
+        if (tile >= args.ntiles) {
+            ++probe;
+            continue;
+        }
         run_tile<MODE>(args, tile, smem);
     }
 }
 
-__global__ void zero_counter(unsigned long long* c) { *c = 0ull; }
+// Resets the eight queue heads of a persistent launch (a kernel, not a
+// memset, so that the reset is safe inside a captured graph).
+__global__ void zero_counter(unsigned long long* c) { c[threadIdx.x] = 0ull; }
 
 }  // namespace
 
@@ -704,32 +726,40 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
                          int chunk, hipStream_t stream, const BatchPtrs* bp) {
     if (ntiles <= 0) return hipSuccess;
     LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr};
-    dim3 grid((unsigned)ntiles), block(LEAF_THREADS);
+    dim3 grid((unsigned)ntiles);
     if (bp) {
         a.Aptrs = bp->A;
         a.Cptrs = bp->C;
         if (bp->counter) {
             a.counter = bp->counter;
-            hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, stream, bp->counter);
+            hipLaunchKernelGGL(zero_counter, dim3(1), dim3(8), 0, stream, bp->counter);
             const int64_t g = ntiles < bp->persistent_blocks ? ntiles : bp->persistent_blocks;
             grid = dim3((unsigned)g);
         }
     }
+#define ATA_LAUNCH_LEAF(M, threads)                                                          \
+    do {                                                                                 \
+        if (a.counter)                                                                   \
+            hipLaunchKernelGGL(leaf_kernel_persistent<M>, grid, dim3(threads), 0, stream, a); \
+        else                                                                             \
+            hipLaunchKernelGGL(leaf_kernel<M>, grid, dim3(threads), 0, stream, a);       \
+    } while (0)
     if (mode == MODE_BF16X3 && tile_cfg == 1) {
-        hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3_LARGE>, grid, block, 0, stream, a);
+        ATA_LAUNCH_LEAF(MODE_BF16X3_LARGE, LEAF_THREADS);
         return hipGetLastError();
     }
     if (mode == MODE_BF16X3 && tile_cfg == 2) {
-        hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3_HUGE>, grid, dim3(512), 0, stream, a);
+        ATA_LAUNCH_LEAF(MODE_BF16X3_HUGE, 512);
         return hipGetLastError();
     }
     switch (mode) {
-        case MODE_F64: hipLaunchKernelGGL(leaf_kernel<MODE_F64>, grid, block, 0, stream, a); break;
-        case MODE_F32: hipLaunchKernelGGL(leaf_kernel<MODE_F32>, grid, block, 0, stream, a); break;
-        case MODE_BF16X3: hipLaunchKernelGGL(leaf_kernel<MODE_BF16X3>, grid, block, 0, stream, a); break;
-        case MODE_FP8: hipLaunchKernelGGL(leaf_kernel<MODE_FP8>, grid, block, 0, stream, a); break;
+        case MODE_F64: ATA_LAUNCH_LEAF(MODE_F64, LEAF_THREADS); break;
+        case MODE_F32: ATA_LAUNCH_LEAF(MODE_F32, LEAF_THREADS); break;
+        case MODE_BF16X3: ATA_LAUNCH_LEAF(MODE_BF16X3, LEAF_THREADS); break;
+        case MODE_FP8: ATA_LAUNCH_LEAF(MODE_FP8, LEAF_THREADS); break;
         default: return hipErrorInvalidValue;
     }
+#undef ATA_LAUNCH_LEAF
     return hipGetLastError();
 }
 
@@ -751,17 +781,17 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
     int nb = 0;
     hipError_t e = hipSuccess;
     if (mode == MODE_BF16X3 && tile_cfg == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_BF16X3_LARGE>, LEAF_THREADS, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_LARGE>, LEAF_THREADS, 0);
     else if (mode == MODE_BF16X3 && tile_cfg == 2)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_BF16X3_HUGE>, 512, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_HUGE>, 512, 0);
     else if (mode == MODE_BF16X3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_BF16X3>, LEAF_THREADS, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3>, LEAF_THREADS, 0);
     else if (mode == MODE_FP8)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_FP8>, LEAF_THREADS, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8>, LEAF_THREADS, 0);
     else if (mode == MODE_F32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_F32>, LEAF_THREADS, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F32>, LEAF_THREADS, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel<MODE_F64>, LEAF_THREADS, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F64>, LEAF_THREADS, 0);
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 

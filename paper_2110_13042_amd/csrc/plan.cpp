@@ -310,7 +310,7 @@ void assign_packed(Plan& p) {
         L.PY = L.kind == LEAF_SYRK ? L.PX : ref(L.Y, L.K, L.pred_node, L.pred_value);
     }
     int64_t e = 0;
-    for (auto& d : p.pack) { d.elem_begin = e; e += d.elems; }
+    for (auto& d : p.pack) { d.elem_begin = e; e = item_align(e + d.elems); }
 }
 
 // FP8: every distinct leaf operand view is quantised on its own (blocks
@@ -368,8 +368,52 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     bld.ata(0, n);
     if (mode == MODE_BF16X3 && m > 0) assign_packed(p);
     if (mode == MODE_FP8 && m > 0) assign_quant(p);
+    if (p.fallback) build_colnorm_tasks(&p.m, &p.n, &p.lda, 1, p.col1, p.col2, &p.col_partial);
     finalize_plan(p);
     return p;
+}
+
+void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda, int64_t count,
+                         std::vector<ColDesc>& col1, std::vector<ColDesc>& col2,
+                         int64_t* partial_total) {
+    col1.clear();
+    col2.clear();
+    int64_t part_off = 0, nu_off = 0, e1 = 0, e2 = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        // about 2048 workgroups of 256 columns x (4 waves x rows / 4), at
+        // least 8 rows per wave
+        const int64_t xblocks = cdiv(std::max<int64_t>(n[i], 1), 256);
+        int64_t chunks = std::max<int64_t>(1, std::min(cdiv(2048, xblocks), cdiv(std::max<int64_t>(m[i], 1), 32)));
+        int64_t rows = cdiv(cdiv(std::max<int64_t>(m[i], 1), chunks), 4) * 4;
+        chunks = cdiv(std::max<int64_t>(m[i], 1), rows);
+        ColDesc d{};
+        d.m = m[i];
+        d.n = n[i];
+        d.lda = lda[i];
+        d.rows = rows;
+        d.nchunks = chunks;
+        d.part_off = part_off;
+        d.nu_off = nu_off;
+        d.prob = (int32_t)i;
+        part_off += chunks * n[i];
+        nu_off += n[i];
+        if (n[i] == 0) continue;
+        ColDesc d1 = d, d2 = d;
+        d1.elems = chunks * xblocks * ITEM_BLOCK;
+        d1.elem_begin = e1;
+        e1 = item_align(e1 + d1.elems);
+        d2.elems = n[i];
+        d2.elem_begin = e2;
+        e2 = item_align(e2 + d2.elems);
+        col1.push_back(d1);
+        col2.push_back(d2);
+    }
+    if (col1.empty()) {
+        ColDesc z{};
+        col1.push_back(z);
+        col2.push_back(z);
+    }
+    *partial_total = part_off;
 }
 
 void finalize_plan(Plan& p) {
@@ -396,14 +440,14 @@ void finalize_plan(Plan& p) {
     p.fb_tiles = t;
     for (auto& lvl : p.presum) {
         int64_t e = 0;
-        for (auto& d : lvl) { d.elem_begin = e; e += d.elems; }
+        for (auto& d : lvl) { d.elem_begin = e; e = item_align(e + d.elems); }
     }
     for (auto& lvl : p.combine) {
         int64_t e = 0;
-        for (auto& d : lvl) { d.elem_begin = e; e += d.elems; }
+        for (auto& d : lvl) { d.elem_begin = e; e = item_align(e + d.elems); }
     }
     int64_t e = 0;
-    for (auto& d : p.pack) { d.elem_begin = e; e += d.elems; }
+    for (auto& d : p.pack) { d.elem_begin = e; e = item_align(e + d.elems); }
     e = 0;
     for (auto& d : p.pack8) { d.elem_begin = e; e += d.elems; }
 }

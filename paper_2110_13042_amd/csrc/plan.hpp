@@ -142,8 +142,11 @@ struct CombineDesc {
 
 // Column norms of one problem of a batch: pass 1 work item = (row chunk,
 // group of four columns); pass 2 work item = one column.
+// Column-norm task of one problem.  Pass 1: a workgroup sums the squares of
+// 256 columns over one chunk of `rows` rows (elems = chunks x column blocks x
+// ITEM_BLOCK items); pass 2: one item per column sums the chunks in order.
 struct ColDesc {
-    int64_t m, n, lda, rows;      // rows per chunk
+    int64_t m, n, lda, rows;      // rows per chunk (a multiple of 4)
     int64_t nchunks;
     int64_t part_off, nu_off;     // doubles in the partial and norm arrays
     int64_t elem_begin, elems;
@@ -183,6 +186,8 @@ struct Plan {
     std::vector<LeafDesc> fb_leaves;                // SYRK leaves under the spread check
     std::vector<std::vector<CombineDesc>> combine;  // [height-1] bottom-up
     std::vector<NodeDesc> nodes;                    // AtA nodes (flags)
+    std::vector<ColDesc> col1, col2;                // column-norm passes (when fallback)
+    int64_t col_partial = 0;                        // doubles of the pass-1 partial sums
     int64_t arena_elems = 0;                        // in the mode's sum/product type
     int64_t total_tiles = 0;
     int64_t fb_tiles = 0;
@@ -198,6 +203,14 @@ int32_t default_max_depth(int32_t mode);
 // Builds the plan (host only).  Throws std::invalid_argument on bad sizes.
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);
 
+// Column-norm tasks of `count` problems (problem i: m[i] x n[i], row stride
+// lda[i]); partial sums and norms of problem i start at the returned offsets.
+// Problems with n = 0 get no task.  col1 / col2 never end up empty (a zero
+// task stands in), and *partial_total is the partial array's length.
+void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda, int64_t count,
+                         std::vector<ColDesc>& col1, std::vector<ColDesc>& col2,
+                         int64_t* partial_total);
+
 // Orders the leaves (longest contraction first) and fills the tile and
 // work-item prefix sums of every phase.
 void finalize_plan(Plan& p);
@@ -206,6 +219,12 @@ void finalize_plan(Plan& p);
 // merged (arena offsets, node indices and problem indices shifted) so that
 // each phase is one launch for the whole batch.
 Plan merge_plans(std::vector<Plan>& parts);
+
+// Work items of the streaming kernels (pre-sums, packing, combines, column
+// norms) run 256 to a workgroup; every task's first item is a multiple of
+// this, so a workgroup never spans two tasks and finds its task once.
+constexpr int64_t ITEM_BLOCK = 256;
+inline int64_t item_align(int64_t e) { return (e + ITEM_BLOCK - 1) / ITEM_BLOCK * ITEM_BLOCK; }
 
 // Output tile of the leaf kernels (shared with the device code): 128 x 128
 // for FP64/FP32 (and the FP64 fallback), 256 x 128 for split-BF16.  A SYRK

@@ -132,3 +132,31 @@ def test_batch_fallback_flags(h):
     h.set("spread_tau", 4096)
     for i, (G, M) in enumerate(zip(got, mats)):
         assert full_error(G, plain.gram_packed(M)) <= 2e-5, i
+
+
+@pytest.mark.parametrize("mode", [ata.F32, ata.F32_BF16X3, ata.F32_FP8E4M3])
+def test_persistent_and_grid_launch_agree(h, mode):
+    """The persistent leaf launch (per-XCD queues) and the one-workgroup-per-tile
+    launch run the same tiles, so the results are bit-identical."""
+    mats = _batch(75, 60, (64, 3000), (16, 1300))
+    h.set("leaf_cutoff", 256)
+    h.set("max_depth", 1)
+    dev = device()
+    As = [torch.from_numpy(M).to(dev) for M in mats]
+    outs = {}
+    for pers in (1, 0):
+        for graph in (0, 1):
+            _say("case: batch launch persistent", pers, "graph", graph, "mode", mode)
+            h.set("batch_persistent", pers)
+            h.set("batch_graph", graph)
+            outs[(pers, graph)] = [C.clone() for C in ata.gram_batched(As, mode, handle=h)]
+            torch.cuda.synchronize()
+    h.set("batch_persistent", 1)
+    h.set("batch_graph", 1)
+    ref = outs[(1, 0)]
+    for key, got in outs.items():
+        for i, (G, R) in enumerate(zip(got, ref)):
+            assert torch.equal(G, R), (key, i)
+    if mode != ata.F32_FP8E4M3:
+        for i in range(0, len(mats), 7):
+            assert full_error(ref[i].double().cpu().numpy(), plain.gram_packed(mats[i])) <= 2e-5
