@@ -164,6 +164,10 @@ def make_handle(ata, args):
         h.set("max_depth", args.max_depth)
     if args.leaf_tile:
         h.set("leaf_tile", args.leaf_tile)
+    if args.xcd_chunk:
+        h.set("xcd_chunk", args.xcd_chunk)
+    if args.tile_band:
+        h.set("tile_band", args.tile_band)
     return h
 
 
@@ -317,6 +321,8 @@ def main() -> int:
     ap.add_argument("--leaf-cutoff", type=int, default=0)
     ap.add_argument("--max-depth", type=int, default=-1)
     ap.add_argument("--leaf-tile", type=int, default=0, help="split-BF16 leaf tile: 0 = 128x128, 1 = 256x128, 2 = 256x256")
+    ap.add_argument("--xcd-chunk", type=int, default=0, help="leaf tiles per XCD per window (0: library default)")
+    ap.add_argument("--tile-band", type=int, default=0, help="GEMM leaf tile rows per band (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=512)
     ap.add_argument("--autotune", action="store_true",

@@ -84,7 +84,8 @@ typedef enum {
        summed phase times since the option was last set (default 0). */
     ATA_OPT_PROFILE = 6,
     /* Output tile of the split-BF16 leaf kernel: 0 = 128 x 128 (default),
-       1 = 256 x 128, 2 = 256 x 256.  Other dtypes ignore it. */
+       1 = 256 x 128, 2 = 256 x 256 on eight waves, 3 = 256 x 256 on four
+       waves of 128 x 128.  Other dtypes ignore it. */
     ATA_OPT_LEAF_TILE = 7,
     /* ata_gram_batched: 1 = capture the batch's launch sequence once per
        shape signature in a hipGraph and replay it (default); 0 = enqueue the
@@ -95,7 +96,14 @@ typedef enum {
        faster of the two on MI355X, since the persistent loop raises the
        kernels' register use); 1 = a persistent grid (resident workgroups
        only) pulling tiles from per-XCD queues.  Results are identical. */
-    ATA_OPT_BATCH_PERSISTENT = 9
+    ATA_OPT_BATCH_PERSISTENT = 9,
+    /* Leaf tile order (performance only; results are identical): in every
+       window of 8 x XCD_CHUNK consecutive tiles each XCD gets XCD_CHUNK
+       consecutive ones, so tiles sharing operand panels share an L2; GEMM
+       leaves number their tiles in bands of TILE_BAND tile rows, column by
+       column.  Both in [1, 4096]. */
+    ATA_OPT_XCD_CHUNK = 10,
+    ATA_OPT_TILE_BAND = 11
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

@@ -116,7 +116,8 @@ struct ata_ctx {
     bool residual = false;
     uint64_t seed = 0x5EEDull;
     int64_t ws_limit = 0;
-    int chunk = 16;
+    int chunk = 16;                    // leaf tiles per XCD per window
+    int band = 4;                      // GEMM leaf tile rows per band
     std::map<PlanKey, std::unique_ptr<DevicePlan>> plans;
     void* arena = nullptr;
     size_t arena_cap = 0;
@@ -359,7 +360,7 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             h->seed = (uint64_t)value;
             return ATA_OK;
         case ATA_OPT_LEAF_TILE:
-            if (value != 0 && value != 1 && value != 2) return ATA_ERR_INVALID_VALUE;
+            if (value != 0 && value != 1 && value != 2 && value != 3) return ATA_ERR_INVALID_VALUE;
             h->popt.tile_cfg = (int32_t)value;
             return ATA_OK;
         case ATA_OPT_BATCH_GRAPH:
@@ -367,6 +368,14 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             return ATA_OK;
         case ATA_OPT_BATCH_PERSISTENT:
             h->batch_persistent = value != 0.0;
+            return ATA_OK;
+        case ATA_OPT_XCD_CHUNK:
+            if (value < 1 || value > 4096) return ATA_ERR_INVALID_VALUE;
+            h->chunk = (int)value;
+            return ATA_OK;
+        case ATA_OPT_TILE_BAND:
+            if (value < 1 || value > 4096) return ATA_ERR_INVALID_VALUE;
+            h->band = (int)value;
             return ATA_OK;
         case ATA_OPT_PROFILE:
             if (h->events_used) (void)drain_events(h);
@@ -524,10 +533,10 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
-                          flags, h->chunk, st);
+                          flags, h->chunk, h->band, st);
     if (e == hipSuccess && !p.fb_leaves.empty())
         e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
-                                   h->arena, flags, h->chunk, st);
+                                   h->arena, flags, h->chunk, h->band, st);
     mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
@@ -617,10 +626,10 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
     mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, nullptr,
-                          nullptr, h->arena, be.d_flags, h->chunk, st, &bp);
+                          nullptr, h->arena, be.d_flags, h->chunk, h->band, st, &bp);
     if (e == hipSuccess && !p.fb_leaves.empty())
         e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, nullptr, nullptr,
-                                   h->arena, be.d_flags, h->chunk, st, &bq);
+                                   h->arena, be.d_flags, h->chunk, h->band, st, &bq);
     mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
@@ -827,7 +836,7 @@ ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n, i
         if (b >= n) break;
     }
     const int32_t dmax = std::min<int32_t>(default_max_depth(mode), 3);
-    const int ntiles = mode == MODE_BF16X3 ? 3 : 1;
+    const int ntiles = mode == MODE_BF16X3 ? 4 : 1;
     ata_status_t rs = ATA_OK;
     for (int64_t b : cutoffs) {
         for (int32_t d = 0; d <= dmax; ++d) {

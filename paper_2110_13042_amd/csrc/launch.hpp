@@ -22,15 +22,18 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg);
 
 // All leaf products of a plan (one grouped launch, one workgroup per tile).
 // tile_cfg selects the output tile of the split-BF16 kernel (0: 128 x 128,
-// 1: 256 x 128); the other modes have one tile shape.
+// 1: 256 x 128, 2: 256 x 256); the other modes have one tile shape.  Tile
+// order: every window of 8 x chunk consecutive tiles gives each XCD chunk
+// consecutive tiles; GEMM leaves number their tiles in bands of `band` tile
+// rows, column by column.
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
-                         int chunk, hipStream_t stream, const BatchPtrs* bp = nullptr);
+                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp = nullptr);
 
 // FP64 fallback of flagged SYRK leaves (FP32 inputs and output); the tasks
 // are the plan's fallback-capable SYRK leaves, unflagged ones exit at once.
 hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t ntiles, const void* A,
-                                  void* C, void* arena, const uint8_t* flags, int chunk,
+                                  void* C, void* arena, const uint8_t* flags, int chunk, int band,
                                   hipStream_t stream, const BatchPtrs* bp = nullptr);
 
 // One Strassen level of pre-sums (S1..S5 / T1..T5 for every node of the level).

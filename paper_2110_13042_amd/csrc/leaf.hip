@@ -45,10 +45,15 @@ constexpr int MODE_FALLBACK = 100;
 // Split-BF16 with the 256 x 128 and 256 x 256 tiles.
 constexpr int MODE_BF16X3_LARGE = 101;
 constexpr int MODE_BF16X3_HUGE = 102;
+constexpr int MODE_BF16X3_WIDE = 103;
+#ifndef ATA_WIDE_STAGES
+#define ATA_WIDE_STAGES 4     // LDS ring depth of the 256 x 256 split-BF16 engine (32 KB each)
+#endif
 constexpr size_t lds_bytes(int mode) {
     return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
+           : mode == MODE_BF16X3_WIDE ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
 constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE ? 512 : LEAF_THREADS; }
@@ -59,7 +64,8 @@ typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 struct LeafArgs {
     const LeafDesc* tasks;
     int ntasks;
-    int chunk;
+    int chunk;                    // consecutive tiles per XCD in each window of 8 chunks
+    int band;                     // GEMM tile rows per band
     int64_t ntiles;
     const void* A;
     void* C;
@@ -113,10 +119,10 @@ __device__ __forceinline__ double2 load2d(const double* p, int64_t ld, int64_t r
 }
 
 // Tile coordinates of the q-th tile of a leaf.  SYRK: lower-triangular rows,
-// row ti holding min(rho (ti + 1), tiles_n) tiles.  GEMM: bands of TILE_BAND
-// tile rows, column by column inside a band.
+// row ti holding min(rho (ti + 1), tiles_n) tiles.  GEMM: bands of B tile
+// rows, column by column inside a band.
 template <int RHO>
-__device__ __forceinline__ void leaf_tile(const LeafDesc& d, int64_t q, int& ti, int& tj) {
+__device__ __forceinline__ void leaf_tile(const LeafDesc& d, int64_t q, int64_t B, int& ti, int& tj) {
     const int64_t tn = d.tiles_n;
     if (d.kind == LEAF_SYRK) {
         const int64_t L = tn / RHO;
@@ -133,10 +139,10 @@ __device__ __forceinline__ void leaf_tile(const LeafDesc& d, int64_t q, int& ti,
             tj = (int)(r % tn);
         }
     } else {
-        const int64_t band = q / (TILE_BAND * tn);
-        const int64_t rows = d.tiles_m - band * TILE_BAND < TILE_BAND ? d.tiles_m - band * TILE_BAND : TILE_BAND;
-        const int64_t local = q - band * TILE_BAND * tn;
-        ti = (int)(band * TILE_BAND + local % rows);
+        const int64_t bnd = q / (B * tn);
+        const int64_t rows = d.tiles_m - bnd * B < B ? d.tiles_m - bnd * B : B;
+        const int64_t local = q - bnd * B * tn;
+        ti = (int)(bnd * B + local % rows);
         tj = (int)(local / rows);
     }
 }
@@ -197,15 +203,18 @@ __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, in
         *reinterpret_cast<float4*>(ys + (lr + 8) * LD32 + lc) = ry1;
     };
 
+    // two slabs in flight (see the split-BF16 engine)
     if (nk > 0) {
         gload(0);
         sstore(0);
     }
+    if (nk > 1) gload(BK);
     __syncthreads();
     const int ko = lane >> 5, io = lane & 31;
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
-        if (kt + 1 < nk) gload((kt + 1) * BK);
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        if (kt + 2 < nk) gload((kt + 2) * BK);
         const float* xs = Xs + cur * BK * LD32 + wm * 64 + io;
         const float* ys = Ys + cur * BK * LD32 + wn * 64 + io;
 #pragma unroll
@@ -218,7 +227,6 @@ __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, in
             acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
         }
-        if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
     for (int a = 0; a < 2; ++a)
@@ -265,7 +273,7 @@ struct BfCfg {
 };
 using BfSmall = BfCfg<2, 2, 2, 2, 4>;   // 128 x 128, 4 waves, 80 KB LDS (two workgroups per CU)
 using BfLarge = BfCfg<2, 2, 4, 2, 4>;   // 256 x 128, 4 waves, 120 KB LDS
-using BfHuge = BfCfg<2, 4, 4, 2, 2>;    // 256 x 256, 8 waves, 16-row slabs, 80 KB LDS
+using BfHuge = BfCfg<2, 4, 4, 2, 2>;    // 256 x 256, 8 waves, 16-row slabs, 96 KB LDS
 
 template <class CFG>
 __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, int tj,
@@ -378,36 +386,38 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[buf][a], fbh[buf][b], acc[a][b], 0, 0, 0);
     };
 
+    // Two slabs in flight: at the top of iteration kt the staging registers
+    // hold slab kt + 1 (loaded one iteration earlier) and go to the free LDS
+    // buffer, then the loads of slab kt + 2 are issued, so every global load
+    // has a whole iteration of MFMA work to arrive.
     if (nk > 0) {
         gload(0);
         sstore(0);
     }
+    if (nk > 1) gload(1);
     __syncthreads();
     if constexpr (NB == 2) {
         if (nk > 0) read_frags(0, 0, 0);
         for (int64_t kt = 0; kt < nk; ++kt) {
             const int cur = (int)(kt & 1);
-            const bool more = kt + 1 < nk;
-            if (more) gload(kt + 1);
+            if (kt + 1 < nk) sstore(cur ^ 1);      // slab kt + 1 into the other LDS buffer
+            if (kt + 2 < nk) gload(kt + 2);
             read_frags(1, cur, 1);                 // second 16-k step of this slab
             __builtin_amdgcn_sched_barrier(0);
             mfmas(0);                              // first step
             __builtin_amdgcn_sched_barrier(0);
-            if (more) sstore(cur ^ 1);             // next slab into the other LDS buffer
-            __builtin_amdgcn_sched_barrier(0);
             mfmas(1);
             __builtin_amdgcn_sched_barrier(0);
             __syncthreads();
-            if (more) read_frags(0, cur ^ 1, 0);
+            if (kt + 1 < nk) read_frags(0, cur ^ 1, 0);
         }
     } else {
         for (int64_t kt = 0; kt < nk; ++kt) {
             const int cur = (int)(kt & 1);
-            const bool more = kt + 1 < nk;
-            if (more) gload(kt + 1);
+            if (kt + 1 < nk) sstore(cur ^ 1);
+            if (kt + 2 < nk) gload(kt + 2);
             read_frags(0, cur, 0);
             mfmas(0);
-            if (more) sstore(cur ^ 1);
             __syncthreads();
         }
     }
@@ -419,6 +429,144 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
             for (int v = 0; v < 16; ++v) {
                 const int r = wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int cc = wn * BNB * 32 + b * 32 + (lane & 31);
+                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena);
+            }
+}
+
+// Split-BF16 x3 with a 256 x 256 tile: four waves of 128 x 128 (4 x 4 blocks
+// of 32 x 32 each), one wave per SIMD.  A wave's 48 MFMAs per 16-k step
+// against 16 fragment reads keep LDS traffic at a third of the 128 x 128
+// engine's per MFMA.  Slabs of 16 k (two 8-k groups) stream into a ring of
+// four LDS stages through buffer loads that write LDS directly (no staging
+// registers, no LDS store instructions): stage s holds Xh, Xl, Yh, Yl, each
+// [group][256 columns] of 16-byte chunks, and lane l of a load lands at
+// 16 l bytes past the instruction's LDS base.  Three slabs are in flight;
+// the fragments of slab kt + 1 are read while slab kt's MFMAs run.  Reads
+// past the packed arrays (and whole groups past K) return zero.
+namespace wide {
+constexpr int TM = 256, TN = 256;
+constexpr int STAGES = ATA_WIDE_STAGES;
+constexpr int ARR = 2 * 256 * 16;             // bytes of one operand half in a stage
+constexpr int STAGE = 4 * ARR;                // 32 KB
+constexpr size_t LDS = (size_t)STAGES * STAGE;
+constexpr int LOADS = 8;                      // buffer->LDS loads per wave per slab
+}  // namespace wide
+
+#define ATA_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+// s_waitcnt until at most 8 n loads of this wave are outstanding (n in 0..3).
+__device__ __forceinline__ void wait_slabs(int64_t n) {
+    if (n <= 0) __builtin_amdgcn_s_waitcnt(0x0F70);        // vmcnt(0)
+    else if (n == 1) __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8)
+    else if (n == 2) __builtin_amdgcn_s_waitcnt(0x4F70);   // vmcnt(16)
+    else __builtin_amdgcn_s_waitcnt(0x4F78);               // vmcnt(24)
+}
+
+__device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float* arena_in, int ti, int tj, float* C,
+                                 float* arena, unsigned char* smem) {
+    using namespace wide;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 1, wn = w & 1;
+    const int64_t K = d.K;
+    // an even number of 16-k slabs (a trailing slab past K loads zeros), so
+    // the K loop is a plain loop over pairs of steps
+    const int64_t nk = ((K + 15) / 16 + 1) & ~int64_t(1);
+
+    // wave w streams operand half w (0 Xh, 1 Xl, 2 Yh, 3 Yl) of every slab
+    const bool isx = w < 2;
+    const __amdgpu_buffer_rsrc_t src = packed_rsrc(arena_in, isx ? d.PX : d.PY, (w & 1) != 0);
+    const uint32_t gs = (uint32_t)((isx ? d.PX.gstride : d.PY.gstride) * 4);
+    const uint32_t col0 = (uint32_t)((isx ? ti * TM : tj * TN) + lane) * 16u;
+    auto issue = [&](int64_t kt) {
+        unsigned char* base = smem + (kt % STAGES) * STAGE + w * ARR;
+#pragma unroll
+        for (int i = 0; i < LOADS; ++i) {
+            const int g = i >> 2, seg = i & 3;
+            const int64_t grow = kt * 2 + g;
+            const uint32_t off = grow * 8 < K ? (uint32_t)grow * gs + col0 + (uint32_t)(seg * 64 * 16)
+                                              : 0x7FFFFFF0u;        // past the array: zeros
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + g * 4096 + seg * 1024), 16,
+                                                     (int)off, 0, 0, 0);
+        }
+    };
+
+    v16f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    // fragment of lane l: column (l % 32) of its block, k = 8 (l / 32) .. + 7
+    const int fo = (lane >> 5) * 4096 + (lane & 31) * 16;
+    v8bf xh[2][4], xl[2][4], yh[2][4], yl[2][4];
+    auto frags = [&](int buf, int64_t kt) {
+        const unsigned char* st = smem + (kt % STAGES) * STAGE + fo;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int xo = (wm * 128 + a * 32) * 16, yo = (wn * 128 + a * 32) * 16;
+            xh[buf][a] = *reinterpret_cast<const v8bf*>(st + 0 * ARR + xo);
+            xl[buf][a] = *reinterpret_cast<const v8bf*>(st + 1 * ARR + xo);
+            yh[buf][a] = *reinterpret_cast<const v8bf*>(st + 2 * ARR + yo);
+            yl[buf][a] = *reinterpret_cast<const v8bf*>(st + 3 * ARR + yo);
+        }
+    };
+    // the three products in separate passes over the 16 blocks, so that
+    // consecutive MFMAs never depend on each other
+    auto mfmas = [&](int buf) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[buf][a], yh[buf][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[buf][a], yl[buf][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[buf][a], yh[buf][b], acc[a][b], 0, 0, 0);
+    };
+    // one K step: make slab kt + 1 visible, refill the stage freed by slab
+    // kt - 1 with slab kt + 3, then slab kt's MFMAs with slab kt + 1's
+    // fragment reads in their shadow
+    constexpr int AHEAD = STAGES - 1;             // slabs in flight
+    auto step = [&](int64_t kt, int cur) {
+        if (kt + 1 < nk) wait_slabs((kt + AHEAD - 1 < nk ? kt + AHEAD - 1 : nk - 1) - kt - 1);
+        __builtin_amdgcn_s_barrier();
+        if (kt + AHEAD < nk) issue(kt + AHEAD);
+        if (kt + 1 < nk) frags(cur ^ 1, kt + 1);
+        mfmas(cur);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);   // three MFMAs
+        }
+    };
+
+    for (int64_t j = 0; j < AHEAD && j < nk; ++j) issue(j);
+    if (nk > 0) {
+        wait_slabs((nk < AHEAD ? nk : AHEAD) - 1);
+        __builtin_amdgcn_s_barrier();
+        frags(0, 0);
+    }
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+        step(kt, 0);
+        step(kt + 1, 1);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int cc = wn * 128 + b * 32 + (lane & 31);
                 store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena);
             }
 }
@@ -485,16 +633,25 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
         }
     };
 
+    // two slabs in flight (see the split-BF16 engine); the block scales of
+    // the next slab are read one iteration ahead
     if (nk > 0) {
         gload(0);
         sstore(0);
     }
+    if (nk > 1) gload(1);
     __syncthreads();
     const int io = lane & 15, ko = 32 * (lane >> 4);
+    int sa_next = nk > 0 ? 127 + sx[ti] : 127, sb_next = nk > 0 ? 127 + sy[tj] : 127;
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
-        if (kt + 1 < nk) gload(kt + 1);
-        const int sa = 127 + sx[kt * sxs + ti], sb = 127 + sy[kt * sys + tj];
+        if (kt + 1 < nk) sstore(cur ^ 1);
+        if (kt + 2 < nk) gload(kt + 2);
+        const int sa = sa_next, sb = sb_next;
+        if (kt + 1 < nk) {
+            sa_next = 127 + sx[(kt + 1) * sxs + ti];
+            sb_next = 127 + sy[(kt + 1) * sys + tj];
+        }
         v8i fa[4], fb[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -514,7 +671,6 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
             for (int b = 0; b < 4; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa[a], fb[b], acc[a][b],
                                                                              0, 0, 0, sa, 0, sb);
-        if (kt + 1 < nk) sstore(cur ^ 1);
         __syncthreads();
     }
 #pragma unroll
@@ -639,7 +795,7 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
     if (d.pred_node >= 0 && (int32_t)args.flags[d.pred_node] != d.pred_value) return;
     const int64_t q = bid - d.tile_begin;
     int ti, tj;
-    leaf_tile<MODE == MODE_BF16X3_LARGE ? 2 : 1>(d, q, ti, tj);
+    leaf_tile<MODE == MODE_BF16X3_LARGE ? 2 : 1>(d, q, args.band, ti, tj);
     // SYRK leaves under the spread check run in exactly one of the two
     // launches: the FP64 fallback kernel when their node is flagged, the
     // mode's own kernel otherwise.
@@ -665,6 +821,10 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
         if (flagged) return;
         tile_fp8(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
                  static_cast<float*>(args.arena), smem);
+    } else if constexpr (MODE == MODE_BF16X3_WIDE) {
+        if (flagged) return;
+        tile_bf16x3_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                         static_cast<float*>(args.arena), smem);
     } else if constexpr (MODE == MODE_BF16X3_HUGE) {
         if (flagged) return;
         tile_bf16x3<BfHuge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
@@ -694,18 +854,21 @@ __global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel(LeafArgs args) 
 template <int MODE>
 __global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel_persistent(LeafArgs args) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
-    __shared__ int64_t next;
+    // the ticket is passed through the first bytes of the tile's LDS, which
+    // no tile touches between the two barriers around it
+    int64_t* next = reinterpret_cast<int64_t*>(smem);
     const uint32_t chunk = (uint32_t)args.chunk;
     const int home = (int)(blockIdx.x & 7);
     for (int probe = 0; probe < 8;) {
         const int q = (home + probe) & 7;
+        __syncthreads();                          // the previous tile is done with LDS
         if (threadIdx.x == 0) {
             const uint64_t k = atomicAdd(args.counter + q, 1ull);
             const uint64_t run = k / chunk;
-            next = (int64_t)((run * 8 + (uint64_t)q) * chunk + (k - run * chunk));
+            *next = (int64_t)((run * 8 + (uint64_t)q) * chunk + (k - run * chunk));
         }
         __syncthreads();
-        const int64_t tile = next;
+        const int64_t tile = *next;
         __syncthreads();
         if (tile >= args.ntiles) {
             ++probe;
@@ -723,9 +886,9 @@ __global__ void zero_counter(unsigned long long* c) { c[threadIdx.x] = 0ull; }
 
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
-                         int chunk, hipStream_t stream, const BatchPtrs* bp) {
+                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp) {
     if (ntiles <= 0) return hipSuccess;
-    LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr};
+    LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr};
     dim3 grid((unsigned)ntiles);
     if (bp) {
         a.Aptrs = bp->A;
@@ -752,6 +915,10 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
         ATA_LAUNCH_LEAF(MODE_BF16X3_HUGE, 512);
         return hipGetLastError();
     }
+    if (mode == MODE_BF16X3 && tile_cfg == 3) {
+        ATA_LAUNCH_LEAF(MODE_BF16X3_WIDE, LEAF_THREADS);
+        return hipGetLastError();
+    }
     switch (mode) {
         case MODE_F64: ATA_LAUNCH_LEAF(MODE_F64, LEAF_THREADS); break;
         case MODE_F32: ATA_LAUNCH_LEAF(MODE_F32, LEAF_THREADS); break;
@@ -764,10 +931,10 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
 }
 
 hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t ntiles, const void* A,
-                                  void* C, void* arena, const uint8_t* flags, int chunk,
+                                  void* C, void* arena, const uint8_t* flags, int chunk, int band,
                                   hipStream_t stream, const BatchPtrs* bp) {
     if (ntiles <= 0) return hipSuccess;
-    LeafArgs a{d_tasks, ntasks, chunk, ntiles, A, C, arena, flags,
+    LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags,
                bp ? bp->A : nullptr, bp ? bp->C : nullptr, nullptr};
     hipLaunchKernelGGL(leaf_kernel<MODE_FALLBACK>, dim3((unsigned)ntiles), dim3(LEAF_THREADS), 0, stream, a);
     return hipGetLastError();
@@ -784,6 +951,8 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_LARGE>, LEAF_THREADS, 0);
     else if (mode == MODE_BF16X3 && tile_cfg == 2)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_HUGE>, 512, 0);
+    else if (mode == MODE_BF16X3 && tile_cfg == 3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_WIDE>, LEAF_THREADS, 0);
     else if (mode == MODE_BF16X3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3>, LEAF_THREADS, 0);
     else if (mode == MODE_FP8)

@@ -161,7 +161,7 @@ struct NodeDesc {
 struct PlanOptions {
     int64_t leaf_cutoff = 0;       // 0: default for the mode
     int32_t max_depth = -1;        // -1: default for the mode
-    int32_t tile_cfg = 0;          // split-BF16 leaf tile: 0 = 128 x 128, 1 = 256 x 128, 2 = 256 x 256
+    int32_t tile_cfg = 0;          // split-BF16 leaf tile: 0 = 128 x 128, 1 = 256 x 128, 2, 3 = 256 x 256
     double spread_tau = 4096.0;    // <= 0: no fallback
 };
 
@@ -236,11 +236,8 @@ constexpr int tile_m_for(int32_t mode, int32_t tile_cfg) {
     return mode == MODE_BF16X3 && tile_cfg >= 1 ? 256 : 128;
 }
 constexpr int tile_n_for(int32_t mode, int32_t tile_cfg) {
-    return mode == MODE_BF16X3 && tile_cfg == 2 ? 256 : 128;
+    return mode == MODE_BF16X3 && tile_cfg >= 2 ? 256 : 128;
 }
-// GEMM tiles are ordered in bands of this many tile rows, column by column
-// inside a band, so consecutive tiles share operand panels.
-constexpr int TILE_BAND = 4;
 int64_t syrk_tiles(int64_t tm, int64_t tn, int64_t rho);
 
 }  // namespace ata

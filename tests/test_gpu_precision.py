@@ -29,7 +29,7 @@ def h():
     hd.close()
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_bf16x3_small_integers_bit_exact(h, tile):
     rng = np.random.default_rng(51)
     h.set("leaf_tile", tile)
@@ -43,7 +43,7 @@ def test_bf16x3_small_integers_bit_exact(h, tile):
         assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth)
 
 
-@pytest.mark.parametrize("depth,tile", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (0, 2), (2, 2)])
+@pytest.mark.parametrize("depth,tile", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (0, 2), (2, 2), (0, 3), (1, 3)])
 def test_bf16x3_matches_emulation(h, depth, tile):
     rng = np.random.default_rng(52 + depth)
     m, n, b = 1536, 1100, 256
