@@ -145,7 +145,17 @@ ata_status_t ata_create(ata_handle_t* out);
 ata_status_t ata_destroy(ata_handle_t h);
 
 /* C_packed = lower(A^T A) (Alg. 1 AtA with the handle's options).
-   m = 0 zero-fills C; n = 0 is a no-op.  A and C must not overlap. */
+   m = 0 zero-fills C; n = 0 is a no-op.  A and C must not overlap.
+   A and C hold doubles for ATA_F64 and floats for the other dtypes.
+   Returns ATA_ERR_INVALID_VALUE for a null handle or pointer with nonzero
+   size, negative m or n, lda < max(1, n), an unknown dtype or overlapping A
+   and C; ATA_ERR_NOT_SUPPORTED when a split-BF16 or FP8 leaf operand would
+   need a packed array of 4 GiB or more (those arrays are read through 32-bit
+   buffer offsets); ATA_ERR_OUT_OF_MEMORY when the workspace cannot be
+   allocated or exceeds ATA_OPT_WORKSPACE_LIMIT; ATA_ERR_HIP when a launch
+   fails.  The first call for a (shape, dtype, options) combination builds and
+   uploads the plan (host work and a synchronous copy); later calls only
+   enqueue kernels. */
 ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n,
                       int64_t lda, ata_dtype_t dtype, void* C_packed,
                       void* stream);
@@ -153,8 +163,11 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n,
 /* batch independent Gram products, C_packed[i] = lower(A[i]^T A[i]), of
    uneven shapes.  Every problem's plan is merged into one: each phase is a
    single launch for the whole batch, and all leaf products of all problems
-   run in one persistent launch whose workgroups pull tiles (longest
-   contraction first) from a queue.  The first call for a shape signature
+   run in one launch, longest contraction first (one workgroup per tile, or
+   with ATA_OPT_BATCH_PERSISTENT a persistent grid pulling tiles from per-XCD
+   queues).  Each problem takes its own leaf cutoff and depth (options, else
+   the autotune table, else the defaults); the leaf tile shape is the
+   handle's.  The first call for a shape signature
    (the m, n, lda of every member plus the handle's options) builds the plan
    and captures the launch sequence in a hipGraph; later calls replay it on an
    internal stream ordered after `stream` by events (the caller's stream
@@ -189,9 +202,10 @@ typedef struct {
 } ata_tune_entry_t;
 
 /* Autotuner: times ata_gram on (A, C_packed) -- device buffers of the given
-   shape, contents are overwritten -- for every candidate leaf cutoff
-   (powers of two from 128 up to the first at or above n), Strassen depth cap
-   (0 up to the dtype's default) and, for ATA_F32_BF16X3, leaf tile, keeps
+   shape; A is only read, C_packed is overwritten -- for every candidate leaf
+   cutoff (powers of two from 128 up to the first at or above n), Strassen
+   depth cap (0 up to the smaller of 3 and the dtype's default) and, for
+   ATA_F32_BF16X3, leaf tile (0..3), keeps
    the fastest in the handle's table under (dtype, shape bucket) and returns
    it in *best (may be NULL).  Buckets are half-octaves of m and of n.
    ata_gram and ata_gram_batched use the table whenever the leaf cutoff and

@@ -399,6 +399,8 @@ ata_status_t ata_plan_query(int64_t m, int64_t n, ata_dtype_t dtype, int64_t lea
     Plan p;
     try {
         p = make_plan((int32_t)dtype, m, n, std::max<int64_t>(1, n), o);
+    } catch (const std::length_error&) {
+        return ATA_ERR_NOT_SUPPORTED;
     } catch (const std::exception&) {
         return ATA_ERR_INVALID_VALUE;
     }
@@ -478,6 +480,8 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
             dp->plan = make_plan(mode, m, n, lda, o);
         } catch (const std::invalid_argument&) {
             return ATA_ERR_INVALID_VALUE;
+        } catch (const std::length_error&) {
+            return ATA_ERR_NOT_SUPPORTED;
         } catch (const std::exception&) {
             return ATA_ERR_INTERNAL;
         }
@@ -703,6 +707,8 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
             be->dp->plan = merge_plans(parts);
         } catch (const std::invalid_argument&) {
             return ATA_ERR_INVALID_VALUE;
+        } catch (const std::length_error&) {
+            return ATA_ERR_NOT_SUPPORTED;
         } catch (const std::exception&) {
             return ATA_ERR_INTERNAL;
         }

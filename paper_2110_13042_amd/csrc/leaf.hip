@@ -478,6 +478,8 @@ __device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float*
     const __amdgpu_buffer_rsrc_t src = packed_rsrc(arena_in, isx ? d.PX : d.PY, (w & 1) != 0);
     const uint32_t gs = (uint32_t)((isx ? d.PX.gstride : d.PY.gstride) * 4);
     const uint32_t col0 = (uint32_t)((isx ? ti * TM : tj * TN) + lane) * 16u;
+    // offset of a zero load: the array's byte size (the first offset past it)
+    const uint32_t past = (uint32_t)(((isx ? d.PX.end - d.PX.off : d.PY.end - d.PY.off)) * 4);
     auto issue = [&](int64_t kt) {
         unsigned char* base = smem + (kt % STAGES) * STAGE + w * ARR;
 #pragma unroll
@@ -485,7 +487,7 @@ __device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float*
             const int g = i >> 2, seg = i & 3;
             const int64_t grow = kt * 2 + g;
             const uint32_t off = grow * 8 < K ? (uint32_t)grow * gs + col0 + (uint32_t)(seg * 64 * 16)
-                                              : 0x7FFFFFF0u;        // past the array: zeros
+                                              : past;               // past the array: zeros
             __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + g * 4096 + seg * 1024), 16,
                                                      (int)off, 0, 0, 0);
         }

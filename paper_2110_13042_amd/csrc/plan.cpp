@@ -84,6 +84,12 @@ struct Target {
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Packed and quantised operands are read through buffer resources with
+// 32-bit byte offsets: one array must stay below 4 GiB.
+void check_buffer_bytes(int64_t floats) {
+    if (floats * 4 > (int64_t)0xFFFFFF00) throw std::length_error("leaf operand array exceeds 4 GiB");
+}
+
 struct Builder {
     Plan& p;
     int64_t b;
@@ -272,6 +278,7 @@ void assign_packed(Plan& p) {
             P.lo_delta = groups * V.cols * 4;
             P.gstride = V.cols * 4;
             P.end = V.off + groups * V.cols * 4;
+            check_buffer_bytes(P.end - P.off);
             return P;
         }
         const int64_t r0 = V.base == BASE_A ? V.off / p.lda : 0, c0 = V.base == BASE_A ? V.off % p.lda : 0;
@@ -281,6 +288,7 @@ void assign_packed(Plan& p) {
             P.lo_delta = a_groups * p.n * 4;
             P.gstride = p.n * 4;
             P.end = base + a_groups * p.n * 4;
+            check_buffer_bytes(P.end - P.off);
             return P;
         }
         const auto key = std::make_tuple(V.base, V.off, V.ld, V.prows, V.pcols, V.cols);
@@ -302,6 +310,7 @@ void assign_packed(Plan& p) {
         P.lo_delta = groups * V.cols * 4;
         P.gstride = V.cols * 4;
         P.end = off + groups * V.cols * 4;
+        check_buffer_bytes(P.end - P.off);
         memo.emplace(key, P);
         return P;
     };
@@ -338,6 +347,7 @@ void assign_quant(Plan& p) {
         Q.scales = d.scales;
         Q.cols_p = cols_p;
         Q.end = d.dst + rows_p * cols_p / 4;
+        check_buffer_bytes(Q.end - Q.off);
         memo.emplace(key, Q);
         return Q;
     };

@@ -76,3 +76,17 @@ def test_gram_argument_errors_need_no_device():
     assert L.ata_gram_batched(None, 0, None, None, None, None, 1, None, None) == 1
     h = ctypes.c_void_p()
     assert L.ata_create(None) == 1
+
+
+def test_plan_query_rejects_packed_operands_of_4_gib():
+    """Split-BF16 and FP8 leaf operands are read with 32-bit buffer offsets:
+    a plan whose packed array reaches 4 GiB is refused as not supported,
+    while the same shape in FP32 (plain pointers) plans normally."""
+    m = 1 << 21                       # 2^21 x 1024: 4 GiB of packed BF16 hi
+    with pytest.raises(ata.AtaError) as e:
+        ata.ata_plan_query(m, 1024, ata.F32_BF16X3, 2048, 0)
+    assert e.value.status == 2
+    info, _ = ata.ata_plan_query(m, 1024, ata.F32, 2048, 0)
+    assert info["syrk_leaves"] == 1
+    info, _ = ata.ata_plan_query(m // 2, 1024, ata.F32_BF16X3, 2048, 0)
+    assert info["syrk_leaves"] == 1

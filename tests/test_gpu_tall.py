@@ -1,0 +1,71 @@
+"""Tall-skinny ill-scaled workload at full size: A 262144 x 4096 FP32, N(0,1)
+with column j scaled by 10^u_j, u_j ~ U[-3,3].  Column-norm spreads of ~10^6
+flag the diagonal AtA nodes for the FP64 fallback.  FP32 and split-BF16 must
+meet 2e-5 on 256 sampled columns of C against the FP64 oracle; the
+diagonally scaled error (D^-1 (C_hat - C) D^-1, D = diag(sqrt(C_jj))) is
+reported with and without the fallback."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import plain
+from paper_2110_13042_amd import ata, workloads
+from gpu_helpers import device, packed_columns
+
+pytestmark = pytest.mark.gpu
+
+N_COLS = 4096
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tall():
+    dev = device()
+    _say("case: tall_scaled_f32_262144x4096 full size (host generation + oracle columns)")
+    A = workloads.make("tall_scaled_f32_262144x4096")
+    S = workloads.sampled_columns(N_COLS, 256, seed=3)
+    ref = plain.gram_cols(A, S)                      # n x |S|
+    d = np.sqrt(plain.colnorms(A))
+    At = torch.from_numpy(A).to(dev)
+    del A
+    yield At, S, ref, d
+    del At
+    torch.cuda.empty_cache()
+
+
+def _errors(Cp, S, ref, d):
+    got = packed_columns(Cp, N_COLS, S)
+    e_s = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    w = d[:, None] * d[S][None, :]
+    e_d = float(np.linalg.norm((got - ref) / w) / np.linalg.norm(ref / w))
+    return e_s, e_d
+
+
+@pytest.mark.parametrize("mode", [ata.F32, ata.F32_BF16X3])
+def test_tall_scaled_sampled_columns(tall, mode):
+    At, S, ref, d = tall
+    out = {}
+    for tau in (4096.0, 0.0):
+        h = ata.Handle(spread_tau=tau)
+        try:
+            _say("case: tall mode", mode, "spread_tau", tau)
+            C = ata.gram(At, mode, handle=h)
+            torch.cuda.synchronize()
+            rep = h.report()
+            out[tau] = _errors(C.double().cpu().numpy(), S, ref, d) + (rep["flagged_nodes"],)
+            _say("  e_S %.3e  e_D %.3e  flagged %d  levels %d  b %d" % (
+                out[tau][0], out[tau][1], out[tau][2], rep["strassen_levels"], rep["leaf_cutoff"]))
+            del C
+        finally:
+            h.close()
+    e_s, e_d, flagged = out[4096.0]
+    assert flagged > 0                   # the ill-scaled diagonal nodes take the FP64 path
+    assert e_s <= 2e-5
+    # the fallback never makes the scaled error worse than running everything in the mode
+    assert e_d <= out[0.0][1] * 1.05 + 1e-12
