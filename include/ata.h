@@ -103,7 +103,13 @@ typedef enum {
        leaves number their tiles in bands of TILE_BAND tile rows, column by
        column.  Both in [1, 4096]. */
     ATA_OPT_XCD_CHUNK = 10,
-    ATA_OPT_TILE_BAND = 11
+    ATA_OPT_TILE_BAND = 11,
+    /* Split-K: when a leaf launch (the dtype's, or the FP64 fallback's) has
+       fewer tiles than this, leaves with a contraction of at least 16384
+       rows are cut into K chunks of at least 8192 rows whose partial sums a
+       reduce pass adds in chunk order, in FP64, rounding once (default 2048;
+       0 = never split).  Tall-skinny A gets enough tiles to fill the GPU. */
+    ATA_OPT_SPLIT_TARGET = 12
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */
@@ -134,6 +140,8 @@ typedef struct {
     int32_t depth;                /* Strassen level of the leaf (0 = none)     */
     int64_t rows, cols, contraction;  /* output rows x cols, summed length     */
     int64_t out_row0, out_col0;   /* position in C when written there, else -1 */
+    int32_t ksplit;               /* K chunks (split-K; 1 = not split)         */
+    int32_t pad_;
 } ata_leaf_t;
 
 /* Create a handle bound to the current HIP device.  Returns ATA_ERR_HIP when

@@ -26,7 +26,7 @@ DTYPE_NAMES = {"f64": F64, "f32": F32, "bf16x3": F32_BF16X3, "fp8": F32_FP8E4M3}
 OPT_LEAF_CUTOFF, OPT_MAX_STRASSEN_DEPTH, OPT_SPREAD_TAU = 0, 1, 2
 OPT_RESIDUAL, OPT_WORKSPACE_LIMIT, OPT_RESIDUAL_SEED, OPT_PROFILE = 3, 4, 5, 6
 OPT_LEAF_TILE, OPT_BATCH_GRAPH, OPT_BATCH_PERSISTENT = 7, 8, 9
-OPT_XCD_CHUNK, OPT_TILE_BAND = 10, 11
+OPT_XCD_CHUNK, OPT_TILE_BAND, OPT_SPLIT_TARGET = 10, 11, 12
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -63,7 +63,7 @@ class Leaf(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
                 ("contraction", ctypes.c_int64), ("out_row0", ctypes.c_int64),
-                ("out_col0", ctypes.c_int64)]
+                ("out_col0", ctypes.c_int64), ("ksplit", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 _LIB = None
@@ -209,7 +209,8 @@ class Handle:
                "workspace_limit": OPT_WORKSPACE_LIMIT, "residual_seed": OPT_RESIDUAL_SEED,
                "profile": OPT_PROFILE, "leaf_tile": OPT_LEAF_TILE,
                "batch_graph": OPT_BATCH_GRAPH, "batch_persistent": OPT_BATCH_PERSISTENT,
-               "xcd_chunk": OPT_XCD_CHUNK, "tile_band": OPT_TILE_BAND}[name]
+               "xcd_chunk": OPT_XCD_CHUNK, "tile_band": OPT_TILE_BAND,
+               "split_target": OPT_SPLIT_TARGET}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

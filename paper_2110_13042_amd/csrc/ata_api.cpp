@@ -31,9 +31,10 @@ struct PlanKey {
     int32_t depth;
     bool fb;
     int32_t tile_cfg;
+    int64_t split;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg) <
-               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg);
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split) <
+               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split);
     }
 };
 
@@ -50,6 +51,7 @@ struct DevicePlan {
     NodeDesc* d_nodes = nullptr;
     ColDesc* d_col1 = nullptr;
     ColDesc* d_col2 = nullptr;
+    ReduceDesc* d_reduce = nullptr;
     ~DevicePlan() { if (d_buf) (void)hipFree(d_buf); }
 };
 
@@ -70,10 +72,11 @@ struct BatchKey {
     int32_t depth;
     bool fb;
     int32_t tile_cfg;
+    int64_t split;
     std::vector<int64_t> shapes;   // m, n, lda per problem
     bool operator<(const BatchKey& o) const {
-        return std::tie(mode, b, depth, fb, tile_cfg, shapes) <
-               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.shapes);
+        return std::tie(mode, b, depth, fb, tile_cfg, split, shapes) <
+               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.shapes);
     }
 };
 
@@ -118,6 +121,7 @@ struct ata_ctx {
     int64_t ws_limit = 0;
     int chunk = 16;                    // leaf tiles per XCD per window
     int band = 4;                      // GEMM leaf tile rows per band
+    int64_t split_target = 2048;       // split-K below this many tiles per leaf launch (0: never)
     std::map<PlanKey, std::unique_ptr<DevicePlan>> plans;
     void* arena = nullptr;
     size_t arena_cap = 0;
@@ -203,6 +207,7 @@ ata_status_t upload_plan(DevicePlan& dp) {
     bytes += align256(p.pack8.size() * sizeof(Pack8Desc));
     bytes += align256(p.col1.size() * sizeof(ColDesc));
     bytes += align256(p.col2.size() * sizeof(ColDesc));
+    bytes += align256(p.reduce.size() * sizeof(ReduceDesc));
     if (bytes == 0) return ATA_OK;
     std::vector<unsigned char> host(bytes, 0);
     if (hipMalloc(&dp.d_buf, bytes) != hipSuccess) {
@@ -225,6 +230,7 @@ ata_status_t upload_plan(DevicePlan& dp) {
     dp.d_pack8 = static_cast<Pack8Desc*>(put(p.pack8.data(), p.pack8.size() * sizeof(Pack8Desc)));
     dp.d_col1 = static_cast<ColDesc*>(put(p.col1.data(), p.col1.size() * sizeof(ColDesc)));
     dp.d_col2 = static_cast<ColDesc*>(put(p.col2.data(), p.col2.size() * sizeof(ColDesc)));
+    dp.d_reduce = static_cast<ReduceDesc*>(put(p.reduce.data(), p.reduce.size() * sizeof(ReduceDesc)));
     return hip_status(hipMemcpy(dp.d_buf, host.data(), bytes, hipMemcpyHostToDevice));
 }
 
@@ -377,6 +383,10 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             if (value < 1 || value > 4096) return ATA_ERR_INVALID_VALUE;
             h->band = (int)value;
             return ATA_OK;
+        case ATA_OPT_SPLIT_TARGET:
+            if (value < 0 || value > 1e9) return ATA_ERR_INVALID_VALUE;
+            h->split_target = (int64_t)value;
+            return ATA_OK;
         case ATA_OPT_PROFILE:
             if (h->events_used) (void)drain_events(h);
             h->profile = value != 0.0;
@@ -416,6 +426,8 @@ ata_status_t ata_plan_query(int64_t m, int64_t n, ata_dtype_t dtype, int64_t lea
         o2.contraction = L.K;
         o2.out_row0 = L.out_kind == OUT_PACKED ? L.out_row0 : -1;
         o2.out_col0 = L.out_kind == OUT_PACKED ? L.out_col0 : -1;
+        o2.ksplit = L.ksplit > 1 ? L.ksplit : 1;
+        o2.pad_ = 0;
     }
     return ATA_OK;
 }
@@ -467,7 +479,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     int32_t depth, tile_cfg;
     choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
-    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg};
+    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -476,6 +488,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         o.max_depth = depth;
         o.spread_tau = fb ? h->popt.spread_tau : 0.0;
         o.tile_cfg = tile_cfg;
+        o.split_target = h->split_target;
         try {
             dp->plan = make_plan(mode, m, n, lda, o);
         } catch (const std::invalid_argument&) {
@@ -541,6 +554,9 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     if (e == hipSuccess && !p.fb_leaves.empty())
         e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
                                    h->arena, flags, h->chunk, h->band, st);
+    if (e == hipSuccess && !p.reduce.empty())
+        e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
+                          C_packed, h->arena, flags, st);
     mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
@@ -634,6 +650,9 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
     if (e == hipSuccess && !p.fb_leaves.empty())
         e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, nullptr, nullptr,
                                    h->arena, be.d_flags, h->chunk, h->band, st, &bq);
+    if (e == hipSuccess && !p.reduce.empty())
+        e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
+                          nullptr, h->arena, be.d_flags, st, &bq);
     mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
@@ -677,7 +696,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     const int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
     std::vector<int64_t> bs((size_t)batch);
     std::vector<int32_t> ds((size_t)batch);
-    BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, {}};
+    BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, h->split_target, {}};
     key.shapes.reserve(5 * (size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
         int32_t tile_i;
@@ -701,10 +720,11 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
                 o.max_depth = ds[(size_t)i];
                 o.spread_tau = fb ? h->popt.spread_tau : 0.0;
                 o.tile_cfg = tile_cfg;
+                o.split_target = 0;          // the merged plan is split as a whole
                 parts.push_back(make_plan(mode, m[i], n[i], lda[i], o));
             }
             be->dp = std::make_unique<DevicePlan>();
-            be->dp->plan = merge_plans(parts);
+            be->dp->plan = merge_plans(parts, h->split_target);
         } catch (const std::invalid_argument&) {
             return ATA_ERR_INVALID_VALUE;
         } catch (const std::length_error&) {
@@ -864,6 +884,10 @@ ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n, i
                 }
                 if (d > 0 && probe.stats.max_levels < d) continue;
                 rs = ata_gram(h, A, m, n, lda, dtype, C_packed, stream);   // warm-up (plans, arena)
+                if (rs == ATA_ERR_NOT_SUPPORTED || rs == ATA_ERR_OUT_OF_MEMORY) {
+                    rs = ATA_OK;                    // this candidate cannot run here: skip it
+                    continue;
+                }
                 if (rs != ATA_OK) break;
                 const int reps = 3;
                 if (hipEventRecord(e0, st) != hipSuccess) { rs = ATA_ERR_HIP; break; }

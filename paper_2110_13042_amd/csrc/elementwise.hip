@@ -256,6 +256,40 @@ __global__ __launch_bounds__(EW_THREADS) void quant8_kernel(const Pack8Desc* tas
     }
 }
 
+// ------------------------------------------------------------- split-K sums
+// Work item = one output element of a split leaf: its K-chunk partials are
+// summed in chunk order in FP64 and rounded once into the leaf's target.
+// Partials come from the FP64 fallback (FP64 array) when the leaf's node is
+// flagged, else from the mode's leaf kernel (arrays of the mode's type).
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void reduce_kernel(const ReduceDesc* tasks, int ntasks,
+                                                            int64_t items, T* C0, T* arena,
+                                                            const uint8_t* flags, void* const* Cptrs) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= items) return;
+    const ReduceDesc& d = tasks[block_task(tasks, ntasks)];
+    const int64_t e = x - d.elem_begin;
+    if (e >= d.elems) return;
+    if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
+    const int64_t i = udiv(e, d.cols), j = e - i * d.cols;
+    if (d.kind == LEAF_SYRK && j > i) return;
+    const int64_t plane = d.rows * d.cols;
+    double s = 0.0;
+    if (d.fb_node >= 0 && flags[d.fb_node]) {
+        const double* p = reinterpret_cast<const double*>(arena + d.part64_off) + e;
+        for (int k = 0; k < d.ksplit; ++k) s += p[k * plane];
+    } else {
+        const T* p = arena + d.part_off + e;
+        for (int k = 0; k < d.ksplit; ++k) s += (double)p[k * plane];
+    }
+    if (d.out_kind == OUT_PACKED) {
+        T* C = Cptrs ? static_cast<T*>(Cptrs[d.prob]) : C0;
+        C[packed_index(d.out_row0 + i, d.out_col0 + j)] = (T)s;
+    } else {
+        arena[d.out_off + i * d.out_ld + j] = (T)s;
+    }
+}
+
 // ---------------------------------------------------------------- combine
 // Work item = one row i and four columns j..j+3 of the n2 x k2 products.
 // C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4,
@@ -617,6 +651,19 @@ hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, c
     hipLaunchKernelGGL(quant8_kernel, dim3((unsigned)blocks), dim3(EW_THREADS), 0, stream, d_tasks,
                        ntasks, static_cast<const float*>(A), static_cast<float*>(arena), flags,
                        bp ? bp->A : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int32_t mode, const ReduceDesc* d_tasks, int ntasks, int64_t items, void* C,
+                         void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp) {
+    if (items <= 0) return hipSuccess;
+    void* const* Cp = bp ? bp->C : nullptr;
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(reduce_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+                           d_tasks, ntasks, items, static_cast<double*>(C), static_cast<double*>(arena), flags, Cp);
+    else
+        hipLaunchKernelGGL(reduce_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+                           d_tasks, ntasks, items, static_cast<float*>(C), static_cast<float*>(arena), flags, Cp);
     return hipGetLastError();
 }
 

@@ -51,6 +51,11 @@ hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, c
                          void* arena, const uint8_t* flags, hipStream_t stream,
                          const BatchPtrs* bp = nullptr);
 
+// Partial sums of the split-K leaves (after both leaf launches).
+hipError_t launch_reduce(int32_t mode, const ReduceDesc* d_tasks, int ntasks, int64_t items, void* C,
+                         void* arena, const uint8_t* flags, hipStream_t stream,
+                         const BatchPtrs* bp = nullptr);
+
 // One height of Strassen combines (seven products -> four quadrants).
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
                           void* C, void* arena, const uint8_t* flags, hipStream_t stream,

@@ -157,14 +157,23 @@ __device__ __forceinline__ bool vec_ok(const T* p, int64_t ld, int width) {
     return ((reinterpret_cast<uintptr_t>(p) & 15) == 0) && (ld % width == 0);
 }
 
-// Store one accumulator element of tile (ti, tj) at tile-local (r, c).
+// Contraction rows [kb, ke) of one tile and its K chunk (split-K leaves).
+struct KRange {
+    int64_t kb, ke;
+    int split;
+};
+
+// Store one accumulator element of tile (ti, tj) at tile-local (r, c): into
+// the leaf's target, or into its chunk's partial sums for a split leaf.
 template <class OutT, int TM = TILE_M, int TN = TILE_N>
 __device__ __forceinline__ void store_elem(const LeafDesc& d, int ti, int tj, int r, int c,
-                                           OutT v, OutT* C, OutT* arena) {
+                                           OutT v, OutT* C, OutT* arena, int split) {
     const int64_t gi = (int64_t)ti * TM + r, gj = (int64_t)tj * TN + c;
     if (gi >= d.rows || gj >= d.cols) return;
     if (d.kind == LEAF_SYRK && gj > gi) return;
-    if (d.out_kind == OUT_PACKED)
+    if (d.ksplit > 1)
+        arena[d.part_off + ((int64_t)split * d.rows + gi) * d.cols + gj] = v;
+    else if (d.out_kind == OUT_PACKED)
         C[packed_index(d.out_row0 + gi, d.out_col0 + gj)] = v;
     else
         arena[d.out_off + gi * d.out_ld + gj] = v;
@@ -172,14 +181,16 @@ __device__ __forceinline__ void store_elem(const LeafDesc& d, int ti, int tj, in
 
 // ---------------------------------------------------------------- FP32 MFMA
 __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, int ti, int tj,
-                         float* C, float* arena, unsigned char* smem) {
+                         float* C, float* arena, unsigned char* smem, const KRange& kr) {
+    Xp += kr.kb * d.X.ld;
+    Yp += kr.kb * d.Y.ld;
     float* Xs = reinterpret_cast<float*>(smem);          // [2][BK][LD32]
     float* Ys = Xs + 2 * BK * LD32;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
     const int lr = t >> 5, lc = (t & 31) << 2;
     const int64_t xc = (int64_t)ti * TILE_M + lc, yc = (int64_t)tj * TILE_N + lc;
     const bool xv = vec_ok(Xp, d.X.ld, 4), yv = vec_ok(Yp, d.Y.ld, 4);
-    const int64_t K = d.K;
+    const int64_t K = kr.ke - kr.kb;
     const int64_t nk = (K + BK - 1) / BK;
 
     v16f acc[2][2];
@@ -234,7 +245,7 @@ __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, in
             for (int v = 0; v < 16; ++v) {
                 const int r = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int c = wn * 64 + b * 32 + (lane & 31);
-                store_elem<float>(d, ti, tj, r, c, acc[a][b][v], C, arena);
+                store_elem<float>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
             }
 }
 
@@ -277,7 +288,7 @@ using BfHuge = BfCfg<2, 4, 4, 2, 2>;    // 256 x 256, 8 waves, 16-row slabs, 96 
 
 template <class CFG>
 __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, int tj,
-                            float* C, float* arena, unsigned char* smem) {
+                            float* C, float* arena, unsigned char* smem, const KRange& kr) {
     constexpr int TM = CFG::TM, TN = CFG::TN, STAGE = CFG::STAGE, LDR = CFG::LDR;
     constexpr int BMB = CFG::BMB, BNB = CFG::BNB, G = CFG::GROUPS, NT = CFG::THREADS;
     unsigned short* lds = reinterpret_cast<unsigned short*>(smem);
@@ -291,7 +302,8 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
     const __amdgpu_buffer_rsrc_t rx[2] = {packed_rsrc(arena_in, d.PX, false), packed_rsrc(arena_in, d.PX, true)};
     const __amdgpu_buffer_rsrc_t ry[2] = {packed_rsrc(arena_in, d.PY, false), packed_rsrc(arena_in, d.PY, true)};
     const uint32_t xgs = (uint32_t)(d.PX.gstride * 4), ygs = (uint32_t)(d.PY.gstride * 4);
-    const int64_t K = d.K;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t gb = kr.kb / 8;                 // first 8-row group of the K chunk
     const int64_t nk = (K + 8 * G - 1) / (8 * G);
 
     v16f acc[BMB][BNB];
@@ -324,10 +336,10 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
             bool isx;
             int g, col;
             pair_of(i, isx, g, col);
-            const int64_t grow = kt * G + g;
-            const uint32_t off = (uint32_t)grow * (isx ? xgs : ygs) +
+            const int64_t lrow = kt * G + g;
+            const uint32_t off = (uint32_t)(gb + lrow) * (isx ? xgs : ygs) +
                                  (uint32_t)(((isx ? ti * TM : tj * TN) + col) * 16);
-            if (grow * 8 < K) {
+            if (lrow * 8 < K) {
                 st_hi[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx[0] : ry[0], (int)off, 0, 0);
                 st_lo[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx[1] : ry[1], (int)off, 0, 0);
             } else {
@@ -429,7 +441,7 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
             for (int v = 0; v < 16; ++v) {
                 const int r = wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int cc = wn * BNB * 32 + b * 32 + (lane & 31);
-                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena);
+                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
             }
 }
 
@@ -463,12 +475,13 @@ __device__ __forceinline__ void wait_slabs(int64_t n) {
 }
 
 __device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float* arena_in, int ti, int tj, float* C,
-                                 float* arena, unsigned char* smem) {
+                                 float* arena, unsigned char* smem, const KRange& kr) {
     using namespace wide;
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = w >> 1, wn = w & 1;
-    const int64_t K = d.K;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t gb = kr.kb / 8;                 // first 8-row group of the K chunk
     // an even number of 16-k slabs (a trailing slab past K loads zeros), so
     // the K loop is a plain loop over pairs of steps
     const int64_t nk = ((K + 15) / 16 + 1) & ~int64_t(1);
@@ -485,8 +498,8 @@ __device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float*
 #pragma unroll
         for (int i = 0; i < LOADS; ++i) {
             const int g = i >> 2, seg = i & 3;
-            const int64_t grow = kt * 2 + g;
-            const uint32_t off = grow * 8 < K ? (uint32_t)grow * gs + col0 + (uint32_t)(seg * 64 * 16)
+            const int64_t lrow = kt * 2 + g;
+            const uint32_t off = lrow * 8 < K ? (uint32_t)(gb + lrow) * gs + col0 + (uint32_t)(seg * 64 * 16)
                                               : past;               // past the array: zeros
             __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + g * 4096 + seg * 1024), 16,
                                                      (int)off, 0, 0, 0);
@@ -569,7 +582,7 @@ __device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float*
             for (int v = 0; v < 16; ++v) {
                 const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int cc = wn * 128 + b * 32 + (lane & 31);
-                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena);
+                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
             }
 }
 
@@ -590,7 +603,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t q8_rsrc(const float* arena, co
 }
 
 __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int tj,
-                         float* C, float* arena, unsigned char* smem) {
+                         float* C, float* arena, unsigned char* smem, const KRange& kr) {
     auto xq_ = [&](int s) { return smem + s * 2 * 128 * LD8; };
     auto yq_ = [&](int s) { return smem + s * 2 * 128 * LD8 + 128 * LD8; };
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
@@ -598,7 +611,8 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
     const int* sx = reinterpret_cast<const int*>(arena_in + d.QX.scales);
     const int* sy = reinterpret_cast<const int*>(arena_in + d.QY.scales);
     const int64_t sxs = d.QX.cols_p / 128, sys = d.QY.cols_p / 128;
-    const int64_t K = d.K;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t sb0 = kr.kb / 128;              // first 128-row slab of the K chunk
     const int64_t nk = (K + 127) / 128;
     const int wave_base = __builtin_amdgcn_readfirstlane(t & ~63);
 
@@ -620,7 +634,7 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
             const int trw2 = isx ? trw : trw - 1024;
             const int g = trw2 >> 7, col = (trw2 & 127) + lane;
             const int64_t cp = isx ? d.QX.cols_p : d.QY.cols_p;
-            const uint32_t off = (uint32_t)(((kt * 8 + g) * cp + (isx ? ti : tj) * 128 + col) * 16);
+            const uint32_t off = (uint32_t)((((sb0 + kt) * 8 + g) * cp + (isx ? ti : tj) * 128 + col) * 16);
             st[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx : ry, (int)off, 0, 0);
         }
     };
@@ -644,15 +658,15 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
     if (nk > 1) gload(1);
     __syncthreads();
     const int io = lane & 15, ko = 32 * (lane >> 4);
-    int sa_next = nk > 0 ? 127 + sx[ti] : 127, sb_next = nk > 0 ? 127 + sy[tj] : 127;
+    int sa_next = nk > 0 ? 127 + sx[sb0 * sxs + ti] : 127, sb_next = nk > 0 ? 127 + sy[sb0 * sys + tj] : 127;
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
         if (kt + 1 < nk) sstore(cur ^ 1);
         if (kt + 2 < nk) gload(kt + 2);
         const int sa = sa_next, sb = sb_next;
         if (kt + 1 < nk) {
-            sa_next = 127 + sx[(kt + 1) * sxs + ti];
-            sb_next = 127 + sy[(kt + 1) * sys + tj];
+            sa_next = 127 + sx[(sb0 + kt + 1) * sxs + ti];
+            sb_next = 127 + sy[(sb0 + kt + 1) * sys + tj];
         }
         v8i fa[4], fb[4];
 #pragma unroll
@@ -683,7 +697,7 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
             for (int v = 0; v < 4; ++v) {
                 const int r = wm * 64 + a * 16 + 4 * (lane >> 4) + v;
                 const int c = wn * 64 + b * 16 + (lane & 15);
-                store_elem<float>(d, ti, tj, r, c, acc[a][b][v], C, arena);
+                store_elem<float>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
             }
 }
 
@@ -692,11 +706,13 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
 // inputs are promoted exactly, the result is rounded to OutT on store).
 template <class InT, class OutT>
 __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, int ti, int tj,
-                         OutT* C, OutT* arena, unsigned char* smem) {
+                         OutT* C, OutT* arena, unsigned char* smem, const KRange& kr) {
+    Xp += kr.kb * d.X.ld;
+    Yp += kr.kb * d.Y.ld;
     double* Xs = reinterpret_cast<double*>(smem);        // [2][BK][LD64]
     double* Ys = Xs + 2 * BK * LD64;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
-    const int64_t K = d.K;
+    const int64_t K = kr.ke - kr.kb;
     const int64_t nk = (K + BK - 1) / BK;
 
     v4d acc[4][4];
@@ -785,7 +801,15 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, int ti
             for (int v = 0; v < 4; ++v) {
                 const int r = wm * 64 + a * 16 + 4 * v + (lane >> 4);
                 const int c = wn * 64 + b * 16 + (lane & 15);
-                store_elem<OutT>(d, ti, tj, r, c, (OutT)acc[a][b][v], C, arena);
+                if (d.ksplit > 1 && sizeof(OutT) == 4) {
+                    // FP64 fallback of a split leaf: its partial sums stay FP64
+                    const int64_t gi = (int64_t)ti * TILE_M + r, gj = (int64_t)tj * TILE_N + c;
+                    if (gi < d.rows && gj < d.cols && !(d.kind == LEAF_SYRK && gj > gi))
+                        reinterpret_cast<double*>(arena + d.part64_off)[((int64_t)kr.split * d.rows + gi) * d.cols + gj] =
+                            acc[a][b][v];
+                } else {
+                    store_elem<OutT>(d, ti, tj, r, c, (OutT)acc[a][b][v], C, arena, kr.split);
+                }
             }
 }
 
@@ -795,7 +819,14 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
     const void* Aptr = args.Aptrs ? args.Aptrs[d.prob] : args.A;
     void* Cptr = args.Cptrs ? args.Cptrs[d.prob] : args.C;
     if (d.pred_node >= 0 && (int32_t)args.flags[d.pred_node] != d.pred_value) return;
-    const int64_t q = bid - d.tile_begin;
+    int64_t q = bid - d.tile_begin;
+    KRange kr{0, d.K, 0};
+    if (d.ksplit > 1) {
+        kr.split = (int)(q / d.tiles_split);
+        q -= (int64_t)kr.split * d.tiles_split;
+        kr.kb = (int64_t)kr.split * d.kchunk;
+        kr.ke = kr.kb + d.kchunk < d.K ? kr.kb + d.kchunk : d.K;
+    }
     int ti, tj;
     leaf_tile<MODE == MODE_BF16X3_LARGE ? 2 : 1>(d, q, args.band, ti, tj);
     // SYRK leaves under the spread check run in exactly one of the two
@@ -805,36 +836,36 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
     if constexpr (MODE == MODE_F64) {
         tile_f64<double, double>(d, view_ptr<double>(d.X, Aptr, args.arena),
                                  view_ptr<double>(d.Y, Aptr, args.arena), ti, tj,
-                                 static_cast<double*>(Cptr), static_cast<double*>(args.arena), smem);
+                                 static_cast<double*>(Cptr), static_cast<double*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FALLBACK) {
         if (!flagged) return;
         tile_f64<float, float>(d, view_ptr<float>(d.X, Aptr, args.arena),
                                view_ptr<float>(d.Y, Aptr, args.arena), ti, tj,
-                               static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem);
+                               static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3) {
         if (flagged) return;
         tile_bf16x3<BfSmall>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                             static_cast<float*>(args.arena), smem);
+                             static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_LARGE) {
         if (flagged) return;
         tile_bf16x3<BfLarge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                             static_cast<float*>(args.arena), smem);
+                             static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FP8) {
         if (flagged) return;
         tile_fp8(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                 static_cast<float*>(args.arena), smem);
+                 static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_WIDE) {
         if (flagged) return;
         tile_bf16x3_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                         static_cast<float*>(args.arena), smem);
+                         static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_HUGE) {
         if (flagged) return;
         tile_bf16x3<BfHuge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                            static_cast<float*>(args.arena), smem);
+                            static_cast<float*>(args.arena), smem, kr);
     } else {
         if (flagged) return;
         tile_f32(d, view_ptr<float>(d.X, Aptr, args.arena), view_ptr<float>(d.Y, Aptr, args.arena),
-                 ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem);
+                 ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
     }
 }
 

@@ -45,7 +45,8 @@ int64_t Plan::launches() const {
     if (!pack.empty()) l += 1;
     if (!pack8.empty()) l += 1;
     if (!fb_leaves.empty()) l += 1;
-    if (fallback) l += 2;  // column norms + flags
+    if (!reduce.empty()) l += 1;
+    if (fallback) l += 3;  // column norm passes + flags
     return l;
 }
 
@@ -379,6 +380,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     if (mode == MODE_BF16X3 && m > 0) assign_packed(p);
     if (mode == MODE_FP8 && m > 0) assign_quant(p);
     if (p.fallback) build_colnorm_tasks(&p.m, &p.n, &p.lda, 1, p.col1, p.col2, &p.col_partial);
+    if (opt.split_target > 0) split_leaves(p, opt.split_target);
     finalize_plan(p);
     return p;
 }
@@ -426,10 +428,57 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
     *partial_total = part_off;
 }
 
+void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
+    if (target <= 0) return;
+    int64_t t_mode = 0, t_fb = 0;
+    for (const auto& L : p.leaves) {
+        if (L.ksplit > 1) return;                  // already split
+        t_mode += L.tiles;
+        if (L.fb_node >= 0)
+            t_fb += syrk_tiles(cdiv(L.rows, TILE_M), cdiv(L.cols, TILE_N), TILE_M / TILE_N);
+    }
+    for (auto& L : p.leaves) {
+        const int64_t most = L.K / min_chunk;      // chunks of at least min_chunk rows
+        if (most < 2) continue;
+        int64_t s = t_mode > 0 && t_mode < target ? std::min(target / t_mode, most) : 1;
+        if (L.fb_node >= 0 && t_fb > 0 && t_fb < target) s = std::max(s, std::min(target / t_fb, most));
+        if (s < 2) continue;
+        const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
+        s = cdiv(L.K, kchunk);
+        if (s < 2) continue;
+        L.ksplit = (int32_t)s;
+        L.kchunk = kchunk;
+        L.tiles_split = L.tiles;
+        L.tiles *= s;
+        L.part_off = p.alloc(s * L.rows * L.cols);
+        if (L.fb_node >= 0) L.part64_off = p.alloc(2 * s * L.rows * L.cols);
+        ReduceDesc R{};
+        R.kind = L.kind;
+        R.out_kind = L.out_kind;
+        R.rows = L.rows;
+        R.cols = L.cols;
+        R.part_off = L.part_off;
+        R.part64_off = L.part64_off;
+        R.out_off = L.out_off;
+        R.out_ld = L.out_ld;
+        R.out_row0 = L.out_row0;
+        R.out_col0 = L.out_col0;
+        R.ksplit = L.ksplit;
+        R.fb_node = L.fb_node;
+        R.pred_node = L.pred_node;
+        R.pred_value = L.pred_value;
+        R.prob = L.prob;
+        R.elems = L.rows * L.cols;
+        p.reduce.push_back(R);
+    }
+}
+
 void finalize_plan(Plan& p) {
-    // LPT: longest contraction first (stable, so ties keep tree order)
+    // LPT: longest per-tile contraction first (a split leaf's tiles cover one
+    // K chunk; stable, so ties keep tree order)
+    auto tile_k = [](const LeafDesc& L) { return L.ksplit > 1 ? L.kchunk : L.K; };
     std::stable_sort(p.leaves.begin(), p.leaves.end(),
-                     [](const LeafDesc& a, const LeafDesc& c) { return a.K > c.K; });
+                     [&](const LeafDesc& a, const LeafDesc& c) { return tile_k(a) > tile_k(c); });
     int64_t t = 0;
     for (auto& L : p.leaves) { L.tile_begin = t; t += L.tiles; }
     p.total_tiles = t;
@@ -442,6 +491,10 @@ void finalize_plan(Plan& p) {
             F.tiles_m = (int32_t)cdiv(F.rows, TILE_M);
             F.tiles_n = (int32_t)cdiv(F.cols, TILE_N);
             F.tiles = syrk_tiles(F.tiles_m, F.tiles_n, TILE_M / TILE_N);
+            if (F.ksplit > 1) {
+                F.tiles_split = F.tiles;
+                F.tiles *= F.ksplit;
+            }
             F.tile_begin = t;
             t += F.tiles;
             p.fb_leaves.push_back(F);
@@ -460,6 +513,8 @@ void finalize_plan(Plan& p) {
     for (auto& d : p.pack) { d.elem_begin = e; e = item_align(e + d.elems); }
     e = 0;
     for (auto& d : p.pack8) { d.elem_begin = e; e += d.elems; }
+    e = 0;
+    for (auto& d : p.reduce) { d.elem_begin = e; e = item_align(e + d.elems); }
 }
 
 namespace {
@@ -470,7 +525,7 @@ void shift_view(View& v, int64_t ab) {
 
 }  // namespace
 
-Plan merge_plans(std::vector<Plan>& parts) {
+Plan merge_plans(std::vector<Plan>& parts, int64_t split_target) {
     Plan out;
     if (parts.empty()) return out;
     out.mode = parts[0].mode;
@@ -551,6 +606,7 @@ Plan merge_plans(std::vector<Plan>& parts) {
         }
         nu_base += p.n;
     }
+    split_leaves(out, split_target);
     finalize_plan(out);
     return out;
 }

@@ -87,7 +87,25 @@ struct LeafDesc {
     Packed PX, PY;            // split-BF16 mode: packed operands
     Packed8 QX, QY;           // FP8 mode: quantised operands
     int32_t prob;             // problem of a batch (selects its A and C)
-    int32_t pad_;
+    int32_t ksplit;           // K chunks (1: none); tile q covers chunk q / tiles_split
+    int64_t kchunk;           // rows per K chunk (a multiple of 256)
+    int64_t tiles_split;      // tiles of one K chunk
+    int64_t part_off;         // split: arena offset of [ksplit][rows][cols] partials (mode type)
+    int64_t part64_off;       // split SYRK leaves under the spread check: FP64 partials
+                              // of the fallback (arena float offset, 8-byte aligned)
+};
+
+// Sum of the K-chunk partials of a split leaf (one work item per output
+// element), in chunk order, in FP64, rounded once into the leaf's target.
+struct ReduceDesc {
+    int32_t kind, out_kind;
+    int64_t rows, cols;
+    int64_t part_off, part64_off;
+    int64_t out_off, out_ld, out_row0, out_col0;
+    int32_t ksplit, fb_node;
+    int32_t pred_node, pred_value;
+    int32_t prob, pad_;
+    int64_t elem_begin, elems;
 };
 
 // Quantise one FP32 operand view to block-scaled e4m3 (one work item per
@@ -140,8 +158,6 @@ struct CombineDesc {
     int32_t prob;
 };
 
-// Column norms of one problem of a batch: pass 1 work item = (row chunk,
-// group of four columns); pass 2 work item = one column.
 // Column-norm task of one problem.  Pass 1: a workgroup sums the squares of
 // 256 columns over one chunk of `rows` rows (elems = chunks x column blocks x
 // ITEM_BLOCK items); pass 2: one item per column sums the chunks in order.
@@ -163,6 +179,7 @@ struct PlanOptions {
     int32_t max_depth = -1;        // -1: default for the mode
     int32_t tile_cfg = 0;          // split-BF16 leaf tile: 0 = 128 x 128, 1 = 256 x 128, 2, 3 = 256 x 256
     double spread_tau = 4096.0;    // <= 0: no fallback
+    int64_t split_target = 2048;   // split K when a launch has fewer tiles (0: never)
 };
 
 struct PlanStats {
@@ -184,6 +201,7 @@ struct Plan {
     std::vector<Pack8Desc> pack8;                   // FP8 operand quantisation
     std::vector<LeafDesc> leaves;                   // LPT order (longest first)
     std::vector<LeafDesc> fb_leaves;                // SYRK leaves under the spread check
+    std::vector<ReduceDesc> reduce;                 // split leaves: partial sums
     std::vector<std::vector<CombineDesc>> combine;  // [height-1] bottom-up
     std::vector<NodeDesc> nodes;                    // AtA nodes (flags)
     std::vector<ColDesc> col1, col2;                // column-norm passes (when fallback)
@@ -211,6 +229,14 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
                          std::vector<ColDesc>& col1, std::vector<ColDesc>& col2,
                          int64_t* partial_total);
 
+// Split-K: when a leaf launch (the mode's, or the FP64 fallback's) has fewer
+// than `target` tiles, leaves with K >= 2 * min_chunk are cut into K chunks
+// of at least min_chunk rows (multiples of 256), each chunk's tiles writing
+// partial sums that a reduce pass adds.  Called before finalize_plan; merged
+// batch plans are split once, after merging.
+constexpr int64_t SPLIT_MIN_CHUNK = 8192;
+void split_leaves(Plan& p, int64_t target, int64_t min_chunk = SPLIT_MIN_CHUNK);
+
 // Orders the leaves (longest contraction first) and fills the tile and
 // work-item prefix sums of every phase.
 void finalize_plan(Plan& p);
@@ -218,7 +244,7 @@ void finalize_plan(Plan& p);
 // One plan for a batch of independent problems: every problem's phases are
 // merged (arena offsets, node indices and problem indices shifted) so that
 // each phase is one launch for the whole batch.
-Plan merge_plans(std::vector<Plan>& parts);
+Plan merge_plans(std::vector<Plan>& parts, int64_t split_target = 0);
 
 // Work items of the streaming kernels (pre-sums, packing, combines, column
 // norms) run 256 to a workgroup; every task's first item is a multiple of

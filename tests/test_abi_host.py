@@ -90,3 +90,20 @@ def test_plan_query_rejects_packed_operands_of_4_gib():
     assert info["syrk_leaves"] == 1
     info, _ = ata.ata_plan_query(m // 2, 1024, ata.F32_BF16X3, 2048, 0)
     assert info["syrk_leaves"] == 1
+
+
+def test_plan_splits_k_only_for_long_contractions_with_few_tiles():
+    # tall-skinny: few output tiles, K = 262144 -> every leaf is split
+    info, leaves = ata.ata_plan_query(262144, 4096, ata.F32, 1024, 1)
+    assert all(L["ksplit"] >= 2 for L in leaves if L["contraction"] >= 16384)
+    assert all(L["contraction"] // L["ksplit"] >= 8192 - 256 for L in leaves)
+    # splitting changes neither the leaves nor the multiplication count
+    assert info["multiplications"] == sum(
+        L["rows"] * (L["rows"] + 1) // 2 * L["contraction"] if L["kind"] == 0
+        else L["rows"] * L["cols"] * L["contraction"] for L in leaves)
+    # square 8192: thousands of tiles already -> no split
+    _, leaves = ata.ata_plan_query(8192, 8192, ata.F32, 1024, 2)
+    assert all(L["ksplit"] == 1 for L in leaves)
+    # short contractions are never split
+    _, leaves = ata.ata_plan_query(8000, 300, ata.F32, 1024, 0)
+    assert all(L["ksplit"] == 1 for L in leaves)
