@@ -260,10 +260,17 @@ def _mode_of(A, dtype):
 _DEFAULT = {}
 
 
+TUNE_TABLE = os.path.join(HERE, "tune_table.json")
+
+
 def default_handle(device_index: int) -> Handle:
-    """One long-lived handle per device (keeps its plan cache and workspace)."""
+    """One long-lived handle per device (keeps its plan cache and workspace),
+    with the packaged autotune table loaded when it exists."""
     if device_index not in _DEFAULT:
-        _DEFAULT[device_index] = Handle()
+        h = Handle()
+        if os.path.exists(TUNE_TABLE):
+            h.tune_load(TUNE_TABLE)
+        _DEFAULT[device_index] = h
     return _DEFAULT[device_index]
 
 
