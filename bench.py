@@ -186,6 +186,12 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
     h = make_handle(ata, args)
     h.set("batch_persistent", args.batch_persistent)
     dt = MODES[mode]
+    tuned = None
+    if not args.no_batch_autotune and not args.leaf_cutoff and args.max_depth < 0:
+        t0 = time.perf_counter()
+        tuned = ata.ata_autotune_batched(h.h, *arrs[:4], dt, arrs[4], sp)
+        print(f"[bench] {mode}: batch autotune {tuned} in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
 
     def timed(fn, steps):
         for _ in range(args.warmup):
@@ -229,6 +235,7 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
                            "value": round(work / (ms_sep * 1e-3) / 1e12, 3)},
         "plan": {"problems": len(As), "multiplications": rep["multiplications"],
                  "leaf_launch": "persistent" if args.batch_persistent else "one workgroup per tile",
+                 "batch_autotune": tuned,
                  "leaves": rep["syrk_leaves"] + rep["gemm_leaves"],
                  "strassen_nodes": rep["strassen_nodes"], "launches_per_step": rep["kernel_launches"],
                  "workspace_bytes": rep["workspace_bytes"]},
@@ -330,6 +337,8 @@ def main() -> int:
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table loaded into the handle")
     ap.add_argument("--no-tune-table", action="store_true")
     ap.add_argument("--tune-save", default="", help="with --autotune: merge the choices into this table")
+    ap.add_argument("--no-batch-autotune", action="store_true",
+                    help="batched workload: skip the (untimed) batch autotuner")
     ap.add_argument("--batch-persistent", type=int, default=0,
                     help="batched leaf launch: 1 = persistent grid with per-XCD queues, 0 = one workgroup per tile")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -109,7 +109,13 @@ typedef enum {
        rows are cut into K chunks of at least 8192 rows whose partial sums a
        reduce pass adds in chunk order, in FP64, rounding once (default 2048;
        0 = never split).  Tall-skinny A gets enough tiles to fill the GPU. */
-    ATA_OPT_SPLIT_TARGET = 12
+    ATA_OPT_SPLIT_TARGET = 12,
+    /* ata_gram_batched: 1 = each member takes the per-shape autotune table
+       entry of its own shape bucket; 0 (default) = members use the handle's
+       options, else the batch autotuner's choice for the batch signature
+       (ata_autotune_batched), else the defaults.  Per-shape choices are
+       timed one problem at a time and need not suit a merged launch. */
+    ATA_OPT_BATCH_USE_TABLE = 13
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */
@@ -222,6 +228,19 @@ typedef struct {
 ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n,
                           int64_t lda, ata_dtype_t dtype, void* C_packed,
                           void* stream, ata_tune_entry_t* best);
+
+/* Batch autotuner: times ata_gram_batched on the given batch (A read, C
+   overwritten) for candidate leaf cutoffs (128 .. 4096), Strassen depth caps
+   (0 up to the smaller of 2 and the dtype's default) and, for
+   ATA_F32_BF16X3, leaf tiles, and keeps the fastest for the batch's
+   signature (dtype, and m, n, lda of every member) in the handle; later
+   ata_gram_batched calls with that signature and default leaf cutoff / depth
+   options use it.  Every candidate builds and caches its plan and graph.
+   Synchronises `stream`.  Batch choices are not saved by ata_tune_save. */
+ata_status_t ata_autotune_batched(ata_handle_t h, int64_t batch, const void* const* A,
+                                  const int64_t* m, const int64_t* n, const int64_t* lda,
+                                  ata_dtype_t dtype, void* const* C_packed, void* stream,
+                                  ata_tune_entry_t* best);
 
 /* Save / load the handle's tune table as JSON (one object per entry with the
    device architecture, dtype, buckets and choice).  Loading merges entries of

@@ -26,7 +26,7 @@ DTYPE_NAMES = {"f64": F64, "f32": F32, "bf16x3": F32_BF16X3, "fp8": F32_FP8E4M3}
 OPT_LEAF_CUTOFF, OPT_MAX_STRASSEN_DEPTH, OPT_SPREAD_TAU = 0, 1, 2
 OPT_RESIDUAL, OPT_WORKSPACE_LIMIT, OPT_RESIDUAL_SEED, OPT_PROFILE = 3, 4, 5, 6
 OPT_LEAF_TILE, OPT_BATCH_GRAPH, OPT_BATCH_PERSISTENT = 7, 8, 9
-OPT_XCD_CHUNK, OPT_TILE_BAND, OPT_SPLIT_TARGET = 10, 11, 12
+OPT_XCD_CHUNK, OPT_TILE_BAND, OPT_SPLIT_TARGET, OPT_BATCH_USE_TABLE = 10, 11, 12, 13
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -91,12 +91,13 @@ def lib() -> ctypes.CDLL:
     L.ata_residual.argtypes = [vp, vp, i64, i64, i64, st, vp, ctypes.c_uint64,
                                ctypes.POINTER(ctypes.c_double), vp]
     L.ata_autotune.argtypes = [vp, vp, i64, i64, i64, st, vp, vp, ctypes.POINTER(TuneEntry)]
+    L.ata_autotune_batched.argtypes = [vp, i64, vp, vp, vp, vp, st, vp, vp, ctypes.POINTER(TuneEntry)]
     L.ata_tune_save.argtypes = [vp, ctypes.c_char_p]
     L.ata_tune_load.argtypes = [vp, ctypes.c_char_p]
     L.ata_status_string.argtypes = [st]
     L.ata_status_string.restype = ctypes.c_char_p
     for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_batched", "ata_set_option",
-                 "ata_get_report", "ata_plan_query", "ata_residual", "ata_autotune",
+                 "ata_get_report", "ata_plan_query", "ata_residual", "ata_autotune", "ata_autotune_batched",
                  "ata_tune_save", "ata_tune_load"):
         getattr(L, name).restype = st
     _LIB = L
@@ -182,6 +183,16 @@ def ata_autotune(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, s
     return {k: getattr(e, k) for k, _ in TuneEntry._fields_}
 
 
+def ata_autotune_batched(h: int, A_ptrs, ms, ns, ldas, dtype: int, C_ptrs, stream: int = 0) -> dict:
+    arrs = (A_ptrs, ms, ns, ldas, C_ptrs)
+    if not isinstance(A_ptrs, ctypes.Array):
+        arrs = batch_arrays(A_ptrs, ms, ns, ldas, C_ptrs)
+    e = TuneEntry()
+    _check(lib().ata_autotune_batched(h, len(arrs[0]), arrs[0], arrs[1], arrs[2], arrs[3], dtype, arrs[4],
+                                      stream, ctypes.byref(e)), "ata_autotune_batched")
+    return {k: getattr(e, k) for k, _ in TuneEntry._fields_}
+
+
 def ata_tune_save(h: int, path: str) -> None:
     _check(lib().ata_tune_save(h, path.encode()), "ata_tune_save")
 
@@ -210,7 +221,7 @@ class Handle:
                "profile": OPT_PROFILE, "leaf_tile": OPT_LEAF_TILE,
                "batch_graph": OPT_BATCH_GRAPH, "batch_persistent": OPT_BATCH_PERSISTENT,
                "xcd_chunk": OPT_XCD_CHUNK, "tile_band": OPT_TILE_BAND,
-               "split_target": OPT_SPLIT_TARGET}[name]
+               "split_target": OPT_SPLIT_TARGET, "batch_use_table": OPT_BATCH_USE_TABLE}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

@@ -80,6 +80,19 @@ struct BatchKey {
     }
 };
 
+std::vector<int64_t> batch_signature(int32_t mode, int64_t batch, const int64_t* m, const int64_t* n,
+                                     const int64_t* lda) {
+    std::vector<int64_t> sig;
+    sig.reserve(1 + 3 * (size_t)batch);
+    sig.push_back(mode);
+    for (int64_t i = 0; i < batch; ++i) {
+        sig.push_back(m[i]);
+        sig.push_back(n[i]);
+        sig.push_back(lda[i]);
+    }
+    return sig;
+}
+
 // A merged batch plan with its own device buffers and captured graph.
 struct BatchEntry {
     std::unique_ptr<DevicePlan> dp;
@@ -138,6 +151,11 @@ struct ata_ctx {
     std::string arch;
     // batches: merged plans, captured graphs, internal capture stream
     std::map<BatchKey, std::unique_ptr<BatchEntry>> batches;
+    // batch autotuning: one (cutoff, depth, tile) per batch signature (dtype,
+    // then m, n, lda of every member); per-shape table entries apply inside
+    // batches only when batch_use_table is set
+    std::map<std::vector<int64_t>, ata_tune_entry_t> batch_tune;
+    bool batch_use_table = false;
     hipStream_t batch_stream = nullptr;
     hipEvent_t batch_in = nullptr;
     bool batch_graph = true;
@@ -239,11 +257,11 @@ bool valid_dtype(int d) { return d >= ATA_F64 && d <= ATA_F32_FP8E4M3; }
 // Leaf cutoff, depth cap and tile of one problem: explicit options win, then
 // the autotune table, then the planner's defaults.
 void choose(const ata_ctx* h, int32_t mode, int64_t m, int64_t n, int64_t& b, int32_t& depth,
-            int32_t& tile) {
+            int32_t& tile, bool use_table = true) {
     b = h->popt.leaf_cutoff;
     depth = h->popt.max_depth;
     tile = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
-    if (b <= 0 && depth < 0) {
+    if (use_table && b <= 0 && depth < 0) {
         auto it = h->tune.find(TuneKey{mode, bucket(m), bucket(n)});
         if (it != h->tune.end()) {
             b = it->second.leaf_cutoff;
@@ -382,6 +400,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
         case ATA_OPT_TILE_BAND:
             if (value < 1 || value > 4096) return ATA_ERR_INVALID_VALUE;
             h->band = (int)value;
+            return ATA_OK;
+        case ATA_OPT_BATCH_USE_TABLE:
+            h->batch_use_table = value != 0.0;
             return ATA_OK;
         case ATA_OPT_SPLIT_TARGET:
             if (value < 0 || value > 1e9) return ATA_ERR_INVALID_VALUE;
@@ -692,15 +713,28 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
     const int32_t mode = (int32_t)dtype;
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0;
-    // the batch runs one leaf kernel, so one tile shape: the handle's
-    const int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
+    // the batch runs one leaf kernel, so one tile shape: the handle's, or the
+    // batch autotuner's for this signature when the options are defaults
+    int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
+    const ata_tune_entry_t* bt = nullptr;
+    if (h->popt.leaf_cutoff <= 0 && h->popt.max_depth < 0 && !h->batch_tune.empty()) {
+        auto f = h->batch_tune.find(batch_signature(mode, batch, m, n, lda));
+        if (f != h->batch_tune.end()) {
+            bt = &f->second;
+            if (mode == MODE_BF16X3) tile_cfg = bt->leaf_tile;
+        }
+    }
     std::vector<int64_t> bs((size_t)batch);
     std::vector<int32_t> ds((size_t)batch);
     BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, h->split_target, {}};
     key.shapes.reserve(5 * (size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
         int32_t tile_i;
-        choose(h, mode, m[i], n[i], bs[(size_t)i], ds[(size_t)i], tile_i);
+        choose(h, mode, m[i], n[i], bs[(size_t)i], ds[(size_t)i], tile_i, h->batch_use_table);
+        if (bt) {
+            bs[(size_t)i] = bt->leaf_cutoff;
+            ds[(size_t)i] = bt->max_depth;
+        }
         key.shapes.push_back(m[i]);
         key.shapes.push_back(n[i]);
         key.shapes.push_back(lda[i]);
@@ -909,6 +943,58 @@ ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n, i
     (void)hipEventDestroy(e1);
     if (rs != ATA_OK) return rs;
     h->tune[TuneKey{mode, bucket(m), bucket(n)}] = top;
+    if (best) *best = top;
+    return ATA_OK;
+}
+
+ata_status_t ata_autotune_batched(ata_handle_t h, int64_t batch, const void* const* A, const int64_t* m,
+                                  const int64_t* n, const int64_t* lda, ata_dtype_t dtype,
+                                  void* const* C_packed, void* stream, ata_tune_entry_t* best) {
+    if (!h || batch <= 0 || !m || !n || !lda || !valid_dtype(dtype)) return ATA_ERR_INVALID_VALUE;
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    const int32_t mode = (int32_t)dtype;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const PlanOptions saved = h->popt;
+    const bool saved_profile = h->profile;
+    h->profile = false;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return ATA_ERR_HIP;
+    ata_tune_entry_t top{0, 0, 0, 1e30};
+    const int ntiles = mode == MODE_BF16X3 ? 4 : 1;
+    const int32_t dmax = std::min<int32_t>(default_max_depth(mode), 2);
+    ata_status_t rs = ATA_OK;
+    for (int64_t b = 128; b <= 4096 && rs == ATA_OK; b *= 2) {
+        for (int32_t d = 0; d <= dmax && rs == ATA_OK; ++d) {
+            for (int tl = 0; tl < ntiles; ++tl) {
+                h->popt.leaf_cutoff = b;
+                h->popt.max_depth = d;
+                h->popt.tile_cfg = tl;
+                rs = ata_gram_batched(h, batch, A, m, n, lda, dtype, C_packed, stream);   // plan + graph
+                if (rs == ATA_ERR_NOT_SUPPORTED || rs == ATA_ERR_OUT_OF_MEMORY) {
+                    rs = ATA_OK;
+                    continue;
+                }
+                if (rs != ATA_OK) break;
+                const int reps = 3;
+                if (hipEventRecord(e0, st) != hipSuccess) { rs = ATA_ERR_HIP; break; }
+                for (int r = 0; r < reps && rs == ATA_OK; ++r)
+                    rs = ata_gram_batched(h, batch, A, m, n, lda, dtype, C_packed, stream);
+                if (rs != ATA_OK) break;
+                float ms = 0.f;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rs = ATA_ERR_HIP; break; }
+                const double per = ms / reps;
+                if (per < top.ms) top = ata_tune_entry_t{b, d, tl, per};
+            }
+        }
+    }
+    h->popt = saved;
+    h->profile = saved_profile;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs != ATA_OK) return rs;
+    if (top.leaf_cutoff == 0) return ATA_ERR_NOT_SUPPORTED;
+    h->batch_tune[batch_signature(mode, batch, m, n, lda)] = top;
     if (best) *best = top;
     return ATA_OK;
 }

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 from oracle import plain
-from paper_2110_13042_amd import ata
+from paper_2110_13042_amd import ata, workloads
 from gpu_helpers import device, full_error, run_gram
 
 pytestmark = pytest.mark.gpu
@@ -55,5 +55,29 @@ def test_autotune_choice_used_and_correct(tmp_path, mode):
             assert h2.report()["leaf_cutoff"] == best["leaf_cutoff"]
         finally:
             h2.close()
+    finally:
+        h.close()
+
+
+def test_batch_autotune_choice_used_and_correct():
+    dev = device()
+    rng, ms, ns = workloads.batch_shapes(24, 83, (64, 3000), (16, 900))
+    mats = [rng.uniform(-1, 1, (int(m), int(n))).astype(np.float32) for m, n in zip(ms, ns)]
+    As = [torch.from_numpy(M).to(dev) for M in mats]
+    Cs = [torch.empty(M.shape[1] * (M.shape[1] + 1) // 2, dtype=torch.float32, device=dev) for M in mats]
+    h = ata.Handle()
+    try:
+        args = ([A.data_ptr() for A in As], [M.shape[0] for M in mats], [M.shape[1] for M in mats],
+                [M.shape[1] for M in mats])
+        _say("case: batch autotune bf16x3, 24 problems")
+        best = ata.ata_autotune_batched(h.h, *args, ata.F32_BF16X3, [C.data_ptr() for C in Cs], 0)
+        _say("  best", best)
+        assert best["leaf_cutoff"] >= 128 and best["ms"] > 0
+        out = ata.gram_batched(As, ata.F32_BF16X3, handle=h)
+        torch.cuda.synchronize()
+        assert h.report()["leaf_cutoff"] == best["leaf_cutoff"] or \
+            all(M.shape[1] <= best["leaf_cutoff"] for M in mats)
+        for M, C in zip(mats, out):
+            assert full_error(C.double().cpu().numpy(), plain.gram_packed(M)) <= 2e-5
     finally:
         h.close()
