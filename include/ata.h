@@ -196,6 +196,43 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch,
                               ata_dtype_t dtype, void* const* C_packed,
                               void* stream);
 
+/* C_packed = alpha * lower(A^T A) + beta * C_packed (the BLAS ?syrk form of
+   the problem statement of Sec. 3.1; ata_gram is alpha = 1, beta = 0).
+   beta = 0: C is not read.  Otherwise the product goes to a workspace
+   buffer of n(n+1)/2 elements first and a final pass combines it with C.
+   Non-finite alpha or beta: ATA_ERR_INVALID_VALUE.  Other errors as for
+   ata_gram. */
+ata_status_t ata_gram_scaled(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
+                             ata_dtype_t dtype, double alpha, double beta, void* C_packed,
+                             void* stream);
+
+/* C_packed = lower(A A^T) for row-major A (m x n, lda >= max(1, n)); C is
+   m x m packed lower (m(m+1)/2 elements).  A is transposed once into a
+   workspace buffer (m n elements), then the AtA plan runs on the n x m
+   transpose.  n = 0 zero-fills C; m = 0 is a no-op.  Errors as for
+   ata_gram. */
+ata_status_t ata_gram_aat(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
+                          ata_dtype_t dtype, void* C_packed, void* stream);
+
+/* Full symmetric n x n matrix C_full (row-major, row stride ldf >= max(1, n))
+   from packed lower storage: C_full[i][j] = C_packed[max(i,j)(max(i,j)+1)/2 +
+   min(i,j)].  The two buffers must not overlap. */
+ata_status_t ata_unpack(ata_handle_t h, const void* C_packed, int64_t n, ata_dtype_t dtype,
+                        void* C_full, int64_t ldf, void* stream);
+
+/* General product C = A^T B by the Strassen recursion alone (the step AtA
+   applies to its off-diagonal blocks, Sec. 3.1, Eq. "Cij"; Strassen's seven
+   products on the 2 x 2 blocks of A^T and B).  A is m x n (row stride lda >=
+   max(1, n)), B is m x k (ldb >= max(1, k)), C is n x k dense row-major
+   (ldc >= max(1, k)); all device pointers of the dtype's element type.  C is
+   overwritten; m = 0 zero-fills it; n = 0 or k = 0 is a no-op.  The handle's
+   leaf cutoff, depth cap, tile and split options apply (the autotune table is
+   consulted with the bucket of max(n, k)); there is no spread check.  Errors
+   as for ata_gram; C must not overlap A or B. */
+ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m, int64_t n,
+                         int64_t k, int64_t lda, int64_t ldb, ata_dtype_t dtype, void* C,
+                         int64_t ldc, void* stream);
+
 /* Freivalds probe of a given product (the check ATA_OPT_RESIDUAL runs after
    ata_gram): *result = ||C x - A^T (A x)||_2 / (||A||_F^2 ||x||_2) with
    x_j = +1 if the top bit of SplitMix64 output j of stream `seed` is 0, else

@@ -130,3 +130,34 @@ int oracle_colnorms(const void* A, int is_f32, int64_t m, int64_t n, int64_t lda
     }
     return 0;
 }
+
+/* General product of the Strassen step (Sec. 3.1, Eq. "Cij": the off-diagonal
+ * block of AtA is a product X^T Y of two column blocks), written out plainly:
+ *
+ *     C[i][j] = sum_{r = 0}^{m-1} A[r][i] * B[r][j],   0 <= i < n, 0 <= j < k,
+ *
+ * ascending r, FP64, no fused multiply-add.  A is m x n (lda), B is m x k
+ * (ldb), both of the same element type; C is n x k dense row-major (ldc).
+ * Threads split the rows i of C; each entry's sum keeps the ascending-r
+ * order, so the bits do not depend on the thread count. */
+int oracle_gemm_tn(const void* A, const void* B, int is_f32, int64_t m, int64_t n, int64_t k,
+                   int64_t lda, int64_t ldb, double* C, int64_t ldc, int nthreads) {
+    if (m < 0 || n < 0 || k < 0 || lda < n || ldb < k || ldc < k || (n > 0 && k > 0 && !C)) return 1;
+    set_threads(nthreads);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < k; ++j) C[i * ldc + j] = 0.0;
+#pragma omp parallel
+    {
+        const int nt = omp_get_num_threads();
+        const int t = omp_get_thread_num();
+        const int64_t i0 = n * t / nt, i1 = n * (t + 1) / nt;
+        for (int64_t r = 0; r < m; ++r) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const double ari = elem(A, is_f32, r * lda + i);
+                double* Ci = C + i * ldc;
+                for (int64_t j = 0; j < k; ++j) Ci[j] += ari * elem(B, is_f32, r * ldb + j);
+            }
+        }
+    }
+    return 0;
+}

@@ -5,7 +5,8 @@ ascending r, FP64, no fused multiply-add (Sec. 3.1, Eq. "Cij").  Pinned in
 ``tests/test_oracle_plain.py`` by hand-computed tiny cases, closed forms
 (identity, orthonormal columns, rank one, all ones), symmetry / PSD /
 diagonal invariants, the Freivalds identity x^T C x = ||A x||^2, and an
-independent library product (numpy float64 matmul).
+independent library product (numpy float64 matmul).  ``gemm_tn`` is the
+plain general product A^T B of the Strassen step, pinned the same way.
 """
 import ctypes
 import os
@@ -29,8 +30,9 @@ def _lib():
         lib.oracle_gram_cols.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, dp, ctypes.c_int]
         lib.oracle_colnorms.argtypes = [vp, ctypes.c_int, i64, i64, i64, dp, ctypes.c_int]
         lib.oracle_threads_used.argtypes = [ctypes.c_int]
+        lib.oracle_gemm_tn.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, i64, i64, dp, i64, ctypes.c_int]
         for f in (lib.oracle_gram_plain, lib.oracle_gram_cols, lib.oracle_colnorms,
-                  lib.oracle_threads_used):
+                  lib.oracle_threads_used, lib.oracle_gemm_tn):
             f.restype = ctypes.c_int
         _LIB = lib
     return _LIB
@@ -46,6 +48,21 @@ def _as_input(A):
         A = np.ascontiguousarray(A)
     lda = A.strides[0] // A.itemsize if A.shape[0] > 1 else A.shape[1]
     return A, int(A.dtype == np.float32), A.shape[0], A.shape[1], max(lda, A.shape[1])
+
+
+def gemm_tn(A, B, nthreads: int = 0) -> np.ndarray:
+    """Dense C = A^T B (n x k, FP64), A m x n and B m x k of one element type."""
+    A, f32, m, n, lda = _as_input(A)
+    B = np.asarray(B, dtype=A.dtype)
+    B, f32b, mb, k, ldb = _as_input(B)
+    if mb != m or f32b != f32:
+        raise ValueError("A and B need the same rows and element type")
+    C = np.empty((n, k), dtype=np.float64)
+    rc = _lib().oracle_gemm_tn(A.ctypes.data, B.ctypes.data, f32, m, n, k, lda, ldb, C.ctypes.data,
+                               max(k, 1), nthreads)
+    if rc:
+        raise ValueError("oracle_gemm_tn rejected its arguments")
+    return C
 
 
 def threads_used(nthreads: int = 0) -> int:

@@ -91,6 +91,10 @@ def lib() -> ctypes.CDLL:
     L.ata_residual.argtypes = [vp, vp, i64, i64, i64, st, vp, ctypes.c_uint64,
                                ctypes.POINTER(ctypes.c_double), vp]
     L.ata_autotune.argtypes = [vp, vp, i64, i64, i64, st, vp, vp, ctypes.POINTER(TuneEntry)]
+    L.ata_gemm_tn.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, st, vp, i64, vp]
+    L.ata_gram_scaled.argtypes = [vp, vp, i64, i64, i64, st, ctypes.c_double, ctypes.c_double, vp, vp]
+    L.ata_gram_aat.argtypes = [vp, vp, i64, i64, i64, st, vp, vp]
+    L.ata_unpack.argtypes = [vp, vp, i64, st, vp, i64, vp]
     L.ata_autotune_batched.argtypes = [vp, i64, vp, vp, vp, vp, st, vp, vp, ctypes.POINTER(TuneEntry)]
     L.ata_tune_save.argtypes = [vp, ctypes.c_char_p]
     L.ata_tune_load.argtypes = [vp, ctypes.c_char_p]
@@ -98,6 +102,7 @@ def lib() -> ctypes.CDLL:
     L.ata_status_string.restype = ctypes.c_char_p
     for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_batched", "ata_set_option",
                  "ata_get_report", "ata_plan_query", "ata_residual", "ata_autotune", "ata_autotune_batched",
+                 "ata_gemm_tn", "ata_gram_scaled", "ata_gram_aat", "ata_unpack",
                  "ata_tune_save", "ata_tune_load"):
         getattr(L, name).restype = st
     _LIB = L
@@ -144,6 +149,24 @@ def ata_gram_batched(h: int, A_ptrs, ms, ns, ldas, dtype: int, C_ptrs, stream: i
         arrs = batch_arrays(A_ptrs, ms, ns, ldas, C_ptrs)
     _check(lib().ata_gram_batched(h, len(arrs[0]), arrs[0], arrs[1], arrs[2], arrs[3], dtype, arrs[4],
                                   stream), "ata_gram_batched")
+
+
+def ata_gemm_tn(h: int, A: int, B: int, m: int, n: int, k: int, lda: int, ldb: int, dtype: int,
+                C: int, ldc: int, stream: int = 0) -> None:
+    _check(lib().ata_gemm_tn(h, A, B, m, n, k, lda, ldb, dtype, C, ldc, stream), "ata_gemm_tn")
+
+
+def ata_gram_scaled(h: int, A: int, m: int, n: int, lda: int, dtype: int, alpha: float, beta: float,
+                    C: int, stream: int = 0) -> None:
+    _check(lib().ata_gram_scaled(h, A, m, n, lda, dtype, alpha, beta, C, stream), "ata_gram_scaled")
+
+
+def ata_gram_aat(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, stream: int = 0) -> None:
+    _check(lib().ata_gram_aat(h, A, m, n, lda, dtype, C, stream), "ata_gram_aat")
+
+
+def ata_unpack(h: int, Cp: int, n: int, dtype: int, F: int, ldf: int, stream: int = 0) -> None:
+    _check(lib().ata_unpack(h, Cp, n, dtype, F, ldf, stream), "ata_unpack")
 
 
 def ata_set_option(h: int, key: int, value: float) -> None:
@@ -283,6 +306,30 @@ def default_handle(device_index: int) -> Handle:
             h.tune_load(TUNE_TABLE)
         _DEFAULT[device_index] = h
     return _DEFAULT[device_index]
+
+
+def gemm_tn(A, B, dtype=None, handle: Handle | None = None, out=None):
+    """Dense C = A^T B (n x k) of 2-D CUDA tensors with contiguous rows."""
+    import torch
+    mode = _mode_of(A, dtype)
+    want = torch.float64 if mode == F64 else torch.float32
+    for X in (A, B):
+        if X.dim() != 2 or not X.is_cuda or X.dtype != want:
+            raise ValueError(f"need 2-D {want} tensors on a GPU")
+        if X.shape[0] > 1 and X.shape[1] > 0 and X.stride(1) != 1:
+            raise ValueError("rows must be contiguous")
+    m, n = A.shape
+    if B.shape[0] != m:
+        raise ValueError("A and B need the same number of rows")
+    k = B.shape[1]
+    C = out if out is not None else torch.empty((n, k), dtype=want, device=A.device)
+    h = handle or default_handle(A.device.index or 0)
+    lda = max(A.stride(0) if m > 1 else n, n, 1)
+    ldb = max(B.stride(0) if m > 1 else k, k, 1)
+    ldc = max(C.stride(0) if n > 1 else k, k, 1)
+    stream = torch.cuda.current_stream(A.device).cuda_stream
+    ata_gemm_tn(h.h, A.data_ptr(), B.data_ptr(), m, n, k, lda, ldb, mode, C.data_ptr(), ldc, stream)
+    return C
 
 
 def gram_batched(As, dtype=None, handle: Handle | None = None, outs=None):

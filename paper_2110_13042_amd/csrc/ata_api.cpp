@@ -80,6 +80,18 @@ struct BatchKey {
     }
 };
 
+// Plan-cache key of a general product C = A^T B.
+struct GemmKey {
+    int32_t mode;
+    int64_t m, n, k, lda, ldb, ldc, b;
+    int32_t depth, tile_cfg;
+    int64_t split;
+    bool operator<(const GemmKey& o) const {
+        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split) <
+               std::tie(o.mode, o.m, o.n, o.k, o.lda, o.ldb, o.ldc, o.b, o.depth, o.tile_cfg, o.split);
+    }
+};
+
 std::vector<int64_t> batch_signature(int32_t mode, int64_t batch, const int64_t* m, const int64_t* n,
                                      const int64_t* lda) {
     std::vector<int64_t> sig;
@@ -151,6 +163,11 @@ struct ata_ctx {
     std::string arch;
     // batches: merged plans, captured graphs, internal capture stream
     std::map<BatchKey, std::unique_ptr<BatchEntry>> batches;
+    std::map<GemmKey, std::unique_ptr<DevicePlan>> gemm_plans;
+    // staging for the BLAS-style conveniences (a scaled product's result, a
+    // transposed input)
+    void* tmp = nullptr;
+    size_t tmp_cap = 0;
     // batch autotuning: one (cutoff, depth, tile) per batch signature (dtype,
     // then m, n, lda of every member); per-shape table entries apply inside
     // batches only when batch_use_table is set
@@ -355,6 +372,7 @@ ata_status_t ata_destroy(ata_handle_t h) {
     clear_events(h);
     if (h->arena) (void)hipFree(h->arena);
     if (h->aux) (void)hipFree(h->aux);
+    if (h->tmp) (void)hipFree(h->tmp);
     delete h;
     return ATA_OK;
 }
@@ -622,6 +640,172 @@ ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n, i
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(buf);
     return e == hipSuccess ? ATA_OK : ATA_ERR_HIP;
+}
+
+ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m, int64_t n, int64_t k,
+                         int64_t lda, int64_t ldb, ata_dtype_t dtype, void* C, int64_t ldc, void* stream) {
+    if (!h || !valid_dtype(dtype) || m < 0 || n < 0 || k < 0 || lda < std::max<int64_t>(1, n) ||
+        ldb < std::max<int64_t>(1, k) || ldc < std::max<int64_t>(1, k))
+        return ATA_ERR_INVALID_VALUE;
+    if (n > 0 && k > 0 && !C) return ATA_ERR_INVALID_VALUE;
+    if (n > 0 && k > 0 && m > 0 && (!A || !B)) return ATA_ERR_INVALID_VALUE;
+    const size_t es = dtype == ATA_F64 ? 8 : 4;
+    if (n > 0 && k > 0) {
+        const uintptr_t c0 = (uintptr_t)C, c1 = c0 + (size_t)((n - 1) * ldc + k) * es;
+        if (m > 0) {
+            const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (size_t)((m - 1) * lda + n) * es;
+            const uintptr_t b0 = (uintptr_t)B, b1 = b0 + (size_t)((m - 1) * ldb + k) * es;
+            if ((a0 < c1 && c0 < a1) || (b0 < c1 && c0 < b1)) return ATA_ERR_INVALID_VALUE;
+        }
+    }
+    h->report = ata_report_t{};
+    h->report.flagged_nodes = -1;
+    h->report.residual = -1.0;
+    h->pending_flags = h->pending_residual = false;
+    if (n == 0 || k == 0) return ATA_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    const int32_t mode = (int32_t)dtype;
+    int64_t b;
+    int32_t depth, tile_cfg;
+    choose(h, mode, m, std::max(n, k), b, depth, tile_cfg);
+    const GemmKey key{mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, h->split_target};
+    auto it = h->gemm_plans.find(key);
+    if (it == h->gemm_plans.end()) {
+        auto dp = std::make_unique<DevicePlan>();
+        PlanOptions o;
+        o.leaf_cutoff = b;
+        o.max_depth = depth;
+        o.spread_tau = 0.0;
+        o.tile_cfg = tile_cfg;
+        o.split_target = h->split_target;
+        try {
+            dp->plan = make_gemm_plan(mode, m, n, k, lda, ldb, ldc, o);
+        } catch (const std::invalid_argument&) {
+            return ATA_ERR_INVALID_VALUE;
+        } catch (const std::length_error&) {
+            return ATA_ERR_NOT_SUPPORTED;
+        } catch (const std::exception&) {
+            return ATA_ERR_INTERNAL;
+        }
+        const ata_status_t s = upload_plan(*dp);
+        if (s != ATA_OK) return s;
+        it = h->gemm_plans.emplace(key, std::move(dp)).first;
+    }
+    DevicePlan& dp = *it->second;
+    const Plan& p = dp.plan;
+    const size_t arena_bytes = (size_t)p.arena_elems * (size_t)p.elem_bytes();
+    if (h->ws_limit > 0 && (int64_t)arena_bytes > h->ws_limit) return ATA_ERR_OUT_OF_MEMORY;
+    const size_t old_cap = h->arena_cap;
+    ata_status_t s = ensure(h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
+    if (s != ATA_OK) return s;
+    if (h->arena_cap != old_cap) ++h->arena_gen;
+    s = ensure(h->aux, h->aux_cap, 256);
+    if (s != ATA_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint8_t* flags = static_cast<const uint8_t*>(h->aux);     // no predicates in this plan
+    hipError_t e = hipSuccess;
+    hipEvent_t* ev = nullptr;
+    if (take_events(h, ev) != ATA_OK) return ATA_ERR_HIP;
+    auto mark = [&](int i) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    mark(1);
+    for (size_t l = 0; e == hipSuccess && l < p.presum.size(); ++l) {
+        const auto& lv = p.presum[l];
+        e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems, A,
+                          h->arena, flags, st, nullptr, B);
+    }
+    if (e == hipSuccess && !p.pack.empty())
+        e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems, A,
+                        h->arena, flags, st, nullptr, B);
+    if (e == hipSuccess && !p.pack8.empty())
+        e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems, A,
+                          h->arena, flags, st, nullptr, B);
+    mark(2);
+    if (e == hipSuccess)
+        e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C, h->arena,
+                          flags, h->chunk, h->band, st, nullptr, B);
+    if (e == hipSuccess && !p.reduce.empty())
+        e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
+                          C, h->arena, flags, st);
+    mark(3);
+    for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
+        const auto& lv = p.combine[l];
+        e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems, C,
+                           h->arena, flags, st);
+    }
+    mark(4);
+    mark(5);
+    if (e != hipSuccess) return ATA_ERR_HIP;
+    fill_report(h->report, p);
+    return ATA_OK;
+}
+
+ata_status_t ata_gram_scaled(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
+                             ata_dtype_t dtype, double alpha, double beta, void* C_packed, void* stream) {
+    if (!h || !valid_dtype(dtype) || !std::isfinite(alpha) || !std::isfinite(beta)) return ATA_ERR_INVALID_VALUE;
+    if (alpha == 1.0 && beta == 0.0) return ata_gram(h, A, m, n, lda, dtype, C_packed, stream);
+    const int32_t mode = (int32_t)dtype;
+    const int64_t len = n * (n + 1) / 2;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (beta == 0.0) {
+        const ata_status_t s = ata_gram(h, A, m, n, lda, dtype, C_packed, stream);
+        if (s != ATA_OK || n == 0) return s;
+        return launch_axpby(mode, C_packed, C_packed, len, alpha, 0.0, st) == hipSuccess ? ATA_OK : ATA_ERR_HIP;
+    }
+    // validate against C first, so that a bad call leaves C untouched
+    if (m < 0 || n < 0 || lda < std::max<int64_t>(1, n) || (n > 0 && !C_packed) || (n > 0 && m > 0 && !A))
+        return ATA_ERR_INVALID_VALUE;
+    if (n == 0) return ATA_OK;
+    const size_t es = dtype == ATA_F64 ? 8 : 4;
+    if (m > 0) {
+        const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (size_t)((m - 1) * lda + n) * es;
+        const uintptr_t c0 = (uintptr_t)C_packed, c1 = c0 + (size_t)len * es;
+        if (a0 < c1 && c0 < a1) return ATA_ERR_INVALID_VALUE;
+    }
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    ata_status_t s = ensure(h->tmp, h->tmp_cap, (size_t)len * es);
+    if (s != ATA_OK) return s;
+    s = ata_gram(h, A, m, n, lda, dtype, h->tmp, stream);
+    if (s != ATA_OK) return s;
+    return launch_axpby(mode, h->tmp, C_packed, len, alpha, beta, st) == hipSuccess ? ATA_OK : ATA_ERR_HIP;
+}
+
+ata_status_t ata_gram_aat(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
+                          ata_dtype_t dtype, void* C_packed, void* stream) {
+    if (!h || !valid_dtype(dtype) || m < 0 || n < 0 || lda < std::max<int64_t>(1, n)) return ATA_ERR_INVALID_VALUE;
+    if (m > 0 && !C_packed) return ATA_ERR_INVALID_VALUE;
+    if (m > 0 && n > 0 && !A) return ATA_ERR_INVALID_VALUE;
+    const size_t es = dtype == ATA_F64 ? 8 : 4;
+    if (m > 0 && n > 0) {
+        const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (size_t)((m - 1) * lda + n) * es;
+        const uintptr_t c0 = (uintptr_t)C_packed, c1 = c0 + (size_t)(m * (m + 1) / 2) * es;
+        if (a0 < c1 && c0 < a1) return ATA_ERR_INVALID_VALUE;
+    }
+    if (m == 0) return ATA_OK;                     // C is 0 x 0
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    // A A^T = (A^T)^T (A^T): transpose once (one HBM pass, O(m n) against the
+    // O(m^2 n) product), then the AtA plan on the n x m transpose
+    ata_status_t s = ensure(h->tmp, h->tmp_cap, std::max<size_t>((size_t)(m * n) * es, 256));
+    if (s != ATA_OK) return s;
+    if (launch_transpose((int32_t)dtype, A, m, n, lda, h->tmp, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return ATA_ERR_HIP;
+    return ata_gram(h, h->tmp, n, m, m, dtype, C_packed, stream);
+}
+
+ata_status_t ata_unpack(ata_handle_t h, const void* C_packed, int64_t n, ata_dtype_t dtype, void* C_full,
+                        int64_t ldf, void* stream) {
+    if (!h || !valid_dtype(dtype) || n < 0 || ldf < std::max<int64_t>(1, n)) return ATA_ERR_INVALID_VALUE;
+    if (n == 0) return ATA_OK;
+    if (!C_packed || !C_full) return ATA_ERR_INVALID_VALUE;
+    const size_t es = dtype == ATA_F64 ? 8 : 4;
+    const uintptr_t p0 = (uintptr_t)C_packed, p1 = p0 + (size_t)(n * (n + 1) / 2) * es;
+    const uintptr_t f0 = (uintptr_t)C_full, f1 = f0 + (size_t)((n - 1) * ldf + n) * es;
+    if (p0 < f1 && f0 < p1) return ATA_ERR_INVALID_VALUE;
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    return launch_unpack((int32_t)dtype, C_packed, n, C_full, ldf, static_cast<hipStream_t>(stream)) == hipSuccess
+               ? ATA_OK : ATA_ERR_HIP;
 }
 
 namespace {

@@ -41,9 +41,9 @@ __device__ __forceinline__ void split8(const float* v, uint4& hi, uint4& lo) {
 // split-BF16 packed layout.  Work item = one chunk (row-group g, column c):
 // eight rows of the four quadrant values, the five sums formed in FP32, then
 // split.
-__device__ void presum_packed(const PresumDesc& d, int64_t e, const float* A, float* arena) {
+__device__ void presum_packed(const PresumDesc& d, int64_t e, const float* A, const float* B, float* arena) {
     const int64_t g = udiv(e, d.n2), c = e - g * d.n2;
-    const float* V = (d.V.base == BASE_A ? A : arena) + d.V.off;
+    const float* V = (d.V.base == BASE_A ? A : d.V.base == BASE_B ? B : arena) + d.V.off;
     const int64_t ld = d.V.ld, pr = d.V.prows, pc = d.V.pcols;
     const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
     float sum[5][8];
@@ -102,7 +102,8 @@ __device__ __forceinline__ void st4(T* p, const typename Vec4<T>::type& v) {
 template <class T>
 __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* tasks, int ntasks,
                                                             int64_t items, const T* A0, T* arena,
-                                                            const uint8_t* flags, const void* const* Aptrs) {
+                                                            const uint8_t* flags, const void* const* Aptrs,
+                                                            const T* B) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
     const PresumDesc& d = tasks[block_task(tasks, ntasks)];
@@ -112,13 +113,13 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
     const T* A = Aptrs ? static_cast<const T*>(Aptrs[d.prob]) : A0;
     if constexpr (sizeof(T) == 4) {
         if (d.packed_out) {
-            presum_packed(d, e, A, arena);
+            presum_packed(d, e, A, B, arena);
             return;
         }
     }
     const int64_t groups = (d.n2 + 3) >> 2;
     const int64_t r = udiv(e, groups), c0 = (e - r * groups) << 2;
-    const T* V = (d.V.base == BASE_A ? A : arena) + d.V.off;
+    const T* V = (d.V.base == BASE_A ? A : d.V.base == BASE_B ? B : arena) + d.V.off;
     const int64_t ld = d.V.ld, pr = d.V.prows, pc = d.V.pcols;
     const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
     const int64_t plane = m2 * n2;
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
 __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks, int ntasks,
                                                           int64_t items, const float* A0,
                                                           float* arena, const uint8_t* flags,
-                                                          const void* const* Aptrs) {
+                                                          const void* const* Aptrs, const float* B) {
     const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
     if (x >= items) return;
     const PackDesc& d = tasks[block_task(tasks, ntasks)];
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
     const float* A = Aptrs ? static_cast<const float*>(Aptrs[d.prob]) : A0;
     const int64_t g = udiv(e, d.cols), c = e - g * d.cols;
-    const float* src = (d.src.base == BASE_A ? A : arena) + d.src.off;
+    const float* src = (d.src.base == BASE_A ? A : d.src.base == BASE_B ? B : arena) + d.src.off;
     float v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
 __global__ __launch_bounds__(EW_THREADS) void quant8_kernel(const Pack8Desc* tasks, int ntasks,
                                                             const float* A0, float* arena,
                                                             const uint8_t* flags,
-                                                            const void* const* Aptrs) {
+                                                            const void* const* Aptrs, const float* B) {
     __shared__ float wmax[EW_THREADS / 64];
     const int64_t x = blockIdx.x;
     const Pack8Desc& d = tasks[find_task(tasks, ntasks, x)];
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(EW_THREADS) void quant8_kernel(const Pack8Desc* tas
     const int64_t blk = x - d.elem_begin;
     const int64_t nbc = d.cols_p / 128;
     const int64_t bi = blk / nbc, bj = blk - bi * nbc;
-    const float* src = (d.src.base == BASE_A ? A : arena) + d.src.off;
+    const float* src = (d.src.base == BASE_A ? A : d.src.base == BASE_B ? B : arena) + d.src.off;
     const int t = threadIdx.x, c = t & 127, h = t >> 7;
     const int64_t col = bj * 128 + c, row0 = bi * 128 + h * 64;
     float v[64];
@@ -285,9 +286,49 @@ __global__ __launch_bounds__(EW_THREADS) void reduce_kernel(const ReduceDesc* ta
     if (d.out_kind == OUT_PACKED) {
         T* C = Cptrs ? static_cast<T*>(Cptrs[d.prob]) : C0;
         C[packed_index(d.out_row0 + i, d.out_col0 + j)] = (T)s;
+    } else if (d.out_kind == OUT_CDENSE) {
+        C0[(d.out_row0 + i) * d.out_ld + d.out_col0 + j] = (T)s;
     } else {
         arena[d.out_off + i * d.out_ld + j] = (T)s;
     }
+}
+
+// ------------------------------------------------- BLAS-style conveniences
+// C = alpha T + beta C over packed arrays (beta = 0: C is not read).
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void axpby_kernel(const T* t, T* c, int64_t len, T alpha, T beta) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= len) return;
+    c[x] = beta == T(0) ? alpha * t[x] : alpha * t[x] + beta * c[x];
+}
+
+// At[j][i] = A[i][j] (A m x n with row stride lda, At n x m dense), through
+// 32 x 33 LDS tiles so both sides are coalesced.
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void transpose_kernel(const T* A, int64_t m, int64_t n, int64_t lda,
+                                                               T* At) {
+    __shared__ T tile[32][33];
+    const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;          // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = i0 + r, j = j0 + tx;
+        if (i < m && j < n) tile[r][tx] = A[i * lda + j];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t j = j0 + r, i = i0 + tx;
+        if (j < n && i < m) At[j * m + i] = tile[tx][r];
+    }
+}
+
+// Full symmetric n x n matrix (row stride ldf) from packed lower storage.
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void unpack_kernel(const T* Cp, int64_t n, T* F, int64_t ldf) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= n * n) return;
+    const int64_t i = x / n, j = x - i * n;
+    const int64_t r = i > j ? i : j, c = i > j ? j : i;
+    F[i * ldf + j] = Cp[packed_index(r, c)];
 }
 
 // ---------------------------------------------------------------- combine
@@ -312,7 +353,8 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
     const T* M = arena + d.m_off + i * k2;
     auto dst = [&](int64_t ii, int64_t jj) -> T* {
         return d.out_kind == OUT_PACKED ? C + packed_index(d.out_row0 + ii, d.out_col0 + jj)
-                                        : arena + d.out_off + ii * d.out_ld + jj;
+               : d.out_kind == OUT_CDENSE ? C + (d.out_row0 + ii) * d.out_ld + d.out_col0 + jj
+                                          : arena + d.out_off + ii * d.out_ld + jj;
     };
     if (i < n1 && j0 + 4 <= k1 && (k2 & 3) == 0) {
         typedef typename Vec4<T>::type V4;
@@ -622,35 +664,37 @@ unsigned blocks_for(int64_t items) { return (unsigned)((items + EW_THREADS - 1) 
 
 hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, int64_t items,
                          const void* A, void* arena, const uint8_t* flags, hipStream_t stream,
-                         const BatchPtrs* bp) {
+                         const BatchPtrs* bp, const void* B) {
     if (items <= 0) return hipSuccess;
     const void* const* Ap = bp ? bp->A : nullptr;
     if (mode == MODE_F64)
         hipLaunchKernelGGL(presum_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<const double*>(A),
-                           static_cast<double*>(arena), flags, Ap);
+                           static_cast<double*>(arena), flags, Ap, static_cast<const double*>(B));
     else
         hipLaunchKernelGGL(presum_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<const float*>(A),
-                           static_cast<float*>(arena), flags, Ap);
+                           static_cast<float*>(arena), flags, Ap, static_cast<const float*>(B));
     return hipGetLastError();
 }
 
 hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const void* A,
-                       void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp) {
+                       void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp,
+                       const void* B) {
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream, d_tasks,
                        ntasks, items, static_cast<const float*>(A), static_cast<float*>(arena), flags,
-                       bp ? bp->A : nullptr);
+                       bp ? bp->A : nullptr, static_cast<const float*>(B));
     return hipGetLastError();
 }
 
 hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, const void* A,
-                         void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp) {
+                         void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp,
+                         const void* B) {
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(quant8_kernel, dim3((unsigned)blocks), dim3(EW_THREADS), 0, stream, d_tasks,
                        ntasks, static_cast<const float*>(A), static_cast<float*>(arena), flags,
-                       bp ? bp->A : nullptr);
+                       bp ? bp->A : nullptr, static_cast<const float*>(B));
     return hipGetLastError();
 }
 
@@ -664,6 +708,42 @@ hipError_t launch_reduce(int32_t mode, const ReduceDesc* d_tasks, int ntasks, in
     else
         hipLaunchKernelGGL(reduce_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<float*>(C), static_cast<float*>(arena), flags, Cp);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(int32_t mode, const void* t, void* c, int64_t len, double alpha, double beta,
+                        hipStream_t stream) {
+    if (len <= 0) return hipSuccess;
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(axpby_kernel<double>, dim3(blocks_for(len)), dim3(EW_THREADS), 0, stream,
+                           static_cast<const double*>(t), static_cast<double*>(c), len, alpha, beta);
+    else
+        hipLaunchKernelGGL(axpby_kernel<float>, dim3(blocks_for(len)), dim3(EW_THREADS), 0, stream,
+                           static_cast<const float*>(t), static_cast<float*>(c), len, (float)alpha, (float)beta);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(int32_t mode, const void* A, int64_t m, int64_t n, int64_t lda, void* At,
+                            hipStream_t stream) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(transpose_kernel<double>, grid, dim3(EW_THREADS), 0, stream,
+                           static_cast<const double*>(A), m, n, lda, static_cast<double*>(At));
+    else
+        hipLaunchKernelGGL(transpose_kernel<float>, grid, dim3(EW_THREADS), 0, stream,
+                           static_cast<const float*>(A), m, n, lda, static_cast<float*>(At));
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int32_t mode, const void* Cp, int64_t n, void* F, int64_t ldf, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(unpack_kernel<double>, dim3(blocks_for(n * n)), dim3(EW_THREADS), 0, stream,
+                           static_cast<const double*>(Cp), n, static_cast<double*>(F), ldf);
+    else
+        hipLaunchKernelGGL(unpack_kernel<float>, dim3(blocks_for(n * n)), dim3(EW_THREADS), 0, stream,
+                           static_cast<const float*>(Cp), n, static_cast<float*>(F), ldf);
     return hipGetLastError();
 }
 

@@ -28,7 +28,8 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg);
 // rows, column by column.
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
-                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp = nullptr);
+                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp = nullptr,
+                         const void* B = nullptr);
 
 // FP64 fallback of flagged SYRK leaves (FP32 inputs and output); the tasks
 // are the plan's fallback-capable SYRK leaves, unflagged ones exit at once.
@@ -39,22 +40,31 @@ hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t n
 // One Strassen level of pre-sums (S1..S5 / T1..T5 for every node of the level).
 hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, int64_t items,
                          const void* A, void* arena, const uint8_t* flags, hipStream_t stream,
-                         const BatchPtrs* bp = nullptr);
+                         const BatchPtrs* bp = nullptr, const void* B = nullptr);
 
 // Split-BF16 packing of the leaf operands (one launch for the whole plan).
 hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const void* A,
                        void* arena, const uint8_t* flags, hipStream_t stream,
-                       const BatchPtrs* bp = nullptr);
+                       const BatchPtrs* bp = nullptr, const void* B = nullptr);
 
 // FP8 quantisation of the leaf operands (one workgroup per 128 x 128 block).
 hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, const void* A,
                          void* arena, const uint8_t* flags, hipStream_t stream,
-                         const BatchPtrs* bp = nullptr);
+                         const BatchPtrs* bp = nullptr, const void* B = nullptr);
 
 // Partial sums of the split-K leaves (after both leaf launches).
 hipError_t launch_reduce(int32_t mode, const ReduceDesc* d_tasks, int ntasks, int64_t items, void* C,
                          void* arena, const uint8_t* flags, hipStream_t stream,
                          const BatchPtrs* bp = nullptr);
+
+// c = alpha t + beta c over len elements (beta = 0: c is not read).
+hipError_t launch_axpby(int32_t mode, const void* t, void* c, int64_t len, double alpha, double beta,
+                        hipStream_t stream);
+// At (n x m dense) = transpose of A (m x n, row stride lda).
+hipError_t launch_transpose(int32_t mode, const void* A, int64_t m, int64_t n, int64_t lda, void* At,
+                            hipStream_t stream);
+// Full symmetric n x n matrix (row stride ldf) from packed lower storage.
+hipError_t launch_unpack(int32_t mode, const void* Cp, int64_t n, void* F, int64_t ldf, hipStream_t stream);
 
 // One height of Strassen combines (seven products -> four quadrants).
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,

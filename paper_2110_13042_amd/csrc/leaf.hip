@@ -74,6 +74,7 @@ struct LeafArgs {
     const void* const* Aptrs;     // batches: A and C of problem d.prob (else A, C)
     void* const* Cptrs;
     unsigned long long* counter;  // persistent mode: eight tile queue heads (else null)
+    const void* B;                // second input of a general product (else null)
 };
 
 __device__ __forceinline__ int find_leaf(const LeafDesc* t, int n, int64_t x) {
@@ -148,8 +149,9 @@ __device__ __forceinline__ void leaf_tile(const LeafDesc& d, int64_t q, int64_t 
 }
 
 template <class T>
-__device__ __forceinline__ const T* view_ptr(const View& v, const void* A, const void* arena) {
-    return (v.base == BASE_A ? static_cast<const T*>(A) : static_cast<const T*>(arena)) + v.off;
+__device__ __forceinline__ const T* view_ptr(const View& v, const void* A, const void* B, const void* arena) {
+    return (v.base == BASE_A ? static_cast<const T*>(A)
+            : v.base == BASE_B ? static_cast<const T*>(B) : static_cast<const T*>(arena)) + v.off;
 }
 
 template <class T>
@@ -173,6 +175,8 @@ __device__ __forceinline__ void store_elem(const LeafDesc& d, int ti, int tj, in
     if (d.kind == LEAF_SYRK && gj > gi) return;
     if (d.ksplit > 1)
         arena[d.part_off + ((int64_t)split * d.rows + gi) * d.cols + gj] = v;
+    else if (d.out_kind == OUT_CDENSE)
+        C[(d.out_row0 + gi) * d.out_ld + d.out_col0 + gj] = v;
     else if (d.out_kind == OUT_PACKED)
         C[packed_index(d.out_row0 + gi, d.out_col0 + gj)] = v;
     else
@@ -834,13 +838,13 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
     // mode's own kernel otherwise.
     const bool flagged = d.fb_node >= 0 && args.flags[d.fb_node];
     if constexpr (MODE == MODE_F64) {
-        tile_f64<double, double>(d, view_ptr<double>(d.X, Aptr, args.arena),
-                                 view_ptr<double>(d.Y, Aptr, args.arena), ti, tj,
+        tile_f64<double, double>(d, view_ptr<double>(d.X, Aptr, args.B, args.arena),
+                                 view_ptr<double>(d.Y, Aptr, args.B, args.arena), ti, tj,
                                  static_cast<double*>(Cptr), static_cast<double*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FALLBACK) {
         if (!flagged) return;
-        tile_f64<float, float>(d, view_ptr<float>(d.X, Aptr, args.arena),
-                               view_ptr<float>(d.Y, Aptr, args.arena), ti, tj,
+        tile_f64<float, float>(d, view_ptr<float>(d.X, Aptr, args.B, args.arena),
+                               view_ptr<float>(d.Y, Aptr, args.B, args.arena), ti, tj,
                                static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3) {
         if (flagged) return;
@@ -864,7 +868,7 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                             static_cast<float*>(args.arena), smem, kr);
     } else {
         if (flagged) return;
-        tile_f32(d, view_ptr<float>(d.X, Aptr, args.arena), view_ptr<float>(d.Y, Aptr, args.arena),
+        tile_f32(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
                  ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
     }
 }
@@ -919,9 +923,9 @@ __global__ void zero_counter(unsigned long long* c) { c[threadIdx.x] = 0ull; }
 
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
-                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp) {
+                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp, const void* B) {
     if (ntiles <= 0) return hipSuccess;
-    LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr};
+    LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr, B};
     dim3 grid((unsigned)ntiles);
     if (bp) {
         a.Aptrs = bp->A;
@@ -968,7 +972,7 @@ hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t n
                                   hipStream_t stream, const BatchPtrs* bp) {
     if (ntiles <= 0) return hipSuccess;
     LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags,
-               bp ? bp->A : nullptr, bp ? bp->C : nullptr, nullptr};
+               bp ? bp->A : nullptr, bp ? bp->C : nullptr, nullptr, nullptr};
     hipLaunchKernelGGL(leaf_kernel<MODE_FALLBACK>, dim3((unsigned)ntiles), dim3(LEAF_THREADS), 0, stream, a);
     return hipGetLastError();
 }

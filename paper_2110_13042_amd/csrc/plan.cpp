@@ -392,10 +392,11 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
     col2.clear();
     int64_t part_off = 0, nu_off = 0, e1 = 0, e2 = 0;
     for (int64_t i = 0; i < count; ++i) {
-        // about 2048 workgroups of 256 columns x (4 waves x rows / 4), at
-        // least 8 rows per wave
+        // up to about 2048 workgroups of 256 columns x (4 waves x rows / 4)
+        // per problem, each wave summing at least 64 rows (eight rounds of
+        // eight 16-byte loads in flight)
         const int64_t xblocks = cdiv(std::max<int64_t>(n[i], 1), 256);
-        int64_t chunks = std::max<int64_t>(1, std::min(cdiv(2048, xblocks), cdiv(std::max<int64_t>(m[i], 1), 32)));
+        int64_t chunks = std::max<int64_t>(1, std::min(cdiv(2048, xblocks), cdiv(std::max<int64_t>(m[i], 1), 256)));
         int64_t rows = cdiv(cdiv(std::max<int64_t>(m[i], 1), chunks), 4) * 4;
         chunks = cdiv(std::max<int64_t>(m[i], 1), rows);
         ColDesc d{};
@@ -426,6 +427,45 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
         col2.push_back(z);
     }
     *partial_total = part_off;
+}
+
+Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
+                    int64_t ldc, const PlanOptions& opt) {
+    if (mode < MODE_F64 || mode > MODE_FP8) throw std::invalid_argument("mode");
+    if (m < 0 || n < 0 || k < 0 || lda < std::max<int64_t>(1, n) || ldb < std::max<int64_t>(1, k) ||
+        ldc < std::max<int64_t>(1, k))
+        throw std::invalid_argument("sizes");
+    Plan p;
+    p.mode = mode;
+    p.gemm = true;
+    p.m = m;
+    p.n = n;
+    p.k = k;
+    p.lda = lda;
+    p.ldb = ldb;
+    p.ldc = ldc;
+    p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, std::max(n, k));
+    p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode);
+    p.fallback = false;
+    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : 0;
+    if (n == 0 || k == 0) return p;
+    Builder bld(p);
+    View X{};
+    X.base = BASE_A;
+    X.ld = lda;
+    X.rows = X.prows = m;
+    X.cols = X.pcols = n;
+    View Y{};
+    Y.base = BASE_B;
+    Y.ld = ldb;
+    Y.rows = Y.prows = m;
+    Y.cols = Y.pcols = k;
+    bld.strassen(X, Y, Target{OUT_CDENSE, 0, ldc, 0, 0}, 0, -1, 0);
+    if (mode == MODE_BF16X3 && m > 0) assign_packed(p);
+    if (mode == MODE_FP8 && m > 0) assign_quant(p);
+    if (opt.split_target > 0) split_leaves(p, opt.split_target);
+    finalize_plan(p);
+    return p;
 }
 
 void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
@@ -520,7 +560,7 @@ void finalize_plan(Plan& p) {
 namespace {
 
 void shift_view(View& v, int64_t ab) {
-    if (v.base != BASE_A) v.off += ab;
+    if (v.base == BASE_ARENA || v.base == BASE_PACKED) v.off += ab;
 }
 
 }  // namespace

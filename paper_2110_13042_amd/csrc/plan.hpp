@@ -29,7 +29,8 @@ enum Mode : int32_t { MODE_F64 = 0, MODE_F32 = 1, MODE_BF16X3 = 2, MODE_FP8 = 3 
 // Base buffers a view can point into.
 // BASE_PACKED: a split-BF16 operand that a pre-sum wrote directly in the
 // packed hi/lo layout (see Packed) at arena offset `off`, `rows` x `cols`.
-enum Base : int32_t { BASE_A = 0, BASE_ARENA = 1, BASE_PACKED = 2 };
+// BASE_B: the second input of a general product C = A^T B.
+enum Base : int32_t { BASE_A = 0, BASE_ARENA = 1, BASE_PACKED = 2, BASE_B = 3 };
 
 // Element (r, c) of the rows x cols logical operand is
 // base[off + r * ld + c] when r < prows and c < pcols, and 0 otherwise.
@@ -66,7 +67,10 @@ struct Packed8 {
 };
 
 enum LeafKind : int32_t { LEAF_SYRK = 0, LEAF_GEMM = 1 };
-enum OutKind : int32_t { OUT_PACKED = 0, OUT_DENSE = 1 };
+// OUT_PACKED: packed lower C at (out_row0, out_col0); OUT_DENSE: arena
+// buffer at out_off with row stride out_ld; OUT_CDENSE: the caller's dense
+// C (row stride out_ld) at (out_row0, out_col0).
+enum OutKind : int32_t { OUT_PACKED = 0, OUT_DENSE = 1, OUT_CDENSE = 2 };
 
 // One leaf product out = X^T Y (SYRK: X == Y, lower triangle only).
 struct LeafDesc {
@@ -192,6 +196,8 @@ struct Plan {
     int32_t mode = MODE_F32;
     int32_t nprob = 1;
     int64_t m = 0, n = 0, lda = 0;
+    bool gemm = false;                              // C = A^T B (n x k, dense) instead of AtA
+    int64_t k = 0, ldb = 0, ldc = 0;                // the general product's B and C
     int64_t b = 0;
     int32_t max_depth = 0;
     int32_t tile_cfg = 0;
@@ -220,6 +226,12 @@ int32_t default_max_depth(int32_t mode);
 
 // Builds the plan (host only).  Throws std::invalid_argument on bad sizes.
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);
+
+// Plan of the general product C = A^T B (A m x n, B m x k, C n x k dense):
+// one Strassen recursion (the paper's FastStrassen step on A^T B) writing
+// the caller's C.  No spread check applies.
+Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, int64_t ldb,
+                    int64_t ldc, const PlanOptions& opt);
 
 // Column-norm tasks of `count` problems (problem i: m[i] x n[i], row stride
 // lda[i]); partial sums and norms of problem i start at the returned offsets.

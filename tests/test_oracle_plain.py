@@ -119,3 +119,42 @@ def test_degenerate_shapes():
     assert plain.gram_packed(np.zeros((4, 0))).size == 0
     with pytest.raises(ValueError):
         plain.unpack(np.zeros(5), 3)
+
+
+# --------------------------------------------------------------- A^T B
+def test_gemm_tn_hand_computed():
+    A = np.array([[1.0, 2.0], [3.0, 4.0]])
+    B = np.array([[5.0], [6.0]])
+    C = plain.gemm_tn(A, B)
+    assert C.shape == (2, 1)
+    assert C[0, 0] == 1 * 5 + 3 * 6 and C[1, 0] == 2 * 5 + 4 * 6
+
+
+def test_gemm_tn_identity_and_transpose_symmetry():
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((9, 4))
+    assert np.array_equal(plain.gemm_tn(np.eye(9), B), B)          # I^T B = B
+    A = rng.standard_normal((40, 7))
+    # (A^T B)^T = B^T A entry for entry: the same products in the same order
+    B2 = rng.standard_normal((40, 5))
+    assert np.array_equal(plain.gemm_tn(A, B2), plain.gemm_tn(B2, A).T)
+
+
+def test_gemm_tn_of_a_with_itself_is_the_gram_product():
+    rng = np.random.default_rng(22)
+    for dt in (np.float64, np.float32):
+        A = rng.standard_normal((123, 17)).astype(dt)
+        C = plain.gemm_tn(A, A)
+        i, j = np.tril_indices(17)
+        assert np.array_equal(C[i, j], plain.gram_packed(A))      # packed order is row-major lower
+
+
+def test_gemm_tn_against_numpy_and_threads():
+    rng = np.random.default_rng(23)
+    A = rng.standard_normal((300, 40))
+    B = rng.standard_normal((300, 25))
+    C = plain.gemm_tn(A, B)
+    ref = A.T @ B
+    assert np.linalg.norm(C - ref) / np.linalg.norm(ref) <= 1e-14
+    assert np.array_equal(plain.gemm_tn(A, B, nthreads=1), plain.gemm_tn(A, B, nthreads=3))
+    assert plain.gemm_tn(np.zeros((0, 4)), np.zeros((0, 2))).tolist() == [[0.0, 0.0]] * 4
