@@ -168,6 +168,8 @@ def make_handle(ata, args):
         h.set("xcd_chunk", args.xcd_chunk)
     if args.tile_band:
         h.set("tile_band", args.tile_band)
+    if args.equilibrate:
+        h.set("equilibrate", 1)
     return h
 
 
@@ -330,6 +332,8 @@ def main() -> int:
     ap.add_argument("--leaf-tile", type=int, default=0, help="split-BF16 leaf tile: 0 = 128x128, 1 = 256x128, 2 = 256x256")
     ap.add_argument("--xcd-chunk", type=int, default=0, help="leaf tiles per XCD per window (0: library default)")
     ap.add_argument("--tile-band", type=int, default=0, help="GEMM leaf tile rows per band (0: library default)")
+    ap.add_argument("--equilibrate", action="store_true",
+                    help="FP32 family: column equilibration instead of the FP64 fallback")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=512)
     ap.add_argument("--autotune", action="store_true",

@@ -65,7 +65,9 @@ typedef enum {
        max(n, k) <= b.  0 = the planner's choice (default). */
     ATA_OPT_LEAF_CUTOFF = 0,
     /* Maximum Strassen levels under one AtA node; -1 = the mode's default
-       (F64: unlimited, F32: 3, BF16X3: 2, FP8: 1). */
+       (F64: unlimited, F32: 3, BF16X3: 2, FP8: 1; F32 and BF16X3 take 0
+       when m >= 65536, since a level's rounding error adds to that of the
+       long contraction). */
     ATA_OPT_MAX_STRASSEN_DEPTH = 1,
     /* Spread threshold tau on column norms for the FP32-family FP64 fallback:
        an AtA node whose max/min squared column norm exceeds tau^2 runs its
@@ -115,7 +117,15 @@ typedef enum {
        options, else the batch autotuner's choice for the batch signature
        (ata_autotune_batched), else the defaults.  Per-shape choices are
        timed one problem at a time and need not suit a merged launch. */
-    ATA_OPT_BATCH_USE_TABLE = 13
+    ATA_OPT_BATCH_USE_TABLE = 13,
+    /* ata_gram, FP32-family dtypes: 1 = column equilibration instead of the
+       FP64 fallback.  Column j of A is scaled by 2^-e_j (e_j = the binary
+       exponent of its norm, so every scaled norm lies in [0.5, 1)) into a
+       workspace copy (m n floats), the plan runs on the copy without the
+       spread check, and C_ij is scaled back by 2^(e_i + e_j).  All scalings
+       are exact; rounding errors become relative to ||a_i|| ||a_j||.  The
+       residual option then checks the scaled product.  Default 0. */
+    ATA_OPT_EQUILIBRATE = 14
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

@@ -164,6 +164,11 @@ struct ata_ctx {
     // batches: merged plans, captured graphs, internal capture stream
     std::map<BatchKey, std::unique_ptr<BatchEntry>> batches;
     std::map<GemmKey, std::unique_ptr<DevicePlan>> gemm_plans;
+    // column equilibration: option, norm tasks per (m, n, lda), buffers
+    bool equilibrate = false;
+    std::map<std::tuple<int64_t, int64_t, int64_t>, std::unique_ptr<DevicePlan>> eq_plans;
+    void* eq = nullptr;
+    size_t eq_cap = 0;
     // staging for the BLAS-style conveniences (a scaled product's result, a
     // transposed input)
     void* tmp = nullptr;
@@ -287,7 +292,7 @@ void choose(const ata_ctx* h, int32_t mode, int64_t m, int64_t n, int64_t& b, in
         }
     }
     if (b <= 0) b = default_leaf_cutoff(mode, m, n);
-    if (depth < 0) depth = default_max_depth(mode);
+    if (depth < 0) depth = default_max_depth(mode, m);
 }
 
 // Bytes of auxiliary device memory one call needs (flags, norms, residual).
@@ -373,6 +378,7 @@ ata_status_t ata_destroy(ata_handle_t h) {
     if (h->arena) (void)hipFree(h->arena);
     if (h->aux) (void)hipFree(h->aux);
     if (h->tmp) (void)hipFree(h->tmp);
+    if (h->eq) (void)hipFree(h->eq);
     delete h;
     return ATA_OK;
 }
@@ -418,6 +424,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
         case ATA_OPT_TILE_BAND:
             if (value < 1 || value > 4096) return ATA_ERR_INVALID_VALUE;
             h->band = (int)value;
+            return ATA_OK;
+        case ATA_OPT_EQUILIBRATE:
+            h->equilibrate = value != 0.0;
             return ATA_OK;
         case ATA_OPT_BATCH_USE_TABLE:
             h->batch_use_table = value != 0.0;
@@ -490,6 +499,61 @@ ata_status_t take_events(ata_ctx* h, hipEvent_t*& ev) {
 
 }  // namespace
 
+namespace {
+
+// Column equilibration (an alternative to the FP64 fallback for ill-scaled
+// columns): scale column j by 2^-e_j so that every column norm lies in
+// [0.5, 1), run the plan on the scaled copy (no spread check needed: the
+// norms now differ by less than 2x), and scale C_ij back by 2^(e_i + e_j).
+// All scalings are exact powers of two, so in exact arithmetic the result is
+// A^T A itself; each entry's rounding error becomes relative to
+// ||a_i|| ||a_j|| instead of to the largest columns.
+ata_status_t gram_equilibrated(ata_ctx* h, const void* A, int64_t m, int64_t n, int64_t lda, ata_dtype_t dtype,
+                               void* C_packed, void* stream) {
+    const auto key = std::make_tuple(m, n, lda);
+    auto it = h->eq_plans.find(key);
+    if (it == h->eq_plans.end()) {
+        auto dp = std::make_unique<DevicePlan>();
+        dp->plan.m = m;
+        dp->plan.n = n;
+        dp->plan.lda = lda;
+        build_colnorm_tasks(&m, &n, &lda, 1, dp->plan.col1, dp->plan.col2, &dp->plan.col_partial);
+        const ata_status_t s = upload_plan(*dp);
+        if (s != ATA_OK) return s;
+        it = h->eq_plans.emplace(key, std::move(dp)).first;
+    }
+    const DevicePlan& ep = *it->second;
+    const Plan& q = ep.plan;
+    const size_t ap_b = align256(sizeof(float) * (size_t)(m * n));
+    const size_t part_b = align256(sizeof(double) * (size_t)std::max<int64_t>(q.col_partial, 1));
+    const size_t nu_b = align256(sizeof(double) * (size_t)n);
+    const size_t e_b = align256(sizeof(int) * (size_t)n);
+    ata_status_t s = ensure(h->eq, h->eq_cap, ap_b + part_b + nu_b + e_b);
+    if (s != ATA_OK) return s;
+    unsigned char* base = static_cast<unsigned char*>(h->eq);
+    float* Ap = reinterpret_cast<float*>(base);
+    double* partial = reinterpret_cast<double*>(base + ap_b);
+    double* nu = reinterpret_cast<double*>(base + ap_b + part_b);
+    int* e = reinterpret_cast<int*>(base + ap_b + part_b + nu_b);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t err = launch_colnorms(ep.d_col1, (int)q.col1.size(), q.col1.back().elem_begin + q.col1.back().elems,
+                                     ep.d_col2, (int)q.col2.size(), q.col2.back().elem_begin + q.col2.back().elems,
+                                     static_cast<const float*>(A), nullptr, partial, nu, st);
+    if (err == hipSuccess) err = launch_eq_scale(static_cast<const float*>(A), m, n, lda, nu, Ap, e, st);
+    if (err != hipSuccess) return ATA_ERR_HIP;
+    // the plan on the scaled copy, without the spread check
+    const double tau = h->popt.spread_tau;
+    h->equilibrate = false;
+    h->popt.spread_tau = 0.0;
+    s = ata_gram(h, Ap, m, n, n, dtype, C_packed, stream);
+    h->equilibrate = true;
+    h->popt.spread_tau = tau;
+    if (s != ATA_OK) return s;
+    return launch_eq_unscale(static_cast<float*>(C_packed), n, e, st) == hipSuccess ? ATA_OK : ATA_ERR_HIP;
+}
+
+}  // namespace
+
 ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
                       ata_dtype_t dtype, void* C_packed, void* stream) {
     if (!h || !valid_dtype(dtype) || m < 0 || n < 0 || lda < std::max<int64_t>(1, n))
@@ -514,6 +578,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     }
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
     const int32_t mode = (int32_t)dtype;
+    if (h->equilibrate && mode != MODE_F64 && m > 0) return gram_equilibrated(h, A, m, n, lda, dtype, C_packed, stream);
     int64_t b;
     int32_t depth, tile_cfg;
     choose(h, mode, m, n, b, depth, tile_cfg);
@@ -1079,7 +1144,7 @@ ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n, i
         cutoffs.push_back(b);
         if (b >= n) break;
     }
-    const int32_t dmax = std::min<int32_t>(default_max_depth(mode), 3);
+    const int32_t dmax = std::min<int32_t>(default_max_depth(mode, m), 3);
     const int ntiles = mode == MODE_BF16X3 ? 4 : 1;
     ata_status_t rs = ATA_OK;
     for (int64_t b : cutoffs) {
@@ -1145,7 +1210,9 @@ ata_status_t ata_autotune_batched(ata_handle_t h, int64_t batch, const void* con
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return ATA_ERR_HIP;
     ata_tune_entry_t top{0, 0, 0, 1e30};
     const int ntiles = mode == MODE_BF16X3 ? 4 : 1;
-    const int32_t dmax = std::min<int32_t>(default_max_depth(mode), 2);
+    int64_t mmax = 0;
+    for (int64_t i = 0; i < batch; ++i) mmax = std::max(mmax, m[i]);
+    const int32_t dmax = std::min<int32_t>(default_max_depth(mode, mmax), 2);
     ata_status_t rs = ATA_OK;
     for (int64_t b = 128; b <= 4096 && rs == ATA_OK; b *= 2) {
         for (int32_t d = 0; d <= dmax && rs == ATA_OK; ++d) {

@@ -331,6 +331,39 @@ __global__ __launch_bounds__(EW_THREADS) void unpack_kernel(const T* Cp, int64_t
     F[i * ldf + j] = Cp[packed_index(r, c)];
 }
 
+// ------------------------------------------------- column equilibration
+// e_j = the binary exponent of the column norm (sqrt(nu_j) = f 2^e_j, f in
+// [0.5, 1)), 0 for a zero column.  Scaling a column by 2^-e_j is exact.
+__device__ __forceinline__ int eq_exponent(double nu) {
+    if (!(nu > 0.0)) return 0;
+    int e;
+    (void)frexp(sqrt(nu), &e);
+    return e;
+}
+
+// Ap (m x n dense) = A diag(2^-e); e_j stored by the threads of row 0.
+__global__ __launch_bounds__(EW_THREADS) void eq_scale_kernel(const float* A, int64_t m, int64_t n, int64_t lda,
+                                                              const double* nu, float* Ap, int* e) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= m * n) return;
+    const int64_t r = udiv(x, n), j = x - r * n;
+    const int ej = eq_exponent(nu[j]);
+    Ap[x] = ldexpf(A[r * lda + j], -ej);
+    if (r == 0) e[j] = ej;
+}
+
+// Packed C_ij *= 2^(e_i + e_j): the Gram product of the scaled columns back
+// to the original scale (exact).
+__global__ __launch_bounds__(EW_THREADS) void eq_unscale_kernel(float* Cp, int64_t n, const int* e) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= n * (n + 1) / 2) return;
+    int64_t i = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while (i > 0 && i * (i + 1) / 2 > x) --i;
+    while ((i + 1) * (i + 2) / 2 <= x) ++i;
+    const int64_t j = x - i * (i + 1) / 2;
+    Cp[x] = ldexpf(Cp[x], e[i] + e[j]);
+}
+
 // ---------------------------------------------------------------- combine
 // Work item = one row i and four columns j..j+3 of the n2 x k2 products.
 // C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4,
@@ -744,6 +777,20 @@ hipError_t launch_unpack(int32_t mode, const void* Cp, int64_t n, void* F, int64
     else
         hipLaunchKernelGGL(unpack_kernel<float>, dim3(blocks_for(n * n)), dim3(EW_THREADS), 0, stream,
                            static_cast<const float*>(Cp), n, static_cast<float*>(F), ldf);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq_scale(const float* A, int64_t m, int64_t n, int64_t lda, const double* nu, float* Ap,
+                           int* e, hipStream_t stream) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eq_scale_kernel, dim3(blocks_for(m * n)), dim3(EW_THREADS), 0, stream, A, m, n, lda, nu,
+                       Ap, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq_unscale(float* Cp, int64_t n, const int* e, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eq_unscale_kernel, dim3(blocks_for(n * (n + 1) / 2)), dim3(EW_THREADS), 0, stream, Cp, n, e);
     return hipGetLastError();
 }
 

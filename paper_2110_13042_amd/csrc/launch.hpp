@@ -66,6 +66,13 @@ hipError_t launch_transpose(int32_t mode, const void* A, int64_t m, int64_t n, i
 // Full symmetric n x n matrix (row stride ldf) from packed lower storage.
 hipError_t launch_unpack(int32_t mode, const void* Cp, int64_t n, void* F, int64_t ldf, hipStream_t stream);
 
+// Column equilibration: Ap (m x n dense) = A diag(2^-e) with e_j the binary
+// exponent of column j's norm (from nu = squared norms); and packed
+// C_ij *= 2^(e_i + e_j) afterwards.
+hipError_t launch_eq_scale(const float* A, int64_t m, int64_t n, int64_t lda, const double* nu, float* Ap,
+                           int* e, hipStream_t stream);
+hipError_t launch_eq_unscale(float* Cp, int64_t n, const int* e, hipStream_t stream);
+
 // One height of Strassen combines (seven products -> four quadrants).
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
                           void* C, void* arena, const uint8_t* flags, hipStream_t stream,

@@ -222,7 +222,8 @@ struct Plan {
 };
 
 int64_t default_leaf_cutoff(int32_t mode, int64_t m, int64_t n);
-int32_t default_max_depth(int32_t mode);
+// Default Strassen depth cap of a mode for contractions of m rows.
+int32_t default_max_depth(int32_t mode, int64_t m);
 
 // Builds the plan (host only).  Throws std::invalid_argument on bad sizes.
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);

@@ -48,6 +48,24 @@ def _errors(Cp, S, ref, d):
 
 
 @pytest.mark.parametrize("mode", [ata.F32, ata.F32_BF16X3])
+def test_tall_scaled_equilibrated(tall, mode):
+    """The same workload with exact column equilibration instead of the fallback."""
+    At, S, ref, d = tall
+    h = ata.Handle(equilibrate=1)
+    try:
+        _say("case: tall mode", mode, "equilibrated")
+        C = ata.gram(At, mode, handle=h)
+        torch.cuda.synchronize()
+        e_s, e_d = _errors(C.double().cpu().numpy(), S, ref, d)
+        _say("  e_S %.3e  e_D %.3e" % (e_s, e_d))
+        del C
+    finally:
+        h.close()
+    assert e_s <= 2e-5
+    assert e_d <= 2e-5
+
+
+@pytest.mark.parametrize("mode", [ata.F32, ata.F32_BF16X3])
 def test_tall_scaled_sampled_columns(tall, mode):
     At, S, ref, d = tall
     out = {}
