@@ -108,9 +108,11 @@ typedef enum {
     ATA_OPT_TILE_BAND = 11,
     /* Split-K: when a leaf launch (the dtype's, or the FP64 fallback's) has
        fewer tiles than this, leaves with a contraction of at least 16384
-       rows are cut into K chunks of at least 8192 rows whose partial sums a
-       reduce pass adds in chunk order, in FP64, rounding once (default 2048;
-       0 = never split).  Tall-skinny A gets enough tiles to fill the GPU. */
+       rows are cut into K chunks of at least 8192 rows (when the launch has
+       fewer than 512 tiles: contractions of 512 rows or more, chunks of at
+       least 256 rows) whose partial sums a reduce pass adds in chunk order,
+       in FP64, rounding once (default 2048; 0 = never split).  Tall-skinny
+       and small problems get enough tiles to fill the GPU. */
     ATA_OPT_SPLIT_TARGET = 12,
     /* ata_gram_batched: 1 = each member takes the per-shape autotune table
        entry of its own shape bucket; 0 (default) = members use the handle's

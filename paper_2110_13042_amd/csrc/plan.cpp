@@ -482,11 +482,15 @@ void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
         if (L.fb_node >= 0)
             t_fb += syrk_tiles(cdiv(L.rows, TILE_M), cdiv(L.cols, TILE_N), TILE_M / TILE_N);
     }
+    // a launch with fewer tiles than two per CU may cut K into chunks as short
+    // as 256 rows (small problems are otherwise latency-bound on their K loops)
+    auto chunk_min = [&](int64_t tiles) { return tiles < 512 ? std::min<int64_t>(min_chunk, 256) : min_chunk; };
     for (auto& L : p.leaves) {
-        const int64_t most = L.K / min_chunk;      // chunks of at least min_chunk rows
-        if (most < 2) continue;
-        int64_t s = t_mode > 0 && t_mode < target ? std::min(target / t_mode, most) : 1;
-        if (L.fb_node >= 0 && t_fb > 0 && t_fb < target) s = std::max(s, std::min(target / t_fb, most));
+        const int64_t most = L.K / chunk_min(t_mode);
+        int64_t s = t_mode > 0 && t_mode < target && most >= 2 ? std::min(target / t_mode, most) : 1;
+        const int64_t most_fb = L.K / chunk_min(t_fb);
+        if (L.fb_node >= 0 && t_fb > 0 && t_fb < target && most_fb >= 2)
+            s = std::max(s, std::min(target / t_fb, most_fb));
         if (s < 2) continue;
         const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
         s = cdiv(L.K, kchunk);

@@ -244,9 +244,10 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
 
 // Split-K: when a leaf launch (the mode's, or the FP64 fallback's) has fewer
 // than `target` tiles, leaves with K >= 2 * min_chunk are cut into K chunks
-// of at least min_chunk rows (multiples of 256), each chunk's tiles writing
-// partial sums that a reduce pass adds.  Called before finalize_plan; merged
-// batch plans are split once, after merging.
+// of at least min_chunk rows (multiples of 256; 256 rows when the launch has
+// fewer than 512 tiles), each chunk's tiles writing partial sums that a
+// reduce pass adds.  Called before finalize_plan; merged batch plans are
+// split once, after merging.
 constexpr int64_t SPLIT_MIN_CHUNK = 8192;
 void split_leaves(Plan& p, int64_t target, int64_t min_chunk = SPLIT_MIN_CHUNK);
 
