@@ -85,9 +85,10 @@ typedef enum {
        every ata_gram call; ata_get_report then synchronises and returns the
        summed phase times since the option was last set (default 0). */
     ATA_OPT_PROFILE = 6,
-    /* Output tile of the split-BF16 leaf kernel: 0 = 128 x 128 (default),
+    /* Output tile of the leaf kernel.  Split-BF16: 0 = 128 x 128 (default),
        1 = 256 x 128, 2 = 256 x 256 on eight waves, 3 = 256 x 256 on four
-       waves of 128 x 128.  Other dtypes ignore it. */
+       waves of 128 x 128.  FP8: 0 = 128 x 128 (default), 3 = 256 x 256 on
+       four waves of 128 x 128 (1 and 2 act as 0).  FP64 and FP32 ignore it. */
     ATA_OPT_LEAF_TILE = 7,
     /* ata_gram_batched: 1 = capture the batch's launch sequence once per
        shape signature in a hipGraph and replay it (default); 0 = enqueue the

@@ -276,19 +276,27 @@ ata_status_t upload_plan(DevicePlan& dp) {
 
 bool valid_dtype(int d) { return d >= ATA_F64 && d <= ATA_F32_FP8E4M3; }
 
+// Modes with a choice of leaf tile, and the tiles worth timing.
+bool tiled_mode(int32_t mode) { return mode == MODE_BF16X3 || mode == MODE_FP8; }
+std::vector<int32_t> tile_candidates(int32_t mode) {
+    if (mode == MODE_BF16X3) return {0, 1, 2, 3};
+    if (mode == MODE_FP8) return {0, 3};
+    return {0};
+}
+
 // Leaf cutoff, depth cap and tile of one problem: explicit options win, then
 // the autotune table, then the planner's defaults.
 void choose(const ata_ctx* h, int32_t mode, int64_t m, int64_t n, int64_t& b, int32_t& depth,
             int32_t& tile, bool use_table = true) {
     b = h->popt.leaf_cutoff;
     depth = h->popt.max_depth;
-    tile = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
+    tile = tiled_mode(mode) ? h->popt.tile_cfg : 0;
     if (use_table && b <= 0 && depth < 0) {
         auto it = h->tune.find(TuneKey{mode, bucket(m), bucket(n)});
         if (it != h->tune.end()) {
             b = it->second.leaf_cutoff;
             depth = it->second.max_depth;
-            if (mode == MODE_BF16X3) tile = it->second.leaf_tile;
+            if (tiled_mode(mode)) tile = it->second.leaf_tile;
         }
     }
     if (b <= 0) b = default_leaf_cutoff(mode, m, n);
@@ -964,13 +972,13 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0;
     // the batch runs one leaf kernel, so one tile shape: the handle's, or the
     // batch autotuner's for this signature when the options are defaults
-    int32_t tile_cfg = mode == MODE_BF16X3 ? h->popt.tile_cfg : 0;
+    int32_t tile_cfg = tiled_mode(mode) ? h->popt.tile_cfg : 0;
     const ata_tune_entry_t* bt = nullptr;
     if (h->popt.leaf_cutoff <= 0 && h->popt.max_depth < 0 && !h->batch_tune.empty()) {
         auto f = h->batch_tune.find(batch_signature(mode, batch, m, n, lda));
         if (f != h->batch_tune.end()) {
             bt = &f->second;
-            if (mode == MODE_BF16X3) tile_cfg = bt->leaf_tile;
+            if (tiled_mode(mode)) tile_cfg = bt->leaf_tile;
         }
     }
     std::vector<int64_t> bs((size_t)batch);
@@ -1145,12 +1153,12 @@ ata_status_t ata_autotune(ata_handle_t h, const void* A, int64_t m, int64_t n, i
         if (b >= n) break;
     }
     const int32_t dmax = std::min<int32_t>(default_max_depth(mode, m), 3);
-    const int ntiles = mode == MODE_BF16X3 ? 4 : 1;
+    const std::vector<int32_t> tiles = tile_candidates(mode);
     ata_status_t rs = ATA_OK;
     for (int64_t b : cutoffs) {
         for (int32_t d = 0; d <= dmax; ++d) {
             if (b >= n && d > 0) break;            // a single leaf: depth does not matter
-            for (int tl = 0; tl < ntiles; ++tl) {
+            for (const int32_t tl : tiles) {
                 h->popt.leaf_cutoff = b;
                 h->popt.max_depth = d;
                 h->popt.tile_cfg = tl;
@@ -1209,14 +1217,14 @@ ata_status_t ata_autotune_batched(ata_handle_t h, int64_t batch, const void* con
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return ATA_ERR_HIP;
     ata_tune_entry_t top{0, 0, 0, 1e30};
-    const int ntiles = mode == MODE_BF16X3 ? 4 : 1;
+    const std::vector<int32_t> tiles = tile_candidates(mode);
     int64_t mmax = 0;
     for (int64_t i = 0; i < batch; ++i) mmax = std::max(mmax, m[i]);
     const int32_t dmax = std::min<int32_t>(default_max_depth(mode, mmax), 2);
     ata_status_t rs = ATA_OK;
     for (int64_t b = 128; b <= 4096 && rs == ATA_OK; b *= 2) {
         for (int32_t d = 0; d <= dmax && rs == ATA_OK; ++d) {
-            for (int tl = 0; tl < ntiles; ++tl) {
+            for (const int32_t tl : tiles) {
                 h->popt.leaf_cutoff = b;
                 h->popt.max_depth = d;
                 h->popt.tile_cfg = tl;

@@ -46,6 +46,7 @@ constexpr int MODE_FALLBACK = 100;
 constexpr int MODE_BF16X3_LARGE = 101;
 constexpr int MODE_BF16X3_HUGE = 102;
 constexpr int MODE_BF16X3_WIDE = 103;
+constexpr int MODE_FP8_WIDE = 104;
 #ifndef ATA_WIDE_STAGES
 #define ATA_WIDE_STAGES 4     // LDS ring depth of the 256 x 256 split-BF16 engine (32 KB each)
 #endif
@@ -54,6 +55,7 @@ constexpr size_t lds_bytes(int mode) {
            : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
            : mode == MODE_BF16X3_WIDE ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
+           : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
 constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE ? 512 : LEAF_THREADS; }
@@ -705,6 +707,111 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
             }
 }
 
+// FP8 e4m3 with a 256 x 256 tile: four waves of 128 x 128 (8 x 8 blocks of
+// 16 x 16 on v_mfma_scale_f32_16x16x128_f8f6f4), one wave per SIMD.  A slab
+// is 128 rows, one scale block deep; each wave's 128 tile rows (columns) are
+// exactly one 128-column scale block of X (of Y), so both E8M0 scales stay
+// uniform per wave and slab.  Slabs stream into two 64 KB LDS stages by
+// buffer loads that write LDS directly: stage layout X[group 0..7][256
+// columns], then Y, of 16-byte chunks (16 consecutive rows of one column);
+// wave w streams X (w < 2) or Y groups 4 (w % 2) .. + 3.  The next slab's
+// loads run under the current slab's 64 MFMAs.
+namespace wide8 {
+constexpr int TM = 256, TN = 256;
+constexpr int HALF = 8 * 256 * 16;            // one operand's slab: 32 KB
+constexpr int STAGE = 2 * HALF;
+}  // namespace wide8
+
+__device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* arena_in, int ti, int tj, float* C,
+                                              float* arena, unsigned char* smem, const KRange& kr) {
+    using namespace wide8;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 1, wn = w & 1;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t nk = (K + 127) / 128;
+    const int64_t sb0 = kr.kb / 128;              // first 128-row slab of the K chunk
+    const bool isx = w < 2;
+    const Packed8& Q = isx ? d.QX : d.QY;
+    const __amdgpu_buffer_rsrc_t src = q8_rsrc(arena_in, Q);
+    const uint32_t past = (uint32_t)((Q.end - Q.off) * 4);
+    const int64_t cp = Q.cols_p;
+    const int64_t col0 = (isx ? (int64_t)ti * TM : (int64_t)tj * TN) + lane;
+    const int gbase = (w & 1) * 4;                // this wave's four row-groups of the slab
+    auto issue = [&](int64_t kt, int stage) {
+        unsigned char* base = smem + stage * STAGE + (isx ? 0 : HALF);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int g = gbase + (i >> 2), seg = i & 3;
+            const int64_t col = col0 + seg * 64;
+            const uint32_t off = col < cp ? (uint32_t)((((sb0 + kt) * 8 + g) * cp + col) * 16) : past;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + (g * 256 + seg * 64) * 16), 16,
+                                                     (int)off, 0, 0, 0);
+        }
+    };
+    // scales: this wave's X and Y column blocks (clamped: a tile column past
+    // the padded width only feeds outputs that are never stored)
+    const int* sx = reinterpret_cast<const int*>(arena_in + d.QX.scales);
+    const int* sy = reinterpret_cast<const int*>(arena_in + d.QY.scales);
+    const int64_t sxs = d.QX.cols_p / 128, sys = d.QY.cols_p / 128;
+    const int64_t bx = (int64_t)ti * 2 + wm < sxs ? (int64_t)ti * 2 + wm : sxs - 1;
+    const int64_t by = (int64_t)tj * 2 + wn < sys ? (int64_t)tj * 2 + wn : sys - 1;
+
+    v4f acc[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.f;
+
+    // fragment of lane l: column (l % 16) of its block, rows 32 (l / 16) ..
+    // + 31 of the slab = groups 2 (l / 16) and 2 (l / 16) + 1
+    const int fo = (2 * (lane >> 4)) * 256 * 16 + (lane & 15) * 16;
+    auto step = [&](int64_t kt) {
+        const int cur = (int)(kt & 1);
+        if (kt + 1 < nk) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // this wave's loads of slab kt are done
+        } else {
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+        }
+        __builtin_amdgcn_s_barrier();             // every wave's loads of slab kt are visible,
+                                                  // and slab kt - 1's stage is free
+        if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
+        const int sa = 127 + sx[(sb0 + kt) * sxs + bx], sb = 127 + sy[(sb0 + kt) * sys + by];
+        const unsigned char* xs = smem + cur * STAGE + fo + (wm * 128) * 16;
+        const unsigned char* ys = smem + cur * STAGE + HALF + fo + (wn * 128) * 16;
+        v8i fb[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const v4u lo = *reinterpret_cast<const v4u*>(ys + b * 16 * 16);
+            const v4u hi = *reinterpret_cast<const v4u*>(ys + b * 16 * 16 + 256 * 16);
+            fb[b] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        }
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            const v4u lo = *reinterpret_cast<const v4u*>(xs + a * 16 * 16);
+            const v4u hi = *reinterpret_cast<const v4u*>(xs + a * 16 * 16 + 256 * 16);
+            const v8i fa = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa, fb[b], acc[a][b], 0, 0, 0, sa, 0, sb);
+        }
+    };
+    if (nk > 0) issue(0, 0);
+    for (int64_t kt = 0; kt < nk; ++kt) step(kt);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 8; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = wm * 128 + a * 16 + 4 * (lane >> 4) + v;
+                const int c = wn * 128 + b * 16 + (lane & 15);
+                store_elem<float, TM, TN>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
+            }
+}
+
 // ---------------------------------------------------------------- FP64 MFMA
 // InT = double (FP64 mode) or float (FP64 fallback of the FP32 family: the
 // inputs are promoted exactly, the result is rounded to OutT on store).
@@ -854,6 +961,10 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
         if (flagged) return;
         tile_bf16x3<BfLarge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
                              static_cast<float*>(args.arena), smem, kr);
+    } else if constexpr (MODE == MODE_FP8_WIDE) {
+        if (flagged) return;
+        tile_fp8_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                      static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FP8) {
         if (flagged) return;
         tile_fp8(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
@@ -956,6 +1067,10 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
         ATA_LAUNCH_LEAF(MODE_BF16X3_WIDE, LEAF_THREADS);
         return hipGetLastError();
     }
+    if (mode == MODE_FP8 && tile_cfg == 3) {
+        ATA_LAUNCH_LEAF(MODE_FP8_WIDE, LEAF_THREADS);
+        return hipGetLastError();
+    }
     switch (mode) {
         case MODE_F64: ATA_LAUNCH_LEAF(MODE_F64, LEAF_THREADS); break;
         case MODE_F32: ATA_LAUNCH_LEAF(MODE_F32, LEAF_THREADS); break;
@@ -992,6 +1107,8 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_WIDE>, LEAF_THREADS, 0);
     else if (mode == MODE_BF16X3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3>, LEAF_THREADS, 0);
+    else if (mode == MODE_FP8 && tile_cfg == 3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8_WIDE>, LEAF_THREADS, 0);
     else if (mode == MODE_FP8)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8>, LEAF_THREADS, 0);
     else if (mode == MODE_F32)

@@ -84,10 +84,13 @@ def test_precision_forms_16384_sampled(h):
             assert err < 0.1
 
 
-def test_fp8_small_integers_bit_exact(h):
+@pytest.mark.parametrize("tile", [0, 3])
+def test_fp8_small_integers_bit_exact(h, tile):
     rng = np.random.default_rng(61)
-    for (m, n, b, depth) in [(300, 513, 128, 1), (1000, 777, 256, 0), (64, 700, 128, 1), (5, 3, 64, 0)]:
-        _say("case: fp8 int", m, n, b, depth)
+    h.set("leaf_tile", tile)
+    for (m, n, b, depth) in [(300, 513, 128, 1), (1000, 777, 256, 0), (64, 700, 128, 1), (5, 3, 64, 0),
+                             (2000, 900, 1024, 0)]:
+        _say("case: fp8 int", m, n, b, depth, "tile", tile)
         A = rng.integers(-2, 3, (m, n)).astype(np.float32)
         h.set("leaf_cutoff", b)
         h.set("max_depth", depth)
@@ -95,15 +98,16 @@ def test_fp8_small_integers_bit_exact(h):
         assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth)
 
 
-@pytest.mark.parametrize("depth", [0, 1])
-def test_fp8_matches_emulation(h, depth):
+@pytest.mark.parametrize("depth,tile", [(0, 0), (1, 0), (0, 3), (1, 3)])
+def test_fp8_matches_emulation(h, depth, tile):
     """Block-scaled e4m3 leaves against the CPU emulation of the same quantisation."""
     rng = np.random.default_rng(62 + depth)
     m, n, b = 1536, 1100, 256
     A = (rng.standard_normal((m, n)) * np.exp(rng.uniform(-2, 2, n))).astype(np.float32)
     h.set("leaf_cutoff", b)
     h.set("max_depth", depth)
-    _say("case: fp8 emulation depth", depth)
+    h.set("leaf_tile", tile)
+    _say("case: fp8 emulation depth", depth, "tile", tile)
     Cp = run_gram(A, ata.F32_FP8E4M3, h)
     emul = emulate.ata_emulated(A, "fp8", b, max_strassen_depth=depth)
     exact = plain.gram_packed(A)
