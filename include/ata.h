@@ -88,17 +88,19 @@ typedef enum {
     /* Output tile of the leaf kernel.  Split-BF16: 0 = 128 x 128 (default),
        1 = 256 x 128, 2 = 256 x 256 on eight waves, 3 = 256 x 256 on four
        waves of 128 x 128.  FP8: 0 = 128 x 128 (default), 3 = 256 x 256 on
-       four waves of 128 x 128 (1 and 2 act as 0).  FP64 and FP32 ignore it. */
+       four waves of 128 x 128 (1 and 2 act as 0).  FP32: 0 = 128 x 128
+       (default), 3 = 256 x 256 on four waves of 128 x 128 (1 and 2 act as
+       0).  FP64 ignores it. */
     ATA_OPT_LEAF_TILE = 7,
     /* ata_gram_batched: 1 = capture the batch's launch sequence once per
        shape signature in a hipGraph and replay it (default); 0 = enqueue the
        launches directly on the caller's stream. */
     ATA_OPT_BATCH_GRAPH = 8,
     /* Batched leaf products: 0 = one workgroup per tile in longest-first,
-       XCD-grouped order, scheduled by the hardware dispatcher (default: the
-       faster of the two on MI355X, since the persistent loop raises the
-       kernels' register use); 1 = a persistent grid (resident workgroups
-       only) pulling tiles from per-XCD queues.  Results are identical. */
+       XCD-grouped order, scheduled by the hardware dispatcher; 1 = a
+       persistent grid (resident workgroups only) pulling tiles from per-XCD
+       queues; -1 = as ATA_OPT_LEAF_PERSISTENT's automatic choice (default).
+       Results are identical. */
     ATA_OPT_BATCH_PERSISTENT = 9,
     /* Leaf tile order (performance only; results are identical): in every
        window of 8 x XCD_CHUNK consecutive tiles each XCD gets XCD_CHUNK
@@ -128,7 +130,16 @@ typedef enum {
        spread check, and C_ij is scaled back by 2^(e_i + e_j).  All scalings
        are exact; rounding errors become relative to ||a_i|| ||a_j||.  The
        residual option then checks the scaled product.  Default 0. */
-    ATA_OPT_EQUILIBRATE = 14
+    ATA_OPT_EQUILIBRATE = 14,
+    /* Leaf products of single-problem calls (ata_gram, ata_gemm_tn and the
+       forms built on them): 0 = one workgroup per tile, scheduled by the
+       hardware dispatcher; 1 = a persistent grid pulling tiles from per-XCD
+       queues; -1 = automatic (default): persistent for the 256 x 256 FP32
+       tile, whose one resident workgroup per CU leaves the dispatcher's
+       placement of tiles with unequal contractions far from longest-first,
+       and one workgroup per tile otherwise (the persistent loop raises the
+       register use of the smaller tiles).  Results are identical. */
+    ATA_OPT_LEAF_PERSISTENT = 15
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

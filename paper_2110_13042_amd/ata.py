@@ -28,6 +28,7 @@ OPT_RESIDUAL, OPT_WORKSPACE_LIMIT, OPT_RESIDUAL_SEED, OPT_PROFILE = 3, 4, 5, 6
 OPT_LEAF_TILE, OPT_BATCH_GRAPH, OPT_BATCH_PERSISTENT = 7, 8, 9
 OPT_XCD_CHUNK, OPT_TILE_BAND, OPT_SPLIT_TARGET, OPT_BATCH_USE_TABLE = 10, 11, 12, 13
 OPT_EQUILIBRATE = 14
+OPT_LEAF_PERSISTENT = 15
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -246,7 +247,7 @@ class Handle:
                "batch_graph": OPT_BATCH_GRAPH, "batch_persistent": OPT_BATCH_PERSISTENT,
                "xcd_chunk": OPT_XCD_CHUNK, "tile_band": OPT_TILE_BAND,
                "split_target": OPT_SPLIT_TARGET, "batch_use_table": OPT_BATCH_USE_TABLE,
-               "equilibrate": OPT_EQUILIBRATE}[name]
+               "equilibrate": OPT_EQUILIBRATE, "leaf_persistent": OPT_LEAF_PERSISTENT}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

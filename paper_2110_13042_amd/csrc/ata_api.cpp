@@ -181,7 +181,8 @@ struct ata_ctx {
     hipStream_t batch_stream = nullptr;
     hipEvent_t batch_in = nullptr;
     bool batch_graph = true;
-    bool batch_persistent = false;
+    int batch_persistent = -1;         // 0 grid, 1 persistent, -1 automatic
+    int leaf_persistent = -1;
     uint64_t arena_gen = 0;
     // phase profiling: six events per profiled call, summed at report time
     bool profile = false;
@@ -277,10 +278,10 @@ ata_status_t upload_plan(DevicePlan& dp) {
 bool valid_dtype(int d) { return d >= ATA_F64 && d <= ATA_F32_FP8E4M3; }
 
 // Modes with a choice of leaf tile, and the tiles worth timing.
-bool tiled_mode(int32_t mode) { return mode == MODE_BF16X3 || mode == MODE_FP8; }
+bool tiled_mode(int32_t mode) { return mode == MODE_BF16X3 || mode == MODE_FP8 || mode == MODE_F32; }
 std::vector<int32_t> tile_candidates(int32_t mode) {
     if (mode == MODE_BF16X3) return {0, 1, 2, 3};
-    if (mode == MODE_FP8) return {0, 3};
+    if (mode == MODE_FP8 || mode == MODE_F32) return {0, 3};
     return {0};
 }
 
@@ -305,12 +306,14 @@ void choose(const ata_ctx* h, int32_t mode, int64_t m, int64_t n, int64_t& b, in
 
 // Bytes of auxiliary device memory one call needs (flags, norms, residual).
 struct AuxLayout {
-    size_t flags_off = 0, part_off = 0, nu_off = 0, res_work_off = 0, res_off = 0, total = 0;
+    size_t counter_off = 0, flags_off = 0, part_off = 0, nu_off = 0, res_work_off = 0, res_off = 0, total = 0;
 };
 
 AuxLayout aux_layout(const Plan& p, bool residual) {
     AuxLayout a;
     size_t off = 0;
+    a.counter_off = off;                     // eight queue heads of a persistent leaf launch
+    off += 256;
     a.flags_off = off;
     off += align256(std::max<size_t>(p.nodes.size(), 1));
     a.part_off = off;
@@ -323,6 +326,13 @@ AuxLayout aux_layout(const Plan& p, bool residual) {
     off += align256(sizeof(double));
     a.total = off;
     return a;
+}
+
+// Leaf launch form: 1 = persistent, 0 = one workgroup per tile, -1 = the
+// automatic choice (persistent for the 256 x 256 FP32 tile only).
+bool persistent_for(int setting, const Plan& p) {
+    if (setting >= 0) return setting == 1;
+    return p.mode == MODE_F32 && p.tile_cfg == 3;
 }
 
 void fill_report(ata_report_t& r, const Plan& p) {
@@ -423,7 +433,8 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             h->batch_graph = value != 0.0;
             return ATA_OK;
         case ATA_OPT_BATCH_PERSISTENT:
-            h->batch_persistent = value != 0.0;
+            if (value != -1.0 && value != 0.0 && value != 1.0) return ATA_ERR_INVALID_VALUE;
+            h->batch_persistent = (int)value;
             return ATA_OK;
         case ATA_OPT_XCD_CHUNK:
             if (value < 1 || value > 4096) return ATA_ERR_INVALID_VALUE;
@@ -435,6 +446,10 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             return ATA_OK;
         case ATA_OPT_EQUILIBRATE:
             h->equilibrate = value != 0.0;
+            return ATA_OK;
+        case ATA_OPT_LEAF_PERSISTENT:
+            if (value != -1.0 && value != 0.0 && value != 1.0) return ATA_ERR_INVALID_VALUE;
+            h->leaf_persistent = (int)value;
             return ATA_OK;
         case ATA_OPT_BATCH_USE_TABLE:
             h->batch_use_table = value != 0.0;
@@ -628,6 +643,12 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     unsigned char* aux = static_cast<unsigned char*>(h->aux);
+    BatchPtrs pq{nullptr, nullptr, reinterpret_cast<unsigned long long*>(aux + ax.counter_off), 0};
+    const BatchPtrs* lp = nullptr;
+    if (persistent_for(h->leaf_persistent, p)) {
+        pq.persistent_blocks = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
+        lp = &pq;
+    }
     uint8_t* flags = aux + ax.flags_off;
     double* partial = reinterpret_cast<double*>(aux + ax.part_off);
     double* nu = reinterpret_cast<double*>(aux + ax.nu_off);
@@ -662,7 +683,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
-                          flags, h->chunk, h->band, st);
+                          flags, h->chunk, h->band, st, lp);
     if (e == hipSuccess && !p.fb_leaves.empty())
         e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
                                    h->arena, flags, h->chunk, h->band, st);
@@ -772,10 +793,16 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     ata_status_t s = ensure(h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
     if (s != ATA_OK) return s;
     if (h->arena_cap != old_cap) ++h->arena_gen;
-    s = ensure(h->aux, h->aux_cap, 256);
+    s = ensure(h->aux, h->aux_cap, 512);
     if (s != ATA_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint8_t* flags = static_cast<const uint8_t*>(h->aux);     // no predicates in this plan
+    BatchPtrs pq{nullptr, nullptr, reinterpret_cast<unsigned long long*>(static_cast<unsigned char*>(h->aux) + 256), 0};
+    const BatchPtrs* lp = nullptr;
+    if (persistent_for(h->leaf_persistent, p)) {
+        pq.persistent_blocks = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
+        lp = &pq;
+    }
     hipError_t e = hipSuccess;
     hipEvent_t* ev = nullptr;
     if (take_events(h, ev) != ATA_OK) return ATA_ERR_HIP;
@@ -798,7 +825,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     mark(2);
     if (e == hipSuccess)
         e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C, h->arena,
-                          flags, h->chunk, h->band, st, nullptr, B);
+                          flags, h->chunk, h->band, st, lp, B);
     if (e == hipSuccess && !p.reduce.empty())
         e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
                           C, h->arena, flags, st);
@@ -896,7 +923,7 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
     mark(0);
     e = hipMemcpyAsync(be.d_A, be.pinned, sizeof(void*) * 2 * (size_t)be.nprob, hipMemcpyHostToDevice, st);
     const int64_t slots = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
-    BatchPtrs bp{be.d_A, be.d_C, h->batch_persistent ? be.d_counter : nullptr, slots};
+    BatchPtrs bp{be.d_A, be.d_C, persistent_for(h->batch_persistent, p) ? be.d_counter : nullptr, slots};
     BatchPtrs bq{be.d_A, be.d_C, nullptr, 0};
     if (e == hipSuccess && p.fallback) {
         const ColDesc& l1 = be.col1.back();
@@ -1097,7 +1124,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
             if (hipStreamCreateWithFlags(&h->batch_stream, hipStreamNonBlocking) != hipSuccess) return ATA_ERR_HIP;
             if (hipEventCreateWithFlags(&h->batch_in, hipEventDisableTiming) != hipSuccess) return ATA_ERR_HIP;
         }
-        if (!be.exec || be.arena_gen != h->arena_gen || be.graph_persistent != h->batch_persistent) {
+        if (!be.exec || be.arena_gen != h->arena_gen || be.graph_persistent != persistent_for(h->batch_persistent, be.dp->plan)) {
             if (be.exec) {
                 if (be.launched && hipEventSynchronize(be.done) != hipSuccess) return ATA_ERR_HIP;
                 (void)hipGraphExecDestroy(be.exec);
@@ -1115,7 +1142,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
             if (e == hipSuccess) e = hipGraphInstantiate(&be.exec, be.graph, nullptr, nullptr, 0);
             if (e != hipSuccess) return ATA_ERR_HIP;
             be.arena_gen = h->arena_gen;
-            be.graph_persistent = h->batch_persistent;
+            be.graph_persistent = persistent_for(h->batch_persistent, be.dp->plan);
         }
         e = hipEventRecord(h->batch_in, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(h->batch_stream, h->batch_in, 0);

@@ -23,6 +23,8 @@
 // exact in FP32); the tile accumulates Xh^T Yh + Xh^T Yl + Xl^T Yh in FP32.
 // The BF16 MFMA wants each lane's eight consecutive k values of one row i
 // together, so the slab is stored i-major in LDS ([i][k], k contiguous).
+#include <atomic>
+
 #include "kernels_common.hpp"
 #include "launch.hpp"
 
@@ -47,15 +49,37 @@ constexpr int MODE_BF16X3_LARGE = 101;
 constexpr int MODE_BF16X3_HUGE = 102;
 constexpr int MODE_BF16X3_WIDE = 103;
 constexpr int MODE_FP8_WIDE = 104;
+constexpr int MODE_F32_WIDE = 105;
 #ifndef ATA_WIDE_STAGES
 #define ATA_WIDE_STAGES 4     // LDS ring depth of the 256 x 256 split-BF16 engine (32 KB each)
 #endif
+#ifndef ATA_F32W_STAGES
+#define ATA_F32W_STAGES 3
+#endif
+#ifndef ATA_F32W_RS
+#define ATA_F32W_RS 288
+#endif
+// Geometry of the FP32 256 x 256 engine (tile_f32_wide).
+namespace wide32 {
+constexpr int TM = 256, TN = 256;
+constexpr int SK = 16;                        // rows per slab
+constexpr int RS = ATA_F32W_RS;               // LDS row stride in floats
+constexpr int HALF = SK * RS * 4;             // one operand's slab: 18 KB
+constexpr int STAGE = 2 * HALF;
+constexpr int STAGES = ATA_F32W_STAGES;       // slabs kt .. kt + STAGES - 2 are in flight
+// s_waitcnt immediate: vmcnt(v) with lgkmcnt(l) (expcnt unconstrained)
+constexpr int waitcnt_imm(int v, int l) { return (v & 15) | ((v >> 4) << 14) | 0x70 | (l << 8); }
+// loads a wave may still have in flight once slab kt + 1 has landed
+constexpr int LATER = 32 * (STAGES - 2) < 63 ? 32 * (STAGES - 2) : 63;
+}  // namespace wide32
+
 constexpr size_t lds_bytes(int mode) {
     return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
            : mode == MODE_BF16X3_WIDE ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
+           : mode == MODE_F32_WIDE ? (size_t)wide32::STAGES * wide32::STAGE
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
 constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE ? 512 : LEAF_THREADS; }
@@ -185,6 +209,9 @@ __device__ __forceinline__ void store_elem(const LeafDesc& d, int ti, int tj, in
         arena[d.out_off + gi * d.out_ld + gj] = v;
 }
 
+// LDS destination of a buffer load that writes LDS directly.
+#define ATA_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
 // ---------------------------------------------------------------- FP32 MFMA
 __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, int ti, int tj,
                          float* C, float* arena, unsigned char* smem, const KRange& kr) {
@@ -252,6 +279,139 @@ __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, in
                 const int r = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int c = wn * 64 + b * 32 + (lane & 31);
                 store_elem<float>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
+            }
+}
+
+// FP32 with a 256 x 256 tile: four waves of 128 x 128 (4 x 4 blocks of
+// 32 x 32 on v_mfma_f32_32x32x2f32), one wave per SIMD: 16 independent MFMAs
+// (1024 cycles) per pair of k rows against 8 LDS reads.  Slabs of 16 rows
+// stream into three 36 KB LDS stages, X[16][288] then Y[16][288] (rows
+// padded so that the two k rows one read serves fall in opposite bank
+// halves), through 4-byte buffer loads that write LDS directly.  Each load
+// covers 64 columns of one row through a buffer resource based at that row
+// and sized to the view's physical columns, or to nothing for rows past K:
+// the hardware's range check supplies the zero padding, with no offsets
+// that grow with the matrix.  The schedule is fixed by hand: the operands of
+// pair kk + 1 are read and one slab row of slab kt + 2 is issued under the
+// MFMAs of pair kk, and the one barrier per slab sits inside the last pair,
+// after which the first operands of slab kt + 1 are read, so the matrix
+// cores do not wait on LDS latency at the slab boundary.
+
+__device__ __forceinline__ void tile_f32_wide(const LeafDesc& d, const float* Xp, const float* Yp, int ti, int tj,
+                                              float* C, float* arena, unsigned char* smem, const KRange& kr) {
+    using namespace wide32;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 1, wn = w & 1;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t nk = (K + SK - 1) / SK;
+    // wave w streams operand (w < 2 ? X : Y), slab rows 8 (w % 2) .. + 7
+    const bool isx = w < 2;
+    const int64_t ld = isx ? d.X.ld : d.Y.ld;
+    const float* P = (isx ? Xp : Yp) + kr.kb * ld;
+    const int prow = (int)((isx ? d.X.pcols : d.Y.pcols) * 4);      // bytes of one physical row
+    const uint32_t cbyte = (uint32_t)(((isx ? (int64_t)ti * TM : (int64_t)tj * TN) + lane) * 4);
+    const int r0 = (w & 1) * 8;
+    // 64 columns (segment seg) of this wave's slab row `part` of slab kt into stage st
+    auto issue = [&](int64_t kt, int st, int part, int seg) {
+        const int rr = r0 + part;
+        const int64_t row = kt * SK + rr;
+        const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(P + row * ld), (short)0, row < K ? prow : 0, 0x00020000);
+        unsigned char* base = smem + st * STAGE + (isx ? 0 : HALF) + rr * RS * 4;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + seg * 256), 4, (int)(cbyte + seg * 256),
+                                                 0, 0, 0);
+    };
+    auto issue_row = [&](int64_t kt, int st, int part) {
+#pragma unroll
+        for (int seg = 0; seg < 4; ++seg) issue(kt, st, part, seg);
+    };
+
+    v16f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    const int ko = lane >> 5, io = lane & 31;
+    float a[2][4], b[2][4];
+    auto read = [&](int st, int kk, int buf) {
+        const float* xs = reinterpret_cast<const float*>(smem + st * STAGE) + wm * 128 + io + (2 * kk + ko) * RS;
+        const float* ys = reinterpret_cast<const float*>(smem + st * STAGE + HALF) + wn * 128 + io + (2 * kk + ko) * RS;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[buf][q] = xs[q * 32];
+            b[buf][q] = ys[q * 32];
+        }
+    };
+    auto mfma = [&](int buf, int i0, int i1) {
+#pragma unroll
+        for (int i = i0; i < i1; ++i)
+            acc[i >> 2][i & 3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][i >> 2], b[buf][i & 3],
+                                                                      acc[i >> 2][i & 3], 0, 0, 0);
+    };
+
+    // Slabs past the end read as zeros, so every step issues the same 32
+    // loads per wave and one wait count serves every step.
+#pragma unroll
+    for (int part = 0; part < 8; ++part) issue_row(0, 0, part);
+#pragma unroll
+    for (int sl = 1; sl < STAGES - 1; ++sl)
+#pragma unroll
+        for (int part = 0; part < 8; ++part) issue_row(sl, sl, part);
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(LATER, 15));   // slab 0 has landed
+    __builtin_amdgcn_s_barrier();
+    read(0, 0, 0);
+    int cur = 0, nxt = 1, fill = STAGES - 1;      // stages of slabs kt, kt + 1, kt + STAGES - 1
+    for (int64_t kt = 0; kt < nk; ++kt) {
+#pragma unroll
+        for (int kk = 0; kk < SK / 2 - 1; ++kk) {
+            const int buf = kk & 1;
+            mfma(buf, 0, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            read(cur, kk + 1, buf ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+            // one load between consecutive MFMAs: a load that holds up issue
+            // then delays no MFMA
+            const int nl = kk == SK / 2 - 2 ? 8 : 4;
+#pragma unroll
+            for (int l = 0; l < nl; ++l) {
+                mfma(buf, 1 + l, 2 + l);
+                __builtin_amdgcn_sched_barrier(0);
+                issue(kt + STAGES - 1, fill, kk + (l >> 2), l & 3);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            mfma(buf, 1 + nl, 16);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        mfma(1, 0, 4);
+        __builtin_amdgcn_sched_barrier(0);
+        // slab kt + 1 has landed (only later slabs' loads may be pending) and
+        // this wave's reads of slab kt are done, so after the barrier slab
+        // kt + 1 is visible and slab kt's stage free
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm(LATER, 0));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        read(nxt, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma(1, 4, 16);
+        __builtin_amdgcn_sched_barrier(0);
+        cur = nxt;
+        nxt = nxt == STAGES - 1 ? 0 : nxt + 1;
+        fill = fill == STAGES - 1 ? 0 : fill + 1;
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);           // the zero slabs past the end have landed
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int c = wn * 128 + b * 32 + (lane & 31);
+                store_elem<float, TM, TN>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
             }
 }
 
@@ -470,7 +630,6 @@ constexpr size_t LDS = (size_t)STAGES * STAGE;
 constexpr int LOADS = 8;                      // buffer->LDS loads per wave per slab
 }  // namespace wide
 
-#define ATA_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 
 // s_waitcnt until at most 8 n loads of this wave are outstanding (n in 0..3).
 __device__ __forceinline__ void wait_slabs(int64_t n) {
@@ -961,6 +1120,10 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
         if (flagged) return;
         tile_bf16x3<BfLarge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
                              static_cast<float*>(args.arena), smem, kr);
+    } else if constexpr (MODE == MODE_F32_WIDE) {
+        if (flagged) return;
+        tile_f32_wide(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
+                      ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FP8_WIDE) {
         if (flagged) return;
         tile_fp8_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
@@ -1071,6 +1234,10 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
         ATA_LAUNCH_LEAF(MODE_FP8_WIDE, LEAF_THREADS);
         return hipGetLastError();
     }
+    if (mode == MODE_F32 && tile_cfg == 3) {
+        ATA_LAUNCH_LEAF(MODE_F32_WIDE, LEAF_THREADS);
+        return hipGetLastError();
+    }
     switch (mode) {
         case MODE_F64: ATA_LAUNCH_LEAF(MODE_F64, LEAF_THREADS); break;
         case MODE_F32: ATA_LAUNCH_LEAF(MODE_F32, LEAF_THREADS); break;
@@ -1097,6 +1264,13 @@ hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t n
 namespace ata {
 
 int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
+    // cached per (mode, tile): the answer depends on the compiled kernels only
+    static std::atomic<int> cache[8][4];
+    const bool cacheable = mode >= 0 && mode < 8 && tile_cfg >= 0 && tile_cfg < 4;
+    if (cacheable) {
+        const int c = cache[mode][tile_cfg].load(std::memory_order_relaxed);
+        if (c > 0) return c;
+    }
     int nb = 0;
     hipError_t e = hipSuccess;
     if (mode == MODE_BF16X3 && tile_cfg == 1)
@@ -1107,6 +1281,8 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_WIDE>, LEAF_THREADS, 0);
     else if (mode == MODE_BF16X3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3>, LEAF_THREADS, 0);
+    else if (mode == MODE_F32 && tile_cfg == 3)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F32_WIDE>, LEAF_THREADS, 0);
     else if (mode == MODE_FP8 && tile_cfg == 3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8_WIDE>, LEAF_THREADS, 0);
     else if (mode == MODE_FP8)
@@ -1115,7 +1291,9 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F32>, LEAF_THREADS, 0);
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F64>, LEAF_THREADS, 0);
-    return e == hipSuccess && nb > 0 ? nb : 1;
+    if (e != hipSuccess || nb <= 0) return 1;
+    if (cacheable) cache[mode][tile_cfg].store(nb, std::memory_order_relaxed);
+    return nb;
 }
 
 }  // namespace ata

@@ -378,7 +378,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, n);
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
-    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : mode == MODE_FP8 && opt.tile_cfg == 3 ? 3 : 0;
+    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : 0;
     if (n == 0) return p;
     Builder bld(p);
     bld.ata(0, n);
@@ -452,7 +452,7 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, std::max(n, k));
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = false;
-    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : mode == MODE_FP8 && opt.tile_cfg == 3 ? 3 : 0;
+    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : 0;
     if (n == 0 || k == 0) return p;
     Builder bld(p);
     View X{};

@@ -201,3 +201,61 @@ def test_full_size_square_f32_8192_sampled(h):
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     _say("  e_S", err, h.report())
     assert err <= 2e-5
+
+
+def test_f32_wide_tile(h):
+    """FP32 leaves on the 256 x 256 tile: exact on integers (Strassen levels,
+    odd splits, a leading dimension that is not a multiple of four, split-K
+    on a tall input) and within 2e-5 of the oracle on random data."""
+    rng = np.random.default_rng(44)
+    h.set("leaf_tile", 3)
+    h.set("spread_tau", 0)
+    try:
+        for (m, n, b, depth, lda) in [(1, 1, 64, 0, 1), (3, 2, 64, 0, 2), (257, 255, 64, 2, 255),
+                                      (300, 513, 100, 1, 515), (1000, 777, 128, 2, 777),
+                                      (64, 1500, 256, 1, 1501), (20000, 300, 300, 0, 301),
+                                      (513, 1025, 512, 1, 1025)]:
+            _say("case: f32 wide int", m, n, b, depth, "lda", lda)
+            A = rng.integers(-2, 3, (m, n)).astype(np.float32)
+            h.set("leaf_cutoff", b)
+            h.set("max_depth", depth)
+            Cp = run_gram(A, ata.F32, h, lda=lda)
+            assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth, lda)
+        for (m, n, b, depth) in [(1031, 1029, 256, 2), (4096, 1536, 512, 1), (129, 1100, 256, 2)]:
+            _say("case: f32 wide random", m, n, b, depth)
+            A = rng.uniform(-1, 1, (m, n)).astype(np.float32)
+            h.set("leaf_cutoff", b)
+            h.set("max_depth", depth)
+            Cp = run_gram(A, ata.F32, h)
+            err = full_error(Cp, plain.gram_packed(A))
+            _say("  e_F", err)
+            assert err <= TOL[ata.F32]
+    finally:
+        h.set("leaf_tile", 0)
+        h.set("spread_tau", 4096)
+
+
+@pytest.mark.parametrize("mode,tile", [(ata.F32, 3), (ata.F32, 0), (ata.F64, 0)])
+def test_persistent_leaf_launch_matches_grid(h, mode, tile):
+    """The persistent leaf launch (per-XCD tile queues) and the one-workgroup-
+    per-tile launch give bit-identical results, on a plan with unequal
+    contractions (Strassen levels) and on a split-K plan."""
+    rng = np.random.default_rng(45)
+    h.set("leaf_tile", tile)
+    try:
+        for (m, n, b, depth) in [(3000, 1100, 256, 2), (40000, 300, 300, 0)]:
+            _say("case: persistent vs grid", mode, "tile", tile, m, n, b, depth)
+            A = rng.uniform(-1, 1, (m, n))
+            h.set("leaf_cutoff", b)
+            h.set("max_depth", depth)
+            outs = []
+            for pers in (0, 1):
+                h.set("leaf_persistent", pers)
+                outs.append(run_gram(A, mode, h))
+            assert np.array_equal(outs[0], outs[1])
+            err = full_error(outs[1], plain.gram_packed(A))
+            _say("  e_F", err)
+            assert err <= TOL[mode]
+    finally:
+        h.set("leaf_persistent", -1)
+        h.set("leaf_tile", 0)
