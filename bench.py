@@ -141,13 +141,14 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
                  "multiplications": rep["multiplications"],
                  "mult_ratio_vs_syrk": round(rep["multiplications"] / (m * n * (n + 1) / 2), 4),
                  "launches_per_step": rep["kernel_launches"], "workspace_bytes": rep["workspace_bytes"],
-                 "leaf_tile": args.leaf_tile if not tuned else tuned["leaf_tile"]},
+                 "leaf_tile": rep["leaf_tile"],
+                 "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile"},
         "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
             ["norms_flags", "presum_pack", "leaves", "combine", "residual"], rep["phase_ms"])},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": traffic_from_profiles(mode, wl),
-                     "kernel": "leaf_kernel (every SYRK/GEMM leaf product of the plan, one grouped launch)",
+                     "kernel": "leaf kernel (every SYRK/GEMM leaf product of the plan, one grouped launch)",
                      "algorithmic_flops_per_launch": leaf_flops,
                      "avg_launch_ms": round(leaf_ms, 4)},
     }
@@ -236,7 +237,8 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
         "separate_calls": {"ms_per_step": round(ms_sep, 4),
                            "value": round(work / (ms_sep * 1e-3) / 1e12, 3)},
         "plan": {"problems": len(As), "multiplications": rep["multiplications"],
-                 "leaf_launch": "persistent" if args.batch_persistent else "one workgroup per tile",
+                 "leaf_tile": rep["leaf_tile"],
+                 "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile",
                  "batch_autotune": tuned,
                  "leaves": rep["syrk_leaves"] + rep["gemm_leaves"],
                  "strassen_nodes": rep["strassen_nodes"], "launches_per_step": rep["kernel_launches"],
@@ -245,7 +247,7 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
             ["norms_flags", "presum_pack", "leaves", "combine", "residual"], prof["phase_ms"])},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel": "leaf_kernel (persistent, every leaf of the 512 merged plans)",
+                     "kernel": "leaf kernel (every leaf of the 512 merged plans, one grouped launch)",
                      "algorithmic_flops_per_launch": leaf_flops, "avg_launch_ms": round(leaf_ms, 4),
                      "timed_on": "eager batched calls (same merged plan, events on the caller's stream)"},
     }
@@ -343,8 +345,9 @@ def main() -> int:
     ap.add_argument("--tune-save", default="", help="with --autotune: merge the choices into this table")
     ap.add_argument("--no-batch-autotune", action="store_true",
                     help="batched workload: skip the (untimed) batch autotuner")
-    ap.add_argument("--batch-persistent", type=int, default=0,
-                    help="batched leaf launch: 1 = persistent grid with per-XCD queues, 0 = one workgroup per tile")
+    ap.add_argument("--batch-persistent", type=int, default=-1,
+                    help="batched leaf launch: 1 = persistent grid with per-XCD queues, 0 = one workgroup per tile, "
+                         "-1 = the library's automatic choice")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

@@ -162,6 +162,10 @@ typedef struct {
     int64_t profiled_calls;       /* calls timed since ATA_OPT_PROFILE was set */
     double phase_ms[5];           /* summed ms: column norms + flags, pre-sums,
                                      leaf products, combines, residual        */
+    int32_t leaf_tile;            /* leaf tile configuration of the plan
+                                     (ATA_OPT_LEAF_TILE's values)             */
+    int32_t leaf_persistent;      /* 1 = the leaf products ran as a persistent
+                                     grid, 0 = one workgroup per tile          */
 } ata_report_t;
 
 /* One leaf of a plan, as returned by ata_plan_query. */

@@ -48,7 +48,8 @@ class Report(ctypes.Structure):
                 ("strassen_nodes", ctypes.c_int64), ("multiplications", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("kernel_launches", ctypes.c_int64),
                 ("flagged_nodes", ctypes.c_int64), ("residual", ctypes.c_double),
-                ("profiled_calls", ctypes.c_int64), ("phase_ms", ctypes.c_double * 5)]
+                ("profiled_calls", ctypes.c_int64), ("phase_ms", ctypes.c_double * 5),
+                ("leaf_tile", ctypes.c_int32), ("leaf_persistent", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

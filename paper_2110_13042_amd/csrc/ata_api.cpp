@@ -351,6 +351,8 @@ void fill_report(ata_report_t& r, const Plan& p) {
     r.kernel_launches = p.launches();
     r.flagged_nodes = -1;
     r.residual = -1.0;
+    r.leaf_tile = p.tile_cfg;
+    r.leaf_persistent = 0;
 }
 
 }  // namespace
@@ -703,6 +705,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     if (e != hipSuccess) return ATA_ERR_HIP;
 
     fill_report(h->report, p);
+    h->report.leaf_persistent = lp ? 1 : 0;
     h->last_stream = st;
     h->pending_flags = p.fallback;
     h->pending_residual = h->residual;
@@ -839,6 +842,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     mark(5);
     if (e != hipSuccess) return ATA_ERR_HIP;
     fill_report(h->report, p);
+    h->report.leaf_persistent = lp ? 1 : 0;
     return ATA_OK;
 }
 
@@ -1153,6 +1157,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     if (e != hipSuccess) return ATA_ERR_HIP;
     be.launched = true;
     fill_report(h->report, mp);
+    h->report.leaf_persistent = persistent_for(h->batch_persistent, mp) ? 1 : 0;
     h->report.m = 0;
     h->report.n = 0;
     h->report.lda = 0;

@@ -2,12 +2,15 @@
 declares, plans like the oracle's recursion, and rejects bad arguments before
 touching a device (CPU only)."""
 import ctypes
+import os
 
 import numpy as np
 import pytest
 
 from oracle import recursive
 from paper_2110_13042_amd import ata
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -111,3 +114,30 @@ def test_plan_splits_k_only_for_long_contractions_with_few_tiles():
     # contractions shorter than two chunks are never split
     _, leaves = ata.ata_plan_query(400, 300, ata.F32, 1024, 0)
     assert all(L["ksplit"] == 1 for L in leaves)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's ctypes mirrors have the sizes and field offsets the C
+    compiler gives the structs of include/ata.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"ata_report_t": ata.Report, "ata_leaf_t": ata.Leaf, "ata_tune_entry_t": ata.TuneEntry}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "ata.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
