@@ -171,6 +171,8 @@ def make_handle(ata, args):
         h.set("tile_band", args.tile_band)
     if args.equilibrate:
         h.set("equilibrate", 1)
+    if args.fuse_presum:
+        h.set("fuse_presum", 1)
     return h
 
 
@@ -348,6 +350,8 @@ def main() -> int:
     ap.add_argument("--batch-persistent", type=int, default=-1,
                     help="batched leaf launch: 1 = persistent grid with per-XCD queues, 0 = one workgroup per tile, "
                          "-1 = the library's automatic choice")
+    ap.add_argument("--fuse-presum", action="store_true",
+                    help="FP32/FP64: form the last Strassen level's pre-sums inside the leaf loads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

@@ -139,7 +139,18 @@ typedef enum {
        placement of tiles with unequal contractions far from longest-first,
        and one workgroup per tile otherwise (the persistent loop raises the
        register use of the smaller tiles).  Results are identical. */
-    ATA_OPT_LEAF_PERSISTENT = 15
+    ATA_OPT_LEAF_PERSISTENT = 15,
+    /* FP64 and FP32: 1 = a Strassen node whose seven products are all leaves
+       forms its pre-sums S1..S5, T1..T5 (Sec. 3.2) while its leaves load
+       their operands: each operand element is the same single IEEE sum or
+       difference of two quadrant elements that the pre-sum pass would have
+       stored, so results are bit-identical, without the pass and its
+       workspace; 0 = the pre-sums are written to the workspace first
+       (default: on MI355X the leaves reading two quadrants per fused
+       operand lose more time than the streaming pre-sum pass costs).
+       Split-BF16 and FP8 always form their last-level pre-sums in the
+       operand packing / quantisation pass. */
+    ATA_OPT_FUSE_PRESUM = 16
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

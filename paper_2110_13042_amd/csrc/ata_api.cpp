@@ -32,9 +32,10 @@ struct PlanKey {
     bool fb;
     int32_t tile_cfg;
     int64_t split;
+    bool fuse;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split) <
-               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split);
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse) <
+               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse);
     }
 };
 
@@ -73,10 +74,11 @@ struct BatchKey {
     bool fb;
     int32_t tile_cfg;
     int64_t split;
+    bool fuse;
     std::vector<int64_t> shapes;   // m, n, lda per problem
     bool operator<(const BatchKey& o) const {
-        return std::tie(mode, b, depth, fb, tile_cfg, split, shapes) <
-               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.shapes);
+        return std::tie(mode, b, depth, fb, tile_cfg, split, fuse, shapes) <
+               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.shapes);
     }
 };
 
@@ -86,9 +88,10 @@ struct GemmKey {
     int64_t m, n, k, lda, ldb, ldc, b;
     int32_t depth, tile_cfg;
     int64_t split;
+    bool fuse;
     bool operator<(const GemmKey& o) const {
-        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split) <
-               std::tie(o.mode, o.m, o.n, o.k, o.lda, o.ldb, o.ldc, o.b, o.depth, o.tile_cfg, o.split);
+        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split, fuse) <
+               std::tie(o.mode, o.m, o.n, o.k, o.lda, o.ldb, o.ldc, o.b, o.depth, o.tile_cfg, o.split, o.fuse);
     }
 };
 
@@ -453,6 +456,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             if (value != -1.0 && value != 0.0 && value != 1.0) return ATA_ERR_INVALID_VALUE;
             h->leaf_persistent = (int)value;
             return ATA_OK;
+        case ATA_OPT_FUSE_PRESUM:
+            h->popt.fuse_presum = value != 0.0;
+            return ATA_OK;
         case ATA_OPT_BATCH_USE_TABLE:
             h->batch_use_table = value != 0.0;
             return ATA_OK;
@@ -608,7 +614,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     int32_t depth, tile_cfg;
     choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
-    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target};
+    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -618,6 +624,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         o.spread_tau = fb ? h->popt.spread_tau : 0.0;
         o.tile_cfg = tile_cfg;
         o.split_target = h->split_target;
+        o.fuse_presum = h->popt.fuse_presum;
         try {
             dp->plan = make_plan(mode, m, n, lda, o);
         } catch (const std::invalid_argument&) {
@@ -765,7 +772,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     int64_t b;
     int32_t depth, tile_cfg;
     choose(h, mode, m, std::max(n, k), b, depth, tile_cfg);
-    const GemmKey key{mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, h->split_target};
+    const GemmKey key{mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, h->split_target, h->popt.fuse_presum};
     auto it = h->gemm_plans.find(key);
     if (it == h->gemm_plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -775,6 +782,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
         o.spread_tau = 0.0;
         o.tile_cfg = tile_cfg;
         o.split_target = h->split_target;
+        o.fuse_presum = h->popt.fuse_presum;
         try {
             dp->plan = make_gemm_plan(mode, m, n, k, lda, ldb, ldc, o);
         } catch (const std::invalid_argument&) {
@@ -1014,7 +1022,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     }
     std::vector<int64_t> bs((size_t)batch);
     std::vector<int32_t> ds((size_t)batch);
-    BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, h->split_target, {}};
+    BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum, {}};
     key.shapes.reserve(5 * (size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
         int32_t tile_i;
@@ -1043,6 +1051,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
                 o.spread_tau = fb ? h->popt.spread_tau : 0.0;
                 o.tile_cfg = tile_cfg;
                 o.split_target = 0;          // the merged plan is split as a whole
+                o.fuse_presum = h->popt.fuse_presum;
                 parts.push_back(make_plan(mode, m[i], n[i], lda[i], o));
             }
             be->dp = std::make_unique<DevicePlan>();

@@ -79,10 +79,14 @@ constexpr size_t lds_bytes(int mode) {
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
            : mode == MODE_BF16X3_WIDE ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
-           : mode == MODE_F32_WIDE ? (size_t)wide32::STAGES * wide32::STAGE
+           : mode == MODE_F32_WIDE ? (size_t)(wide32::STAGES * wide32::STAGE > 8 * wide32::HALF ? wide32::STAGES * wide32::STAGE : 8 * wide32::HALF)
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
 constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE ? 512 : LEAF_THREADS; }
+// Resident workgroups per CU the one-tile-per-workgroup kernel is compiled
+// for: the 128 x 128 FP32 engine keeps four (64 VGPRs + 64 accumulators per
+// lane) with its fused pre-sum loads included.
+constexpr int min_blocks_for(int mode) { return mode == MODE_F32 ? 4 : 1; }
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
@@ -209,20 +213,42 @@ __device__ __forceinline__ void store_elem(const LeafDesc& d, int ti, int tj, in
         arena[d.out_off + gi * d.out_ld + gj] = v;
 }
 
+// Rows of a view inside its physical extent, counted from the K chunk's
+// first row and clipped to the chunk.
+__device__ __forceinline__ int64_t rows_in(const View& v, const KRange& kr) {
+    const int64_t r = v.prows - kr.kb, K = kr.ke - kr.kb;
+    return r < 0 ? 0 : r < K ? r : K;
+}
+
+// a + s b for a fused pre-sum (s = +1 or -1: the exact product, one rounding,
+// i.e. the IEEE sum or difference the pre-sum pass stores).
+__device__ __forceinline__ float4 add_term(float4 a, float4 b, float s) {
+    return make_float4(fmaf(s, b.x, a.x), fmaf(s, b.y, a.y), fmaf(s, b.z, a.z), fmaf(s, b.w, a.w));
+}
+__device__ __forceinline__ double2 add_term(double2 a, double2 b, double s) {
+    return make_double2(fma(s, b.x, a.x), fma(s, b.y, a.y));
+}
+
 // LDS destination of a buffer load that writes LDS directly.
 #define ATA_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 
 // ---------------------------------------------------------------- FP32 MFMA
-__device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, int ti, int tj,
-                         float* C, float* arena, unsigned char* smem, const KRange& kr) {
+__device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, const float* X2p, const float* Y2p,
+                         int ti, int tj, float* C, float* arena, unsigned char* smem, const KRange& kr) {
     Xp += kr.kb * d.X.ld;
     Yp += kr.kb * d.Y.ld;
+    X2p += kr.kb * d.X2.ld;
+    Y2p += kr.kb * d.Y2.ld;
+    const int64_t xl = rows_in(d.X, kr), yl = rows_in(d.Y, kr);
+    const int64_t x2l = d.sx2 ? rows_in(d.X2, kr) : 0, y2l = d.sy2 ? rows_in(d.Y2, kr) : 0;
+    const float sx = (float)d.sx2, sy = (float)d.sy2;
     float* Xs = reinterpret_cast<float*>(smem);          // [2][BK][LD32]
     float* Ys = Xs + 2 * BK * LD32;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
     const int lr = t >> 5, lc = (t & 31) << 2;
     const int64_t xc = (int64_t)ti * TILE_M + lc, yc = (int64_t)tj * TILE_N + lc;
     const bool xv = vec_ok(Xp, d.X.ld, 4), yv = vec_ok(Yp, d.Y.ld, 4);
+    const bool x2v = vec_ok(X2p, d.X2.ld, 4), y2v = vec_ok(Y2p, d.Y2.ld, 4);
     const int64_t K = kr.ke - kr.kb;
     const int64_t nk = (K + BK - 1) / BK;
 
@@ -233,10 +259,18 @@ __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, in
 
     float4 rx0, rx1, ry0, ry1;
     auto gload = [&](int64_t k0) {
-        rx0 = load4f(Xp, d.X.ld, k0 + lr, xc, K, d.X.pcols, xv);
-        rx1 = load4f(Xp, d.X.ld, k0 + lr + 8, xc, K, d.X.pcols, xv);
-        ry0 = load4f(Yp, d.Y.ld, k0 + lr, yc, K, d.Y.pcols, yv);
-        ry1 = load4f(Yp, d.Y.ld, k0 + lr + 8, yc, K, d.Y.pcols, yv);
+        rx0 = load4f(Xp, d.X.ld, k0 + lr, xc, xl, d.X.pcols, xv);
+        rx1 = load4f(Xp, d.X.ld, k0 + lr + 8, xc, xl, d.X.pcols, xv);
+        ry0 = load4f(Yp, d.Y.ld, k0 + lr, yc, yl, d.Y.pcols, yv);
+        ry1 = load4f(Yp, d.Y.ld, k0 + lr + 8, yc, yl, d.Y.pcols, yv);
+        if (d.sx2) {
+            rx0 = add_term(rx0, load4f(X2p, d.X2.ld, k0 + lr, xc, x2l, d.X2.pcols, x2v), sx);
+            rx1 = add_term(rx1, load4f(X2p, d.X2.ld, k0 + lr + 8, xc, x2l, d.X2.pcols, x2v), sx);
+        }
+        if (d.sy2) {
+            ry0 = add_term(ry0, load4f(Y2p, d.Y2.ld, k0 + lr, yc, y2l, d.Y2.pcols, y2v), sy);
+            ry1 = add_term(ry1, load4f(Y2p, d.Y2.ld, k0 + lr + 8, yc, y2l, d.Y2.pcols, y2v), sy);
+        }
     };
     auto sstore = [&](int buf) {
         float* xs = Xs + buf * BK * LD32;
@@ -403,6 +437,146 @@ __device__ __forceinline__ void tile_f32_wide(const LeafDesc& d, const float* Xp
         fill = fill == STAGES - 1 ? 0 : fill + 1;
     }
     __builtin_amdgcn_s_waitcnt(0x0F70);           // the zero slabs past the end have landed
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int c = wn * 128 + b * 32 + (lane & 31);
+                store_elem<float, TM, TN>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
+            }
+}
+
+// The same engine for leaves with fused pre-sums: a side whose operand is
+// the sum or difference of two views streams both into LDS and combines them
+// as the MFMA operands are read (the IEEE sum or difference the pre-sum pass
+// would have stored; a plain side skips the combine).  Two 72 KB stages of
+// X, X2, Y and Y2 slabs; slab kt + 1 is loaded under the first k-row pairs
+// of slab kt, one load between consecutive MFMAs.  V16: every term's rows
+// start 16-byte aligned and hold a multiple of four physical columns, so one
+// 16-byte load per lane moves a whole 256-column row (16 loads per wave per
+// slab); otherwise 4-byte loads (64 per wave per slab).
+template <bool V16>
+__device__ __forceinline__ void tile_f32_wide_sum(const LeafDesc& d, const float* Xp, const float* Yp,
+                                                  const float* X2p, const float* Y2p, int ti, int tj,
+                                                  float* C, float* arena, unsigned char* smem, const KRange& kr) {
+    using namespace wide32;
+    constexpr int QS = 4 * HALF;                  // one stage: X, X2, Y, Y2
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 1, wn = w & 1;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t nk = (K + SK - 1) / SK;
+    // wave w streams both terms of side (w < 2 ? X : Y), slab rows 8 (w % 2) .. + 7
+    // every descriptor field the loop needs, read once (the loads that
+    // write LDS are opaque memory operations, so the compiler would re-read
+    // the descriptor after each one)
+    const bool isx = w < 2;
+    const int64_t lda_ = isx ? d.X.ld : d.Y.ld, ldb_ = isx ? d.X2.ld : d.Y2.ld;
+    const bool two = (isx ? d.sx2 : d.sy2) != 0;
+    const float* Pa = (isx ? Xp : Yp) + kr.kb * lda_;
+    const float* Pb = (isx ? X2p : Y2p) + kr.kb * ldb_;
+    const int64_t la = isx ? rows_in(d.X, kr) : rows_in(d.Y, kr);
+    const int64_t lb = !two ? 0 : isx ? rows_in(d.X2, kr) : rows_in(d.Y2, kr);
+    const int pa = (int)((isx ? d.X.pcols : d.Y.pcols) * 4), pb = (int)((isx ? d.X2.pcols : d.Y2.pcols) * 4);
+    const int64_t col0 = isx ? (int64_t)ti * TM : (int64_t)tj * TN;
+    const uint32_t cbyte = (uint32_t)((col0 + (V16 ? 4 : 1) * lane) * 4);
+    const int r0 = (w & 1) * 8;
+    constexpr int NL = V16 ? 16 : 64;             // loads per wave per slab
+    // load l of this wave's share of slab kt: term, row and (4-byte form) 64-column segment
+    auto issue = [&](int64_t kt, int st, int l) {
+        const int term = V16 ? l >> 3 : l >> 5;
+        const int rr = r0 + (V16 ? l & 7 : (l >> 2) & 7), seg = V16 ? 0 : l & 3;
+        const int64_t row = kt * SK + rr;
+        const float* rp = term ? Pb + row * ldb_ : Pa + row * lda_;
+        const int nrec = row < (term ? lb : la) ? (term ? pb : pa) : 0;
+        const __amdgpu_buffer_rsrc_t src =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(rp), (short)0, nrec, 0x00020000);
+        unsigned char* base = smem + st * QS + (isx ? 0 : 2 * HALF) + term * HALF + rr * RS * 4;
+        if constexpr (V16)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base), 16, (int)cbyte, 0, 0, 0);
+        else
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + seg * 256), 4, (int)(cbyte + seg * 256),
+                                                     0, 0, 0);
+    };
+
+    v16f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    const int ko = lane >> 5, io = lane & 31;
+    const int sx2 = __builtin_amdgcn_readfirstlane(d.sx2), sy2 = __builtin_amdgcn_readfirstlane(d.sy2);
+    const bool fx = sx2 != 0, fy = sy2 != 0;
+    const float sx = (float)sx2, sy = (float)sy2;
+    float a[2][4], b[2][4];
+    auto read = [&](int st, int kk, int buf) {
+        const float* xs = reinterpret_cast<const float*>(smem + st * QS) + wm * 128 + io + (2 * kk + ko) * RS;
+        const float* ys = reinterpret_cast<const float*>(smem + st * QS + 2 * HALF) + wn * 128 + io +
+                          (2 * kk + ko) * RS;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float x1 = xs[q * 32], x2 = xs[HALF / 4 + q * 32];
+            const float y1 = ys[q * 32], y2 = ys[HALF / 4 + q * 32];
+            a[buf][q] = fx ? fmaf(sx, x2, x1) : x1;
+            b[buf][q] = fy ? fmaf(sy, y2, y1) : y1;
+        }
+    };
+    auto mfma = [&](int buf, int i0, int i1) {
+#pragma unroll
+        for (int i = i0; i < i1; ++i)
+            acc[i >> 2][i & 3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][i >> 2], b[buf][i & 3],
+                                                                      acc[i >> 2][i & 3], 0, 0, 0);
+    };
+
+#pragma unroll
+    for (int l = 0; l < NL; ++l) issue(0, 0, l);
+    __builtin_amdgcn_s_waitcnt(0x0F70);           // vmcnt(0): slab 0 has landed
+    __builtin_amdgcn_s_barrier();
+    read(0, 0, 0);
+    int cur = 0;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int nxt = cur ^ 1;
+#pragma unroll
+        for (int kk = 0; kk < SK / 2 - 1; ++kk) {
+            const int buf = kk & 1;
+            mfma(buf, 0, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            read(cur, kk + 1, buf ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kk < NL / 16) {
+                // slab kt + 1 (zeros past the end) into the stage slab kt - 1 left
+#pragma unroll
+                for (int l = 0; l < 15; ++l) {
+                    mfma(buf, 1 + l, 2 + l);
+                    __builtin_amdgcn_sched_barrier(0);
+                    issue(kt + 1, nxt, kk * 16 + l);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                issue(kt + 1, nxt, kk * 16 + 15);
+            } else {
+                mfma(buf, 1, 16);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        mfma(1, 0, 4);
+        __builtin_amdgcn_sched_barrier(0);
+        // slab kt + 1 has landed and this wave's reads of slab kt are done:
+        // after the barrier slab kt + 1 is visible and slab kt's stage free
+        __builtin_amdgcn_s_waitcnt(0x0070);       // vmcnt(0) lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        read(nxt, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma(1, 4, 16);
+        __builtin_amdgcn_sched_barrier(0);
+        cur = nxt;
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -975,10 +1149,14 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
 // InT = double (FP64 mode) or float (FP64 fallback of the FP32 family: the
 // inputs are promoted exactly, the result is rounded to OutT on store).
 template <class InT, class OutT>
-__device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, int ti, int tj,
-                         OutT* C, OutT* arena, unsigned char* smem, const KRange& kr) {
+__device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, const InT* X2p, const InT* Y2p,
+                         int ti, int tj, OutT* C, OutT* arena, unsigned char* smem, const KRange& kr) {
     Xp += kr.kb * d.X.ld;
     Yp += kr.kb * d.Y.ld;
+    X2p += kr.kb * d.X2.ld;
+    Y2p += kr.kb * d.Y2.ld;
+    const int64_t xl = rows_in(d.X, kr), yl = rows_in(d.Y, kr);
+    const int64_t x2l = d.sx2 ? rows_in(d.X2, kr) : 0, y2l = d.sy2 ? rows_in(d.Y2, kr) : 0;
     double* Xs = reinterpret_cast<double*>(smem);        // [2][BK][LD64]
     double* Ys = Xs + 2 * BK * LD64;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
@@ -998,21 +1176,30 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, int ti
     const int64_t xc = (int64_t)ti * TILE_M + lc, yc = (int64_t)tj * TILE_N + lc;
     const bool xv = vec_ok(Xp, d.X.ld, 16 / (int)sizeof(InT));
     const bool yv = vec_ok(Yp, d.Y.ld, 16 / (int)sizeof(InT));
+    const bool x2v = vec_ok(X2p, d.X2.ld, 16 / (int)sizeof(InT));
+    const bool y2v = vec_ok(Y2p, d.Y2.ld, 16 / (int)sizeof(InT));
 
     auto gload = [&](int64_t k0) {
         if constexpr (sizeof(InT) == 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double2 x = load2d(Xp, d.X.ld, k0 + lr + q * rstep, xc, K, d.X.pcols, xv);
-                const double2 y = load2d(Yp, d.Y.ld, k0 + lr + q * rstep, yc, K, d.Y.pcols, yv);
+                double2 x = load2d(Xp, d.X.ld, k0 + lr + q * rstep, xc, xl, d.X.pcols, xv);
+                double2 y = load2d(Yp, d.Y.ld, k0 + lr + q * rstep, yc, yl, d.Y.pcols, yv);
+                if (d.sx2)
+                    x = add_term(x, load2d(X2p, d.X2.ld, k0 + lr + q * rstep, xc, x2l, d.X2.pcols, x2v),
+                                 (double)d.sx2);
+                if (d.sy2)
+                    y = add_term(y, load2d(Y2p, d.Y2.ld, k0 + lr + q * rstep, yc, y2l, d.Y2.pcols, y2v),
+                                 (double)d.sy2);
                 rx[2 * q] = x.x; rx[2 * q + 1] = x.y;
                 ry[2 * q] = y.x; ry[2 * q + 1] = y.y;
             }
         } else {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const float4 x = load4f(Xp, d.X.ld, k0 + lr + q * rstep, xc, K, d.X.pcols, xv);
-                const float4 y = load4f(Yp, d.Y.ld, k0 + lr + q * rstep, yc, K, d.Y.pcols, yv);
+                // the FP64 fallback's SYRK leaves have no fused pre-sums
+                const float4 x = load4f(Xp, d.X.ld, k0 + lr + q * rstep, xc, xl, d.X.pcols, xv);
+                const float4 y = load4f(Yp, d.Y.ld, k0 + lr + q * rstep, yc, yl, d.Y.pcols, yv);
                 rx[4 * q] = x.x; rx[4 * q + 1] = x.y; rx[4 * q + 2] = x.z; rx[4 * q + 3] = x.w;
                 ry[4 * q] = y.x; ry[4 * q + 1] = y.y; ry[4 * q + 2] = y.z; ry[4 * q + 3] = y.w;
             }
@@ -1105,13 +1292,16 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
     const bool flagged = d.fb_node >= 0 && args.flags[d.fb_node];
     if constexpr (MODE == MODE_F64) {
         tile_f64<double, double>(d, view_ptr<double>(d.X, Aptr, args.B, args.arena),
-                                 view_ptr<double>(d.Y, Aptr, args.B, args.arena), ti, tj,
+                                 view_ptr<double>(d.Y, Aptr, args.B, args.arena),
+                                 view_ptr<double>(d.X2, Aptr, args.B, args.arena),
+                                 view_ptr<double>(d.Y2, Aptr, args.B, args.arena), ti, tj,
                                  static_cast<double*>(Cptr), static_cast<double*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FALLBACK) {
         if (!flagged) return;
-        tile_f64<float, float>(d, view_ptr<float>(d.X, Aptr, args.B, args.arena),
-                               view_ptr<float>(d.Y, Aptr, args.B, args.arena), ti, tj,
-                               static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
+        const float* Xf = view_ptr<float>(d.X, Aptr, args.B, args.arena);
+        const float* Yf = view_ptr<float>(d.Y, Aptr, args.B, args.arena);
+        tile_f64<float, float>(d, Xf, Yf, Xf, Yf, ti, tj, static_cast<float*>(Cptr),
+                               static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3) {
         if (flagged) return;
         tile_bf16x3<BfSmall>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
@@ -1122,8 +1312,25 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                              static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_F32_WIDE) {
         if (flagged) return;
-        tile_f32_wide(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
-                      ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
+        if (d.sx2 | d.sy2) {
+            const float* X1 = view_ptr<float>(d.X, Aptr, args.B, args.arena);
+            const float* Y1 = view_ptr<float>(d.Y, Aptr, args.B, args.arena);
+            const float* X2 = view_ptr<float>(d.X2, Aptr, args.B, args.arena);
+            const float* Y2 = view_ptr<float>(d.Y2, Aptr, args.B, args.arena);
+            // 16-byte rows: aligned bases and strides, whole 16-byte column groups
+            auto v16 = [](const float* p, const View& v) {
+                return ((reinterpret_cast<uintptr_t>(p) & 15) | ((v.ld | v.pcols) & 3)) == 0;
+            };
+            if (v16(X1, d.X) && v16(Y1, d.Y) && (!d.sx2 || v16(X2, d.X2)) && (!d.sy2 || v16(Y2, d.Y2)))
+                tile_f32_wide_sum<true>(d, X1, Y1, X2, Y2, ti, tj, static_cast<float*>(Cptr),
+                                        static_cast<float*>(args.arena), smem, kr);
+            else
+                tile_f32_wide_sum<false>(d, X1, Y1, X2, Y2, ti, tj, static_cast<float*>(Cptr),
+                                         static_cast<float*>(args.arena), smem, kr);
+        } else
+            tile_f32_wide(d, view_ptr<float>(d.X, Aptr, args.B, args.arena),
+                          view_ptr<float>(d.Y, Aptr, args.B, args.arena), ti, tj, static_cast<float*>(Cptr),
+                          static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FP8_WIDE) {
         if (flagged) return;
         tile_fp8_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
@@ -1143,13 +1350,14 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
     } else {
         if (flagged) return;
         tile_f32(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
+                 view_ptr<float>(d.X2, Aptr, args.B, args.arena), view_ptr<float>(d.Y2, Aptr, args.B, args.arena),
                  ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
     }
 }
 
 // One workgroup per tile (XCD-aware order).
 template <int MODE>
-__global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel(LeafArgs args) {
+__global__ __launch_bounds__(threads_for(MODE), min_blocks_for(MODE)) void leaf_kernel(LeafArgs args) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
     run_tile<MODE>(args, xcd_remap(blockIdx.x, args.ntiles, args.chunk), smem);
 }

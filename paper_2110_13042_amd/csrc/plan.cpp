@@ -117,16 +117,37 @@ struct Builder {
         return v;
     }
 
+    // One side of a leaf: a view, or the sum / difference of two views.
+    struct Operand {
+        View a, b{};
+        int32_t sign = 0;     // operand = a + sign * b; 0: a alone
+        // rows the leaf contracts over: a sum spans the logical rows, as the
+        // pre-sum buffer it replaces does (rows past both terms' physical
+        // extents read as zero), so K and the split-K chunks are the same
+        int64_t prows() const { return sign ? a.rows : a.prows; }
+    };
+
     void add_leaf(int32_t kind, const View& X, const View& Y, const Target& t, int depth,
                   int32_t pred_node, int32_t pred_value, int32_t fb_node) {
+        add_leaf(kind, Operand{X}, Operand{Y}, t, depth, pred_node, pred_value, fb_node);
+    }
+
+    void add_leaf(int32_t kind, const Operand& OX, const Operand& OY, const Target& t, int depth,
+                  int32_t pred_node, int32_t pred_value, int32_t fb_node) {
+        const View& X = OX.a;
+        const View& Y = OY.a;
         LeafDesc L{};
         L.kind = kind;
         L.out_kind = t.kind;
         L.X = X;
         L.Y = Y;
+        L.X2 = OX.b;
+        L.Y2 = OY.b;
+        L.sx2 = OX.sign;
+        L.sy2 = OY.sign;
         L.rows = X.cols;
         L.cols = Y.cols;
-        L.K = std::min(X.prows, Y.prows);
+        L.K = std::min(OX.prows(), OY.prows());
         const int tmz = tile_m_for(p.mode, p.tile_cfg), tnz = tile_n_for(p.mode, p.tile_cfg);
         L.tiles_m = (int32_t)cdiv(L.rows, tmz);
         L.tiles_n = (int32_t)cdiv(L.cols, tnz);
@@ -198,6 +219,36 @@ struct Builder {
         const bool children_leaf = std::max(n2, k2) <= b || std::min(m2, std::min(n2, k2)) <= 1 ||
                                    depth + 1 >= maxd;
         const bool packed = p.mode == MODE_BF16X3 && children_leaf;
+        const View X11 = sub(X, 0, m1, m2, 0, n1, n2), X12 = sub(X, 0, m1, m2, n1, n2, n2);
+        const View X21 = sub(X, m1, m2, m2, 0, n1, n2), X22 = sub(X, m1, m2, m2, n1, n2, n2);
+        const View Y11 = sub(Y, 0, m1, m2, 0, k1, k2), Y12 = sub(Y, 0, m1, m2, k1, k2, k2);
+        const View Y21 = sub(Y, m1, m2, m2, 0, k1, k2), Y22 = sub(Y, m1, m2, m2, k1, k2, k2);
+        auto Mt = [&](int i, int64_t M) { return Target{OUT_DENSE, M + (i - 1) * n2 * k2, k2, 0, 0}; };
+        if (p.fuse && children_leaf && (p.mode == MODE_F32 || p.mode == MODE_F64)) {
+            // the seven products are leaves: each forms its pre-sums while
+            // loading its operands (same IEEE sums as the pre-sum pass)
+            const int64_t M = alloc(7 * n2 * k2);
+            auto op = [](const View& a, const View& b, int32_t sg) { return Operand{a, b, sg}; };
+            const Operand S1 = op(X11, X22, 1), S2 = op(X12, X22, 1), S3 = op(X11, X21, 1);
+            const Operand S4 = op(X12, X11, -1), S5 = op(X21, X22, -1);
+            const Operand T1 = op(Y11, Y22, 1), T2 = op(Y12, Y22, -1), T3 = op(Y21, Y11, -1);
+            const Operand T4 = op(Y11, Y12, 1), T5 = op(Y21, Y22, 1);
+            add_leaf(LEAF_GEMM, S1, T1, Mt(1, M), depth + 1, pn, pv, -1);            // M1 = S1^T T1
+            add_leaf(LEAF_GEMM, S2, Operand{Y11}, Mt(2, M), depth + 1, pn, pv, -1);  // M2 = S2^T Y11
+            add_leaf(LEAF_GEMM, Operand{X11}, T2, Mt(3, M), depth + 1, pn, pv, -1);  // M3 = X11^T T2
+            add_leaf(LEAF_GEMM, Operand{X22}, T3, Mt(4, M), depth + 1, pn, pv, -1);  // M4 = X22^T T3
+            add_leaf(LEAF_GEMM, S3, Operand{Y22}, Mt(5, M), depth + 1, pn, pv, -1);  // M5 = S3^T Y22
+            add_leaf(LEAF_GEMM, S4, T4, Mt(6, M), depth + 1, pn, pv, -1);            // M6 = S4^T T4
+            add_leaf(LEAF_GEMM, S5, T5, Mt(7, M), depth + 1, pn, pv, -1);            // M7 = S5^T T5
+            if ((int)p.combine.size() < 1) p.combine.resize(1);
+            CombineDesc c{};
+            c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
+            c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
+            c.elems = n2 * cdiv(k2, 4); c.pred_node = pn; c.pred_value = pv;
+            p.combine[0].push_back(c);
+            if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
+            return 1;
+        }
         const int64_t groups = cdiv(m2, 8);
         const int64_t s_each = packed ? groups * n2 * 8 : m2 * n2;
         const int64_t t_each = packed ? groups * k2 * 8 : m2 * k2;
@@ -213,10 +264,6 @@ struct Builder {
         pt.elems = packed ? groups * k2 : m2 * cdiv(k2, 4);
         p.presum[depth].push_back(pt);
 
-        const View X11 = sub(X, 0, m1, m2, 0, n1, n2), X12 = sub(X, 0, m1, m2, n1, n2, n2);
-        const View X21 = sub(X, m1, m2, m2, 0, n1, n2), X22 = sub(X, m1, m2, m2, n1, n2, n2);
-        const View Y11 = sub(Y, 0, m1, m2, 0, k1, k2), Y22 = sub(Y, m1, m2, m2, k1, k2, k2);
-        (void)X12; (void)X21;
         auto Sv = [&](int i) {
             View v = arena_view(S + (i - 1) * s_each, m2, n2);
             if (packed) v.base = BASE_PACKED;
@@ -227,15 +274,14 @@ struct Builder {
             if (packed) v.base = BASE_PACKED;
             return v;
         };
-        auto Mt = [&](int i) { return Target{OUT_DENSE, M + (i - 1) * n2 * k2, k2, 0, 0}; };
         int h = 0;
-        h = std::max(h, strassen(Sv(1), Tv(1), Mt(1), depth + 1, pn, pv));  // M1 = S1^T T1
-        h = std::max(h, strassen(Sv(2), Y11, Mt(2), depth + 1, pn, pv));    // M2 = S2^T Y11
-        h = std::max(h, strassen(X11, Tv(2), Mt(3), depth + 1, pn, pv));    // M3 = X11^T T2
-        h = std::max(h, strassen(X22, Tv(3), Mt(4), depth + 1, pn, pv));    // M4 = X22^T T3
-        h = std::max(h, strassen(Sv(3), Y22, Mt(5), depth + 1, pn, pv));    // M5 = S3^T Y22
-        h = std::max(h, strassen(Sv(4), Tv(4), Mt(6), depth + 1, pn, pv));  // M6 = S4^T T4
-        h = std::max(h, strassen(Sv(5), Tv(5), Mt(7), depth + 1, pn, pv));  // M7 = S5^T T5
+        h = std::max(h, strassen(Sv(1), Tv(1), Mt(1, M), depth + 1, pn, pv));  // M1 = S1^T T1
+        h = std::max(h, strassen(Sv(2), Y11, Mt(2, M), depth + 1, pn, pv));    // M2 = S2^T Y11
+        h = std::max(h, strassen(X11, Tv(2), Mt(3, M), depth + 1, pn, pv));    // M3 = X11^T T2
+        h = std::max(h, strassen(X22, Tv(3), Mt(4, M), depth + 1, pn, pv));    // M4 = X22^T T3
+        h = std::max(h, strassen(Sv(3), Y22, Mt(5, M), depth + 1, pn, pv));    // M5 = S3^T Y22
+        h = std::max(h, strassen(Sv(4), Tv(4), Mt(6, M), depth + 1, pn, pv));  // M6 = S4^T T4
+        h = std::max(h, strassen(Sv(5), Tv(5), Mt(7, M), depth + 1, pn, pv));  // M7 = S5^T T5
         const int height = h + 1;
         if ((int)p.combine.size() < height) p.combine.resize(height);
         CombineDesc c{};
@@ -379,6 +425,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : 0;
+    p.fuse = opt.fuse_presum;
     if (n == 0) return p;
     Builder bld(p);
     bld.ata(0, n);
@@ -453,6 +500,7 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = false;
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : 0;
+    p.fuse = opt.fuse_presum;
     if (n == 0 || k == 0) return p;
     Builder bld(p);
     View X{};
@@ -580,6 +628,7 @@ Plan merge_plans(std::vector<Plan>& parts, int64_t split_target) {
     out.mode = parts[0].mode;
     out.nprob = (int32_t)parts.size();
     out.tile_cfg = parts[0].tile_cfg;
+    out.fuse = parts[0].fuse;
     out.max_depth = 0;
     int64_t node_base = 0;
     for (size_t q = 0; q < parts.size(); ++q) {
@@ -594,6 +643,8 @@ Plan merge_plans(std::vector<Plan>& parts, int64_t split_target) {
         for (auto L : p.leaves) {
             shift_view(L.X, ab);
             shift_view(L.Y, ab);
+            shift_view(L.X2, ab);
+            shift_view(L.Y2, ab);
             if (L.out_kind == OUT_DENSE) L.out_off += ab;
             L.PX.off += ab; L.PX.end += ab; L.PY.off += ab; L.PY.end += ab;
             L.QX.off += ab; L.QX.scales += ab; L.QX.end += ab;

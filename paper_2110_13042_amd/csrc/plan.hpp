@@ -81,6 +81,12 @@ struct LeafDesc {
     int64_t tiles;            // tiles of this task
     int64_t K;                // contraction length (rows)
     View X, Y;
+    // Fused Strassen pre-sums (FP32 and FP64 leaves of a node whose seven
+    // products are all leaves): operand = X + sx2 * X2 (sx2 = +1 or -1, each
+    // term zero outside its own physical extent), formed as the operand is
+    // loaded; sx2 = 0: X alone.  Likewise Y.
+    View X2, Y2;
+    int32_t sx2, sy2;
     int64_t rows, cols;       // logical output (rows = X.cols, cols = Y.cols)
     int64_t out_off, out_ld;  // OUT_DENSE: arena element offset and row stride
     int64_t out_row0, out_col0;  // OUT_PACKED: position in C
@@ -184,6 +190,7 @@ struct PlanOptions {
     int32_t tile_cfg = 0;          // leaf tile: 0 = 128 x 128; split-BF16 1 = 256 x 128, 2, 3 = 256 x 256; FP32, FP8 3 = 256 x 256
     double spread_tau = 4096.0;    // <= 0: no fallback
     int64_t split_target = 2048;   // split K when a launch has fewer tiles (0: never)
+    bool fuse_presum = false;      // FP32/FP64: last-level pre-sums formed in the leaf loads
 };
 
 struct PlanStats {
@@ -202,6 +209,7 @@ struct Plan {
     int32_t max_depth = 0;
     int32_t tile_cfg = 0;
     bool fallback = false;
+    bool fuse = false;                              // last-level pre-sums fused into the leaves
     std::vector<std::vector<PresumDesc>> presum;    // [level-1] top-down
     std::vector<PackDesc> pack;                     // split-BF16 operand packing
     std::vector<Pack8Desc> pack8;                   // FP8 operand quantisation
