@@ -627,6 +627,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         o.fuse_presum = h->popt.fuse_presum;
         try {
             dp->plan = make_plan(mode, m, n, lda, o);
+            if (dp->plan.fallback) fuse_pack_into_norms(dp->plan, dp->plan.col1);
         } catch (const std::invalid_argument&) {
             return ATA_ERR_INVALID_VALUE;
         } catch (const std::length_error&) {
@@ -673,7 +674,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     if (p.fallback) {
         e = launch_colnorms(dp.d_col1, (int)p.col1.size(), p.col1.back().elem_begin + p.col1.back().elems,
                             dp.d_col2, (int)p.col2.size(), p.col2.back().elem_begin + p.col2.back().elems,
-                            static_cast<const float*>(A), nullptr, partial, nu, st);
+                            static_cast<const float*>(A), nullptr, partial, nu, st, h->arena);
         if (e == hipSuccess)
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
@@ -942,7 +943,7 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
         const ColDesc& l2 = be.col2.back();
         e = launch_colnorms(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
                             (int)be.col2.size(), l2.elem_begin + l2.elems, nullptr, be.d_A, be.d_partial,
-                            be.d_nu, st);
+                            be.d_nu, st, h->arena);
         if (e == hipSuccess)
             e = launch_flags(be.d_nu, dp.d_nodes, (int)p.nodes.size(),
                              h->popt.spread_tau * h->popt.spread_tau, be.d_flags, st);
@@ -1064,14 +1065,16 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
             return ATA_ERR_INTERNAL;
         }
         const Plan& mp = be->dp->plan;
-        ata_status_t st0 = upload_plan(*be->dp);
-        if (st0 != ATA_OK) return st0;
-        // column-norm tasks (every problem, so the merged norm array is complete)
+        // column-norm tasks (every problem, so the merged norm array is
+        // complete); split-BF16 members' A packing moves into pass 1
         int64_t part_off = 0, nu_off = 0;
         if (mp.fallback) {
             build_colnorm_tasks(m, n, lda, batch, be->col1, be->col2, &part_off);
+            fuse_pack_into_norms(be->dp->plan, be->col1);
             for (int64_t i = 0; i < batch; ++i) nu_off += n[i];
         }
+        ata_status_t st0 = upload_plan(*be->dp);
+        if (st0 != ATA_OK) return st0;
         // auxiliary device buffer owned by the batch entry
         const size_t ptr_b = align256(sizeof(void*) * 2 * (size_t)batch);
         const size_t cnt_b = 256;

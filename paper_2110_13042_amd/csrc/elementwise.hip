@@ -473,13 +473,49 @@ __device__ __forceinline__ void sumsq4(const float* p, int64_t ld, int64_t r0, i
     }
 }
 
+// Sums of squares of columns jb + lane + 64 c (c = 0..3) over rows [r0, r1)
+// (r0 a multiple of 8) that also writes their split-BF16 packing: chunk
+// (g, j) = rows 8g..8g+7 of column j, zero past the matrix's last row (r1 is
+// a multiple of 8 or the row count).  Columns 64 apart per lane keep both the
+// loads (a row segment of 64 columns per instruction) and the 16-byte chunk
+// stores contiguous across the wave.  Rows are summed in order, as in sumsq4.
+__device__ __forceinline__ void sumsq_pack(const float* A, int64_t ld, int64_t r0, int64_t r1, int64_t jb,
+                                           int lane, int64_t n, double s[4], float* hi_base, int64_t lo_delta) {
+    for (int64_t r = r0; r < r1; r += 8) {
+        float v[4][8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int64_t j = jb + lane + 64 * c;
+                v[c][q] = (r + q < r1 && j < n) ? A[(r + q) * ld + j] : 0.f;
+            }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s[c] += (double)v[c][q] * (double)v[c][q];
+        const int64_t g = r >> 3;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t j = jb + lane + 64 * c;
+            if (j < n) {
+                uint4 h, l;
+                split8(v[c], h, l);
+                reinterpret_cast<uint4*>(hi_base)[g * n + j] = h;
+                reinterpret_cast<uint4*>(hi_base + lo_delta)[g * n + j] = l;
+            }
+        }
+    }
+}
+
 // Column norms, pass 1: a workgroup covers 256 columns (four per lane) of one
 // row chunk; its four waves take consecutive quarters of the chunk's rows and
 // their sums are added in wave order through LDS (deterministic).
 // partial[part_off + chunk * n + j] = sum of a_rj^2 over the chunk's rows.
 __global__ __launch_bounds__(EW_THREADS) void colnorm_pass1(const ColDesc* tasks, int ntasks,
                                                             int64_t items, const float* A0,
-                                                            const void* const* Aptrs, double* partial) {
+                                                            const void* const* Aptrs, double* partial,
+                                                            float* arena) {
     __shared__ double red[3][64][4];
     const int64_t x0 = (int64_t)blockIdx.x * EW_THREADS;
     if (x0 >= items) return;
@@ -497,21 +533,27 @@ __global__ __launch_bounds__(EW_THREADS) void colnorm_pass1(const ColDesc* tasks
     const int cols = j0 >= d.n ? 0 : (d.n - j0 < 4 ? (int)(d.n - j0) : 4);
     const bool vec = cols == 4 && ((reinterpret_cast<uintptr_t>(A) | (uintptr_t)(d.lda * 4)) & 15) == 0;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    if (cols > 0) sumsq4(A + j0, d.lda, r0, r1, vec, cols, s);
+    if (d.pack)
+        sumsq_pack(A, d.lda, r0, r1, xb * 256, lane, d.n, s, arena + d.pack_dst, d.pack_lo);
+    else if (cols > 0)
+        sumsq4(A + j0, d.lda, r0, r1, vec, cols, s);
     if (wave > 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) red[wave - 1][lane][c] = s[c];
     }
     __syncthreads();
-    if (wave == 0 && cols > 0) {
+    if (wave == 0) {
 #pragma unroll
         for (int w = 0; w < 3; ++w)
 #pragma unroll
             for (int c = 0; c < 4; ++c) s[c] += red[w][lane][c];
-        double* p = partial + d.part_off + chunk * d.n + j0;
+        double* p = partial + d.part_off + chunk * d.n;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (c < cols) p[c] = s[c];
+        for (int c = 0; c < 4; ++c) {
+            // this lane's columns: j0 + c, or xb * 256 + lane + 64 c with the packing
+            const int64_t j = d.pack ? xb * 256 + lane + 64 * c : j0 + c;
+            if (j < d.n) p[j] = s[c];
+        }
     }
 }
 
@@ -814,10 +856,10 @@ int64_t residual_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / N
 
 hipError_t launch_colnorms(const ColDesc* d_pass1, int n1, int64_t items1, const ColDesc* d_pass2,
                            int n2, int64_t items2, const float* A, const void* const* Aptrs,
-                           double* partial, double* nu, hipStream_t stream) {
+                           double* partial, double* nu, hipStream_t stream, void* arena) {
     if (items1 > 0)
         hipLaunchKernelGGL(colnorm_pass1, dim3(blocks_for(items1)), dim3(EW_THREADS), 0, stream,
-                           d_pass1, n1, items1, A, Aptrs, partial);
+                           d_pass1, n1, items1, A, Aptrs, partial, static_cast<float*>(arena));
     if (items2 > 0)
         hipLaunchKernelGGL(colnorm_pass2, dim3(blocks_for(items2)), dim3(EW_THREADS), 0, stream,
                            d_pass2, n2, items2, partial, nu);

@@ -437,6 +437,27 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     return p;
 }
 
+void fuse_pack_into_norms(Plan& p, std::vector<ColDesc>& col1) {
+    if (p.mode != MODE_BF16X3) return;
+    for (auto& c : col1) {
+        if (c.n <= 0 || c.m <= 0) continue;
+        for (size_t i = 0; i < p.pack.size(); ++i) {
+            const PackDesc& d = p.pack[i];
+            if (d.prob != c.prob || d.pred_node >= 0 || d.src.base != BASE_A || d.src.off != 0 ||
+                d.src.ld != c.lda || d.src.prows != c.m || d.src.pcols != c.n || d.cols != c.n ||
+                d.groups != cdiv(c.m, 8))
+                continue;
+            c.pack = 1;
+            c.pack_dst = d.dst;
+            c.pack_lo = d.lo_delta;
+            p.pack.erase(p.pack.begin() + (std::ptrdiff_t)i);
+            break;
+        }
+    }
+    int64_t e = 0;
+    for (auto& d : p.pack) { d.elem_begin = e; e = item_align(e + d.elems); }
+}
+
 void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda, int64_t count,
                          std::vector<ColDesc>& col1, std::vector<ColDesc>& col2,
                          int64_t* partial_total) {
@@ -449,7 +470,9 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
         // eight 16-byte loads in flight)
         const int64_t xblocks = cdiv(std::max<int64_t>(n[i], 1), 256);
         int64_t chunks = std::max<int64_t>(1, std::min(cdiv(2048, xblocks), cdiv(std::max<int64_t>(m[i], 1), 256)));
-        int64_t rows = cdiv(cdiv(std::max<int64_t>(m[i], 1), chunks), 4) * 4;
+        // rows per chunk: a multiple of 32, so each wave's quarter starts on
+        // an 8-row group (the split-BF16 packing's unit)
+        int64_t rows = cdiv(cdiv(std::max<int64_t>(m[i], 1), chunks), 32) * 32;
         chunks = cdiv(std::max<int64_t>(m[i], 1), rows);
         ColDesc d{};
         d.m = m[i];

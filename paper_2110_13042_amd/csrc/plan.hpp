@@ -172,11 +172,13 @@ struct CombineDesc {
 // 256 columns over one chunk of `rows` rows (elems = chunks x column blocks x
 // ITEM_BLOCK items); pass 2: one item per column sums the chunks in order.
 struct ColDesc {
-    int64_t m, n, lda, rows;      // rows per chunk (a multiple of 4)
+    int64_t m, n, lda, rows;      // rows per chunk (a multiple of 32)
     int64_t nchunks;
     int64_t part_off, nu_off;     // doubles in the partial and norm arrays
     int64_t elem_begin, elems;
-    int32_t prob, pad_;
+    int32_t prob;
+    int32_t pack;                 // pass 1 also writes A's split-BF16 packing (one read of A)
+    int64_t pack_dst, pack_lo;    // that packing: hi array and hi -> lo distance (floats)
 };
 
 // AtA node for the spread flags: columns [c0, c0 + w).
@@ -258,6 +260,12 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
 // split once, after merging.
 constexpr int64_t SPLIT_MIN_CHUNK = 8192;
 void split_leaves(Plan& p, int64_t target, int64_t min_chunk = SPLIT_MIN_CHUNK);
+// Split-BF16 plans with column norms: hand each problem's whole-A packing to
+// its column-norm pass 1 task (which reads A anyway) and drop it from the
+// pack launch.  Applied by the caller to the plan it executes (a single
+// plan, or a batch's merged plan with its own pass 1 tasks), never to the
+// parts of a batch.
+void fuse_pack_into_norms(Plan& p, std::vector<ColDesc>& col1);
 
 // Orders the leaves (longest contraction first) and fills the tile and
 // work-item prefix sums of every phase.

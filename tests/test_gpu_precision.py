@@ -8,6 +8,7 @@ import sys
 
 import numpy as np
 import pytest
+import torch
 
 from oracle import emulate, plain
 from paper_2110_13042_amd import ata, workloads
@@ -121,3 +122,46 @@ def test_fp8_matches_emulation(h, depth, tile):
     # a wrong rounding or a misplaced block would fail it.
     assert d_emul <= 5e-5
     assert d_emul <= 1e-2 * e_q
+
+
+@pytest.mark.parametrize("tile", [0, 2])
+def test_bf16x3_packing_in_norm_pass_matches_pack_kernel(tile):
+    """With the spread check on, the column-norm pass also writes A's split
+    packing; with it off, the pack kernel does.  On well-scaled data no node
+    is flagged, so both must give the same bits (ragged m, n and padded lda;
+    single problems and a batch).  Split-K is off: the spread check changes
+    how the planner splits the fallback-capable leaves, and with it the
+    summation order."""
+    rng = np.random.default_rng(53)
+    dev = device()
+    outs = {}
+    for tau in (0.0, 4096.0):
+        hd = ata.Handle(spread_tau=tau)
+        hd.set("leaf_tile", tile)
+        hd.set("split_target", 0)
+        res = []
+        for (m, n, b, depth, lda) in [(1000, 777, 128, 1, 779), (37, 300, 64, 0, 300), (4099, 1030, 256, 1, 1032),
+                                      (8, 5, 64, 0, 5)]:
+            _say("case: bf16x3 norm-pass packing", tau, tile, m, n, b, depth, lda)
+            A = rng.uniform(-1, 1, (m, n)).astype(np.float32) if tau == 0.0 else outs[(m, n)][0]
+            hd.set("leaf_cutoff", b)
+            hd.set("max_depth", depth)
+            res.append(run_gram(A, ata.F32_BF16X3, hd, lda=lda))
+            if tau == 0.0:
+                outs[(m, n)] = (A, res[-1])
+        As = [outs[k][0] for k in outs]
+        Ts = [torch.from_numpy(a).to(dev) for a in As]
+        hd.set("leaf_cutoff", 128)
+        hd.set("max_depth", 1)
+        batch = [c.double().cpu().numpy() for c in ata.gram_batched(Ts, ata.F32_BF16X3, handle=hd)]
+        torch.cuda.synchronize()
+        if tau == 0.0:
+            ref_single, ref_batch = res, batch
+        else:
+            rep = hd.report()
+            assert rep["flagged_nodes"] in (0, -1)
+            for a, b_ in zip(ref_single, res):
+                assert np.array_equal(a, b_)
+            for a, b_ in zip(ref_batch, batch):
+                assert np.array_equal(a, b_)
+        hd.close()
