@@ -283,6 +283,23 @@ ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n,
                           int64_t lda, ata_dtype_t dtype, const void* C_packed,
                           uint64_t seed, double* result, void* stream);
 
+/* Sampled-column check in FP64 on the GPU (the residual's column form):
+   for the `count` column indices in the host array `cols` (each in [0, n),
+   repeats allowed), forms the reference columns (A^T A)[:, j] = A^T a_j with
+   FP64 products and sums (a product of two FP32 inputs is exact in FP64),
+   reads the same columns of the packed C (C[i][j] for i >= j, C[j][i]
+   above the diagonal), and stores ||C_S - (A^T A)_S||_F / ||(A^T A)_S||_F
+   in *result (0 for n = 0 or count = 0; +inf when the reference is zero and
+   C is not).  Reported, not enforced.  A and C_packed are device buffers of
+   the dtype's element type.  Allocates and frees a temporary of about
+   8 (m count + n count / 512) bytes; blocks until the result is on the host
+   (synchronises `stream`).  ATA_ERR_INVALID_VALUE for a bad size, a null
+   pointer or a column index out of range, before any device work. */
+ata_status_t ata_check_columns(ata_handle_t h, const void* A, int64_t m, int64_t n,
+                               int64_t lda, ata_dtype_t dtype, const void* C_packed,
+                               const int64_t* cols, int64_t count, double* result,
+                               void* stream);
+
 /* One autotuned plan choice. */
 typedef struct {
     int64_t leaf_cutoff;
@@ -294,8 +311,8 @@ typedef struct {
 /* Autotuner: times ata_gram on (A, C_packed) -- device buffers of the given
    shape; A is only read, C_packed is overwritten -- for every candidate leaf
    cutoff (powers of two from 128 up to the first at or above n), Strassen
-   depth cap (0 up to the smaller of 3 and the dtype's default) and, for
-   ATA_F32_BF16X3, leaf tile (0..3), keeps
+   depth cap (0 up to the smaller of 3 and the dtype's default) and leaf
+   tile (ATA_F32_BF16X3: 0..3; ATA_F32 and ATA_F32_FP8E4M3: 0 or 3), keeps
    the fastest in the handle's table under (dtype, shape bucket) and returns
    it in *best (may be NULL).  Buckets are half-octaves of m and of n.
    ata_gram and ata_gram_batched use the table whenever the leaf cutoff and

@@ -92,6 +92,8 @@ def lib() -> ctypes.CDLL:
     L.ata_get_report.argtypes = [vp, ctypes.POINTER(Report)]
     L.ata_plan_query.argtypes = [i64, i64, st, i64, i32, ctypes.POINTER(Report),
                                  ctypes.POINTER(Leaf), i64, ctypes.POINTER(i64)]
+    L.ata_check_columns.argtypes = [vp, vp, i64, i64, i64, st, vp, ctypes.POINTER(i64), i64,
+                                    ctypes.POINTER(ctypes.c_double), vp]
     L.ata_residual.argtypes = [vp, vp, i64, i64, i64, st, vp, ctypes.c_uint64,
                                ctypes.POINTER(ctypes.c_double), vp]
     L.ata_autotune.argtypes = [vp, vp, i64, i64, i64, st, vp, vp, ctypes.POINTER(TuneEntry)]
@@ -105,7 +107,8 @@ def lib() -> ctypes.CDLL:
     L.ata_status_string.argtypes = [st]
     L.ata_status_string.restype = ctypes.c_char_p
     for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_batched", "ata_set_option",
-                 "ata_get_report", "ata_plan_query", "ata_residual", "ata_autotune", "ata_autotune_batched",
+                 "ata_get_report", "ata_plan_query", "ata_residual", "ata_check_columns", "ata_autotune",
+                 "ata_autotune_batched",
                  "ata_gemm_tn", "ata_gram_scaled", "ata_gram_aat", "ata_unpack",
                  "ata_tune_save", "ata_tune_load"):
         getattr(L, name).restype = st
@@ -201,6 +204,16 @@ def ata_residual(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, s
     r = ctypes.c_double()
     _check(lib().ata_residual(h, A, m, n, lda, dtype, C, seed, ctypes.byref(r), stream),
            "ata_residual")
+    return r.value
+
+
+def ata_check_columns(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, cols,
+                      stream: int = 0) -> float:
+    """FP64 sampled-column check on the GPU: ||C_S - (A^T A)_S||_F / ||(A^T A)_S||_F."""
+    arr = (ctypes.c_int64 * max(len(cols), 1))(*[int(c) for c in cols])
+    r = ctypes.c_double()
+    _check(lib().ata_check_columns(h, A, m, n, lda, dtype, C, arr, len(cols), ctypes.byref(r), stream),
+           "ata_check_columns")
     return r.value
 
 

@@ -747,6 +747,47 @@ ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n, i
     return e == hipSuccess ? ATA_OK : ATA_ERR_HIP;
 }
 
+ata_status_t ata_check_columns(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
+                               ata_dtype_t dtype, const void* C_packed, const int64_t* cols, int64_t count,
+                               double* result, void* stream) {
+    if (!h || !result || !valid_dtype(dtype) || m < 0 || n < 0 || count < 0 || lda < std::max<int64_t>(1, n))
+        return ATA_ERR_INVALID_VALUE;
+    if (count > 0 && !cols) return ATA_ERR_INVALID_VALUE;
+    for (int64_t k = 0; k < count; ++k)
+        if (cols[k] < 0 || cols[k] >= n) return ATA_ERR_INVALID_VALUE;
+    if (n > 0 && count > 0 && (!C_packed || (m > 0 && !A))) return ATA_ERR_INVALID_VALUE;
+    *result = 0.0;
+    if (n == 0 || count == 0) return ATA_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    const int64_t wg = ((n + 63) / 64) * ((count + 15) / 16);
+    const size_t work_b = align256(sizeof(double) * (size_t)column_check_work_elems(m, n, count));
+    const size_t cols_b = align256(sizeof(int64_t) * (size_t)count);
+    void* buf = nullptr;
+    size_t cap = 0;
+    ata_status_t s = ensure(buf, cap, work_b + cols_b);
+    if (s != ATA_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* work = static_cast<double*>(buf);
+    int64_t* d_cols = reinterpret_cast<int64_t*>(static_cast<unsigned char*>(buf) + work_b);
+    std::vector<double> part((size_t)(2 * wg));
+    const int32_t mode = dtype == ATA_F64 ? MODE_F64 : MODE_F32;
+    hipError_t e = hipMemcpyAsync(d_cols, cols, sizeof(int64_t) * (size_t)count, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_column_check(mode, A, m, n, lda, C_packed, d_cols, count, work, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(part.data(), work + m * count, sizeof(double) * part.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return ATA_ERR_HIP;
+    // workgroup sums added in workgroup order on the host (deterministic)
+    double d2 = 0.0, r2 = 0.0;
+    for (int64_t b = 0; b < wg; ++b) {
+        d2 += part[(size_t)(2 * b)];
+        r2 += part[(size_t)(2 * b + 1)];
+    }
+    *result = r2 > 0.0 ? std::sqrt(d2 / r2) : (d2 > 0.0 ? INFINITY : 0.0);
+    return ATA_OK;
+}
+
 ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m, int64_t n, int64_t k,
                          int64_t lda, int64_t ldb, ata_dtype_t dtype, void* C, int64_t ldc, void* stream) {
     if (!h || !valid_dtype(dtype) || m < 0 || n < 0 || k < 0 || lda < std::max<int64_t>(1, n) ||

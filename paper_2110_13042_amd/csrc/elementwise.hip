@@ -735,6 +735,77 @@ __global__ __launch_bounds__(EW_THREADS) void res_final(const double* wrow, cons
 
 unsigned blocks_for(int64_t items) { return (unsigned)((items + EW_THREADS - 1) / EW_THREADS); }
 
+// ------------------------------------------------- sampled-column check
+// G[r][k] = A[r][cols[k]] in FP64 (the sampled columns, gathered once).
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void cc_gather(const T* A, int64_t m, int64_t lda, const int64_t* cols,
+                                                        int64_t count, double* G) {
+    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+    if (x >= m * count) return;
+    const int64_t r = udiv(x, count), k = x - r * count;
+    G[x] = (double)A[r * lda + cols[k]];
+}
+
+// Exact-as-FP64 reference columns (A^T A)[:, cols[s0 .. s0 + 15]] for the 64
+// output rows i0 .. i0 + 63 of a workgroup: lane l takes row i0 + l, wave w a
+// quarter of A's rows, products and sums in FP64 (a product of two FP32
+// values is exact in FP64); the quarters are added in wave order.  Then
+// per-workgroup sums of (C - ref)^2 and ref^2 over its outputs, C read from
+// the packed lower triangle.  out[2 b], out[2 b + 1] for workgroup b.
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void cc_check(const T* A, int64_t m, int64_t n, int64_t lda,
+                                                       const double* G, const int64_t* cols, int64_t count,
+                                                       const T* Cp, double* out) {
+    __shared__ double red[3][64][16];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t s0 = (int64_t)blockIdx.y * 16;
+    const int ns = count - s0 < 16 ? (int)(count - s0) : 16;
+    const int64_t q = (m + 3) / 4;
+    const int64_t r0 = wave * q < m ? wave * q : m, r1 = (wave + 1) * q < m ? (wave + 1) * q : m;
+    double acc[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+    if (i < n) {
+        for (int64_t r = r0; r < r1; ++r) {
+            const double a = (double)A[r * lda + i];
+            const double* g = G + r * count + s0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                if (k < ns) acc[k] = fma(a, g[k], acc[k]);
+        }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) red[wave - 1][lane][k] = acc[k];
+    }
+    __syncthreads();
+    double d2 = 0.0, r2 = 0.0;
+    if (wave == 0 && i < n) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k >= ns) continue;
+            const double ref = acc[k] + red[0][lane][k] + red[1][lane][k] + red[2][lane][k];
+            const int64_t j = cols[s0 + k];
+            const double c = (double)(i >= j ? Cp[packed_index(i, j)] : Cp[packed_index(j, i)]);
+            d2 += (c - ref) * (c - ref);
+            r2 += ref * ref;
+        }
+    }
+    // wave 0 sums its lanes in a fixed tree order
+    if (wave == 0) {
+        for (int off = 32; off > 0; off >>= 1) {
+            d2 += __shfl_down(d2, off, 64);
+            r2 += __shfl_down(r2, off, 64);
+        }
+        if (lane == 0) {
+            const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+            out[2 * b] = d2;
+            out[2 * b + 1] = r2;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, int64_t items,
@@ -913,6 +984,34 @@ hipError_t launch_residual(int32_t mode, const void* A, int64_t m, int64_t n, in
     hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), blk, 0, stream, fpart, chunks, n, fro);
     hipLaunchKernelGGL(sum_partials, dim3(blocks_for(n)), blk, 0, stream, wpart, bands, n, wcol);
     hipLaunchKernelGGL(res_final, dim3(1), blk, 0, stream, wrow, wcol, z, fro, n, out);
+    return hipGetLastError();
+}
+
+int64_t column_check_work_elems(int64_t m, int64_t n, int64_t count) {
+    return m * count + 2 * ((n + 63) / 64) * ((count + 15) / 16);
+}
+
+hipError_t launch_column_check(int32_t mode, const void* A, int64_t m, int64_t n, int64_t lda, const void* C,
+                               const int64_t* d_cols, int64_t count, double* work, hipStream_t stream) {
+    if (n <= 0 || count <= 0) return hipSuccess;
+    double* G = work;
+    double* out = work + m * count;
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((count + 15) / 16));
+    if (mode == MODE_F64) {
+        const double* a = static_cast<const double*>(A);
+        if (m > 0)
+            hipLaunchKernelGGL(cc_gather<double>, dim3(blocks_for(m * count)), dim3(EW_THREADS), 0, stream, a, m, lda,
+                               d_cols, count, G);
+        hipLaunchKernelGGL(cc_check<double>, grid, dim3(EW_THREADS), 0, stream, a, m, n, lda, G, d_cols, count,
+                           static_cast<const double*>(C), out);
+    } else {
+        const float* a = static_cast<const float*>(A);
+        if (m > 0)
+            hipLaunchKernelGGL(cc_gather<float>, dim3(blocks_for(m * count)), dim3(EW_THREADS), 0, stream, a, m, lda,
+                               d_cols, count, G);
+        hipLaunchKernelGGL(cc_check<float>, grid, dim3(EW_THREADS), 0, stream, a, m, n, lda, G, d_cols, count,
+                           static_cast<const float*>(C), out);
+    }
     return hipGetLastError();
 }
 

@@ -92,6 +92,15 @@ hipError_t launch_flags(const double* nu, const NodeDesc* d_nodes, int nnodes, d
 // Freivalds residual ||C x - A^T (A x)|| / (||A||_F^2 ||x||), x_j = +-1 from
 // SplitMix64(seed, j).  `work` must hold residual_work_elems(m, n) doubles.
 int64_t residual_work_elems(int64_t m, int64_t n);
+
+// Sampled-column check: FP64 columns (A^T A)[:, cols[k]] against the packed
+// C.  d_cols: device array of `count` column indices; `work` must hold
+// column_check_work_elems(m, n, count) doubles; on return the last
+// 2 * ceil(n / 64) * ceil(count / 16) of them hold per-workgroup
+// (sum (C - ref)^2, sum ref^2) pairs.
+int64_t column_check_work_elems(int64_t m, int64_t n, int64_t count);
+hipError_t launch_column_check(int32_t mode, const void* A, int64_t m, int64_t n, int64_t lda, const void* C,
+                               const int64_t* d_cols, int64_t count, double* work, hipStream_t stream);
 hipError_t launch_residual(int32_t mode, const void* A, int64_t m, int64_t n, int64_t lda,
                            const void* C, uint64_t seed, double* work, double* out,
                            hipStream_t stream);

@@ -79,6 +79,9 @@ def test_gram_argument_errors_need_no_device():
     assert L.ata_gram_batched(None, 0, None, None, None, None, 1, None, None) == 1
     h = ctypes.c_void_p()
     assert L.ata_create(None) == 1
+    r = ctypes.c_double()
+    cols = (ctypes.c_int64 * 2)(0, 1)
+    assert L.ata_check_columns(None, None, 4, 4, 4, 1, None, cols, 2, ctypes.byref(r), None) == 1
 
 
 def test_plan_query_rejects_packed_operands_of_4_gib():
