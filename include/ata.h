@@ -89,8 +89,8 @@ typedef enum {
        1 = 256 x 128, 2 = 256 x 256 on eight waves, 3 = 256 x 256 on four
        waves of 128 x 128.  FP8: 0 = 128 x 128 (default), 3 = 256 x 256 on
        four waves of 128 x 128 (1 and 2 act as 0).  FP32: 0 = 128 x 128
-       (default), 3 = 256 x 256 on four waves of 128 x 128 (1 and 2 act as
-       0).  FP64 ignores it. */
+       (default), 2 = 256 x 256 on eight waves of 128 x 64, 3 = 256 x 256 on
+       four waves of 128 x 128 (1 acts as 0).  FP64 ignores it. */
     ATA_OPT_LEAF_TILE = 7,
     /* ata_gram_batched: 1 = capture the batch's launch sequence once per
        shape signature in a hipGraph and replay it (default); 0 = enqueue the
@@ -312,7 +312,7 @@ typedef struct {
    shape; A is only read, C_packed is overwritten -- for every candidate leaf
    cutoff (powers of two from 128 up to the first at or above n), Strassen
    depth cap (0 up to the smaller of 3 and the dtype's default) and leaf
-   tile (ATA_F32_BF16X3: 0..3; ATA_F32 and ATA_F32_FP8E4M3: 0 or 3), keeps
+   tile (ATA_F32_BF16X3: 0..3; ATA_F32: 0, 2 or 3; ATA_F32_FP8E4M3: 0 or 3), keeps
    the fastest in the handle's table under (dtype, shape bucket) and returns
    it in *best (may be NULL).  Buckets are half-octaves of m and of n.
    ata_gram and ata_gram_batched use the table whenever the leaf cutoff and

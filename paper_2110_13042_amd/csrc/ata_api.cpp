@@ -284,7 +284,8 @@ bool valid_dtype(int d) { return d >= ATA_F64 && d <= ATA_F32_FP8E4M3; }
 bool tiled_mode(int32_t mode) { return mode == MODE_BF16X3 || mode == MODE_FP8 || mode == MODE_F32; }
 std::vector<int32_t> tile_candidates(int32_t mode) {
     if (mode == MODE_BF16X3) return {0, 1, 2, 3};
-    if (mode == MODE_FP8 || mode == MODE_F32) return {0, 3};
+    if (mode == MODE_F32) return {0, 2, 3};
+    if (mode == MODE_FP8) return {0, 3};
     return {0};
 }
 
@@ -335,7 +336,7 @@ AuxLayout aux_layout(const Plan& p, bool residual) {
 // automatic choice (persistent for the 256 x 256 FP32 tile only).
 bool persistent_for(int setting, const Plan& p) {
     if (setting >= 0) return setting == 1;
-    return p.mode == MODE_F32 && p.tile_cfg == 3;
+    return p.mode == MODE_F32 && p.tile_cfg >= 2;
 }
 
 void fill_report(ata_report_t& r, const Plan& p) {

@@ -50,6 +50,7 @@ constexpr int MODE_BF16X3_HUGE = 102;
 constexpr int MODE_BF16X3_WIDE = 103;
 constexpr int MODE_FP8_WIDE = 104;
 constexpr int MODE_F32_WIDE = 105;
+constexpr int MODE_F32_WIDE8 = 106;
 #ifndef ATA_WIDE_STAGES
 #define ATA_WIDE_STAGES 4     // LDS ring depth of the 256 x 256 split-BF16 engine (32 KB each)
 #endif
@@ -80,9 +81,10 @@ constexpr size_t lds_bytes(int mode) {
            : mode == MODE_BF16X3_WIDE ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
            : mode == MODE_F32_WIDE ? (size_t)(wide32::STAGES * wide32::STAGE > 8 * wide32::HALF ? wide32::STAGES * wide32::STAGE : 8 * wide32::HALF)
+           : mode == MODE_F32_WIDE8 ? (size_t)wide32::STAGES * wide32::STAGE
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
-constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE ? 512 : LEAF_THREADS; }
+constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE || mode == MODE_F32_WIDE8 ? 512 : LEAF_THREADS; }
 // Resident workgroups per CU the one-tile-per-workgroup kernel is compiled
 // for: the 128 x 128 FP32 engine keeps four (64 VGPRs + 64 accumulators per
 // lane) with its fused pre-sum loads included.
@@ -445,6 +447,122 @@ __device__ __forceinline__ void tile_f32_wide(const LeafDesc& d, const float* Xp
             for (int v = 0; v < 16; ++v) {
                 const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int c = wn * 128 + b * 32 + (lane & 31);
+                store_elem<float, TM, TN>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
+            }
+}
+
+// The 256 x 256 FP32 tile on eight waves of 128 x 64 (4 x 2 blocks of 32 x 32,
+// 128 accumulators per lane), two waves per SIMD: while one wave waits on a
+// load's issue or an LDS read, the other's MFMAs keep the matrix core busy.
+// Same slabs, stages, per-row buffer resources and fixed schedule as the
+// four-wave form; each wave streams four rows of X (waves 0-3) or Y (4-7).
+__device__ __forceinline__ void tile_f32_wide8(const LeafDesc& d, const float* Xp, const float* Yp, int ti, int tj,
+                                               float* C, float* arena, unsigned char* smem, const KRange& kr) {
+    using namespace wide32;
+    constexpr int LATER8 = 16 * (STAGES - 2) < 63 ? 16 * (STAGES - 2) : 63;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 2, wn = w & 3;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t nk = (K + SK - 1) / SK;
+    const bool isx = w < 4;
+    const int64_t ld = isx ? d.X.ld : d.Y.ld;
+    const float* P = (isx ? Xp : Yp) + kr.kb * ld;
+    const int64_t lim = isx ? rows_in(d.X, kr) : rows_in(d.Y, kr);
+    const int prow = (int)((isx ? d.X.pcols : d.Y.pcols) * 4);
+    const uint32_t cbyte = (uint32_t)(((isx ? (int64_t)ti * TM : (int64_t)tj * TN) + lane) * 4);
+    const int r0 = (w & 3) * 4;
+    // load l (0..15) of this wave's share of slab kt: row r0 + l / 4, segment l % 4
+    auto issue = [&](int64_t kt, int st, int l) {
+        const int rr = r0 + (l >> 2), seg = l & 3;
+        const int64_t row = kt * SK + rr;
+        const __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float*>(P + row * ld), (short)0, row < lim ? prow : 0, 0x00020000);
+        unsigned char* base = smem + st * STAGE + (isx ? 0 : HALF) + rr * RS * 4;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + seg * 256), 4, (int)(cbyte + seg * 256),
+                                                 0, 0, 0);
+    };
+
+    v16f acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    const int ko = lane >> 5, io = lane & 31;
+    float a[2][4], b[2][2];
+    auto read = [&](int st, int kk, int buf) {
+        const float* xs = reinterpret_cast<const float*>(smem + st * STAGE) + wm * 128 + io + (2 * kk + ko) * RS;
+        const float* ys = reinterpret_cast<const float*>(smem + st * STAGE + HALF) + wn * 64 + io + (2 * kk + ko) * RS;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[buf][q] = xs[q * 32];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) b[buf][q] = ys[q * 32];
+    };
+    auto mfma = [&](int buf, int i0, int i1) {
+#pragma unroll
+        for (int i = i0; i < i1; ++i)
+            acc[i >> 1][i & 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[buf][i >> 1], b[buf][i & 1],
+                                                                      acc[i >> 1][i & 1], 0, 0, 0);
+    };
+
+#pragma unroll
+    for (int l = 0; l < 16; ++l) issue(0, 0, l);
+#pragma unroll
+    for (int sl = 1; sl < STAGES - 1; ++sl)
+#pragma unroll
+        for (int l = 0; l < 16; ++l) issue(sl, sl, l);
+    __builtin_amdgcn_s_waitcnt(waitcnt_imm(LATER8, 15));  // slab 0 has landed
+    __builtin_amdgcn_s_barrier();
+    read(0, 0, 0);
+    int cur = 0, nxt = 1, fill = STAGES - 1;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+#pragma unroll
+        for (int kk = 0; kk < SK / 2 - 1; ++kk) {
+            const int buf = kk & 1;
+            mfma(buf, 0, 1);
+            __builtin_amdgcn_sched_barrier(0);
+            read(cur, kk + 1, buf ^ 1);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kk < 4) {
+                // four of slab kt + STAGES - 1's sixteen loads, one per MFMA
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    mfma(buf, 1 + l, 2 + l);
+                    __builtin_amdgcn_sched_barrier(0);
+                    issue(kt + STAGES - 1, fill, kk * 4 + l);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                mfma(buf, 5, 8);
+            } else {
+                mfma(buf, 1, 8);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        mfma(1, 0, 2);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(waitcnt_imm(LATER8, 0));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        read(nxt, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma(1, 2, 8);
+        __builtin_amdgcn_sched_barrier(0);
+        cur = nxt;
+        nxt = nxt == STAGES - 1 ? 0 : nxt + 1;
+        fill = fill == STAGES - 1 ? 0 : fill + 1;
+    }
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int c = wn * 64 + b * 32 + (lane & 31);
                 store_elem<float, TM, TN>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
             }
 }
@@ -1331,6 +1449,10 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
             tile_f32_wide(d, view_ptr<float>(d.X, Aptr, args.B, args.arena),
                           view_ptr<float>(d.Y, Aptr, args.B, args.arena), ti, tj, static_cast<float*>(Cptr),
                           static_cast<float*>(args.arena), smem, kr);
+    } else if constexpr (MODE == MODE_F32_WIDE8) {
+        if (flagged) return;
+        tile_f32_wide8(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
+                       ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_FP8_WIDE) {
         if (flagged) return;
         tile_fp8_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
@@ -1446,6 +1568,10 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
         ATA_LAUNCH_LEAF(MODE_F32_WIDE, LEAF_THREADS);
         return hipGetLastError();
     }
+    if (mode == MODE_F32 && tile_cfg == 2) {
+        ATA_LAUNCH_LEAF(MODE_F32_WIDE8, 512);
+        return hipGetLastError();
+    }
     switch (mode) {
         case MODE_F64: ATA_LAUNCH_LEAF(MODE_F64, LEAF_THREADS); break;
         case MODE_F32: ATA_LAUNCH_LEAF(MODE_F32, LEAF_THREADS); break;
@@ -1491,6 +1617,8 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3>, LEAF_THREADS, 0);
     else if (mode == MODE_F32 && tile_cfg == 3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F32_WIDE>, LEAF_THREADS, 0);
+    else if (mode == MODE_F32 && tile_cfg == 2)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F32_WIDE8>, 512, 0);
     else if (mode == MODE_FP8 && tile_cfg == 3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8_WIDE>, LEAF_THREADS, 0);
     else if (mode == MODE_FP8)

@@ -224,7 +224,7 @@ struct Builder {
         const View Y11 = sub(Y, 0, m1, m2, 0, k1, k2), Y12 = sub(Y, 0, m1, m2, k1, k2, k2);
         const View Y21 = sub(Y, m1, m2, m2, 0, k1, k2), Y22 = sub(Y, m1, m2, m2, k1, k2, k2);
         auto Mt = [&](int i, int64_t M) { return Target{OUT_DENSE, M + (i - 1) * n2 * k2, k2, 0, 0}; };
-        if (p.fuse && children_leaf && (p.mode == MODE_F32 || p.mode == MODE_F64)) {
+        if (p.fuse && children_leaf && ((p.mode == MODE_F32 && p.tile_cfg != 2) || p.mode == MODE_F64)) {
             // the seven products are leaves: each forms its pre-sums while
             // loading its operands (same IEEE sums as the pre-sum pass)
             const int64_t M = alloc(7 * n2 * k2);
@@ -424,7 +424,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, n);
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
-    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : 0;
+    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
     p.fuse = opt.fuse_presum;
     if (n == 0) return p;
     Builder bld(p);
@@ -522,7 +522,7 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, std::max(n, k));
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = false;
-    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : 0;
+    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
     p.fuse = opt.fuse_presum;
     if (n == 0 || k == 0) return p;
     Builder bld(p);

@@ -189,7 +189,7 @@ struct NodeDesc {
 struct PlanOptions {
     int64_t leaf_cutoff = 0;       // 0: default for the mode
     int32_t max_depth = -1;        // -1: default for the mode
-    int32_t tile_cfg = 0;          // leaf tile: 0 = 128 x 128; split-BF16 1 = 256 x 128, 2, 3 = 256 x 256; FP32, FP8 3 = 256 x 256
+    int32_t tile_cfg = 0;          // leaf tile: 0 = 128 x 128; split-BF16 1 = 256 x 128, 2, 3 = 256 x 256; FP32 2, 3 and FP8 3 = 256 x 256
     double spread_tau = 4096.0;    // <= 0: no fallback
     int64_t split_target = 2048;   // split K when a launch has fewer tiles (0: never)
     bool fuse_presum = false;      // FP32/FP64: last-level pre-sums formed in the leaf loads
@@ -289,10 +289,10 @@ inline int64_t item_align(int64_t e) { return (e + ITEM_BLOCK - 1) / ITEM_BLOCK 
 constexpr int TILE_M = 128;
 constexpr int TILE_N = 128;
 constexpr int tile_m_for(int32_t mode, int32_t tile_cfg) {
-    return (mode == MODE_BF16X3 && tile_cfg >= 1) || ((mode == MODE_FP8 || mode == MODE_F32) && tile_cfg == 3) ? 256 : 128;
+    return (mode == MODE_BF16X3 && tile_cfg >= 1) || (mode == MODE_FP8 && tile_cfg == 3) || (mode == MODE_F32 && tile_cfg >= 2) ? 256 : 128;
 }
 constexpr int tile_n_for(int32_t mode, int32_t tile_cfg) {
-    return (mode == MODE_BF16X3 && tile_cfg >= 2) || ((mode == MODE_FP8 || mode == MODE_F32) && tile_cfg == 3) ? 256 : 128;
+    return (mode == MODE_BF16X3 && tile_cfg >= 2) || (mode == MODE_FP8 && tile_cfg == 3) || (mode == MODE_F32 && tile_cfg >= 2) ? 256 : 128;
 }
 int64_t syrk_tiles(int64_t tm, int64_t tn, int64_t rho);
 

@@ -203,12 +203,14 @@ def test_full_size_square_f32_8192_sampled(h):
     assert err <= 2e-5
 
 
-def test_f32_wide_tile(h):
-    """FP32 leaves on the 256 x 256 tile: exact on integers (Strassen levels,
-    odd splits, a leading dimension that is not a multiple of four, split-K
-    on a tall input) and within 2e-5 of the oracle on random data."""
+@pytest.mark.parametrize("tile", [3, 2])
+def test_f32_wide_tile(h, tile):
+    """FP32 leaves on the 256 x 256 tiles (four and eight waves): exact on
+    integers (Strassen levels, odd splits, a leading dimension that is not a
+    multiple of four, split-K on a tall input) and within 2e-5 of the oracle
+    on random data."""
     rng = np.random.default_rng(44)
-    h.set("leaf_tile", 3)
+    h.set("leaf_tile", tile)
     h.set("spread_tau", 0)
     try:
         for (m, n, b, depth, lda) in [(1, 1, 64, 0, 1), (3, 2, 64, 0, 2), (257, 255, 64, 2, 255),
@@ -235,7 +237,7 @@ def test_f32_wide_tile(h):
         h.set("spread_tau", 4096)
 
 
-@pytest.mark.parametrize("mode,tile", [(ata.F32, 3), (ata.F32, 0), (ata.F64, 0)])
+@pytest.mark.parametrize("mode,tile", [(ata.F32, 3), (ata.F32, 2), (ata.F32, 0), (ata.F64, 0)])
 def test_persistent_leaf_launch_matches_grid(h, mode, tile):
     """The persistent leaf launch (per-XCD tile queues) and the one-workgroup-
     per-tile launch give bit-identical results, on a plan with unequal
