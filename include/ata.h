@@ -87,7 +87,8 @@ typedef enum {
     ATA_OPT_PROFILE = 6,
     /* Output tile of the leaf kernel.  Split-BF16: 0 = 128 x 128 (default),
        1 = 256 x 128, 2 = 256 x 256 on eight waves, 3 = 256 x 256 on four
-       waves of 128 x 128.  FP8: 0 = 128 x 128 (default), 3 = 256 x 256 on
+       waves of 128 x 128 with operands streamed into LDS by buffer loads,
+       4 = the same stream on eight waves of 128 x 64.  FP8: 0 = 128 x 128 (default), 3 = 256 x 256 on
        four waves of 128 x 128 (1 and 2 act as 0).  FP32: 0 = 128 x 128
        (default), 2 = 256 x 256 on eight waves of 128 x 64, 3 = 256 x 256 on
        four waves of 128 x 128 (1 acts as 0).  FP64 ignores it. */
@@ -312,8 +313,10 @@ typedef struct {
    shape; A is only read, C_packed is overwritten -- for every candidate leaf
    cutoff (powers of two from 128 up to the first at or above n), Strassen
    depth cap (0 up to the smaller of 3 and the dtype's default) and leaf
-   tile (ATA_F32_BF16X3: 0..3; ATA_F32: 0, 2 or 3; ATA_F32_FP8E4M3: 0 or 3), keeps
-   the fastest in the handle's table under (dtype, shape bucket) and returns
+   tile (ATA_F32_BF16X3: 0..4; ATA_F32: 0, 2 or 3; ATA_F32_FP8E4M3: 0 or 3)
+   once, times the four fastest again in three interleaved rounds (each
+   scoring its best round), keeps the winner in the handle's table under
+   (dtype, shape bucket) and returns
    it in *best (may be NULL).  Buckets are half-octaves of m and of n.
    ata_gram and ata_gram_batched use the table whenever the leaf cutoff and
    depth options are left at their defaults (0 and -1).  Synchronises

@@ -51,6 +51,7 @@ constexpr int MODE_BF16X3_WIDE = 103;
 constexpr int MODE_FP8_WIDE = 104;
 constexpr int MODE_F32_WIDE = 105;
 constexpr int MODE_F32_WIDE8 = 106;
+constexpr int MODE_BF16X3_WIDE8 = 107;
 #ifndef ATA_WIDE_STAGES
 #define ATA_WIDE_STAGES 4     // LDS ring depth of the 256 x 256 split-BF16 engine (32 KB each)
 #endif
@@ -82,9 +83,12 @@ constexpr size_t lds_bytes(int mode) {
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
            : mode == MODE_F32_WIDE ? (size_t)(wide32::STAGES * wide32::STAGE > 8 * wide32::HALF ? wide32::STAGES * wide32::STAGE : 8 * wide32::HALF)
            : mode == MODE_F32_WIDE8 ? (size_t)wide32::STAGES * wide32::STAGE
+           : mode == MODE_BF16X3_WIDE8 ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
-constexpr int threads_for(int mode) { return mode == MODE_BF16X3_HUGE || mode == MODE_F32_WIDE8 ? 512 : LEAF_THREADS; }
+constexpr int threads_for(int mode) {
+    return mode == MODE_BF16X3_HUGE || mode == MODE_F32_WIDE8 || mode == MODE_BF16X3_WIDE8 ? 512 : LEAF_THREADS;
+}
 // Resident workgroups per CU the one-tile-per-workgroup kernel is compiled
 // for: the 128 x 128 FP32 engine keeps four (64 VGPRs + 64 accumulators per
 // lane) with its fused pre-sum loads included.
@@ -1043,6 +1047,124 @@ __device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float*
             }
 }
 
+// The same split-BF16 256 x 256 tile on eight waves of 128 x 64 (4 x 2 blocks,
+// 128 accumulators per lane), two waves per SIMD, so that one wave's MFMAs
+// cover the other's loads and LDS reads.  Same packed slabs and LDS ring;
+// each operand half is streamed by two waves, one 8-row group each.
+__device__ __forceinline__ void tile_bf16x3_wide8(const LeafDesc& d, const float* arena_in, int ti, int tj, float* C,
+                                                  float* arena, unsigned char* smem, const KRange& kr) {
+    using namespace wide;
+    constexpr int L8 = 4;                          // buffer->LDS loads per wave per slab
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 2, wn = w & 3;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t gb = kr.kb / 8;
+    const int64_t nk = ((K + 15) / 16 + 1) & ~int64_t(1);
+
+    // waves 2h and 2h + 1 stream operand half h (0 Xh, 1 Xl, 2 Yh, 3 Yl), group w % 2 of every slab
+    const int half = w >> 1, g = w & 1;
+    const bool isx = half < 2;
+    const __amdgpu_buffer_rsrc_t src = packed_rsrc(arena_in, isx ? d.PX : d.PY, (half & 1) != 0);
+    const uint32_t gs = (uint32_t)((isx ? d.PX.gstride : d.PY.gstride) * 4);
+    const uint32_t col0 = (uint32_t)((isx ? ti * TM : tj * TN) + lane) * 16u;
+    const uint32_t past = (uint32_t)(((isx ? d.PX.end - d.PX.off : d.PY.end - d.PY.off)) * 4);
+    auto issue = [&](int64_t kt) {
+        unsigned char* base = smem + (kt % STAGES) * STAGE + half * ARR + g * 4096;
+        const int64_t lrow = kt * 2 + g;
+        const bool in = lrow * 8 < K;
+#pragma unroll
+        for (int seg = 0; seg < L8; ++seg) {
+            const uint32_t off = in ? (uint32_t)(gb + lrow) * gs + col0 + (uint32_t)(seg * 64 * 16) : past;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + seg * 1024), 16, (int)off, 0, 0, 0);
+        }
+    };
+    // at most 4 n loads of this wave outstanding
+    auto wait_n = [](int64_t n) {
+        if (n <= 0) __builtin_amdgcn_s_waitcnt(0x0F70);        // vmcnt(0)
+        else if (n == 1) __builtin_amdgcn_s_waitcnt(0x0F74);   // vmcnt(4)
+        else if (n == 2) __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8)
+        else __builtin_amdgcn_s_waitcnt(0x0F7C);               // vmcnt(12)
+    };
+
+    v16f acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    const int fo = (lane >> 5) * 4096 + (lane & 31) * 16;
+    v8bf xh[2][4], xl[2][4], yh[2][2], yl[2][2];
+    auto frags = [&](int buf, int64_t kt) {
+        const unsigned char* st = smem + (kt % STAGES) * STAGE + fo;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int xo = (wm * 128 + a * 32) * 16;
+            xh[buf][a] = *reinterpret_cast<const v8bf*>(st + 0 * ARR + xo);
+            xl[buf][a] = *reinterpret_cast<const v8bf*>(st + 1 * ARR + xo);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int yo = (wn * 64 + b * 32) * 16;
+            yh[buf][b] = *reinterpret_cast<const v8bf*>(st + 2 * ARR + yo);
+            yl[buf][b] = *reinterpret_cast<const v8bf*>(st + 3 * ARR + yo);
+        }
+    };
+    auto mfmas = [&](int buf) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[buf][a], yh[buf][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[buf][a], yl[buf][b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[buf][a], yh[buf][b], acc[a][b], 0, 0, 0);
+    };
+    constexpr int AHEAD = STAGES - 1;
+    auto step = [&](int64_t kt, int cur) {
+        if (kt + 1 < nk) wait_n((kt + AHEAD - 1 < nk ? kt + AHEAD - 1 : nk - 1) - kt - 1);
+        __builtin_amdgcn_s_barrier();
+        if (kt + AHEAD < nk) issue(kt + AHEAD);
+        if (kt + 1 < nk) frags(cur ^ 1, kt + 1);
+        mfmas(cur);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // two MFMAs
+        }
+    };
+
+    for (int64_t j = 0; j < AHEAD && j < nk; ++j) issue(j);
+    if (nk > 0) {
+        wait_n((nk < AHEAD ? nk : AHEAD) - 1);
+        __builtin_amdgcn_s_barrier();
+        frags(0, 0);
+    }
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+        step(kt, 0);
+        step(kt + 1, 1);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int cc = wn * 64 + b * 32 + (lane & 31);
+                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
+            }
+}
+
 // ------------------------------------------------------------ FP8 e4m3
 // 128 x 128 tile, four waves (2 x 2), each 64 x 64 = 4 x 4 blocks of 16 x 16
 // on v_mfma_scale_f32_16x16x128_f8f6f4.  A slab is 128 rows, i.e. exactly one
@@ -1461,6 +1583,10 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
         if (flagged) return;
         tile_fp8(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
                  static_cast<float*>(args.arena), smem, kr);
+    } else if constexpr (MODE == MODE_BF16X3_WIDE8) {
+        if (flagged) return;
+        tile_bf16x3_wide8(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                          static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_WIDE) {
         if (flagged) return;
         tile_bf16x3_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
@@ -1560,6 +1686,10 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
         ATA_LAUNCH_LEAF(MODE_BF16X3_WIDE, LEAF_THREADS);
         return hipGetLastError();
     }
+    if (mode == MODE_BF16X3 && tile_cfg == 4) {
+        ATA_LAUNCH_LEAF(MODE_BF16X3_WIDE8, 512);
+        return hipGetLastError();
+    }
     if (mode == MODE_FP8 && tile_cfg == 3) {
         ATA_LAUNCH_LEAF(MODE_FP8_WIDE, LEAF_THREADS);
         return hipGetLastError();
@@ -1599,8 +1729,8 @@ namespace ata {
 
 int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
     // cached per (mode, tile): the answer depends on the compiled kernels only
-    static std::atomic<int> cache[8][4];
-    const bool cacheable = mode >= 0 && mode < 8 && tile_cfg >= 0 && tile_cfg < 4;
+    static std::atomic<int> cache[8][8];
+    const bool cacheable = mode >= 0 && mode < 8 && tile_cfg >= 0 && tile_cfg < 8;
     if (cacheable) {
         const int c = cache[mode][tile_cfg].load(std::memory_order_relaxed);
         if (c > 0) return c;
@@ -1613,6 +1743,8 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_HUGE>, 512, 0);
     else if (mode == MODE_BF16X3 && tile_cfg == 3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_WIDE>, LEAF_THREADS, 0);
+    else if (mode == MODE_BF16X3 && tile_cfg == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3_WIDE8>, 512, 0);
     else if (mode == MODE_BF16X3)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_BF16X3>, LEAF_THREADS, 0);
     else if (mode == MODE_F32 && tile_cfg == 3)

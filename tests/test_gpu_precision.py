@@ -30,7 +30,7 @@ def h():
     hd.close()
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 def test_bf16x3_small_integers_bit_exact(h, tile):
     rng = np.random.default_rng(51)
     h.set("leaf_tile", tile)
@@ -44,7 +44,8 @@ def test_bf16x3_small_integers_bit_exact(h, tile):
         assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth)
 
 
-@pytest.mark.parametrize("depth,tile", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (0, 2), (2, 2), (0, 3), (1, 3)])
+@pytest.mark.parametrize("depth,tile", [(0, 0), (1, 0), (2, 0), (0, 1), (1, 1), (0, 2), (2, 2), (0, 3), (1, 3),
+                                        (0, 4), (1, 4)])
 def test_bf16x3_matches_emulation(h, depth, tile):
     rng = np.random.default_rng(52 + depth)
     m, n, b = 1536, 1100, 256
@@ -124,7 +125,7 @@ def test_fp8_matches_emulation(h, depth, tile):
     assert d_emul <= 1e-2 * e_q
 
 
-@pytest.mark.parametrize("tile", [0, 2])
+@pytest.mark.parametrize("tile", [0, 2, 4])
 def test_bf16x3_packing_in_norm_pass_matches_pack_kernel(tile):
     """With the spread check on, the column-norm pass also writes A's split
     packing; with it off, the pack kernel does.  On well-scaled data no node
