@@ -332,6 +332,13 @@ AuxLayout aux_layout(const Plan& p, bool residual) {
     return a;
 }
 
+// Does any column-norm pass 1 task also write a split-BF16 packing?
+bool has_pack(const std::vector<ColDesc>& col1) {
+    for (const auto& c : col1)
+        if (c.pack) return true;
+    return false;
+}
+
 // Leaf launch form: 1 = persistent, 0 = one workgroup per tile, -1 = the
 // automatic choice (persistent for the 256 x 256 FP32 tile only).
 bool persistent_for(int setting, const Plan& p) {
@@ -675,7 +682,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     if (p.fallback) {
         e = launch_colnorms(dp.d_col1, (int)p.col1.size(), p.col1.back().elem_begin + p.col1.back().elems,
                             dp.d_col2, (int)p.col2.size(), p.col2.back().elem_begin + p.col2.back().elems,
-                            static_cast<const float*>(A), nullptr, partial, nu, st, h->arena);
+                            static_cast<const float*>(A), nullptr, partial, nu, st, h->arena, has_pack(p.col1));
         if (e == hipSuccess)
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
@@ -985,7 +992,7 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
         const ColDesc& l2 = be.col2.back();
         e = launch_colnorms(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
                             (int)be.col2.size(), l2.elem_begin + l2.elems, nullptr, be.d_A, be.d_partial,
-                            be.d_nu, st, h->arena);
+                            be.d_nu, st, h->arena, has_pack(be.col1));
         if (e == hipSuccess)
             e = launch_flags(be.d_nu, dp.d_nodes, (int)p.nodes.size(),
                              h->popt.spread_tau * h->popt.spread_tau, be.d_flags, st);

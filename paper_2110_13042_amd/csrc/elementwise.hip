@@ -512,6 +512,9 @@ __device__ __forceinline__ void sumsq_pack(const float* A, int64_t ld, int64_t r
 // row chunk; its four waves take consecutive quarters of the chunk's rows and
 // their sums are added in wave order through LDS (deterministic).
 // partial[part_off + chunk * n + j] = sum of a_rj^2 over the chunk's rows.
+// PACK: the launch has tasks that also write the split-BF16 packing (a
+// separate instantiation, so that the plain form keeps its occupancy).
+template <bool PACK>
 __global__ __launch_bounds__(EW_THREADS) void colnorm_pass1(const ColDesc* tasks, int ntasks,
                                                             int64_t items, const float* A0,
                                                             const void* const* Aptrs, double* partial,
@@ -533,7 +536,8 @@ __global__ __launch_bounds__(EW_THREADS) void colnorm_pass1(const ColDesc* tasks
     const int cols = j0 >= d.n ? 0 : (d.n - j0 < 4 ? (int)(d.n - j0) : 4);
     const bool vec = cols == 4 && ((reinterpret_cast<uintptr_t>(A) | (uintptr_t)(d.lda * 4)) & 15) == 0;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    if (d.pack)
+    const bool pack = PACK && d.pack;
+    if (pack)
         sumsq_pack(A, d.lda, r0, r1, xb * 256, lane, d.n, s, arena + d.pack_dst, d.pack_lo);
     else if (cols > 0)
         sumsq4(A + j0, d.lda, r0, r1, vec, cols, s);
@@ -551,7 +555,7 @@ __global__ __launch_bounds__(EW_THREADS) void colnorm_pass1(const ColDesc* tasks
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             // this lane's columns: j0 + c, or xb * 256 + lane + 64 c with the packing
-            const int64_t j = d.pack ? xb * 256 + lane + 64 * c : j0 + c;
+            const int64_t j = pack ? xb * 256 + lane + 64 * c : j0 + c;
             if (j < d.n) p[j] = s[c];
         }
     }
@@ -927,9 +931,12 @@ int64_t residual_chunks(int64_t m) { return m <= 0 ? 1 : (m + NORM_ROWS - 1) / N
 
 hipError_t launch_colnorms(const ColDesc* d_pass1, int n1, int64_t items1, const ColDesc* d_pass2,
                            int n2, int64_t items2, const float* A, const void* const* Aptrs,
-                           double* partial, double* nu, hipStream_t stream, void* arena) {
-    if (items1 > 0)
-        hipLaunchKernelGGL(colnorm_pass1, dim3(blocks_for(items1)), dim3(EW_THREADS), 0, stream,
+                           double* partial, double* nu, hipStream_t stream, void* arena, bool pack) {
+    if (items1 > 0 && pack)
+        hipLaunchKernelGGL(colnorm_pass1<true>, dim3(blocks_for(items1)), dim3(EW_THREADS), 0, stream,
+                           d_pass1, n1, items1, A, Aptrs, partial, static_cast<float*>(arena));
+    else if (items1 > 0)
+        hipLaunchKernelGGL(colnorm_pass1<false>, dim3(blocks_for(items1)), dim3(EW_THREADS), 0, stream,
                            d_pass1, n1, items1, A, Aptrs, partial, static_cast<float*>(arena));
     if (items2 > 0)
         hipLaunchKernelGGL(colnorm_pass2, dim3(blocks_for(items2)), dim3(EW_THREADS), 0, stream,

@@ -83,7 +83,8 @@ hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, 
 // into `nu`).  A: the matrix when Aptrs is null, else Aptrs[prob].
 hipError_t launch_colnorms(const ColDesc* d_pass1, int n1, int64_t items1, const ColDesc* d_pass2,
                            int n2, int64_t items2, const float* A, const void* const* Aptrs,
-                           double* partial, double* nu, hipStream_t stream, void* arena = nullptr);
+                           double* partial, double* nu, hipStream_t stream, void* arena = nullptr,
+                           bool pack = false);
 
 // flags[i] = spread of nu over node i's columns > tau^2 (1/0); count in *count.
 hipError_t launch_flags(const double* nu, const NodeDesc* d_nodes, int nnodes, double tau2,
