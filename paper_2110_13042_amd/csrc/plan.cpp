@@ -465,11 +465,12 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
     col2.clear();
     int64_t part_off = 0, nu_off = 0, e1 = 0, e2 = 0;
     for (int64_t i = 0; i < count; ++i) {
-        // up to about 2048 workgroups of 256 columns x (4 waves x rows / 4)
-        // per problem, each wave summing at least 64 rows (eight rounds of
-        // eight 16-byte loads in flight)
+        // up to about 4096 workgroups of 256 columns x (4 waves x rows / 4)
+        // per problem, each wave summing at least 32 rows (four rounds of
+        // eight 16-byte loads in flight), so that even a mid-sized matrix
+        // has eight waves per SIMD in flight
         const int64_t xblocks = cdiv(std::max<int64_t>(n[i], 1), 256);
-        int64_t chunks = std::max<int64_t>(1, std::min(cdiv(2048, xblocks), cdiv(std::max<int64_t>(m[i], 1), 256)));
+        int64_t chunks = std::max<int64_t>(1, std::min(cdiv(4096, xblocks), cdiv(std::max<int64_t>(m[i], 1), 128)));
         // rows per chunk: a multiple of 32, so each wave's quarter starts on
         // an 8-row group (the split-BF16 packing's unit)
         int64_t rows = cdiv(cdiv(std::max<int64_t>(m[i], 1), chunks), 32) * 32;
