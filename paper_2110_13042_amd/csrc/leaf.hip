@@ -55,6 +55,12 @@ constexpr int MODE_BF16X3_WIDE8 = 107;
 #ifndef ATA_WIDE_STAGES
 #define ATA_WIDE_STAGES 4     // LDS ring depth of the 256 x 256 split-BF16 engine (32 KB each)
 #endif
+#ifndef ATA_F32W8_SK
+#define ATA_F32W8_SK 32       // rows per slab of the eight-wave FP32 engine
+#endif
+#ifndef ATA_F32W8_ST
+#define ATA_F32W8_ST 2        // its LDS stages (72 KB each)
+#endif
 #ifndef ATA_F32W_STAGES
 #define ATA_F32W_STAGES 3
 #endif
@@ -82,7 +88,7 @@ constexpr size_t lds_bytes(int mode) {
            : mode == MODE_BF16X3_WIDE ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
            : mode == MODE_F32_WIDE ? (size_t)(wide32::STAGES * wide32::STAGE > 8 * wide32::HALF ? wide32::STAGES * wide32::STAGE : 8 * wide32::HALF)
-           : mode == MODE_F32_WIDE8 ? (size_t)wide32::STAGES * wide32::STAGE
+           : mode == MODE_F32_WIDE8 ? (size_t)ATA_F32W8_ST * 2 * ATA_F32W8_SK * wide32::RS * 4
            : mode == MODE_BF16X3_WIDE8 ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
@@ -458,12 +464,24 @@ __device__ __forceinline__ void tile_f32_wide(const LeafDesc& d, const float* Xp
 // The 256 x 256 FP32 tile on eight waves of 128 x 64 (4 x 2 blocks of 32 x 32,
 // 128 accumulators per lane), two waves per SIMD: while one wave waits on a
 // load's issue or an LDS read, the other's MFMAs keep the matrix core busy.
-// Same slabs, stages, per-row buffer resources and fixed schedule as the
-// four-wave form; each wave streams four rows of X (waves 0-3) or Y (4-7).
+// Same per-row buffer resources and fixed schedule as the four-wave form,
+// with slabs of 32 rows in two stages (half the barriers; a slab's loads are
+// issued in the first eight of its sixteen k-row pairs); each wave streams
+// eight rows of X (waves 0-3) or Y (4-7).
+template <int SK8, int ST8>
 __device__ __forceinline__ void tile_f32_wide8(const LeafDesc& d, const float* Xp, const float* Yp, int ti, int tj,
                                                float* C, float* arena, unsigned char* smem, const KRange& kr) {
-    using namespace wide32;
-    constexpr int LATER8 = 16 * (STAGES - 2) < 63 ? 16 * (STAGES - 2) : 63;
+    using wide32::TM;
+    using wide32::TN;
+    using wide32::RS;
+    using wide32::waitcnt_imm;
+    constexpr int SK = SK8;                       // rows per slab
+    constexpr int STAGES = ST8;
+    constexpr int HALF = SK * RS * 4;
+    constexpr int STAGE = 2 * HALF;
+    constexpr int RPW = SK / 4;                   // slab rows per wave
+    constexpr int NL = RPW * 4;                   // loads per wave per slab
+    constexpr int LATER8 = NL * (STAGES - 2) < 63 ? NL * (STAGES - 2) : 63;
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = w >> 2, wn = w & 3;
@@ -475,8 +493,8 @@ __device__ __forceinline__ void tile_f32_wide8(const LeafDesc& d, const float* X
     const int64_t lim = isx ? rows_in(d.X, kr) : rows_in(d.Y, kr);
     const int prow = (int)((isx ? d.X.pcols : d.Y.pcols) * 4);
     const uint32_t cbyte = (uint32_t)(((isx ? (int64_t)ti * TM : (int64_t)tj * TN) + lane) * 4);
-    const int r0 = (w & 3) * 4;
-    // load l (0..15) of this wave's share of slab kt: row r0 + l / 4, segment l % 4
+    const int r0 = (w & 3) * RPW;
+    // load l (0..NL-1) of this wave's share of slab kt: row r0 + l / 4, segment l % 4
     auto issue = [&](int64_t kt, int st, int l) {
         const int rr = r0 + (l >> 2), seg = l & 3;
         const int64_t row = kt * SK + rr;
@@ -513,11 +531,11 @@ __device__ __forceinline__ void tile_f32_wide8(const LeafDesc& d, const float* X
     };
 
 #pragma unroll
-    for (int l = 0; l < 16; ++l) issue(0, 0, l);
+    for (int l = 0; l < NL; ++l) issue(0, 0, l);
 #pragma unroll
     for (int sl = 1; sl < STAGES - 1; ++sl)
 #pragma unroll
-        for (int l = 0; l < 16; ++l) issue(sl, sl, l);
+        for (int l = 0; l < NL; ++l) issue(sl, sl, l);
     __builtin_amdgcn_s_waitcnt(waitcnt_imm(LATER8, 15));  // slab 0 has landed
     __builtin_amdgcn_s_barrier();
     read(0, 0, 0);
@@ -530,8 +548,8 @@ __device__ __forceinline__ void tile_f32_wide8(const LeafDesc& d, const float* X
             __builtin_amdgcn_sched_barrier(0);
             read(cur, kk + 1, buf ^ 1);
             __builtin_amdgcn_sched_barrier(0);
-            if (kk < 4) {
-                // four of slab kt + STAGES - 1's sixteen loads, one per MFMA
+            if (kk < NL / 4) {
+                // four of slab kt + STAGES - 1's loads, one per MFMA
 #pragma unroll
                 for (int l = 0; l < 4; ++l) {
                     mfma(buf, 1 + l, 2 + l);
@@ -1573,8 +1591,10 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                           static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_F32_WIDE8) {
         if (flagged) return;
-        tile_f32_wide8(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
-                       ti, tj, static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem, kr);
+        tile_f32_wide8<ATA_F32W8_SK, ATA_F32W8_ST>(d, view_ptr<float>(d.X, Aptr, args.B, args.arena),
+                                                  view_ptr<float>(d.Y, Aptr, args.B, args.arena), ti, tj,
+                                                  static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem,
+                                                  kr);
     } else if constexpr (MODE == MODE_FP8_WIDE) {
         if (flagged) return;
         tile_fp8_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
