@@ -142,6 +142,7 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
                  "mult_ratio_vs_syrk": round(rep["multiplications"] / (m * n * (n + 1) / 2), 4),
                  "launches_per_step": rep["kernel_launches"], "workspace_bytes": rep["workspace_bytes"],
                  "leaf_tile": rep["leaf_tile"],
+                 "strassen_form": "winograd" if args.winograd else "strassen",
                  "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile"},
         "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
             ["norms_flags", "presum_pack", "leaves", "combine", "residual"], rep["phase_ms"])},
@@ -173,6 +174,8 @@ def make_handle(ata, args):
         h.set("equilibrate", 1)
     if args.fuse_presum:
         h.set("fuse_presum", 1)
+    if args.winograd:
+        h.set("strassen_form", 1)
     return h
 
 
@@ -240,6 +243,7 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
                            "value": round(work / (ms_sep * 1e-3) / 1e12, 3)},
         "plan": {"problems": len(As), "multiplications": rep["multiplications"],
                  "leaf_tile": rep["leaf_tile"],
+                 "strassen_form": "winograd" if args.winograd else "strassen",
                  "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile",
                  "batch_autotune": tuned,
                  "leaves": rep["syrk_leaves"] + rep["gemm_leaves"],
@@ -352,6 +356,8 @@ def main() -> int:
                          "-1 = the library's automatic choice")
     ap.add_argument("--fuse-presum", action="store_true",
                     help="FP32/FP64: form the last Strassen level's pre-sums inside the leaf loads")
+    ap.add_argument("--winograd", action="store_true",
+                    help="Strassen nodes in Winograd's form (four chained pre-sums per operand)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

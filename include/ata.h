@@ -151,7 +151,17 @@ typedef enum {
        operand lose more time than the streaming pre-sum pass costs).
        Split-BF16 and FP8 always form their last-level pre-sums in the
        operand packing / quantisation pass. */
-    ATA_OPT_FUSE_PRESUM = 16
+    ATA_OPT_FUSE_PRESUM = 16,
+    /* Form of every Strassen node (the AtB step of Sec. 3.2, Alg. 1):
+       0 (default) = Strassen's seven products with ten pre-sums and eight
+       post-additions, as the paper uses; 1 = Winograd's variant with the
+       same seven-product count but four chained pre-sums per operand
+       (S2 = S1 - X11, S4 = X21 - S2; T2 = Y22 - T1, T4 = T2 - Y21) and seven
+       post-additions sharing partial sums, so two fewer workspace sums per
+       node.  Both are exact in exact arithmetic; Winograd's rounding-error
+       constant is somewhat larger.  With 1, ATA_OPT_FUSE_PRESUM is ignored
+       (a chained sum is not one rounding of two quadrant elements). */
+    ATA_OPT_STRASSEN_FORM = 17
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

@@ -30,6 +30,7 @@ OPT_XCD_CHUNK, OPT_TILE_BAND, OPT_SPLIT_TARGET, OPT_BATCH_USE_TABLE = 10, 11, 12
 OPT_EQUILIBRATE = 14
 OPT_LEAF_PERSISTENT = 15
 OPT_FUSE_PRESUM = 16
+OPT_STRASSEN_FORM = 17
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -263,7 +264,7 @@ class Handle:
                "xcd_chunk": OPT_XCD_CHUNK, "tile_band": OPT_TILE_BAND,
                "split_target": OPT_SPLIT_TARGET, "batch_use_table": OPT_BATCH_USE_TABLE,
                "equilibrate": OPT_EQUILIBRATE, "leaf_persistent": OPT_LEAF_PERSISTENT,
-               "fuse_presum": OPT_FUSE_PRESUM}[name]
+               "fuse_presum": OPT_FUSE_PRESUM, "strassen_form": OPT_STRASSEN_FORM}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

@@ -33,9 +33,10 @@ struct PlanKey {
     int32_t tile_cfg;
     int64_t split;
     bool fuse;
+    int32_t variant;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse) <
-               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse);
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant) <
+               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant);
     }
 };
 
@@ -75,10 +76,11 @@ struct BatchKey {
     int32_t tile_cfg;
     int64_t split;
     bool fuse;
+    int32_t variant;
     std::vector<int64_t> shapes;   // m, n, lda per problem
     bool operator<(const BatchKey& o) const {
-        return std::tie(mode, b, depth, fb, tile_cfg, split, fuse, shapes) <
-               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.shapes);
+        return std::tie(mode, b, depth, fb, tile_cfg, split, fuse, variant, shapes) <
+               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant, o.shapes);
     }
 };
 
@@ -89,9 +91,11 @@ struct GemmKey {
     int32_t depth, tile_cfg;
     int64_t split;
     bool fuse;
+    int32_t variant;
     bool operator<(const GemmKey& o) const {
-        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split, fuse) <
-               std::tie(o.mode, o.m, o.n, o.k, o.lda, o.ldb, o.ldc, o.b, o.depth, o.tile_cfg, o.split, o.fuse);
+        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split, fuse, variant) <
+               std::tie(o.mode, o.m, o.n, o.k, o.lda, o.ldb, o.ldc, o.b, o.depth, o.tile_cfg, o.split, o.fuse,
+                        o.variant);
     }
 };
 
@@ -467,6 +471,10 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
         case ATA_OPT_FUSE_PRESUM:
             h->popt.fuse_presum = value != 0.0;
             return ATA_OK;
+        case ATA_OPT_STRASSEN_FORM:
+            if (value != 0.0 && value != 1.0) return ATA_ERR_INVALID_VALUE;
+            h->popt.variant = (int32_t)value;
+            return ATA_OK;
         case ATA_OPT_BATCH_USE_TABLE:
             h->batch_use_table = value != 0.0;
             return ATA_OK;
@@ -622,7 +630,8 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     int32_t depth, tile_cfg;
     choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
-    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum};
+    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
+                       h->popt.variant};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -633,6 +642,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         o.tile_cfg = tile_cfg;
         o.split_target = h->split_target;
         o.fuse_presum = h->popt.fuse_presum;
+        o.variant = h->popt.variant;
         try {
             dp->plan = make_plan(mode, m, n, lda, o);
             if (dp->plan.fallback) fuse_pack_into_norms(dp->plan, dp->plan.col1);
@@ -822,7 +832,8 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     int64_t b;
     int32_t depth, tile_cfg;
     choose(h, mode, m, std::max(n, k), b, depth, tile_cfg);
-    const GemmKey key{mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, h->split_target, h->popt.fuse_presum};
+    const GemmKey key{mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, h->split_target, h->popt.fuse_presum,
+                       h->popt.variant};
     auto it = h->gemm_plans.find(key);
     if (it == h->gemm_plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -833,6 +844,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
         o.tile_cfg = tile_cfg;
         o.split_target = h->split_target;
         o.fuse_presum = h->popt.fuse_presum;
+        o.variant = h->popt.variant;
         try {
             dp->plan = make_gemm_plan(mode, m, n, k, lda, ldb, ldc, o);
         } catch (const std::invalid_argument&) {
@@ -1072,7 +1084,8 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     }
     std::vector<int64_t> bs((size_t)batch);
     std::vector<int32_t> ds((size_t)batch);
-    BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum, {}};
+    BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
+                 h->popt.variant, {}};
     key.shapes.reserve(5 * (size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
         int32_t tile_i;
@@ -1102,6 +1115,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
                 o.tile_cfg = tile_cfg;
                 o.split_target = 0;          // the merged plan is split as a whole
                 o.fuse_presum = h->popt.fuse_presum;
+                o.variant = h->popt.variant;
                 parts.push_back(make_plan(mode, m[i], n[i], lda[i], o));
             }
             be->dp = std::make_unique<DevicePlan>();

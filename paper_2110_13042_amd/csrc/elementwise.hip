@@ -16,7 +16,8 @@ static_assert(EW_THREADS == ITEM_BLOCK, "one workgroup per aligned item block");
 // Work item = one row r and four consecutive columns c..c+3 of the m2 x n2
 // sums.  Reads the four quadrant values of the parent operand (zero outside
 // its physical extent and outside the quadrant's real size) and writes the
-// five sums, including the zero padding of the ceil-sized buffers.
+// five sums (Winograd: four, the chained ones from the rounded earlier sums),
+// including the zero padding of the ceil-sized buffers.
 __device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
     typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
     const v2bf p = {(__bf16)a, (__bf16)b};          // round to nearest even
@@ -39,8 +40,8 @@ __device__ __forceinline__ void split8(const float* v, uint4& hi, uint4& lo) {
 
 // Pre-sums of a node whose products are all leaves, written straight into the
 // split-BF16 packed layout.  Work item = one chunk (row-group g, column c):
-// eight rows of the four quadrant values, the five sums formed in FP32, then
-// split.
+// eight rows of the four quadrant values, the five (Winograd: four) sums
+// formed in FP32, then split.
 __device__ void presum_packed(const PresumDesc& d, int64_t e, const float* A, const float* B, float* arena) {
     const int64_t g = udiv(e, d.n2), c = e - g * d.n2;
     const float* V = (d.V.base == BASE_A ? A : d.V.base == BASE_B ? B : arena) + d.V.off;
@@ -56,7 +57,16 @@ __device__ void presum_packed(const PresumDesc& d, int64_t e, const float* A, co
             return in ? V[rr * ld + cc] : 0.f;
         };
         const float a11 = get(0, 0), a12 = get(0, 1), a21 = get(1, 0), a22 = get(1, 1);
-        if (d.side == 0) {
+        if (d.variant == 1) {
+            if (d.side == 0) {
+                sum[0][q] = a12 + a22; sum[1][q] = sum[0][q] - a11;
+                sum[2][q] = a11 - a12; sum[3][q] = a21 - sum[1][q];
+            } else {
+                sum[0][q] = a12 - a11; sum[1][q] = a22 - sum[0][q];
+                sum[2][q] = a22 - a12; sum[3][q] = sum[1][q] - a21;
+            }
+            sum[4][q] = 0.f;
+        } else if (d.side == 0) {
             sum[0][q] = a11 + a22; sum[1][q] = a12 + a22; sum[2][q] = a11 + a21;
             sum[3][q] = a12 - a11; sum[4][q] = a21 - a22;
         } else {
@@ -65,8 +75,10 @@ __device__ void presum_packed(const PresumDesc& d, int64_t e, const float* A, co
         }
     }
     const int64_t groups = (m2 + 7) / 8, each = groups * n2 * 8, lo_delta = groups * n2 * 4;
+    const int nsums = d.variant == 1 ? 4 : 5;
 #pragma unroll
     for (int i = 0; i < 5; ++i) {
+        if (i >= nsums) break;
         uint4 hi, lo;
         split8(sum[i], hi, lo);
         float* base = arena + d.out_off + i * each;
@@ -132,6 +144,22 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
         typedef typename Vec4<T>::type V4;
         const V4 a11 = ld4(V + r * ld + c0), a12 = ld4(V + r * ld + n1 + c0);
         const V4 a21 = ld4(V + (m1 + r) * ld + c0), a22 = ld4(V + (m1 + r) * ld + n1 + c0);
+        if (d.variant == 1) {
+            if (d.side == 0) {
+                const V4 s1 = V4OP(a12, +, a22), s2 = V4OP(s1, -, a11);
+                st4(out + 0 * plane + c0, s1);                     // S1 = X12 + X22
+                st4(out + 1 * plane + c0, s2);                     // S2 = S1 - X11
+                st4(out + 2 * plane + c0, V4 V4OP(a11, -, a12));   // S3 = X11 - X12
+                st4(out + 3 * plane + c0, V4 V4OP(a21, -, s2));    // S4 = X21 - S2
+            } else {
+                const V4 t1 = V4OP(a12, -, a11), t2 = V4OP(a22, -, t1);
+                st4(out + 0 * plane + c0, t1);                     // T1 = Y12 - Y11
+                st4(out + 1 * plane + c0, t2);                     // T2 = Y22 - T1
+                st4(out + 2 * plane + c0, V4 V4OP(a22, -, a12));   // T3 = Y22 - Y12
+                st4(out + 3 * plane + c0, V4 V4OP(t2, -, a21));    // T4 = T2 - Y21
+            }
+            return;
+        }
         if (d.side == 0) {
             st4(out + 0 * plane + c0, V4 V4OP(a11, +, a22));   // S1 = X11 + X22
             st4(out + 1 * plane + c0, V4 V4OP(a12, +, a22));   // S2 = X12 + X22
@@ -157,7 +185,21 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
         const int64_t c = c0 + q;
         if (c >= n2) break;
         const T a11 = get(0, 0, c), a12 = get(0, 1, c), a21 = get(1, 0, c), a22 = get(1, 1, c);
-        if (d.side == 0) {
+        if (d.variant == 1) {
+            if (d.side == 0) {
+                const T s1 = a12 + a22, s2 = s1 - a11;
+                out[0 * plane + c] = s1;
+                out[1 * plane + c] = s2;
+                out[2 * plane + c] = a11 - a12;
+                out[3 * plane + c] = a21 - s2;
+            } else {
+                const T t1 = a12 - a11, t2 = a22 - t1;
+                out[0 * plane + c] = t1;
+                out[1 * plane + c] = t2;
+                out[2 * plane + c] = a22 - a12;
+                out[3 * plane + c] = t2 - a21;
+            }
+        } else if (d.side == 0) {
             out[0 * plane + c] = a11 + a22;
             out[1 * plane + c] = a12 + a22;
             out[2 * plane + c] = a11 + a21;
@@ -368,7 +410,9 @@ __global__ __launch_bounds__(EW_THREADS) void eq_unscale_kernel(float* Cp, int64
 // Work item = one row i and four columns j..j+3 of the n2 x k2 products.
 // C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4,
 // C22 = M1 - M2 + M3 + M6, each summed left to right; only the leading part
-// of a product reaches a floor-sized quadrant.
+// of a product reaches a floor-sized quadrant.  Winograd's form shares partial
+// sums: U2 = M1 + M6, U3 = U2 + M7, C11 = M1 + M2, C12 = (U2 + M5) + M3,
+// C21 = U3 - M4, C22 = U3 + M5.
 template <class T>
 __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* tasks, int ntasks,
                                                              int64_t items, T* C0, T* arena,
@@ -394,14 +438,25 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
         const V4 m1 = ld4(M + j0), m2 = ld4(M + plane + j0), m3 = ld4(M + 2 * plane + j0);
         const V4 m4 = ld4(M + 3 * plane + j0), m5 = ld4(M + 4 * plane + j0);
         const V4 m6 = ld4(M + 5 * plane + j0), m7 = ld4(M + 6 * plane + j0);
-        const V4 t14 = V4OP(m1, +, m4);
-        const V4 t145 = V4OP(t14, -, m5);
-        const V4 c11 = V4OP(t145, +, m7);
-        const V4 c12 = V4OP(m3, +, m5);
-        const V4 c21 = V4OP(m2, +, m4);
-        const V4 t12 = V4OP(m1, -, m2);
-        const V4 t123 = V4OP(t12, +, m3);
-        const V4 c22 = V4OP(t123, +, m6);
+        V4 c11, c12, c21, c22;
+        if (d.variant == 1) {
+            const V4 u2 = V4OP(m1, +, m6);
+            const V4 u3 = V4OP(u2, +, m7);
+            const V4 u4 = V4OP(u2, +, m5);
+            c11 = V4 V4OP(m1, +, m2);
+            c12 = V4 V4OP(u4, +, m3);
+            c21 = V4 V4OP(u3, -, m4);
+            c22 = V4 V4OP(u3, +, m5);
+        } else {
+            const V4 t14 = V4OP(m1, +, m4);
+            const V4 t145 = V4OP(t14, -, m5);
+            c11 = V4 V4OP(t145, +, m7);
+            c12 = V4 V4OP(m3, +, m5);
+            c21 = V4 V4OP(m2, +, m4);
+            const V4 t12 = V4OP(m1, -, m2);
+            const V4 t123 = V4OP(t12, +, m3);
+            c22 = V4 V4OP(t123, +, m6);
+        }
         T* p11 = dst(i, j0);
         T* p12 = dst(i, k1 + j0);
         T* p21 = dst(n1 + i, j0);
@@ -424,6 +479,16 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
         if (j >= k2) break;
         const T m1 = M[j], m2 = M[plane + j], m3 = M[2 * plane + j], m4 = M[3 * plane + j];
         const T m5 = M[4 * plane + j], m6 = M[5 * plane + j], m7 = M[6 * plane + j];
+        if (d.variant == 1) {
+            const T u2 = m1 + m6, u3 = u2 + m7;
+            if (i < n1) {
+                if (j < k1) *dst(i, j) = m1 + m2;
+                *dst(i, k1 + j) = (u2 + m5) + m3;
+            }
+            if (j < k1) *dst(n1 + i, j) = u3 - m4;
+            *dst(n1 + i, k1 + j) = u3 + m5;
+            continue;
+        }
         if (i < n1) {
             if (j < k1) *dst(i, j) = ((m1 + m4) - m5) + m7;
             *dst(i, k1 + j) = m3 + m5;

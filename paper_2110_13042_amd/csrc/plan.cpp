@@ -224,7 +224,8 @@ struct Builder {
         const View Y11 = sub(Y, 0, m1, m2, 0, k1, k2), Y12 = sub(Y, 0, m1, m2, k1, k2, k2);
         const View Y21 = sub(Y, m1, m2, m2, 0, k1, k2), Y22 = sub(Y, m1, m2, m2, k1, k2, k2);
         auto Mt = [&](int i, int64_t M) { return Target{OUT_DENSE, M + (i - 1) * n2 * k2, k2, 0, 0}; };
-        if (p.fuse && children_leaf && ((p.mode == MODE_F32 && p.tile_cfg != 2) || p.mode == MODE_F64)) {
+        if (p.fuse && p.variant == 0 && children_leaf &&
+            ((p.mode == MODE_F32 && p.tile_cfg != 2) || p.mode == MODE_F64)) {
             // the seven products are leaves: each forms its pre-sums while
             // loading its operands (same IEEE sums as the pre-sum pass)
             const int64_t M = alloc(7 * n2 * k2);
@@ -249,15 +250,18 @@ struct Builder {
             if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
             return 1;
         }
+        const bool wino = p.variant == 1;
+        const int nsums = wino ? 4 : 5;
         const int64_t groups = cdiv(m2, 8);
         const int64_t s_each = packed ? groups * n2 * 8 : m2 * n2;
         const int64_t t_each = packed ? groups * k2 * 8 : m2 * k2;
-        const int64_t S = alloc(5 * s_each), T = alloc(5 * t_each), M = alloc(7 * n2 * k2);
+        const int64_t S = alloc(nsums * s_each), T = alloc(nsums * t_each), M = alloc(7 * n2 * k2);
         if ((int)p.presum.size() <= depth) p.presum.resize(depth + 1);
         PresumDesc ps{};
         ps.V = X; ps.m1 = m1; ps.m2 = m2; ps.n1 = n1; ps.n2 = n2; ps.out_off = S;
         ps.elems = packed ? groups * n2 : m2 * cdiv(n2, 4);
         ps.side = 0; ps.pred_node = pn; ps.pred_value = pv; ps.packed_out = packed ? 1 : 0;
+        ps.variant = p.variant;
         p.presum[depth].push_back(ps);
         PresumDesc pt = ps;
         pt.V = Y; pt.n1 = k1; pt.n2 = k2; pt.out_off = T; pt.side = 1;
@@ -275,19 +279,32 @@ struct Builder {
             return v;
         };
         int h = 0;
-        h = std::max(h, strassen(Sv(1), Tv(1), Mt(1, M), depth + 1, pn, pv));  // M1 = S1^T T1
-        h = std::max(h, strassen(Sv(2), Y11, Mt(2, M), depth + 1, pn, pv));    // M2 = S2^T Y11
-        h = std::max(h, strassen(X11, Tv(2), Mt(3, M), depth + 1, pn, pv));    // M3 = X11^T T2
-        h = std::max(h, strassen(X22, Tv(3), Mt(4, M), depth + 1, pn, pv));    // M4 = X22^T T3
-        h = std::max(h, strassen(Sv(3), Y22, Mt(5, M), depth + 1, pn, pv));    // M5 = S3^T Y22
-        h = std::max(h, strassen(Sv(4), Tv(4), Mt(6, M), depth + 1, pn, pv));  // M6 = S4^T T4
-        h = std::max(h, strassen(Sv(5), Tv(5), Mt(7, M), depth + 1, pn, pv));  // M7 = S5^T T5
+        if (wino) {
+            // Winograd's form of C = X^T Y (Xt_ij = X_ji^T), with S1 = X12 + X22,
+            // S2 = S1 - X11, S3 = X11 - X12, S4 = X21 - S2, T1 = Y12 - Y11,
+            // T2 = Y22 - T1, T3 = Y22 - Y12, T4 = T2 - Y21
+            h = std::max(h, strassen(X11, Y11, Mt(1, M), depth + 1, pn, pv));      // M1 = X11^T Y11
+            h = std::max(h, strassen(X21, Y21, Mt(2, M), depth + 1, pn, pv));      // M2 = X21^T Y21
+            h = std::max(h, strassen(Sv(4), Y22, Mt(3, M), depth + 1, pn, pv));    // M3 = S4^T Y22
+            h = std::max(h, strassen(X22, Tv(4), Mt(4, M), depth + 1, pn, pv));    // M4 = X22^T T4
+            h = std::max(h, strassen(Sv(1), Tv(1), Mt(5, M), depth + 1, pn, pv));  // M5 = S1^T T1
+            h = std::max(h, strassen(Sv(2), Tv(2), Mt(6, M), depth + 1, pn, pv));  // M6 = S2^T T2
+            h = std::max(h, strassen(Sv(3), Tv(3), Mt(7, M), depth + 1, pn, pv));  // M7 = S3^T T3
+        } else {
+            h = std::max(h, strassen(Sv(1), Tv(1), Mt(1, M), depth + 1, pn, pv));  // M1 = S1^T T1
+            h = std::max(h, strassen(Sv(2), Y11, Mt(2, M), depth + 1, pn, pv));    // M2 = S2^T Y11
+            h = std::max(h, strassen(X11, Tv(2), Mt(3, M), depth + 1, pn, pv));    // M3 = X11^T T2
+            h = std::max(h, strassen(X22, Tv(3), Mt(4, M), depth + 1, pn, pv));    // M4 = X22^T T3
+            h = std::max(h, strassen(Sv(3), Y22, Mt(5, M), depth + 1, pn, pv));    // M5 = S3^T Y22
+            h = std::max(h, strassen(Sv(4), Tv(4), Mt(6, M), depth + 1, pn, pv));  // M6 = S4^T T4
+            h = std::max(h, strassen(Sv(5), Tv(5), Mt(7, M), depth + 1, pn, pv));  // M7 = S5^T T5
+        }
         const int height = h + 1;
         if ((int)p.combine.size() < height) p.combine.resize(height);
         CombineDesc c{};
         c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
         c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
-        c.elems = n2 * cdiv(k2, 4); c.pred_node = pn; c.pred_value = pv;
+        c.elems = n2 * cdiv(k2, 4); c.pred_node = pn; c.pred_value = pv; c.variant = p.variant;
         p.combine[height - 1].push_back(c);
         if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
         return height;
@@ -426,6 +443,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
     p.fuse = opt.fuse_presum;
+    p.variant = opt.variant;
     if (n == 0) return p;
     Builder bld(p);
     bld.ata(0, n);
@@ -525,6 +543,7 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.fallback = false;
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
     p.fuse = opt.fuse_presum;
+    p.variant = opt.variant;
     if (n == 0 || k == 0) return p;
     Builder bld(p);
     View X{};
@@ -653,6 +672,7 @@ Plan merge_plans(std::vector<Plan>& parts, int64_t split_target) {
     out.nprob = (int32_t)parts.size();
     out.tile_cfg = parts[0].tile_cfg;
     out.fuse = parts[0].fuse;
+    out.variant = parts[0].variant;
     out.max_depth = 0;
     int64_t node_base = 0;
     for (size_t q = 0; q < parts.size(); ++q) {

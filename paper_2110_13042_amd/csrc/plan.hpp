@@ -141,7 +141,8 @@ struct PackDesc {
     int32_t prob, pad_;
 };
 
-// Five Strassen pre-sums of one operand (X side: S1..S5, Y side: T1..T5).
+// Pre-sums of one operand: Strassen's five (X side: S1..S5, Y side: T1..T5)
+// or Winograd's four chained ones (variant 1).
 struct PresumDesc {
     View V;                   // the parent operand (m x n logical)
     int64_t m1, m2, n1, n2;
@@ -150,12 +151,14 @@ struct PresumDesc {
     int64_t elems;
     int32_t side;             // 0 = X (S sums), 1 = Y (T sums)
     int32_t pred_node, pred_value;
-    int32_t packed_out;       // 1: write the five sums split and packed (work item = one
+    int32_t packed_out;       // 1: write the sums split and packed (work item = one
                               // 16-byte chunk; sum i at out_off + i * ceil(m2/8) * n2 * 8)
-    int32_t prob, pad_;
+    int32_t prob;
+    int32_t variant;          // 0: Strassen, five sums; 1: Winograd, four sums
 };
 
-// Strassen combine: seven n2 x k2 products into the four quadrants.
+// Strassen (or Winograd) combine: seven n2 x k2 products into the four
+// quadrants.
 struct CombineDesc {
     int64_t m_off;            // arena: seven n2 x k2 buffers, row stride k2
     int64_t n1, n2, k1, k2;
@@ -166,6 +169,7 @@ struct CombineDesc {
     int64_t elem_begin, elems;
     int32_t pred_value;
     int32_t prob;
+    int32_t variant, pad_;        // 0: Strassen, 1: Winograd
 };
 
 // Column-norm task of one problem.  Pass 1: a workgroup sums the squares of
@@ -193,6 +197,7 @@ struct PlanOptions {
     double spread_tau = 4096.0;    // <= 0: no fallback
     int64_t split_target = 2048;   // split K when a launch has fewer tiles (0: never)
     bool fuse_presum = false;      // FP32/FP64: last-level pre-sums formed in the leaf loads
+    int32_t variant = 0;           // Strassen node: 0 = Strassen's form, 1 = Winograd's
 };
 
 struct PlanStats {
@@ -212,6 +217,7 @@ struct Plan {
     int32_t tile_cfg = 0;
     bool fallback = false;
     bool fuse = false;                              // last-level pre-sums fused into the leaves
+    int32_t variant = 0;                            // 0: Strassen nodes, 1: Winograd nodes
     std::vector<std::vector<PresumDesc>> presum;    // [level-1] top-down
     std::vector<PackDesc> pack;                     // split-BF16 operand packing
     std::vector<Pack8Desc> pack8;                   // FP8 operand quantisation

@@ -1,0 +1,143 @@
+"""Winograd's form of the Strassen node (ATA_OPT_STRASSEN_FORM = 1): the same
+seven products per node as Strassen's (Sec. 3.2), formed from four chained
+pre-sums per operand and combined with seven additions that share partial
+sums.  Small integers make every sum and product exact, so each mode must
+reproduce the plain product bit for bit; random inputs must meet the modes'
+tolerances against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import plain
+from paper_2110_13042_amd import ata
+from gpu_helpers import device, full_error, run_gram
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def h():
+    device()
+    hd = ata.Handle(spread_tau=0)
+    hd.set("strassen_form", 1)
+    yield hd
+    hd.close()
+
+
+# (m, n, b, depth, lda): odd splits at every level, lda > n, a short wide case
+INT_CASES = [(257, 255, 64, 2, 255), (1000, 777, 100, 3, 781), (513, 1025, 256, 1, 1025),
+             (64, 1500, 128, 3, 1500), (3001, 900, 128, 2, 900)]
+
+
+@pytest.mark.parametrize("mode,tile", [(ata.F64, 0), (ata.F32, 0), (ata.F32, 2), (ata.F32, 3),
+                                       (ata.F32_BF16X3, 0), (ata.F32_BF16X3, 4),
+                                       (ata.F32_FP8E4M3, 0), (ata.F32_FP8E4M3, 3)])
+def test_winograd_integers_exact(h, mode, tile):
+    rng = np.random.default_rng(91)
+    h.set("leaf_tile", tile)
+    try:
+        for (m, n, b, depth, lda) in INT_CASES:
+            if mode == ata.F32_FP8E4M3:
+                depth = min(depth, 1)       # chained sums of sums leave e4m3's exact integers
+            _say("case: winograd int", mode, "tile", tile, m, n, b, depth, lda)
+            A = rng.integers(-2, 3, (m, n)).astype(np.float64)
+            h.set("leaf_cutoff", b)
+            h.set("max_depth", depth)
+            Cp = run_gram(A, mode, h, lda=lda)
+            assert h.report()["strassen_levels"] >= 1
+            assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth)
+    finally:
+        h.set("leaf_tile", 0)
+
+
+@pytest.mark.parametrize("mode,tol", [(ata.F64, 1e-12), (ata.F32, 2e-5), (ata.F32_BF16X3, 2e-5)])
+def test_winograd_random_within_tolerance(h, mode, tol):
+    """Uniform[-1, 1] inputs, up to three Winograd levels; the error of the
+    Strassen form on the same plan is printed beside it."""
+    rng = np.random.default_rng(92)
+    for (m, n, b, depth) in [(2047, 1500, 256, 3), (3000, 2048, 512, 2), (5000, 900, 256, 2)]:
+        A = rng.uniform(-1, 1, (m, n))
+        ref = plain.gram_packed(A)
+        h.set("leaf_cutoff", b)
+        h.set("max_depth", depth)
+        errs = []
+        try:
+            for form in (0, 1):
+                h.set("strassen_form", form)
+                errs.append(full_error(run_gram(A, mode, h), ref))
+        finally:
+            h.set("strassen_form", 1)
+        _say("case: winograd random", mode, m, n, b, depth, "levels", h.report()["strassen_levels"],
+             "e_F strassen / winograd", errs)
+        assert errs[1] <= tol, (m, n, b, depth)
+
+
+def test_winograd_gemm_tn_integers_exact(h):
+    """C = A^T B on its own (the recursion's general product), dense output
+    with padded leading dimensions."""
+    rng = np.random.default_rng(93)
+    dev = device()
+    for mode in (ata.F64, ata.F32, ata.F32_BF16X3):
+        dt = torch.float64 if mode == ata.F64 else torch.float32
+        for (m, n, k, b, depth) in [(300, 257, 190, 64, 2), (1000, 300, 300, 128, 1), (129, 65, 400, 32, 3)]:
+            _say("case: winograd gemm_tn", mode, m, n, k, b, depth)
+            A = rng.integers(-2, 3, (m, n)).astype(np.float64)
+            B = rng.integers(-2, 3, (m, k)).astype(np.float64)
+            At = torch.zeros((m, n + 3), dtype=dt, device=dev)
+            Bt = torch.zeros((m, k + 1), dtype=dt, device=dev)
+            At[:, :n] = torch.from_numpy(A).to(dev, dt)
+            Bt[:, :k] = torch.from_numpy(B).to(dev, dt)
+            C = torch.full((n, k + 2), 7.0, dtype=dt, device=dev)
+            h.set("leaf_cutoff", b)
+            h.set("max_depth", depth)
+            ata.ata_gemm_tn(h.h, At.data_ptr(), Bt.data_ptr(), m, n, k, n + 3, k + 1, mode, C.data_ptr(), k + 2,
+                            torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            out = C.double().cpu().numpy()
+            assert np.all(out[:, k:] == 7.0)
+            assert np.array_equal(out[:, :k], plain.gemm_tn(A, B)), (mode, m, n, k, b, depth)
+
+
+def test_winograd_batch_integers_exact(h):
+    rng = np.random.default_rng(94)
+    dev = device()
+    mats = [rng.integers(-2, 3, (int(rng.integers(1, 700)), int(rng.integers(1, 600)))).astype(np.float32)
+            for _ in range(20)]
+    h.set("leaf_cutoff", 128)
+    h.set("max_depth", 2)
+    for mode in (ata.F32, ata.F32_BF16X3):
+        _say("case: winograd batch mode", mode, "problems", len(mats))
+        As = [torch.from_numpy(M).to(dev) for M in mats]
+        Cs = ata.gram_batched(As, mode, handle=h)
+        torch.cuda.synchronize()
+        for i, (C, M) in enumerate(zip(Cs, mats)):
+            assert np.array_equal(C.double().cpu().numpy(), plain.gram_packed(M)), (mode, i, M.shape)
+
+
+def test_winograd_shrinks_the_workspace(h):
+    """Four pre-sum buffers per operand instead of five."""
+    A = np.random.default_rng(95).uniform(-1, 1, (2048, 2048)).astype(np.float32)
+    h.set("leaf_cutoff", 512)
+    h.set("max_depth", 1)
+    ws = []
+    try:
+        for form in (0, 1):
+            h.set("strassen_form", form)
+            run_gram(A, ata.F32, h)
+            ws.append(h.report()["workspace_bytes"])
+    finally:
+        h.set("strassen_form", 1)
+    _say("workspace strassen / winograd", ws)
+    assert ws[1] < ws[0]
+
+
+def test_winograd_option_rejects_other_values(h):
+    with pytest.raises(ata.AtaError):
+        h.set("strassen_form", 2)
