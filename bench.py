@@ -143,6 +143,7 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
                  "launches_per_step": rep["kernel_launches"], "workspace_bytes": rep["workspace_bytes"],
                  "leaf_tile": rep["leaf_tile"],
                  "strassen_form": "winograd" if args.winograd else "strassen",
+                 "tail_split": [rep["tail_split_leaves"], rep["tail_split_chunks"]],
                  "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile"},
         "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
             ["norms_flags", "presum_pack", "leaves", "combine", "residual"], rep["phase_ms"])},
@@ -176,6 +177,10 @@ def make_handle(ata, args):
         h.set("fuse_presum", 1)
     if args.winograd:
         h.set("strassen_form", 1)
+    if args.no_balance_tail:
+        h.set("balance_tail", 0)
+    if args.spread_tau >= 0:
+        h.set("spread_tau", args.spread_tau)
     return h
 
 
@@ -244,6 +249,7 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
         "plan": {"problems": len(As), "multiplications": rep["multiplications"],
                  "leaf_tile": rep["leaf_tile"],
                  "strassen_form": "winograd" if args.winograd else "strassen",
+                 "tail_split": [rep["tail_split_leaves"], rep["tail_split_chunks"]],
                  "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile",
                  "batch_autotune": tuned,
                  "leaves": rep["syrk_leaves"] + rep["gemm_leaves"],
@@ -358,6 +364,10 @@ def main() -> int:
                     help="FP32/FP64: form the last Strassen level's pre-sums inside the leaf loads")
     ap.add_argument("--winograd", action="store_true",
                     help="Strassen nodes in Winograd's form (four chained pre-sums per operand)")
+    ap.add_argument("--spread-tau", type=float, default=-1.0,
+                    help="column-norm spread threshold of the FP64 fallback (0: no spread check; default: the library's)")
+    ap.add_argument("--no-balance-tail", action="store_true",
+                    help="do not cut the leaves of an underfilled last round of the leaf launch into K chunks")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

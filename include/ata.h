@@ -161,7 +161,22 @@ typedef enum {
        node.  Both are exact in exact arithmetic; Winograd's rounding-error
        constant is somewhat larger.  With 1, ATA_OPT_FUSE_PRESUM is ignored
        (a chained sum is not one rounding of two quadrant elements). */
-    ATA_OPT_STRASSEN_FORM = 17
+    ATA_OPT_STRASSEN_FORM = 17,
+    /* 1 (default) = balance the last round of the leaf launch.  The leaf
+       tiles run longest-first on the device's resident workgroups (CUs x
+       workgroups per CU).  When the final round would leave most of them
+       idle (for example 528 equal 256 x 256 tiles on 256 slots: two full
+       rounds, then 16 tiles), the smallest leaves covering that tail are
+       cut into K chunks whose partial sums the split-K reduce adds in FP64
+       (rounded once), so the chunk tiles fill the last round.  The cut is
+       chosen on the host by simulating the launch's list scheduling, and
+       kept only when it shortens the simulated time by 4% or more; plans
+       already split for a small launch, leaves under the spread check and
+       the plain alternatives of flagged nodes are left alone.  Results of
+       a cut leaf can differ from the uncut ones by rounding only.
+       ata_report_t.tail_split_leaves tells whether a plan was cut.
+       0 = never. */
+    ATA_OPT_BALANCE_TAIL = 18
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */
@@ -188,6 +203,8 @@ typedef struct {
                                      (ATA_OPT_LEAF_TILE's values)             */
     int32_t leaf_persistent;      /* 1 = the leaf products ran as a persistent
                                      grid, 0 = one workgroup per tile          */
+    int32_t tail_split_leaves;    /* leaves cut by the tail balancer (0: none) */
+    int32_t tail_split_chunks;    /* K chunks per cut leaf                     */
 } ata_report_t;
 
 /* One leaf of a plan, as returned by ata_plan_query. */

@@ -31,6 +31,7 @@ OPT_EQUILIBRATE = 14
 OPT_LEAF_PERSISTENT = 15
 OPT_FUSE_PRESUM = 16
 OPT_STRASSEN_FORM = 17
+OPT_BALANCE_TAIL = 18
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -51,7 +52,8 @@ class Report(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_int64), ("kernel_launches", ctypes.c_int64),
                 ("flagged_nodes", ctypes.c_int64), ("residual", ctypes.c_double),
                 ("profiled_calls", ctypes.c_int64), ("phase_ms", ctypes.c_double * 5),
-                ("leaf_tile", ctypes.c_int32), ("leaf_persistent", ctypes.c_int32)]
+                ("leaf_tile", ctypes.c_int32), ("leaf_persistent", ctypes.c_int32),
+                ("tail_split_leaves", ctypes.c_int32), ("tail_split_chunks", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -264,7 +266,8 @@ class Handle:
                "xcd_chunk": OPT_XCD_CHUNK, "tile_band": OPT_TILE_BAND,
                "split_target": OPT_SPLIT_TARGET, "batch_use_table": OPT_BATCH_USE_TABLE,
                "equilibrate": OPT_EQUILIBRATE, "leaf_persistent": OPT_LEAF_PERSISTENT,
-               "fuse_presum": OPT_FUSE_PRESUM, "strassen_form": OPT_STRASSEN_FORM}[name]
+               "fuse_presum": OPT_FUSE_PRESUM, "strassen_form": OPT_STRASSEN_FORM,
+               "balance_tail": OPT_BALANCE_TAIL}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

@@ -34,9 +34,11 @@ struct PlanKey {
     int64_t split;
     bool fuse;
     int32_t variant;
+    int64_t slots;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant) <
-               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant);
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant, slots) <
+               std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant,
+                        o.slots);
     }
 };
 
@@ -77,10 +79,11 @@ struct BatchKey {
     int64_t split;
     bool fuse;
     int32_t variant;
+    int64_t slots;
     std::vector<int64_t> shapes;   // m, n, lda per problem
     bool operator<(const BatchKey& o) const {
-        return std::tie(mode, b, depth, fb, tile_cfg, split, fuse, variant, shapes) <
-               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant, o.shapes);
+        return std::tie(mode, b, depth, fb, tile_cfg, split, fuse, variant, slots, shapes) <
+               std::tie(o.mode, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant, o.slots, o.shapes);
     }
 };
 
@@ -92,10 +95,11 @@ struct GemmKey {
     int64_t split;
     bool fuse;
     int32_t variant;
+    int64_t slots;
     bool operator<(const GemmKey& o) const {
-        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split, fuse, variant) <
+        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split, fuse, variant, slots) <
                std::tie(o.mode, o.m, o.n, o.k, o.lda, o.ldb, o.ldc, o.b, o.depth, o.tile_cfg, o.split, o.fuse,
-                        o.variant);
+                        o.variant, o.slots);
     }
 };
 
@@ -190,6 +194,7 @@ struct ata_ctx {
     bool batch_graph = true;
     int batch_persistent = -1;         // 0 grid, 1 persistent, -1 automatic
     int leaf_persistent = -1;
+    bool balance_tail = true;          // split the leaves of an underfilled last round
     uint64_t arena_gen = 0;
     // phase profiling: six events per profiled call, summed at report time
     bool profile = false;
@@ -350,6 +355,12 @@ bool persistent_for(int setting, const Plan& p) {
     return p.mode == MODE_F32 && p.tile_cfg >= 2;
 }
 
+// Resident leaf workgroups of the device (256 CUs) for the tail balancer,
+// or 0 when it is off.
+int64_t tail_slots(const ata_ctx* h, int32_t mode, int32_t tile_cfg) {
+    return h->balance_tail ? (int64_t)leaf_blocks_per_cu(mode, tile_cfg) * 256 : 0;
+}
+
 void fill_report(ata_report_t& r, const Plan& p) {
     r.m = p.m;
     r.n = p.n;
@@ -368,6 +379,8 @@ void fill_report(ata_report_t& r, const Plan& p) {
     r.residual = -1.0;
     r.leaf_tile = p.tile_cfg;
     r.leaf_persistent = 0;
+    r.tail_split_leaves = p.tail_leaves;
+    r.tail_split_chunks = p.tail_chunks;
 }
 
 }  // namespace
@@ -470,6 +483,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             return ATA_OK;
         case ATA_OPT_FUSE_PRESUM:
             h->popt.fuse_presum = value != 0.0;
+            return ATA_OK;
+        case ATA_OPT_BALANCE_TAIL:
+            h->balance_tail = value != 0.0;
             return ATA_OK;
         case ATA_OPT_STRASSEN_FORM:
             if (value != 0.0 && value != 1.0) return ATA_ERR_INVALID_VALUE;
@@ -630,8 +646,9 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     int32_t depth, tile_cfg;
     choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
+    const int64_t slots = tail_slots(h, mode, tile_cfg);
     const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
-                       h->popt.variant};
+                       h->popt.variant, slots};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -643,6 +660,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         o.split_target = h->split_target;
         o.fuse_presum = h->popt.fuse_presum;
         o.variant = h->popt.variant;
+        o.slots = slots;
         try {
             dp->plan = make_plan(mode, m, n, lda, o);
             if (dp->plan.fallback) fuse_pack_into_norms(dp->plan, dp->plan.col1);
@@ -832,8 +850,9 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     int64_t b;
     int32_t depth, tile_cfg;
     choose(h, mode, m, std::max(n, k), b, depth, tile_cfg);
+    const int64_t slots = tail_slots(h, mode, tile_cfg);
     const GemmKey key{mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, h->split_target, h->popt.fuse_presum,
-                       h->popt.variant};
+                       h->popt.variant, slots};
     auto it = h->gemm_plans.find(key);
     if (it == h->gemm_plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -845,6 +864,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
         o.split_target = h->split_target;
         o.fuse_presum = h->popt.fuse_presum;
         o.variant = h->popt.variant;
+        o.slots = slots;
         try {
             dp->plan = make_gemm_plan(mode, m, n, k, lda, ldb, ldc, o);
         } catch (const std::invalid_argument&) {
@@ -1084,8 +1104,9 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     }
     std::vector<int64_t> bs((size_t)batch);
     std::vector<int32_t> ds((size_t)batch);
+    const int64_t slots = tail_slots(h, mode, tile_cfg);
     BatchKey key{mode, h->popt.leaf_cutoff, h->popt.max_depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
-                 h->popt.variant, {}};
+                 h->popt.variant, slots, {}};
     key.shapes.reserve(5 * (size_t)batch);
     for (int64_t i = 0; i < batch; ++i) {
         int32_t tile_i;
@@ -1119,7 +1140,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
                 parts.push_back(make_plan(mode, m[i], n[i], lda[i], o));
             }
             be->dp = std::make_unique<DevicePlan>();
-            be->dp->plan = merge_plans(parts, h->split_target);
+            be->dp->plan = merge_plans(parts, h->split_target, slots);
         } catch (const std::invalid_argument&) {
             return ATA_ERR_INVALID_VALUE;
         } catch (const std::length_error&) {

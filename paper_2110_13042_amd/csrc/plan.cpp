@@ -2,6 +2,8 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <map>
 #include <stdexcept>
 #include <tuple>
@@ -451,6 +453,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     if (mode == MODE_FP8 && m > 0) assign_quant(p);
     if (p.fallback) build_colnorm_tasks(&p.m, &p.n, &p.lda, 1, p.col1, p.col2, &p.col_partial);
     if (opt.split_target > 0) split_leaves(p, opt.split_target);
+    if (opt.slots > 0) balance_tail(p, opt.slots);
     finalize_plan(p);
     return p;
 }
@@ -560,9 +563,48 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
     if (mode == MODE_BF16X3 && m > 0) assign_packed(p);
     if (mode == MODE_FP8 && m > 0) assign_quant(p);
     if (opt.split_target > 0) split_leaves(p, opt.split_target);
+    if (opt.slots > 0) balance_tail(p, opt.slots);
     finalize_plan(p);
     return p;
 }
+
+namespace {
+
+// Cuts leaf L into K chunks of a multiple of 256 rows (about K / s each),
+// with the partial buffers and the reduce task.  False if that leaves one
+// chunk.
+bool split_leaf(Plan& p, LeafDesc& L, int64_t s) {
+    const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
+    s = cdiv(L.K, kchunk);
+    if (s < 2) return false;
+    L.ksplit = (int32_t)s;
+    L.kchunk = kchunk;
+    L.tiles_split = L.tiles;
+    L.tiles *= s;
+    L.part_off = p.alloc(s * L.rows * L.cols);
+    if (L.fb_node >= 0) L.part64_off = p.alloc(2 * s * L.rows * L.cols);
+    ReduceDesc R{};
+    R.kind = L.kind;
+    R.out_kind = L.out_kind;
+    R.rows = L.rows;
+    R.cols = L.cols;
+    R.part_off = L.part_off;
+    R.part64_off = L.part64_off;
+    R.out_off = L.out_off;
+    R.out_ld = L.out_ld;
+    R.out_row0 = L.out_row0;
+    R.out_col0 = L.out_col0;
+    R.ksplit = L.ksplit;
+    R.fb_node = L.fb_node;
+    R.pred_node = L.pred_node;
+    R.pred_value = L.pred_value;
+    R.prob = L.prob;
+    R.elems = L.rows * L.cols;
+    p.reduce.push_back(R);
+    return true;
+}
+
+}  // namespace
 
 void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
     if (target <= 0) return;
@@ -583,34 +625,127 @@ void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
         if (L.fb_node >= 0 && t_fb > 0 && t_fb < target && most_fb >= 2)
             s = std::max(s, std::min(target / t_fb, most_fb));
         if (s < 2) continue;
-        const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
-        s = cdiv(L.K, kchunk);
-        if (s < 2) continue;
-        L.ksplit = (int32_t)s;
-        L.kchunk = kchunk;
-        L.tiles_split = L.tiles;
-        L.tiles *= s;
-        L.part_off = p.alloc(s * L.rows * L.cols);
-        if (L.fb_node >= 0) L.part64_off = p.alloc(2 * s * L.rows * L.cols);
-        ReduceDesc R{};
-        R.kind = L.kind;
-        R.out_kind = L.out_kind;
-        R.rows = L.rows;
-        R.cols = L.cols;
-        R.part_off = L.part_off;
-        R.part64_off = L.part64_off;
-        R.out_off = L.out_off;
-        R.out_ld = L.out_ld;
-        R.out_row0 = L.out_row0;
-        R.out_col0 = L.out_col0;
-        R.ksplit = L.ksplit;
-        R.fb_node = L.fb_node;
-        R.pred_node = L.pred_node;
-        R.pred_value = L.pred_value;
-        R.prob = L.prob;
-        R.elems = L.rows * L.cols;
-        p.reduce.push_back(R);
+        split_leaf(p, L, s);
     }
+}
+
+namespace {
+
+// Contraction rows per tile of a leaf (what the kernels loop over), and the
+// rows a tile of it costs in a launch: the plain alternative of a flagged
+// node (pred_value 1) usually finds its node unflagged and exits at once.
+int64_t tile_rows(const LeafDesc& L) { return L.ksplit > 1 ? L.kchunk : L.K; }
+int64_t tile_cost(const LeafDesc& L) {
+    return L.pred_node >= 0 && L.pred_value == 1 ? 0 : tile_rows(L);
+}
+
+// Makespan of list scheduling: tiles in longest-first launch order, each
+// taken by the first free slot.  `split[i]` > 1 cuts leaf i into that many K
+// chunks (as split_leaf would).
+int64_t simulate_makespan(const Plan& p, const std::vector<int64_t>& split, int64_t slots) {
+    struct Run { int64_t rows, cost, tiles; };
+    std::vector<Run> runs;
+    runs.reserve(p.leaves.size());
+    for (size_t i = 0; i < p.leaves.size(); ++i) {
+        const LeafDesc& L = p.leaves[i];
+        int64_t rows = tile_rows(L), cost = tile_cost(L), tiles = L.tiles;
+        if (split[i] > 1) {
+            const int64_t kchunk = cdiv(cdiv(L.K, split[i]), 256) * 256;
+            rows = cost = kchunk;
+            tiles = L.tiles * cdiv(L.K, kchunk);
+        }
+        runs.push_back(Run{rows, cost, tiles});
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.rows > b.rows; });
+    std::priority_queue<int64_t, std::vector<int64_t>, std::greater<int64_t>> free_at;
+    for (int64_t i = 0; i < slots; ++i) free_at.push(0);
+    int64_t end = 0;
+    for (const Run& r : runs) {
+        for (int64_t t = 0; t < r.tiles; ++t) {
+            const int64_t f = free_at.top() + r.cost;
+            free_at.pop();
+            free_at.push(f);
+            end = std::max(end, f);
+        }
+    }
+    return end;
+}
+
+}  // namespace
+
+void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
+    if (slots <= 0 || p.leaves.empty()) return;
+    int64_t total_tiles = 0;
+    for (const auto& L : p.leaves) {
+        if (L.ksplit > 1) return;                  // split_leaves has cut this plan
+        total_tiles += L.tiles;
+    }
+    if (total_tiles > 64 * slots) return;         // the tail is a small part of the launch
+    const size_t nl = p.leaves.size();
+    std::vector<int64_t> none(nl, 1);
+    const int64_t base = simulate_makespan(p, none, slots);
+    // candidates: smallest work first (fewest partials), later leaves first on ties
+    std::vector<size_t> cand;
+    for (size_t i = 0; i < nl; ++i) {
+        const LeafDesc& L = p.leaves[i];
+        if (L.fb_node >= 0 || tile_cost(L) == 0 || L.K < 512) continue;
+        cand.push_back(i);
+    }
+    std::stable_sort(cand.begin(), cand.end(), [&](size_t a, size_t b) {
+        const int64_t wa = p.leaves[a].tiles * p.leaves[a].K, wb = p.leaves[b].tiles * p.leaves[b].K;
+        return wa != wb ? wa < wb : a > b;
+    });
+    // Partial sums cost HBM time: each chunk tile writes its partial tile and
+    // the reduce reads it back.  In the makespan's unit (contraction rows of
+    // one tile on one slot) at the mode's peak MFMA rate per CU and 5 TB/s:
+    // rows = bytes * 2 / 5000 B/ns / (ns per tile row).
+    const double flop_ns_per_cu = p.mode == MODE_F64 ? 307.0 : p.mode == MODE_F32 ? 614.0
+                                : p.mode == MODE_BF16X3 ? 9766.0 / 3.0 : 19531.0;
+    const double tile_row_ns = 2.0 * tile_m_for(p.mode, p.tile_cfg) * tile_n_for(p.mode, p.tile_cfg) / flop_ns_per_cu;
+    const double row_per_byte = 2.0 / 5000.0 / tile_row_ns;
+    const int64_t part_cap = int64_t(1) << 28;    // bytes of partials at most
+    auto partial_bytes = [&](const LeafDesc& L, int64_t s) {
+        const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
+        return cdiv(L.K, kchunk) * L.rows * L.cols * p.elem_bytes();
+    };
+    double best = (double)base;
+    int64_t best_s = 0;
+    size_t best_n = 0;
+    for (const int32_t s : {2, 3, 4, 6, 8, 12, 16, 24, 32}) {
+        if (s > max_split) break;
+        std::vector<int64_t> split(nl, 1);
+        int64_t sel = 0, last_bucket = -1, bytes = 0;
+        for (size_t j = 0; j < cand.size(); ++j) {
+            const LeafDesc& L = p.leaves[cand[j]];
+            if (L.K / 256 < s) continue;
+            bytes += partial_bytes(L, s);
+            if (bytes > part_cap) break;
+            split[cand[j]] = s;
+            sel += L.tiles;
+            if (sel > 2 * slots) break;            // more than a tail
+            const int64_t bucket = sel * s * 16 / slots;    // simulate once per 1/16 round of chunk tiles
+            if (bucket == last_bucket && j + 1 < cand.size()) continue;
+            last_bucket = bucket;
+            const double t = (double)simulate_makespan(p, split, slots) + (double)bytes * row_per_byte;
+            if (t < best) {
+                best = t;
+                best_s = s;
+                best_n = j + 1;
+            }
+        }
+    }
+    if (best_s == 0 || best > 0.96 * (double)base) return;
+    int32_t cut = 0;
+    int64_t bytes = 0;
+    for (size_t j = 0; j < best_n; ++j) {
+        LeafDesc& L = p.leaves[cand[j]];
+        if (L.K / 256 < best_s) continue;
+        bytes += partial_bytes(L, best_s);
+        if (bytes > part_cap) break;
+        if (split_leaf(p, L, best_s)) ++cut;
+    }
+    p.tail_leaves = cut;
+    p.tail_chunks = (int32_t)best_s;
 }
 
 void finalize_plan(Plan& p) {
@@ -665,7 +800,7 @@ void shift_view(View& v, int64_t ab) {
 
 }  // namespace
 
-Plan merge_plans(std::vector<Plan>& parts, int64_t split_target) {
+Plan merge_plans(std::vector<Plan>& parts, int64_t split_target, int64_t slots) {
     Plan out;
     if (parts.empty()) return out;
     out.mode = parts[0].mode;
@@ -751,6 +886,7 @@ Plan merge_plans(std::vector<Plan>& parts, int64_t split_target) {
         nu_base += p.n;
     }
     split_leaves(out, split_target);
+    if (slots > 0) balance_tail(out, slots);
     finalize_plan(out);
     return out;
 }

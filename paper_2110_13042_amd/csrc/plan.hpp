@@ -198,6 +198,8 @@ struct PlanOptions {
     int64_t split_target = 2048;   // split K when a launch has fewer tiles (0: never)
     bool fuse_presum = false;      // FP32/FP64: last-level pre-sums formed in the leaf loads
     int32_t variant = 0;           // Strassen node: 0 = Strassen's form, 1 = Winograd's
+    int64_t slots = 0;             // > 0: balance the leaf launch's last round over this
+                                   // many resident workgroups (balance_tail)
 };
 
 struct PlanStats {
@@ -218,6 +220,7 @@ struct Plan {
     bool fallback = false;
     bool fuse = false;                              // last-level pre-sums fused into the leaves
     int32_t variant = 0;                            // 0: Strassen nodes, 1: Winograd nodes
+    int32_t tail_leaves = 0, tail_chunks = 0;       // leaves balance_tail cut, K chunks each
     std::vector<std::vector<PresumDesc>> presum;    // [level-1] top-down
     std::vector<PackDesc> pack;                     // split-BF16 operand packing
     std::vector<Pack8Desc> pack8;                   // FP8 operand quantisation
@@ -266,6 +269,17 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
 // split once, after merging.
 constexpr int64_t SPLIT_MIN_CHUNK = 8192;
 void split_leaves(Plan& p, int64_t target, int64_t min_chunk = SPLIT_MIN_CHUNK);
+// Tail balancing of the leaf launch.  Its tiles run longest-first on `slots`
+// resident workgroups; when the last round is left partly idle (for example
+// 528 equal tiles on 256 slots: two full rounds and 16 tiles), the smallest
+// leaves covering that tail are cut into K chunks (same machinery as above),
+// so their chunk tiles run last and fill the final round.  The cut is chosen
+// by simulating list scheduling of the tiles' contraction lengths, and kept
+// only when it shortens that makespan by at least 4%.  Plans that
+// split_leaves has already split are left alone, and so are leaves under the
+// spread check and the idle alternatives of flagged nodes.
+void balance_tail(Plan& p, int64_t slots, int32_t max_split = 16);
+
 // Split-BF16 plans with column norms: hand each problem's whole-A packing to
 // its column-norm pass 1 task (which reads A anyway) and drop it from the
 // pack launch.  Applied by the caller to the plan it executes (a single
@@ -280,7 +294,7 @@ void finalize_plan(Plan& p);
 // One plan for a batch of independent problems: every problem's phases are
 // merged (arena offsets, node indices and problem indices shifted) so that
 // each phase is one launch for the whole batch.
-Plan merge_plans(std::vector<Plan>& parts, int64_t split_target = 0);
+Plan merge_plans(std::vector<Plan>& parts, int64_t split_target = 0, int64_t slots = 0);
 
 // Work items of the streaming kernels (pre-sums, packing, combines, column
 // norms) run 256 to a workgroup; every task's first item is a multiple of

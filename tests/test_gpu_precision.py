@@ -130,9 +130,9 @@ def test_bf16x3_packing_in_norm_pass_matches_pack_kernel(tile):
     """With the spread check on, the column-norm pass also writes A's split
     packing; with it off, the pack kernel does.  On well-scaled data no node
     is flagged, so both must give the same bits (ragged m, n and padded lda;
-    single problems and a batch).  Split-K is off: the spread check changes
-    how the planner splits the fallback-capable leaves, and with it the
-    summation order."""
+    single problems and a batch).  Split-K and tail balancing are off: the
+    spread check changes how the planner splits the fallback-capable leaves,
+    and with it the summation order."""
     rng = np.random.default_rng(53)
     dev = device()
     outs = {}
@@ -140,6 +140,7 @@ def test_bf16x3_packing_in_norm_pass_matches_pack_kernel(tile):
         hd = ata.Handle(spread_tau=tau)
         hd.set("leaf_tile", tile)
         hd.set("split_target", 0)
+        hd.set("balance_tail", 0)
         res = []
         for (m, n, b, depth, lda) in [(1000, 777, 128, 1, 779), (37, 300, 64, 0, 300), (4099, 1030, 256, 1, 1032),
                                       (8, 5, 64, 0, 5)]:
