@@ -67,7 +67,10 @@ typedef enum {
     /* Maximum Strassen levels under one AtA node; -1 = the mode's default
        (F64: unlimited, F32: 3, BF16X3: 2, FP8: 1; F32 and BF16X3 take 0
        when m >= 65536, since a level's rounding error adds to that of the
-       long contraction). */
+       long contraction).  ata_gram and ata_gemm_tn use fewer levels when the
+       plan's workspace would not fit in the device's free memory (plus the
+       arena the handle holds) with 1 GiB to spare: every level's sums and
+       products are resident at once, about 7/4 more per level. */
     ATA_OPT_MAX_STRASSEN_DEPTH = 1,
     /* Spread threshold tau on column norms for the FP32-family FP64 fallback:
        an AtA node whose max/min squared column norm exceeds tau^2 runs its

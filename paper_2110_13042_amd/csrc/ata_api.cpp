@@ -355,6 +355,18 @@ bool persistent_for(int setting, const Plan& p) {
     return p.mode == MODE_F32 && p.tile_cfg >= 2;
 }
 
+// Does the plan's workspace fit in the device memory that is free (the arena
+// the handle already holds counts as free), with 1 GiB to spare?  The GPU
+// keeps every Strassen level's sums and products at once (a level's products
+// run concurrently), so the workspace grows about 7/4 per level: a plan for a
+// large matrix gets fewer levels rather than an allocation failure.
+bool fits_device(const ata_ctx* h, const Plan& p) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return true;
+    const double need = (double)p.arena_elems * (double)p.elem_bytes();
+    return need + (double)(1ull << 30) <= (double)free_b + (double)h->arena_cap;
+}
+
 // Resident leaf workgroups of the device (256 CUs) for the tail balancer,
 // or 0 when it is off.
 int64_t tail_slots(const ata_ctx* h, int32_t mode, int32_t tile_cfg) {
@@ -663,6 +675,10 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         o.slots = slots;
         try {
             dp->plan = make_plan(mode, m, n, lda, o);
+            while (dp->plan.stats.max_levels > 0 && !fits_device(h, dp->plan)) {
+                o.max_depth = dp->plan.stats.max_levels - 1;
+                dp->plan = make_plan(mode, m, n, lda, o);
+            }
             if (dp->plan.fallback) fuse_pack_into_norms(dp->plan, dp->plan.col1);
         } catch (const std::invalid_argument&) {
             return ATA_ERR_INVALID_VALUE;
@@ -867,6 +883,10 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
         o.slots = slots;
         try {
             dp->plan = make_gemm_plan(mode, m, n, k, lda, ldb, ldc, o);
+            while (dp->plan.stats.max_levels > 0 && !fits_device(h, dp->plan)) {
+                o.max_depth = dp->plan.stats.max_levels - 1;
+                dp->plan = make_gemm_plan(mode, m, n, k, lda, ldb, ldc, o);
+            }
         } catch (const std::invalid_argument&) {
             return ATA_ERR_INVALID_VALUE;
         } catch (const std::length_error&) {

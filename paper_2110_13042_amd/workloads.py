@@ -44,6 +44,12 @@ WORKLOADS = {
     "normal_f32_16384": Workload(
         "normal_f32_16384", "f32", 16384, 16384, 4, "normal",
         "A 16384x16384, i.i.d. N(0,1), FP32; 256 sampled columns"),
+    # the square sizes of the paper's shared- vs distributed-memory table
+    # (Sec. 5), for context beside its CPU times
+    **{f"paper_square_f64_{k}": Workload(
+        f"paper_square_f64_{k}", "f64", k, k, k // 1000, "uniform",
+        f"A {k}x{k}, i.i.d. uniform[-1,1], FP64 (a square size of the paper's Sec. 5 table)")
+       for k in (30000, 40000, 50000, 60000)},
     "batch_512_uneven_f32": Workload(
         "batch_512_uneven_f32", "f32", 0, 0, 5, "batch",
         "512 problems, m log-uniform in [256,8192], n log-uniform in [64,2048], "
