@@ -129,12 +129,41 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
             return;
         }
     }
-    const int64_t groups = (d.n2 + 3) >> 2;
-    const int64_t r = udiv(e, groups), c0 = (e - r * groups) << 2;
     const T* V = (d.V.base == BASE_A ? A : d.V.base == BASE_B ? B : arena) + d.V.off;
     const int64_t ld = d.V.ld, pr = d.V.prows, pc = d.V.pcols;
     const int64_t m1 = d.m1, m2 = d.m2, n1 = d.n1, n2 = d.n2;
     const int64_t plane = m2 * n2;
+    if (d.unit == 1) {
+        // one column per work item: rows whose starts are not 16-byte
+        // aligned, read and written by consecutive lanes at consecutive
+        // addresses
+        const int64_t r = udiv(e, n2), c = e - r * n2;
+        auto get1 = [&](int qr, int qc) -> T {
+            const int64_t rr = qr ? m1 + r : r, cc = qc ? n1 + c : c;
+            const bool in = r < (qr ? m2 : m1) && c < (qc ? n2 : n1) && rr < pr && cc < pc;
+            return in ? V[rr * ld + cc] : T(0);
+        };
+        const T a11 = get1(0, 0), a12 = get1(0, 1), a21 = get1(1, 0), a22 = get1(1, 1);
+        T* o = arena + d.out_off + r * n2 + c;
+        if (d.variant == 1) {
+            if (d.side == 0) {
+                const T s1 = a12 + a22, s2 = s1 - a11;
+                o[0] = s1; o[plane] = s2; o[2 * plane] = a11 - a12; o[3 * plane] = a21 - s2;
+            } else {
+                const T t1 = a12 - a11, t2 = a22 - t1;
+                o[0] = t1; o[plane] = t2; o[2 * plane] = a22 - a12; o[3 * plane] = t2 - a21;
+            }
+        } else if (d.side == 0) {
+            o[0] = a11 + a22; o[plane] = a12 + a22; o[2 * plane] = a11 + a21;
+            o[3 * plane] = a12 - a11; o[4 * plane] = a21 - a22;
+        } else {
+            o[0] = a11 + a22; o[plane] = a12 - a22; o[2 * plane] = a21 - a11;
+            o[3 * plane] = a11 + a12; o[4 * plane] = a21 + a22;
+        }
+        return;
+    }
+    const int64_t groups = (d.n2 + 3) >> 2;
+    const int64_t r = udiv(e, groups), c0 = (e - r * groups) << 2;
     T* out = arena + d.out_off + r * n2;
     // fast path: four full columns in every quadrant, 16-byte aligned rows
     const bool inside = r < m1 && m1 + r < pr && c0 + 4 <= n1 && n1 + c0 + 4 <= pc;
@@ -407,7 +436,8 @@ __global__ __launch_bounds__(EW_THREADS) void eq_unscale_kernel(float* Cp, int64
 }
 
 // ---------------------------------------------------------------- combine
-// Work item = one row i and four columns j..j+3 of the n2 x k2 products.
+// Work item = one row i and four columns j..j+3 of the n2 x k2 products (one
+// column when k2 is not a multiple of four).
 // C11 = M1 + M4 - M5 + M7, C12 = M3 + M5, C21 = M2 + M4,
 // C22 = M1 - M2 + M3 + M6, each summed left to right; only the leading part
 // of a product reaches a floor-sized quadrant.  Winograd's form shares partial
@@ -424,8 +454,10 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
     if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
     T* C = Cptrs ? static_cast<T*>(Cptrs[d.prob]) : C0;
-    const int64_t groups = (d.k2 + 3) >> 2;
-    const int64_t i = udiv(e, groups), j0 = (e - i * groups) << 2;
+    // four columns per work item, or one when k2 is not a multiple of four
+    const int w = d.unit == 1 ? 1 : 4;
+    const int64_t groups = w == 1 ? d.k2 : (d.k2 + 3) >> 2;
+    const int64_t i = udiv(e, groups), j0 = w == 1 ? e - i * groups : (e - i * groups) << 2;
     const int64_t n1 = d.n1, k1 = d.k1, k2 = d.k2, plane = d.n2 * d.k2;
     const T* M = arena + d.m_off + i * k2;
     auto dst = [&](int64_t ii, int64_t jj) -> T* {
@@ -433,7 +465,7 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
                : d.out_kind == OUT_CDENSE ? C + (d.out_row0 + ii) * d.out_ld + d.out_col0 + jj
                                           : arena + d.out_off + ii * d.out_ld + jj;
     };
-    if (i < n1 && j0 + 4 <= k1 && (k2 & 3) == 0) {
+    if (w == 4 && i < n1 && j0 + 4 <= k1 && (k2 & 3) == 0) {
         typedef typename Vec4<T>::type V4;
         const V4 m1 = ld4(M + j0), m2 = ld4(M + plane + j0), m3 = ld4(M + 2 * plane + j0);
         const V4 m4 = ld4(M + 3 * plane + j0), m5 = ld4(M + 4 * plane + j0);
@@ -476,7 +508,7 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int64_t j = j0 + q;
-        if (j >= k2) break;
+        if (q >= w || j >= k2) break;
         const T m1 = M[j], m2 = M[plane + j], m3 = M[2 * plane + j], m4 = M[3 * plane + j];
         const T m5 = M[4 * plane + j], m6 = M[5 * plane + j], m7 = M[6 * plane + j];
         if (d.variant == 1) {

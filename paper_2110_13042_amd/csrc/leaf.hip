@@ -128,6 +128,30 @@ __device__ __forceinline__ int find_leaf(const LeafDesc* t, int n, int64_t x) {
     return lo;
 }
 
+// A load through the global address space.  Operand pointers reach the
+// kernels as generic pointers, and a generic (flat) load also counts against
+// the LDS wait counter: every wait for an LDS read in the K loop would then
+// wait for the next slab's prefetch as well, exposing its latency.
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+    typedef const __attribute__((address_space(1))) T GT;
+    return *(GT*)p;
+}
+// HIP's vector structs would be copied through a generic reference: load the
+// native vector type instead.
+__device__ __forceinline__ float4 gld(const float4* p) {
+    typedef float nv4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(1))) nv4 GT;
+    const nv4 v = *(GT*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 gld(const double2* p) {
+    typedef double nv2 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) nv2 GT;
+    const nv2 v = *(GT*)p;
+    return make_double2(v.x, v.y);
+}
+
 // Four consecutive elements (r, c..c+3) of a zero-padded float operand.
 __device__ __forceinline__ float4 load4f(const float* p, int64_t ld, int64_t r, int64_t c,
                                          int64_t K, int64_t pc, bool vec) {
@@ -135,12 +159,12 @@ __device__ __forceinline__ float4 load4f(const float* p, int64_t ld, int64_t r, 
     if (r < K) {
         const float* q = p + r * ld + c;
         if (vec && c + 3 < pc) {
-            v = *reinterpret_cast<const float4*>(q);
+            v = gld(reinterpret_cast<const float4*>(q));
         } else {
-            if (c < pc) v.x = q[0];
-            if (c + 1 < pc) v.y = q[1];
-            if (c + 2 < pc) v.z = q[2];
-            if (c + 3 < pc) v.w = q[3];
+            if (c < pc) v.x = gld(q);
+            if (c + 1 < pc) v.y = gld(q + 1);
+            if (c + 2 < pc) v.z = gld(q + 2);
+            if (c + 3 < pc) v.w = gld(q + 3);
         }
     }
     return v;
@@ -152,10 +176,10 @@ __device__ __forceinline__ double2 load2d(const double* p, int64_t ld, int64_t r
     if (r < K) {
         const double* q = p + r * ld + c;
         if (vec && c + 1 < pc) {
-            v = *reinterpret_cast<const double2*>(q);
+            v = gld(reinterpret_cast<const double2*>(q));
         } else {
-            if (c < pc) v.x = q[0];
-            if (c + 1 < pc) v.y = q[1];
+            if (c < pc) v.x = gld(q);
+            if (c + 1 < pc) v.y = gld(q + 1);
         }
     }
     return v;

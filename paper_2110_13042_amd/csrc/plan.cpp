@@ -247,7 +247,8 @@ struct Builder {
             CombineDesc c{};
             c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
             c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
-            c.elems = n2 * cdiv(k2, 4); c.pred_node = pn; c.pred_value = pv;
+            c.unit = k2 % 4 == 0 ? 4 : 1;
+            c.elems = n2 * cdiv(k2, c.unit); c.pred_node = pn; c.pred_value = pv;
             p.combine[0].push_back(c);
             if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
             return 1;
@@ -261,13 +262,22 @@ struct Builder {
         if ((int)p.presum.size() <= depth) p.presum.resize(depth + 1);
         PresumDesc ps{};
         ps.V = X; ps.m1 = m1; ps.m2 = m2; ps.n1 = n1; ps.n2 = n2; ps.out_off = S;
-        ps.elems = packed ? groups * n2 : m2 * cdiv(n2, 4);
+        // four columns per work item when every row of the quadrants and of
+        // the sums starts 16-byte aligned (A itself is checked on the device),
+        // else one: consecutive lanes then still read consecutive elements
+        const int64_t es = p.elem_bytes();
+        auto unit_of = [&](const View& V, int64_t c1, int64_t c2) {
+            return ((V.off * es) | (V.ld * es) | (c1 * es) | (c2 * es)) % 16 == 0 ? 4 : 1;
+        };
+        ps.unit = unit_of(X, n1, n2);
+        ps.elems = packed ? groups * n2 : m2 * cdiv(n2, ps.unit);
         ps.side = 0; ps.pred_node = pn; ps.pred_value = pv; ps.packed_out = packed ? 1 : 0;
         ps.variant = p.variant;
         p.presum[depth].push_back(ps);
         PresumDesc pt = ps;
         pt.V = Y; pt.n1 = k1; pt.n2 = k2; pt.out_off = T; pt.side = 1;
-        pt.elems = packed ? groups * k2 : m2 * cdiv(k2, 4);
+        pt.unit = unit_of(Y, k1, k2);
+        pt.elems = packed ? groups * k2 : m2 * cdiv(k2, pt.unit);
         p.presum[depth].push_back(pt);
 
         auto Sv = [&](int i) {
@@ -306,7 +316,8 @@ struct Builder {
         CombineDesc c{};
         c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
         c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
-        c.elems = n2 * cdiv(k2, 4); c.pred_node = pn; c.pred_value = pv; c.variant = p.variant;
+        c.unit = k2 % 4 == 0 ? 4 : 1;
+        c.elems = n2 * cdiv(k2, c.unit); c.pred_node = pn; c.pred_value = pv; c.variant = p.variant;
         p.combine[height - 1].push_back(c);
         if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
         return height;

@@ -155,6 +155,8 @@ struct PresumDesc {
                               // 16-byte chunk; sum i at out_off + i * ceil(m2/8) * n2 * 8)
     int32_t prob;
     int32_t variant;          // 0: Strassen, five sums; 1: Winograd, four sums
+    int32_t unit;             // columns per work item: 4 (16-byte vectors) or 1 (any alignment)
+    int32_t pad_;
 };
 
 // Strassen (or Winograd) combine: seven n2 x k2 products into the four
@@ -169,7 +171,8 @@ struct CombineDesc {
     int64_t elem_begin, elems;
     int32_t pred_value;
     int32_t prob;
-    int32_t variant, pad_;        // 0: Strassen, 1: Winograd
+    int32_t variant;              // 0: Strassen, 1: Winograd
+    int32_t unit;                 // columns per work item: 4 or 1 (k2 not a multiple of 4)
 };
 
 // Column-norm task of one problem.  Pass 1: a workgroup sums the squares of
