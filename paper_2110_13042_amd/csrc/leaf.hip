@@ -98,7 +98,13 @@ constexpr int threads_for(int mode) {
 // Resident workgroups per CU the one-tile-per-workgroup kernel is compiled
 // for: the 128 x 128 FP32 engine keeps four (64 VGPRs + 64 accumulators per
 // lane) with its fused pre-sum loads included.
-constexpr int min_blocks_for(int mode) { return mode == MODE_F32 ? 4 : 1; }
+// Minimum waves per SIMD the register allocation must allow: four for the
+// 128 x 128 FP32 engine, two for the FP64 engines (their 66.5 KB of LDS
+// allow two workgroups per CU), so that one wave's MFMAs cover the other's
+// waits.
+constexpr int min_blocks_for(int mode) {
+    return mode == MODE_F32 ? 4 : mode == MODE_F64 || mode == MODE_FALLBACK ? 2 : 1;
+}
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
@@ -1663,7 +1669,8 @@ __global__ __launch_bounds__(threads_for(MODE), min_blocks_for(MODE)) void leaf_
 // grows with its ticket, so the first ticket past the end means the queue is
 // empty for good.
 template <int MODE>
-__global__ __launch_bounds__(threads_for(MODE)) void leaf_kernel_persistent(LeafArgs args) {
+__global__ __launch_bounds__(threads_for(MODE), MODE == MODE_F64 || MODE == MODE_FALLBACK ? 2 : 1)
+void leaf_kernel_persistent(LeafArgs args) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
     // the ticket is passed through the first bytes of the tile's LDS, which
     // no tile touches between the two barriers around it
