@@ -112,13 +112,13 @@ __device__ __forceinline__ void st4(T* p, const typename Vec4<T>::type& v) {
 #define V4OP(a, op, b) {a.x op b.x, a.y op b.y, a.z op b.z, a.w op b.w}
 
 template <class T>
-__global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* tasks, int ntasks,
+__device__ __forceinline__ void presum_kernel_block(const PresumDesc* tasks, int ntasks,
                                                             int64_t items, const T* A0, T* arena,
                                                             const uint8_t* flags, const void* const* Aptrs,
-                                                            const T* B) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+                                                            const T* B, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const PresumDesc& d = tasks[block_task(tasks, ntasks)];
+    const PresumDesc& d = tasks[block_task(tasks, ntasks, vb)];
     const int64_t e = x - d.elem_begin;
     if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
@@ -244,17 +244,27 @@ __global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* ta
     }
 }
 
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void presum_kernel(const PresumDesc* tasks, int ntasks,
+                                                            int64_t items, const T* A0, T* arena,
+                                                            const uint8_t* flags, const void* const* Aptrs,
+                                                            const T* B) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < items; vb += gridDim.x)
+        presum_kernel_block(tasks, ntasks, items, A0, arena, flags, Aptrs, B, vb);
+}
+
 // ------------------------------------------------------ split-BF16 packing
 
 // Work item = one 16-byte chunk (row-group g, column c): rows 8g..8g+7 of
 // column c split into hi = bf16(a) and lo = bf16(a - hi).
-__global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks, int ntasks,
+__device__ __forceinline__ void pack_kernel_block(const PackDesc* tasks, int ntasks,
                                                           int64_t items, const float* A0,
                                                           float* arena, const uint8_t* flags,
-                                                          const void* const* Aptrs, const float* B) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+                                                          const void* const* Aptrs, const float* B, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const PackDesc& d = tasks[block_task(tasks, ntasks)];
+    const PackDesc& d = tasks[block_task(tasks, ntasks, vb)];
     const int64_t e = x - d.elem_begin;
     if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
@@ -271,6 +281,15 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
     split8(v, hi, lo);
     reinterpret_cast<uint4*>(arena + d.dst)[g * d.cols + c] = hi;
     reinterpret_cast<uint4*>(arena + d.dst + d.lo_delta)[g * d.cols + c] = lo;
+}
+
+__global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks, int ntasks,
+                                                          int64_t items, const float* A0,
+                                                          float* arena, const uint8_t* flags,
+                                                          const void* const* Aptrs, const float* B) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < items; vb += gridDim.x)
+        pack_kernel_block(tasks, ntasks, items, A0, arena, flags, Aptrs, B, vb);
 }
 
 // ------------------------------------------------------------ FP8 quantising
@@ -334,12 +353,12 @@ __global__ __launch_bounds__(EW_THREADS) void quant8_kernel(const Pack8Desc* tas
 // Partials come from the FP64 fallback (FP64 array) when the leaf's node is
 // flagged, else from the mode's leaf kernel (arrays of the mode's type).
 template <class T>
-__global__ __launch_bounds__(EW_THREADS) void reduce_kernel(const ReduceDesc* tasks, int ntasks,
+__device__ __forceinline__ void reduce_kernel_block(const ReduceDesc* tasks, int ntasks,
                                                             int64_t items, T* C0, T* arena,
-                                                            const uint8_t* flags, void* const* Cptrs) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+                                                            const uint8_t* flags, void* const* Cptrs, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const ReduceDesc& d = tasks[block_task(tasks, ntasks)];
+    const ReduceDesc& d = tasks[block_task(tasks, ntasks, vb)];
     const int64_t e = x - d.elem_begin;
     if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
@@ -364,13 +383,29 @@ __global__ __launch_bounds__(EW_THREADS) void reduce_kernel(const ReduceDesc* ta
     }
 }
 
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void reduce_kernel(const ReduceDesc* tasks, int ntasks,
+                                                            int64_t items, T* C0, T* arena,
+                                                            const uint8_t* flags, void* const* Cptrs) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < items; vb += gridDim.x)
+        reduce_kernel_block(tasks, ntasks, items, C0, arena, flags, Cptrs, vb);
+}
+
 // ------------------------------------------------- BLAS-style conveniences
 // C = alpha T + beta C over packed arrays (beta = 0: C is not read).
 template <class T>
-__global__ __launch_bounds__(EW_THREADS) void axpby_kernel(const T* t, T* c, int64_t len, T alpha, T beta) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+__device__ __forceinline__ void axpby_kernel_block(const T* t, T* c, int64_t len, T alpha, T beta, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= len) return;
     c[x] = beta == T(0) ? alpha * t[x] : alpha * t[x] + beta * c[x];
+}
+
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void axpby_kernel(const T* t, T* c, int64_t len, T alpha, T beta) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < len; vb += gridDim.x)
+        axpby_kernel_block(t, c, len, alpha, beta, vb);
 }
 
 // At[j][i] = A[i][j] (A m x n with row stride lda, At n x m dense), through
@@ -394,12 +429,19 @@ __global__ __launch_bounds__(EW_THREADS) void transpose_kernel(const T* A, int64
 
 // Full symmetric n x n matrix (row stride ldf) from packed lower storage.
 template <class T>
-__global__ __launch_bounds__(EW_THREADS) void unpack_kernel(const T* Cp, int64_t n, T* F, int64_t ldf) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+__device__ __forceinline__ void unpack_kernel_block(const T* Cp, int64_t n, T* F, int64_t ldf, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= n * n) return;
     const int64_t i = x / n, j = x - i * n;
     const int64_t r = i > j ? i : j, c = i > j ? j : i;
     F[i * ldf + j] = Cp[packed_index(r, c)];
+}
+
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void unpack_kernel(const T* Cp, int64_t n, T* F, int64_t ldf) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < n * n; vb += gridDim.x)
+        unpack_kernel_block(Cp, n, F, ldf, vb);
 }
 
 // ------------------------------------------------- column equilibration
@@ -413,9 +455,9 @@ __device__ __forceinline__ int eq_exponent(double nu) {
 }
 
 // Ap (m x n dense) = A diag(2^-e); e_j stored by the threads of row 0.
-__global__ __launch_bounds__(EW_THREADS) void eq_scale_kernel(const float* A, int64_t m, int64_t n, int64_t lda,
-                                                              const double* nu, float* Ap, int* e) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+__device__ __forceinline__ void eq_scale_kernel_block(const float* A, int64_t m, int64_t n, int64_t lda,
+                                                              const double* nu, float* Ap, int* e, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= m * n) return;
     const int64_t r = udiv(x, n), j = x - r * n;
     const int ej = eq_exponent(nu[j]);
@@ -423,16 +465,29 @@ __global__ __launch_bounds__(EW_THREADS) void eq_scale_kernel(const float* A, in
     if (r == 0) e[j] = ej;
 }
 
+__global__ __launch_bounds__(EW_THREADS) void eq_scale_kernel(const float* A, int64_t m, int64_t n, int64_t lda,
+                                                              const double* nu, float* Ap, int* e) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < m * n; vb += gridDim.x)
+        eq_scale_kernel_block(A, m, n, lda, nu, Ap, e, vb);
+}
+
 // Packed C_ij *= 2^(e_i + e_j): the Gram product of the scaled columns back
 // to the original scale (exact).
-__global__ __launch_bounds__(EW_THREADS) void eq_unscale_kernel(float* Cp, int64_t n, const int* e) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+__device__ __forceinline__ void eq_unscale_kernel_block(float* Cp, int64_t n, const int* e, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= n * (n + 1) / 2) return;
     int64_t i = (int64_t)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
     while (i > 0 && i * (i + 1) / 2 > x) --i;
     while ((i + 1) * (i + 2) / 2 <= x) ++i;
     const int64_t j = x - i * (i + 1) / 2;
     Cp[x] = ldexpf(Cp[x], e[i] + e[j]);
+}
+
+__global__ __launch_bounds__(EW_THREADS) void eq_unscale_kernel(float* Cp, int64_t n, const int* e) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < n * (n + 1) / 2; vb += gridDim.x)
+        eq_unscale_kernel_block(Cp, n, e, vb);
 }
 
 // ---------------------------------------------------------------- combine
@@ -444,12 +499,12 @@ __global__ __launch_bounds__(EW_THREADS) void eq_unscale_kernel(float* Cp, int64
 // sums: U2 = M1 + M6, U3 = U2 + M7, C11 = M1 + M2, C12 = (U2 + M5) + M3,
 // C21 = U3 - M4, C22 = U3 + M5.
 template <class T>
-__global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* tasks, int ntasks,
+__device__ __forceinline__ void combine_kernel_block(const CombineDesc* tasks, int ntasks,
                                                              int64_t items, T* C0, T* arena,
-                                                             const uint8_t* flags, void* const* Cptrs) {
-    const int64_t x = (int64_t)blockIdx.x * EW_THREADS + threadIdx.x;
+                                                             const uint8_t* flags, void* const* Cptrs, int64_t vb) {
+    const int64_t x = vb * EW_THREADS + threadIdx.x;
     if (x >= items) return;
-    const CombineDesc& d = tasks[block_task(tasks, ntasks)];
+    const CombineDesc& d = tasks[block_task(tasks, ntasks, vb)];
     const int64_t e = x - d.elem_begin;
     if (e >= d.elems) return;
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
@@ -528,6 +583,15 @@ __global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* 
         if (j < k1) *dst(n1 + i, j) = m2 + m4;
         *dst(n1 + i, k1 + j) = ((m1 - m2) + m3) + m6;
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void combine_kernel(const CombineDesc* tasks, int ntasks,
+                                                             int64_t items, T* C0, T* arena,
+                                                             const uint8_t* flags, void* const* Cptrs) {
+    // the grid (at most ew_grid() workgroups) walks the virtual blocks
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < items; vb += gridDim.x)
+        combine_kernel_block(tasks, ntasks, items, C0, arena, flags, Cptrs, vb);
 }
 
 // ------------------------------------------------------------ column norms
@@ -836,6 +900,14 @@ __global__ __launch_bounds__(EW_THREADS) void res_final(const double* wrow, cons
 
 unsigned blocks_for(int64_t items) { return (unsigned)((items + EW_THREADS - 1) / EW_THREADS); }
 
+// Grid of the streaming kernels that walk virtual blocks.  A dispatch holds
+// its size in work-items as a 32-bit count, so a launch of more than 2^32
+// work-items would wrap; 2^20 workgroups of 256 fill the GPU many times over.
+unsigned ew_grid(int64_t items) {
+    const unsigned b = blocks_for(items);
+    return b < (1u << 20) ? (b > 0 ? b : 1u) : (1u << 20);
+}
+
 // ------------------------------------------------- sampled-column check
 // G[r][k] = A[r][cols[k]] in FP64 (the sampled columns, gathered once).
 template <class T>
@@ -915,11 +987,11 @@ hipError_t launch_presum(int32_t mode, const PresumDesc* d_tasks, int ntasks, in
     if (items <= 0) return hipSuccess;
     const void* const* Ap = bp ? bp->A : nullptr;
     if (mode == MODE_F64)
-        hipLaunchKernelGGL(presum_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(presum_kernel<double>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<const double*>(A),
                            static_cast<double*>(arena), flags, Ap, static_cast<const double*>(B));
     else
-        hipLaunchKernelGGL(presum_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(presum_kernel<float>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<const float*>(A),
                            static_cast<float*>(arena), flags, Ap, static_cast<const float*>(B));
     return hipGetLastError();
@@ -929,7 +1001,7 @@ hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const
                        void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp,
                        const void* B) {
     if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream, d_tasks,
+    hipLaunchKernelGGL(pack_kernel, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream, d_tasks,
                        ntasks, items, static_cast<const float*>(A), static_cast<float*>(arena), flags,
                        bp ? bp->A : nullptr, static_cast<const float*>(B));
     return hipGetLastError();
@@ -950,10 +1022,10 @@ hipError_t launch_reduce(int32_t mode, const ReduceDesc* d_tasks, int ntasks, in
     if (items <= 0) return hipSuccess;
     void* const* Cp = bp ? bp->C : nullptr;
     if (mode == MODE_F64)
-        hipLaunchKernelGGL(reduce_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(reduce_kernel<double>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<double*>(C), static_cast<double*>(arena), flags, Cp);
     else
-        hipLaunchKernelGGL(reduce_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(reduce_kernel<float>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<float*>(C), static_cast<float*>(arena), flags, Cp);
     return hipGetLastError();
 }
@@ -962,10 +1034,10 @@ hipError_t launch_axpby(int32_t mode, const void* t, void* c, int64_t len, doubl
                         hipStream_t stream) {
     if (len <= 0) return hipSuccess;
     if (mode == MODE_F64)
-        hipLaunchKernelGGL(axpby_kernel<double>, dim3(blocks_for(len)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(axpby_kernel<double>, dim3(ew_grid(len)), dim3(EW_THREADS), 0, stream,
                            static_cast<const double*>(t), static_cast<double*>(c), len, alpha, beta);
     else
-        hipLaunchKernelGGL(axpby_kernel<float>, dim3(blocks_for(len)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(axpby_kernel<float>, dim3(ew_grid(len)), dim3(EW_THREADS), 0, stream,
                            static_cast<const float*>(t), static_cast<float*>(c), len, (float)alpha, (float)beta);
     return hipGetLastError();
 }
@@ -986,10 +1058,10 @@ hipError_t launch_transpose(int32_t mode, const void* A, int64_t m, int64_t n, i
 hipError_t launch_unpack(int32_t mode, const void* Cp, int64_t n, void* F, int64_t ldf, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     if (mode == MODE_F64)
-        hipLaunchKernelGGL(unpack_kernel<double>, dim3(blocks_for(n * n)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(unpack_kernel<double>, dim3(ew_grid(n * n)), dim3(EW_THREADS), 0, stream,
                            static_cast<const double*>(Cp), n, static_cast<double*>(F), ldf);
     else
-        hipLaunchKernelGGL(unpack_kernel<float>, dim3(blocks_for(n * n)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(unpack_kernel<float>, dim3(ew_grid(n * n)), dim3(EW_THREADS), 0, stream,
                            static_cast<const float*>(Cp), n, static_cast<float*>(F), ldf);
     return hipGetLastError();
 }
@@ -997,14 +1069,14 @@ hipError_t launch_unpack(int32_t mode, const void* Cp, int64_t n, void* F, int64
 hipError_t launch_eq_scale(const float* A, int64_t m, int64_t n, int64_t lda, const double* nu, float* Ap,
                            int* e, hipStream_t stream) {
     if (m <= 0 || n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eq_scale_kernel, dim3(blocks_for(m * n)), dim3(EW_THREADS), 0, stream, A, m, n, lda, nu,
+    hipLaunchKernelGGL(eq_scale_kernel, dim3(ew_grid(m * n)), dim3(EW_THREADS), 0, stream, A, m, n, lda, nu,
                        Ap, e);
     return hipGetLastError();
 }
 
 hipError_t launch_eq_unscale(float* Cp, int64_t n, const int* e, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eq_unscale_kernel, dim3(blocks_for(n * (n + 1) / 2)), dim3(EW_THREADS), 0, stream, Cp, n, e);
+    hipLaunchKernelGGL(eq_unscale_kernel, dim3(ew_grid(n * (n + 1) / 2)), dim3(EW_THREADS), 0, stream, Cp, n, e);
     return hipGetLastError();
 }
 
@@ -1014,11 +1086,11 @@ hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, 
     if (items <= 0) return hipSuccess;
     void* const* Cp = bp ? bp->C : nullptr;
     if (mode == MODE_F64)
-        hipLaunchKernelGGL(combine_kernel<double>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(combine_kernel<double>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<double*>(C),
                            static_cast<double*>(arena), flags, Cp);
     else
-        hipLaunchKernelGGL(combine_kernel<float>, dim3(blocks_for(items)), dim3(EW_THREADS), 0, stream,
+        hipLaunchKernelGGL(combine_kernel<float>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream,
                            d_tasks, ntasks, items, static_cast<float*>(C),
                            static_cast<float*>(arena), flags, Cp);
     return hipGetLastError();

@@ -48,6 +48,11 @@ template <class D>
 __device__ __forceinline__ int block_task(const D* tasks, int ntasks) {
     return find_task(tasks, ntasks, (int64_t)blockIdx.x * ITEM_BLOCK);
 }
+// The same for virtual block vb of a launch whose workgroups loop over blocks.
+template <class D>
+__device__ __forceinline__ int block_task(const D* tasks, int ntasks, int64_t vb) {
+    return find_task(tasks, ntasks, vb * ITEM_BLOCK);
+}
 
 // a / b for 0 <= a, 0 < b; 32-bit division when both operands fit.
 __device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {

@@ -1706,6 +1706,8 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
                          int chunk, int band, hipStream_t stream, const BatchPtrs* bp, const void* B) {
     if (ntiles <= 0) return hipSuccess;
+    // a dispatch counts its work-items in 32 bits: refuse a grid that would wrap
+    if (!(bp && bp->counter) && ntiles > (int64_t)(0xFFFFFFFFu / 512u)) return hipErrorInvalidConfiguration;
     LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr, B};
     dim3 grid((unsigned)ntiles);
     if (bp) {
