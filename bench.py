@@ -165,7 +165,7 @@ def make_handle(ata, args):
         h.set("leaf_cutoff", args.leaf_cutoff)
     if args.max_depth >= 0:
         h.set("max_depth", args.max_depth)
-    if args.leaf_tile:
+    if args.leaf_tile >= 0:
         h.set("leaf_tile", args.leaf_tile)
     if args.xcd_chunk:
         h.set("xcd_chunk", args.xcd_chunk)
@@ -343,7 +343,8 @@ def main() -> int:
     ap.add_argument("--workload", default="square_f32_8192")
     ap.add_argument("--leaf-cutoff", type=int, default=0)
     ap.add_argument("--max-depth", type=int, default=-1)
-    ap.add_argument("--leaf-tile", type=int, default=0, help="split-BF16 leaf tile: 0 = 128x128, 1 = 256x128, 2 = 256x256")
+    ap.add_argument("--leaf-tile", type=int, default=-1,
+                    help="leaf tile (ATA_OPT_LEAF_TILE): -1 = automatic (tune table, else by shape)")
     ap.add_argument("--xcd-chunk", type=int, default=0, help="leaf tiles per XCD per window (0: library default)")
     ap.add_argument("--tile-band", type=int, default=0, help="GEMM leaf tile rows per band (0: library default)")
     ap.add_argument("--equilibrate", action="store_true",

@@ -88,13 +88,18 @@ typedef enum {
        every ata_gram call; ata_get_report then synchronises and returns the
        summed phase times since the option was last set (default 0). */
     ATA_OPT_PROFILE = 6,
-    /* Output tile of the leaf kernel.  Split-BF16: 0 = 128 x 128 (default),
-       1 = 256 x 128, 2 = 256 x 256 on eight waves, 3 = 256 x 256 on four
-       waves of 128 x 128 with operands streamed into LDS by buffer loads,
-       4 = the same stream on eight waves of 128 x 64.  FP8: 0 = 128 x 128 (default), 3 = 256 x 256 on
-       four waves of 128 x 128 (1 and 2 act as 0).  FP32: 0 = 128 x 128
-       (default), 2 = 256 x 256 on eight waves of 128 x 64, 3 = 256 x 256 on
-       four waves of 128 x 128 (1 acts as 0).  FP64 ignores it. */
+    /* Output tile of the leaf kernel.  -1 (default) = automatic: the
+       autotune table's tile for the shape's bucket, else tile 2 for FP32
+       when m, n >= 2048 (with leaf cutoff 2048 unless set) and for
+       split-BF16 when m, n >= 4096, else tile 0; an explicit value also
+       wins over the table.  Split-BF16: 0 = 128 x 128, 1 = 256 x 128,
+       2 = 256 x 256 on eight waves, 3 = 256 x 256 on four waves of
+       128 x 128 with operands streamed into LDS by buffer loads, 4 = the same
+       stream on eight waves of 128 x 64.  FP8: 0 = 128 x 128, 3 = 256 x 256
+       on four waves of 128 x 128 (1 and 2 act as 0).  FP32: 0 = 128 x 128,
+       2 = 256 x 256 on eight waves of 128 x 64, 3 = 256 x 256 on four waves
+       of 128 x 128 (1 acts as 0).  FP64 ignores it.  Batches use tile 0
+       unless set or chosen by the batch autotuner. */
     ATA_OPT_LEAF_TILE = 7,
     /* ata_gram_batched: 1 = capture the batch's launch sequence once per
        shape signature in a hipGraph and replay it (default); 0 = enqueue the

@@ -310,10 +310,11 @@ void choose(const ata_ctx* h, int32_t mode, int64_t m, int64_t n, int64_t& b, in
         if (it != h->tune.end()) {
             b = it->second.leaf_cutoff;
             depth = it->second.max_depth;
-            if (tiled_mode(mode)) tile = it->second.leaf_tile;
+            if (tile < 0) tile = it->second.leaf_tile;
         }
     }
-    if (b <= 0) b = default_leaf_cutoff(mode, m, n);
+    if (tile < 0) tile = default_leaf_tile(mode, m, n);
+    if (b <= 0) b = default_leaf_cutoff(mode, m, n, tile);
     if (depth < 0) depth = default_max_depth(mode, m);
 }
 
@@ -420,6 +421,7 @@ ata_status_t ata_create(ata_handle_t* out) {
     ata_ctx* h = new (std::nothrow) ata_ctx;
     if (!h) return ATA_ERR_OUT_OF_MEMORY;
     h->device = dev;
+    h->popt.tile_cfg = -1;                 // automatic: autotune table, else by shape
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) h->arch = prop.gcnArchName;
     *out = h;
@@ -468,7 +470,8 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             h->seed = (uint64_t)value;
             return ATA_OK;
         case ATA_OPT_LEAF_TILE:
-            if (value != 0 && value != 1 && value != 2 && value != 3 && value != 4) return ATA_ERR_INVALID_VALUE;
+            if (value != -1 && value != 0 && value != 1 && value != 2 && value != 3 && value != 4)
+                return ATA_ERR_INVALID_VALUE;
             h->popt.tile_cfg = (int32_t)value;
             return ATA_OK;
         case ATA_OPT_BATCH_GRAPH:
@@ -1113,7 +1116,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0;
     // the batch runs one leaf kernel, so one tile shape: the handle's, or the
     // batch autotuner's for this signature when the options are defaults
-    int32_t tile_cfg = tiled_mode(mode) ? h->popt.tile_cfg : 0;
+    int32_t tile_cfg = tiled_mode(mode) && h->popt.tile_cfg > 0 ? h->popt.tile_cfg : 0;
     const ata_tune_entry_t* bt = nullptr;
     if (h->popt.leaf_cutoff <= 0 && h->popt.max_depth < 0 && !h->batch_tune.empty()) {
         auto f = h->batch_tune.find(batch_signature(mode, batch, m, n, lda));

@@ -10,14 +10,20 @@
 
 namespace ata {
 
-int64_t default_leaf_cutoff(int32_t mode, int64_t m, int64_t n) {
+int64_t default_leaf_cutoff(int32_t mode, int64_t m, int64_t n, int32_t tile_cfg) {
     (void)m;
     switch (mode) {
         case MODE_F64: return n <= 2048 ? 256 : 512;
-        case MODE_F32: return 1024;
+        case MODE_F32: return tile_cfg >= 2 ? 2048 : 1024;
         case MODE_BF16X3: return 2048;
         default: return 2048;
     }
+}
+
+int32_t default_leaf_tile(int32_t mode, int64_t m, int64_t n) {
+    if (mode == MODE_F32) return m >= 2048 && n >= 2048 ? 2 : 0;
+    if (mode == MODE_BF16X3) return m >= 4096 && n >= 4096 ? 2 : 0;
+    return 0;
 }
 
 int32_t default_max_depth(int32_t mode, int64_t m) {
@@ -451,7 +457,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.m = m;
     p.n = n;
     p.lda = lda;
-    p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, n);
+    p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, n, opt.tile_cfg);
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
@@ -552,7 +558,7 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.lda = lda;
     p.ldb = ldb;
     p.ldc = ldc;
-    p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, std::max(n, k));
+    p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, std::max(n, k), opt.tile_cfg);
     p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
     p.fallback = false;
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;

@@ -243,7 +243,10 @@ struct Plan {
     int64_t launches() const;
 };
 
-int64_t default_leaf_cutoff(int32_t mode, int64_t m, int64_t n);
+int64_t default_leaf_cutoff(int32_t mode, int64_t m, int64_t n, int32_t tile_cfg = 0);
+// Leaf tile of a shape with no explicit choice and no autotune entry: the
+// 256 x 256 eight-wave engines once the output has enough tiles of them.
+int32_t default_leaf_tile(int32_t mode, int64_t m, int64_t n);
 // Default Strassen depth cap of a mode for contractions of m rows.
 int32_t default_max_depth(int32_t mode, int64_t m);
 
