@@ -240,7 +240,8 @@ ata_status_t ata_destroy(ata_handle_t h);
    size, negative m or n, lda < max(1, n), an unknown dtype or overlapping A
    and C; ATA_ERR_NOT_SUPPORTED when a split-BF16 or FP8 leaf operand would
    need a packed array of 4 GiB or more (those arrays are read through 32-bit
-   buffer offsets); ATA_ERR_OUT_OF_MEMORY when the workspace cannot be
+   buffer offsets; when one packing of all of A would, split-BF16 packs each
+   leaf operand on its own instead); ATA_ERR_OUT_OF_MEMORY when the workspace cannot be
    allocated or exceeds ATA_OPT_WORKSPACE_LIMIT; ATA_ERR_HIP when a launch
    fails.  The first call for a (shape, dtype, options) combination builds and
    uploads the plan (host work and a synchronous copy); later calls only

@@ -370,7 +370,10 @@ void assign_packed(Plan& p) {
             return P;
         }
         const int64_t r0 = V.base == BASE_A ? V.off / p.lda : 0, c0 = V.base == BASE_A ? V.off % p.lda : 0;
-        if (V.base == BASE_A && r0 % 8 == 0 && V.pcols == V.cols && (K % 8 == 0 || r0 + K == p.m)) {
+        // (a whole-A packing past the 4 GiB reach of a buffer resource gives
+        // way to packings of the views themselves)
+        const bool a_fits = std::max<int64_t>(1, cdiv(p.m, 8)) * p.n * 16 <= (int64_t)0xFFFFFF00;
+        if (V.base == BASE_A && a_fits && r0 % 8 == 0 && V.pcols == V.cols && (K % 8 == 0 || r0 + K == p.m)) {
             const int64_t base = packed_a();
             P.off = base + (r0 / 8) * p.n * 4 + c0 * 4;
             P.lo_delta = a_groups * p.n * 4;

@@ -144,3 +144,14 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_split_bf16_plans_past_the_whole_a_packing_limit():
+    """A 50000^2 split-BF16 plan: one hi/lo packing of all of A would pass the
+    4 GiB reach of a buffer resource, so the planner packs each leaf operand
+    on its own instead of rejecting the shape; the multiplication count is the
+    same as for an FP32 plan of that shape."""
+    info, leaves = ata.ata_plan_query(50000, 50000, ata.F32_BF16X3, 2048, 1)
+    ref, _ = ata.ata_plan_query(50000, 50000, ata.F32, 2048, 1)
+    assert info["strassen_levels"] == 1 and len(leaves) > 0
+    assert info["multiplications"] == ref["multiplications"]
