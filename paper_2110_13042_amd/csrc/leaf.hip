@@ -1462,23 +1462,26 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, const 
     if constexpr (sizeof(InT) == 8) { lr = t >> 6; lc = (t & 63) << 1; rstep = 4; }
     else { lr = t >> 5; lc = (t & 31) << 2; rstep = 8; }
     const int64_t xc = (int64_t)ti * TILE_M + lc, yc = (int64_t)tj * TILE_N + lc;
-    const bool xv = vec_ok(Xp, d.X.ld, 16 / (int)sizeof(InT));
-    const bool yv = vec_ok(Yp, d.Y.ld, 16 / (int)sizeof(InT));
-    const bool x2v = vec_ok(X2p, d.X2.ld, 16 / (int)sizeof(InT));
-    const bool y2v = vec_ok(Y2p, d.Y2.ld, 16 / (int)sizeof(InT));
+    // descriptor fields in registers: read through the reference, they are
+    // reloaded after every LDS store of the K loop
+    const int64_t xld = d.X.ld, yld = d.Y.ld, xpc = d.X.pcols, ypc = d.Y.pcols;
+    const int64_t x2ld = d.X2.ld, y2ld = d.Y2.ld, x2pc = d.X2.pcols, y2pc = d.Y2.pcols;
+    const int32_t sx2 = d.sx2, sy2 = d.sy2;
+    const bool xv = vec_ok(Xp, xld, 16 / (int)sizeof(InT));
+    const bool yv = vec_ok(Yp, yld, 16 / (int)sizeof(InT));
+    const bool x2v = vec_ok(X2p, x2ld, 16 / (int)sizeof(InT));
+    const bool y2v = vec_ok(Y2p, y2ld, 16 / (int)sizeof(InT));
 
     auto gload = [&](int64_t k0) {
         if constexpr (sizeof(InT) == 8) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                double2 x = load2d(Xp, d.X.ld, k0 + lr + q * rstep, xc, xl, d.X.pcols, xv);
-                double2 y = load2d(Yp, d.Y.ld, k0 + lr + q * rstep, yc, yl, d.Y.pcols, yv);
-                if (d.sx2)
-                    x = add_term(x, load2d(X2p, d.X2.ld, k0 + lr + q * rstep, xc, x2l, d.X2.pcols, x2v),
-                                 (double)d.sx2);
-                if (d.sy2)
-                    y = add_term(y, load2d(Y2p, d.Y2.ld, k0 + lr + q * rstep, yc, y2l, d.Y2.pcols, y2v),
-                                 (double)d.sy2);
+                double2 x = load2d(Xp, xld, k0 + lr + q * rstep, xc, xl, xpc, xv);
+                double2 y = load2d(Yp, yld, k0 + lr + q * rstep, yc, yl, ypc, yv);
+                if (sx2)
+                    x = add_term(x, load2d(X2p, x2ld, k0 + lr + q * rstep, xc, x2l, x2pc, x2v), (double)sx2);
+                if (sy2)
+                    y = add_term(y, load2d(Y2p, y2ld, k0 + lr + q * rstep, yc, y2l, y2pc, y2v), (double)sy2);
                 rx[2 * q] = x.x; rx[2 * q + 1] = x.y;
                 ry[2 * q] = y.x; ry[2 * q + 1] = y.y;
             }
@@ -1486,8 +1489,8 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, const 
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 // the FP64 fallback's SYRK leaves have no fused pre-sums
-                const float4 x = load4f(Xp, d.X.ld, k0 + lr + q * rstep, xc, xl, d.X.pcols, xv);
-                const float4 y = load4f(Yp, d.Y.ld, k0 + lr + q * rstep, yc, yl, d.Y.pcols, yv);
+                const float4 x = load4f(Xp, xld, k0 + lr + q * rstep, xc, xl, xpc, xv);
+                const float4 y = load4f(Yp, yld, k0 + lr + q * rstep, yc, yl, ypc, yv);
                 rx[4 * q] = x.x; rx[4 * q + 1] = x.y; rx[4 * q + 2] = x.z; rx[4 * q + 3] = x.w;
                 ry[4 * q] = y.x; ry[4 * q + 1] = y.y; ry[4 * q + 2] = y.z; ry[4 * q + 3] = y.w;
             }
