@@ -350,7 +350,8 @@ def main() -> int:
     ap.add_argument("--equilibrate", action="store_true",
                     help="FP32 family: column equilibration instead of the FP64 fallback")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-samples", type=int, default=512)
+    ap.add_argument("--cpu-samples", type=int, default=4096,
+                    help="full columns of C the CPU oracle computes for the baseline and the error sample")
     ap.add_argument("--autotune", action="store_true",
                     help="tune leaf cutoff / depth / tile for the workload before the warmup (untimed)")
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table loaded into the handle")
