@@ -367,9 +367,11 @@ __device__ __forceinline__ void reduce_kernel_block(const ReduceDesc* tasks, int
     const int64_t plane = d.rows * d.cols;
     double s = 0.0;
     if (d.fb_node >= 0 && flags[d.fb_node]) {
+        if (d.ksplit_fb <= 1) return;          // the unsplit fallback wrote the target
         const double* p = reinterpret_cast<const double*>(arena + d.part64_off) + e;
-        for (int k = 0; k < d.ksplit; ++k) s += p[k * plane];
+        for (int k = 0; k < d.ksplit_fb; ++k) s += p[k * plane];
     } else {
+        if (d.ksplit <= 1) return;             // the unsplit leaf wrote the target
         const T* p = arena + d.part_off + e;
         for (int k = 0; k < d.ksplit; ++k) s += (double)p[k * plane];
     }

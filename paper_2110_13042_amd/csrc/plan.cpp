@@ -590,19 +590,35 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
 
 namespace {
 
-// Cuts leaf L into K chunks of a multiple of 256 rows (about K / s each),
-// with the partial buffers and the reduce task.  False if that leaves one
-// chunk.
-bool split_leaf(Plan& p, LeafDesc& L, int64_t s) {
-    const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
-    s = cdiv(L.K, kchunk);
-    if (s < 2) return false;
-    L.ksplit = (int32_t)s;
-    L.kchunk = kchunk;
-    L.tiles_split = L.tiles;
-    L.tiles *= s;
-    L.part_off = p.alloc(s * L.rows * L.cols);
-    if (L.fb_node >= 0) L.part64_off = p.alloc(2 * s * L.rows * L.cols);
+// Cuts leaf L into K chunks of a multiple of 256 rows: about K / s each in
+// the mode's launch and, for a leaf under the spread check, about K / s_fb
+// each in the FP64 fallback's launch (partial buffers and one reduce task).
+// False if neither side ends up with two chunks.
+bool split_leaf(Plan& p, LeafDesc& L, int64_t s, int64_t s_fb = 1) {
+    bool cut = false;
+    if (s >= 2) {
+        const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
+        s = cdiv(L.K, kchunk);
+        if (s >= 2) {
+            L.ksplit = (int32_t)s;
+            L.kchunk = kchunk;
+            L.tiles_split = L.tiles;
+            L.tiles *= s;
+            L.part_off = p.alloc(s * L.rows * L.cols);
+            cut = true;
+        }
+    }
+    if (L.fb_node >= 0 && s_fb >= 2) {
+        const int64_t kchunk = cdiv(cdiv(L.K, s_fb), 256) * 256;
+        s_fb = cdiv(L.K, kchunk);
+        if (s_fb >= 2) {
+            L.fb_ksplit = (int32_t)s_fb;
+            L.fb_kchunk = kchunk;
+            L.part64_off = p.alloc(2 * s_fb * L.rows * L.cols);
+            cut = true;
+        }
+    }
+    if (!cut) return false;
     ReduceDesc R{};
     R.kind = L.kind;
     R.out_kind = L.out_kind;
@@ -614,7 +630,8 @@ bool split_leaf(Plan& p, LeafDesc& L, int64_t s) {
     R.out_ld = L.out_ld;
     R.out_row0 = L.out_row0;
     R.out_col0 = L.out_col0;
-    R.ksplit = L.ksplit;
+    R.ksplit = L.ksplit > 1 ? L.ksplit : 1;
+    R.ksplit_fb = L.fb_ksplit > 1 ? L.fb_ksplit : 1;
     R.fb_node = L.fb_node;
     R.pred_node = L.pred_node;
     R.pred_value = L.pred_value;
@@ -630,7 +647,7 @@ void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
     if (target <= 0) return;
     int64_t t_mode = 0, t_fb = 0;
     for (const auto& L : p.leaves) {
-        if (L.ksplit > 1) return;                  // already split
+        if (L.ksplit > 1 || L.fb_ksplit > 1) return;   // already split
         t_mode += L.tiles;
         if (L.fb_node >= 0)
             t_fb += syrk_tiles(cdiv(L.rows, TILE_M), cdiv(L.cols, TILE_N), TILE_M / TILE_N);
@@ -638,14 +655,16 @@ void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
     // a launch with fewer tiles than two per CU may cut K into chunks as short
     // as 256 rows (small problems are otherwise latency-bound on their K loops)
     auto chunk_min = [&](int64_t tiles) { return tiles < 512 ? std::min<int64_t>(min_chunk, 256) : min_chunk; };
+    // each launch is split for its own tile count: the fallback's launch of a
+    // leaf under the spread check may be cut while the mode's is not
     for (auto& L : p.leaves) {
         const int64_t most = L.K / chunk_min(t_mode);
-        int64_t s = t_mode > 0 && t_mode < target && most >= 2 ? std::min(target / t_mode, most) : 1;
+        const int64_t s = t_mode > 0 && t_mode < target && most >= 2 ? std::min(target / t_mode, most) : 1;
         const int64_t most_fb = L.K / chunk_min(t_fb);
-        if (L.fb_node >= 0 && t_fb > 0 && t_fb < target && most_fb >= 2)
-            s = std::max(s, std::min(target / t_fb, most_fb));
-        if (s < 2) continue;
-        split_leaf(p, L, s);
+        const int64_t s_fb = L.fb_node >= 0 && t_fb > 0 && t_fb < target && most_fb >= 2
+                                 ? std::min(target / t_fb, most_fb) : 1;
+        if (s < 2 && s_fb < 2) continue;
+        split_leaf(p, L, s, s_fb);
     }
 }
 
@@ -697,7 +716,7 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
     if (slots <= 0 || p.leaves.empty()) return;
     int64_t total_tiles = 0;
     for (const auto& L : p.leaves) {
-        if (L.ksplit > 1) return;                  // split_leaves has cut this plan
+        if (L.ksplit > 1) return;                  // split_leaves has cut this launch
         total_tiles += L.tiles;
     }
     if (total_tiles > 64 * slots) return;         // the tail is a small part of the launch
@@ -786,6 +805,8 @@ void finalize_plan(Plan& p) {
             F.tiles_m = (int32_t)cdiv(F.rows, TILE_M);
             F.tiles_n = (int32_t)cdiv(F.cols, TILE_N);
             F.tiles = syrk_tiles(F.tiles_m, F.tiles_n, TILE_M / TILE_N);
+            F.ksplit = L.fb_ksplit > 1 ? L.fb_ksplit : 1;
+            F.kchunk = L.fb_kchunk;
             if (F.ksplit > 1) {
                 F.tiles_split = F.tiles;
                 F.tiles *= F.ksplit;

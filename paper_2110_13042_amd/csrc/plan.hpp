@@ -103,18 +103,26 @@ struct LeafDesc {
     int64_t part_off;         // split: arena offset of [ksplit][rows][cols] partials (mode type)
     int64_t part64_off;       // split SYRK leaves under the spread check: FP64 partials
                               // of the fallback (arena float offset, 8-byte aligned)
+    // The FP64 fallback's own K split of a leaf under the spread check (its
+    // launch is small, so it may cut where the mode's launch need not):
+    // fb_ksplit chunks of fb_kchunk rows (<= 1: none), partials at part64_off.
+    int32_t fb_ksplit;
+    int32_t pad2_;
+    int64_t fb_kchunk;
 };
 
 // Sum of the K-chunk partials of a split leaf (one work item per output
 // element), in chunk order, in FP64, rounded once into the leaf's target.
+// A leaf under the spread check takes the fallback's partials when its node
+// is flagged, the mode's otherwise; an unsplit side wrote the target itself.
 struct ReduceDesc {
     int32_t kind, out_kind;
     int64_t rows, cols;
     int64_t part_off, part64_off;
     int64_t out_off, out_ld, out_row0, out_col0;
-    int32_t ksplit, fb_node;
+    int32_t ksplit, fb_node;      // the mode's chunks (<= 1: its leaf wrote the target)
     int32_t pred_node, pred_value;
-    int32_t prob, pad_;
+    int32_t prob, ksplit_fb;      // the fallback's chunks (<= 1: it wrote the target)
     int64_t elem_begin, elems;
 };
 
