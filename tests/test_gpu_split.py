@@ -94,6 +94,37 @@ def test_split_k_with_fp64_fallback():
         h.close()
 
 
+def test_fallback_split_alone():
+    """The FP64 fallback launch is split on its own: with a split target of
+    100 tiles, the FP32 launch (136 tiles of 128 x 128) stays whole while the
+    fallback's (8 diagonal leaves, 24 tiles) is cut into 4 K chunks.  Flagged
+    leaves then take the reduce of the FP64 partials, unflagged ones were
+    written by the FP32 kernel directly."""
+    A = workloads.scaled_normal(4096, 2048, seed=94, span=2.0)
+    ref = plain.gram_packed(A)
+    h = ata.Handle()
+    try:
+        h.set("leaf_cutoff", 256)
+        h.set("max_depth", 0)
+        h.set("leaf_tile", 0)
+        h.set("spread_tau", 30.0)
+        h.set("split_target", 100)
+        h.set("balance_tail", 0)
+        _say("case: fallback split alone")
+        Cs = run_gram(A, ata.F32, h)
+        rep = h.report()
+        _say("  flagged", rep["flagged_nodes"], "error", full_error(Cs, ref))
+        assert rep["flagged_nodes"] > 0
+        assert full_error(Cs, ref) <= 2e-5
+        n = A.shape[1]
+        idx = np.arange(n)
+        diag = Cs[idx * (idx + 1) // 2 + idx]
+        rdiag = ref[idx * (idx + 1) // 2 + idx]
+        assert np.max(np.abs(diag - rdiag) / rdiag) <= 2 ** -23
+    finally:
+        h.close()
+
+
 def test_split_k_in_batch():
     rng = np.random.default_rng(94)
     shapes = [(20000, 200), (300, 100), (17000, 64), (1000, 900), (40000, 33)]
