@@ -590,14 +590,20 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
 
 namespace {
 
-// Cuts leaf L into K chunks of a multiple of 256 rows: about K / s each in
+// Row granule of a K chunk: the FP64 and FP32 engines take any multiple of
+// their 16- or 32-row slabs, the packed split-BF16 and FP8 operands 256.
+// The FP64 fallback reads its operands unpacked.
+int64_t split_granule(const Plan& p) { return p.mode == MODE_F64 || p.mode == MODE_F32 ? 128 : 256; }
+
+// Cuts leaf L into K chunks of a multiple of the granule: about K / s each in
 // the mode's launch and, for a leaf under the spread check, about K / s_fb
 // each in the FP64 fallback's launch (partial buffers and one reduce task).
 // False if neither side ends up with two chunks.
 bool split_leaf(Plan& p, LeafDesc& L, int64_t s, int64_t s_fb = 1) {
     bool cut = false;
     if (s >= 2) {
-        const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
+        const int64_t g = split_granule(p);
+        const int64_t kchunk = cdiv(cdiv(L.K, s), g) * g;
         s = cdiv(L.K, kchunk);
         if (s >= 2) {
             L.ksplit = (int32_t)s;
@@ -609,7 +615,7 @@ bool split_leaf(Plan& p, LeafDesc& L, int64_t s, int64_t s_fb = 1) {
         }
     }
     if (L.fb_node >= 0 && s_fb >= 2) {
-        const int64_t kchunk = cdiv(cdiv(L.K, s_fb), 256) * 256;
+        const int64_t kchunk = cdiv(cdiv(L.K, s_fb), 128) * 128;
         s_fb = cdiv(L.K, kchunk);
         if (s_fb >= 2) {
             L.fb_ksplit = (int32_t)s_fb;
@@ -654,13 +660,13 @@ void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
     }
     // a launch with fewer tiles than two per CU may cut K into chunks as short
     // as 256 rows (small problems are otherwise latency-bound on their K loops)
-    auto chunk_min = [&](int64_t tiles) { return tiles < 512 ? std::min<int64_t>(min_chunk, 256) : min_chunk; };
+    auto chunk_min = [&](int64_t tiles, int64_t g) { return tiles < 512 ? std::min<int64_t>(min_chunk, g) : min_chunk; };
     // each launch is split for its own tile count: the fallback's launch of a
     // leaf under the spread check may be cut while the mode's is not
     for (auto& L : p.leaves) {
-        const int64_t most = L.K / chunk_min(t_mode);
+        const int64_t most = L.K / chunk_min(t_mode, split_granule(p));
         const int64_t s = t_mode > 0 && t_mode < target && most >= 2 ? std::min(target / t_mode, most) : 1;
-        const int64_t most_fb = L.K / chunk_min(t_fb);
+        const int64_t most_fb = L.K / chunk_min(t_fb, 128);
         const int64_t s_fb = L.fb_node >= 0 && t_fb > 0 && t_fb < target && most_fb >= 2
                                  ? std::min(target / t_fb, most_fb) : 1;
         if (s < 2 && s_fb < 2) continue;
@@ -689,7 +695,8 @@ int64_t simulate_makespan(const Plan& p, const std::vector<int64_t>& split, int6
         const LeafDesc& L = p.leaves[i];
         int64_t rows = tile_rows(L), cost = tile_cost(L), tiles = L.tiles;
         if (split[i] > 1) {
-            const int64_t kchunk = cdiv(cdiv(L.K, split[i]), 256) * 256;
+            const int64_t g = split_granule(p);
+            const int64_t kchunk = cdiv(cdiv(L.K, split[i]), g) * g;
             rows = cost = kchunk;
             tiles = L.tiles * cdiv(L.K, kchunk);
         }
@@ -727,7 +734,7 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
     std::vector<size_t> cand;
     for (size_t i = 0; i < nl; ++i) {
         const LeafDesc& L = p.leaves[i];
-        if (L.fb_node >= 0 || tile_cost(L) == 0 || L.K < 512) continue;
+        if (L.fb_node >= 0 || tile_cost(L) == 0 || L.K < 2 * split_granule(p)) continue;
         cand.push_back(i);
     }
     std::stable_sort(cand.begin(), cand.end(), [&](size_t a, size_t b) {
@@ -744,7 +751,8 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
     const double row_per_byte = 2.0 / 5000.0 / tile_row_ns;
     const int64_t part_cap = int64_t(1) << 28;    // bytes of partials at most
     auto partial_bytes = [&](const LeafDesc& L, int64_t s) {
-        const int64_t kchunk = cdiv(cdiv(L.K, s), 256) * 256;
+        const int64_t g = split_granule(p);
+        const int64_t kchunk = cdiv(cdiv(L.K, s), g) * g;
         return cdiv(L.K, kchunk) * L.rows * L.cols * p.elem_bytes();
     };
     double best = (double)base;
@@ -756,7 +764,7 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
         int64_t sel = 0, last_bucket = -1, bytes = 0;
         for (size_t j = 0; j < cand.size(); ++j) {
             const LeafDesc& L = p.leaves[cand[j]];
-            if (L.K / 256 < s) continue;
+            if (L.K / split_granule(p) < s) continue;
             bytes += partial_bytes(L, s);
             if (bytes > part_cap) break;
             split[cand[j]] = s;
@@ -778,7 +786,7 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
     int64_t bytes = 0;
     for (size_t j = 0; j < best_n; ++j) {
         LeafDesc& L = p.leaves[cand[j]];
-        if (L.K / 256 < best_s) continue;
+        if (L.K / split_granule(p) < best_s) continue;
         bytes += partial_bytes(L, best_s);
         if (bytes > part_cap) break;
         if (split_leaf(p, L, best_s)) ++cut;

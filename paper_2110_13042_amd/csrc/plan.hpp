@@ -98,7 +98,7 @@ struct LeafDesc {
     Packed8 QX, QY;           // FP8 mode: quantised operands
     int32_t prob;             // problem of a batch (selects its A and C)
     int32_t ksplit;           // K chunks (1: none); tile q covers chunk q / tiles_split
-    int64_t kchunk;           // rows per K chunk (a multiple of 256)
+    int64_t kchunk;           // rows per K chunk (a multiple of 256; 128 for FP64 and FP32)
     int64_t tiles_split;      // tiles of one K chunk
     int64_t part_off;         // split: arena offset of [ksplit][rows][cols] partials (mode type)
     int64_t part64_off;       // split SYRK leaves under the spread check: FP64 partials
@@ -277,9 +277,10 @@ void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda,
 
 // Split-K: when a leaf launch (the mode's, or the FP64 fallback's) has fewer
 // than `target` tiles, leaves with K >= 2 * min_chunk are cut into K chunks
-// of at least min_chunk rows (multiples of 256; 256 rows when the launch has
-// fewer than 512 tiles), each chunk's tiles writing partial sums that a
-// reduce pass adds.  Called before finalize_plan; merged batch plans are
+// of at least min_chunk rows (multiples of 256, or of 128 for FP64, FP32
+// and the FP64 fallback; down to that granule when the launch has fewer
+// than 512 tiles), each chunk's tiles writing partial sums that a reduce
+// pass adds.  The two launches are judged on their own tile counts.  Called before finalize_plan; merged batch plans are
 // split once, after merging.
 constexpr int64_t SPLIT_MIN_CHUNK = 8192;
 void split_leaves(Plan& p, int64_t target, int64_t min_chunk = SPLIT_MIN_CHUNK);

@@ -111,11 +111,15 @@ def test_plan_splits_k_only_for_long_contractions_with_few_tiles():
     _, leaves = ata.ata_plan_query(8192, 8192, ata.F32, 1024, 2)
     assert all(L["ksplit"] == 1 for L in leaves)
     # a launch with very few tiles splits even moderate contractions, in
-    # chunks of at least 256 rows
+    # chunks of at least 128 rows (FP32; 256 for the packed split-BF16 operands)
     _, leaves = ata.ata_plan_query(8000, 300, ata.F32, 1024, 0)
+    assert leaves[0]["ksplit"] >= 2 and 8000 / leaves[0]["ksplit"] >= 128
+    _, leaves = ata.ata_plan_query(8000, 300, ata.F32_BF16X3, 1024, 0)
     assert leaves[0]["ksplit"] >= 2 and 8000 / leaves[0]["ksplit"] >= 256
     # contractions shorter than two chunks are never split
-    _, leaves = ata.ata_plan_query(400, 300, ata.F32, 1024, 0)
+    _, leaves = ata.ata_plan_query(250, 300, ata.F32, 1024, 0)
+    assert all(L["ksplit"] == 1 for L in leaves)
+    _, leaves = ata.ata_plan_query(400, 300, ata.F32_BF16X3, 1024, 0)
     assert all(L["ksplit"] == 1 for L in leaves)
 
 
