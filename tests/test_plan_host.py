@@ -1,0 +1,130 @@
+"""Host-side checks of the planner's scheduling decisions (CPU only): the
+planner source is compiled with the host compiler into a small driver that
+prints the plans' structure.  Covers the tail balancer, the FP64 fallback's
+own K split, the K-chunk granule, the per-operand split-BF16 packing past the
+4 GiB buffer reach, the pre-sum work-item width and Winograd's workspace."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2110_13042_amd", "csrc")
+
+DRIVER = r"""
+#include "plan.hpp"
+#include <algorithm>
+#include <cstdio>
+#include <stdexcept>
+using namespace ata;
+
+static void show(const char* tag, int32_t mode, int64_t m, int64_t n, int64_t b, int32_t d, int32_t tile,
+                 double tau, int64_t slots, int32_t variant = 0) {
+    PlanOptions o;
+    o.leaf_cutoff = b; o.max_depth = d; o.tile_cfg = tile; o.spread_tau = tau;
+    o.split_target = 2048; o.slots = slots; o.variant = variant;
+    try {
+        Plan p = make_plan(mode, m, n, n, o);
+        int64_t mode_split = 0, fb_split = 0, max_ks = 0, max_fbks = 0, min_chunk = 1 << 30;
+        for (const auto& L : p.leaves) {
+            if (L.ksplit > 1) { ++mode_split; max_ks = std::max<int64_t>(max_ks, L.ksplit);
+                                min_chunk = std::min<int64_t>(min_chunk, L.kchunk); }
+            if (L.fb_ksplit > 1) { ++fb_split; max_fbks = std::max<int64_t>(max_fbks, L.fb_ksplit); }
+        }
+        int64_t unit1 = 0, unit4 = 0, presums = 0;
+        for (const auto& lv : p.presum)
+            for (const auto& t : lv) { ++presums; (t.unit == 1 ? unit1 : unit4) += 1; }
+        printf("%s tiles=%lld fb_tiles=%lld tail=%d chunks=%d mode_split=%lld max_ks=%lld min_chunk=%lld "
+               "fb_split=%lld max_fbks=%lld packs=%zu presums=%lld unit1=%lld unit4=%lld arena=%lld levels=%d\n",
+               tag, (long long)p.total_tiles, (long long)p.fb_tiles, p.tail_leaves, p.tail_chunks,
+               (long long)mode_split, (long long)max_ks, (long long)(mode_split ? min_chunk : 0),
+               (long long)fb_split, (long long)max_fbks, p.pack.size(), (long long)presums,
+               (long long)unit1, (long long)unit4, (long long)p.arena_elems, p.stats.max_levels);
+    } catch (const std::exception& e) {
+        printf("%s error=%s\n", tag, e.what());
+    }
+}
+
+int main() {
+    show("bf16_tail", MODE_BF16X3, 8192, 8192, 256, 0, 2, 4096.0, 256);
+    show("bf16_nobal", MODE_BF16X3, 8192, 8192, 256, 0, 2, 4096.0, 0);
+    show("f32_balanced", MODE_F32, 8192, 8192, 2048, 1, 2, 4096.0, 256);
+    show("f64_small", MODE_F64, 1024, 1024, 256, 1, 0, 0.0, 512);
+    show("bf16_big", MODE_BF16X3, 50000, 50000, 2048, 1, 2, 4096.0, 256);
+    show("bf16_mid", MODE_BF16X3, 40000, 40000, 2048, 1, 2, 4096.0, 256);
+    show("f64_odd", MODE_F64, 30000, 30000, 512, 2, 0, 0.0, 0);
+    show("f32_pow2", MODE_F32, 16384, 16384, 2048, 2, 2, 0.0, 0);
+    show("strassen", MODE_F32, 2048, 2048, 512, 1, 0, 0.0, 0, 0);
+    show("winograd", MODE_F32, 2048, 2048, 512, 1, 0, 0.0, 0, 1);
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def plans(tmp_path_factory):
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    d = tmp_path_factory.mktemp("plan")
+    src = d / "driver.cpp"
+    src.write_text(DRIVER)
+    exe = d / "driver"
+    subprocess.run([cxx, "-O1", "-std=c++17", "-I", CSRC, str(src), os.path.join(CSRC, "plan.cpp"),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    res = {}
+    for line in out.strip().splitlines():
+        tag, *kv = line.split()
+        res[tag] = {k: (v if k == "error" else int(v)) for k, v in (x.split("=", 1) for x in kv)}
+    return res
+
+
+def test_tail_balancer_fills_the_last_round(plans):
+    """8192^2 on 256^2 tiles: 528 equal tiles on 256 slots.  The balancer cuts
+    16 one-tile leaves into 16 K chunks (768 tiles); without slots, nothing."""
+    p, q = plans["bf16_tail"], plans["bf16_nobal"]
+    assert q["tiles"] == 528 and q["tail"] == 0 and q["mode_split"] == 0
+    assert p["tail"] == 16 and p["chunks"] == 16 and p["tiles"] == 528 - 16 + 16 * 16
+
+
+def test_fallback_split_leaves_the_mode_launch_whole(plans):
+    """The 32 diagonal leaves under the spread check get K chunks in the FP64
+    fallback launch only; the mode launch keeps them whole."""
+    p = plans["bf16_nobal"]
+    assert p["fb_split"] == 32 and p["max_fbks"] >= 2
+    assert p["mode_split"] == 0
+
+
+def test_balanced_fp32_plan_is_left_alone(plans):
+    p = plans["f32_balanced"]
+    assert p["tail"] == 0 and p["levels"] == 1
+
+
+def test_fp64_k_chunks_down_to_128_rows(plans):
+    """A small FP64 launch cuts its 1024-row contractions into 128-row chunks."""
+    p = plans["f64_small"]
+    assert p["max_ks"] == 8 and p["min_chunk"] == 128
+
+
+def test_split_bf16_packs_each_operand_past_the_buffer_reach(plans):
+    """50000^2: one packing of A would pass 4 GiB, so each leaf operand gets its
+    own; 40000^2 still shares one whole-A packing for its aligned views."""
+    big, mid = plans["bf16_big"], plans["bf16_mid"]
+    assert "error" not in big and big["packs"] > 1
+    assert "error" not in mid and mid["packs"] == 1
+
+
+def test_presum_work_item_width_follows_alignment(plans):
+    """Rows whose starts are not 16-byte aligned (odd splits of 30000) take one
+    column per work item; power-of-two shapes keep four."""
+    odd, pow2 = plans["f64_odd"], plans["f32_pow2"]
+    assert odd["unit1"] > 0
+    assert pow2["unit1"] == 0 and pow2["unit4"] == pow2["presums"] > 0
+
+
+def test_winograd_needs_less_workspace(plans):
+    """Four pre-sum buffers per operand instead of five."""
+    assert plans["winograd"]["arena"] < plans["strassen"]["arena"]
+    assert plans["winograd"]["levels"] == plans["strassen"]["levels"] == 1
