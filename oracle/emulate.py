@@ -28,7 +28,12 @@ rounding of the bit pattern; the e4m3 rounding against torch's
 ``float8_e4m3fn`` cast and against hand-listed codes; the scale rule at and
 around powers of two; the emulated products against exact FP64 on operands
 that are already representable; SplitMix64 against the published first
-outputs for seed 0 (fixture ``tests/golden/splitmix64.txt``).
+outputs for seed 0 (fixture ``tests/golden/splitmix64.txt``); the residual's
+value and normalisation on hand-computed cases
+(``tests/golden/freivalds_hand.txt``); the recursion with Strassen levels
+bit-exact against the plain FP64 product on small integers in both modes, and
+the FP32 rounding of the pre-sums on a hand-derived two-level case
+(``tests/golden/emulated_presum_rounding.txt``).
 """
 from __future__ import annotations
 

@@ -1,5 +1,6 @@
 """Pins for the reduced-precision emulation, spread flags and residual (CPU only)."""
 import numpy as np
+import pytest
 import torch
 
 from oracle import emulate, plain, recursive
@@ -126,3 +127,105 @@ def test_spread_flags():
     assert emulate.spread_flags(nu, nodes, tau=1e3) == [False, False, False, False]
     c = recursive.count(10, 8, 2)
     assert len(emulate.spread_flags(nu, c.ata_list, 10.0)) == c.ata_nodes
+
+
+def _read_freivalds_cases():
+    cases = []
+    for line in open(golden_path("freivalds_hand.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        name, mn, a, c, seed, res, _why = [f.strip() for f in line.split("|", 6)]
+        m, n = (int(v) for v in mn.split())
+        A = np.array([float(v) for v in a.split()]).reshape(m, n)
+        Cp = np.array([float(v) for v in c.split()])
+        cases.append((name, A, Cp, int(seed), float(res)))
+    return cases
+
+
+def test_freivalds_residual_hand_cases():
+    """The residual's value, normalisation included, on hand-computed cases
+    (tests/golden/freivalds_hand.txt): ||E x|| / (||A||_F^2 ||x||)."""
+    cases = _read_freivalds_cases()
+    assert len(cases) == 6
+    for name, A, Cp, seed, want in cases:
+        got = emulate.freivalds_residual(A, Cp, seed)
+        if want == 0:
+            assert got == 0, name
+        else:
+            assert abs(got - want) <= 1e-15 * want, (name, got, want)
+    # the sign-dependent pair: the same E under two seeds gives 1 vs sqrt(5)
+    by = {c[0]: c[4] for c in cases}
+    assert abs(by["off_sg"] / by["off_s0"] - np.sqrt(5)) < 1e-15
+
+
+def test_freivalds_residual_planted_normalisations_fail():
+    """Plausible normalisation mistakes give values the hand cases reject."""
+    A, Cp, seed, want = None, None, None, None
+    for name, A_, Cp_, seed_, want_ in _read_freivalds_cases():
+        if name == "sq3":
+            A, Cp, seed, want = A_, Cp_, seed_, want_
+    n = A.shape[1]
+    x = emulate.probe_signs(n, seed)
+    C = plain.unpack(Cp, n)
+    num = np.linalg.norm(C @ x - A.T @ (A @ x))
+    fro2 = float(np.sum(A * A))
+    wrong = [num / (fro2 * float(x @ x)),               # ||x||^2 for ||x||
+             num / (np.sqrt(fro2) * np.linalg.norm(x)),  # ||A||_F for ||A||_F^2
+             num / fro2]                                 # no ||x||
+    for w in wrong:
+        assert abs(w - want) > 1e-3 * want
+
+
+def _read_rounding_case():
+    A = None
+    deltas = []
+    b = depth = None
+    for line in open(golden_path("emulated_presum_rounding.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        f = line.split()
+        if f[0] == "shape":
+            A = np.zeros((int(f[1]), int(f[2])), dtype=np.float32)
+        elif f[0] == "cutoff":
+            b = int(f[1])
+        elif f[0] == "depth":
+            depth = int(f[1])
+        elif f[0] == "a":
+            A[int(f[1]), int(f[2])] = float.fromhex(f[3])
+        elif f[0] == "d":
+            deltas.append((int(f[1]), int(f[2]), float.fromhex(f[3])))
+    return A, b, depth, deltas
+
+
+def test_emulated_presum_rounding_hand_case():
+    """Two Strassen levels: each pre-sum is rounded to FP32 before it is split
+    (hand-derived in tests/golden/emulated_presum_rounding.txt)."""
+    A, b, depth, deltas = _read_rounding_case()
+    n = A.shape[1]
+    want = plain.unpack(plain.gram_packed(A), n)
+    for r, c, d in deltas:
+        want[r, c] += d
+    rr, cc = np.tril_indices(n)
+    got = emulate.ata_emulated(A, "bf16x3", b=b, max_strassen_depth=depth)
+    assert np.array_equal(got, want[rr, cc])
+    # planted mistake: the same recursion without the FP32 rounding of the
+    # pre-sums (only the final leaf operand is rounded) misses the fixture
+    unrounded, _ = recursive.ata(A, b, split_m=False, max_strassen_depth=depth,
+                                 leaf_product=emulate.bf16x3_product)
+    assert not np.array_equal(unrounded, want[rr, cc])
+
+
+@pytest.mark.parametrize("mode,lim", [("bf16x3", 8), ("fp8", 4)])
+@pytest.mark.parametrize("m,n,b,depth", [(37, 29, 4, 1), (37, 29, 4, 2), (64, 48, 8, 2),
+                                         (130, 67, 16, 2), (9, 40, 5, 2)])
+def test_emulated_integers_exact_with_strassen(mode, lim, m, n, b, depth):
+    """Small integers whose pre-sums stay exact in the mode's operand format
+    (|sum| <= 4 lim: <= 32 for bf16, <= 16 for e4m3 after the power-of-two
+    block scale) give exactly the plain FP64 Gram product at Strassen depth
+    1 and 2, odd splits included."""
+    rng = np.random.default_rng(1000 + m + n + b + depth)
+    A = rng.integers(-lim, lim + 1, (m, n)).astype(np.float32)
+    got = emulate.ata_emulated(A, mode, b=b, max_strassen_depth=depth)
+    c = recursive.count(m, n, b, split_m=False, max_strassen_depth=depth)
+    assert c.strassen_nodes > 0
+    assert np.array_equal(got, plain.gram_packed(A))
