@@ -23,8 +23,17 @@
  *     library overwrites C (alpha = 1, beta = 0; Sec. 3.1 drops beta because
  *     C can be scaled beforehand).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *     All device work is enqueued on it; no entry point of the compute path
- *     synchronises the host, except where stated.
+ *     hipStream_t is itself an opaque pointer type, so the two are the same
+ *     value at the ABI level; the header takes void* so that it needs no HIP
+ *     header.  All device work is enqueued on it; no entry point of the
+ *     compute path synchronises the host, except where stated.
+ *   - Workspace: a handle keeps one workspace and grows it when a call needs
+ *     more.  Calls may be recorded into a caller's graph (stream capture)
+ *     once the same call has run eagerly, so that nothing is allocated while
+ *     capturing.  After a call has been recorded, a later call that grows the
+ *     workspace keeps the superseded buffers alive until ata_destroy, so a
+ *     live graph never points at freed memory; the graph itself still uses
+ *     the old buffers, which later eager calls no longer write.
  *   - Errors are returned, never thrown.  Argument errors are detected before
  *     anything is enqueued, and C is left untouched.  Device faults are
  *     asynchronous and surface at a later call or at the caller's sync.
@@ -394,6 +403,22 @@ ata_status_t ata_plan_query(int64_t m, int64_t n, ata_dtype_t dtype,
                             int64_t leaf_cutoff, int32_t max_depth,
                             ata_report_t* info, ata_leaf_t* leaves, int64_t cap,
                             int64_t* n_leaves);
+
+/* Column norms and spread flags of the last ata_gram call, when that call ran
+   the spread check of the FP64 fallback (an FP32-family dtype with
+   ATA_OPT_SPREAD_TAU > 0, m > 0, no equilibration).  nu (host, n doubles,
+   n must equal that call's n) receives nu_j = sum_r A[r][j]^2 summed in FP64;
+   node_c0, node_w and flags (host arrays of `cap` entries) receive, for each
+   AtA node of the plan in the recursion's pre-order (a node, then its left
+   column half, then its right half: Alg. 1's call order), its first column,
+   its width and its flag (1 when max nu / min nu over the node's nonzero
+   columns exceeds tau^2, else 0).  Any of the arrays may be NULL; *count
+   (may be NULL) receives the number of nodes.  Synchronises the stream of
+   that call when nu or flags is requested.  ATA_ERR_INVALID_VALUE when the
+   handle's last call was not such an ata_gram call (a later call of
+   another compute entry point clears it) or n differs. */
+ata_status_t ata_get_spread(ata_handle_t h, double* nu, int64_t n, int64_t* node_c0,
+                            int64_t* node_w, uint8_t* flags, int64_t cap, int64_t* count);
 
 /* Static description of a status code. */
 const char* ata_status_string(ata_status_t s);

@@ -107,13 +107,16 @@ def lib() -> ctypes.CDLL:
     L.ata_autotune_batched.argtypes = [vp, i64, vp, vp, vp, vp, st, vp, vp, ctypes.POINTER(TuneEntry)]
     L.ata_tune_save.argtypes = [vp, ctypes.c_char_p]
     L.ata_tune_load.argtypes = [vp, ctypes.c_char_p]
+    L.ata_get_spread.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64, ctypes.POINTER(i64),
+                                 ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_uint8), i64,
+                                 ctypes.POINTER(i64)]
     L.ata_status_string.argtypes = [st]
     L.ata_status_string.restype = ctypes.c_char_p
     for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_batched", "ata_set_option",
                  "ata_get_report", "ata_plan_query", "ata_residual", "ata_check_columns", "ata_autotune",
                  "ata_autotune_batched",
                  "ata_gemm_tn", "ata_gram_scaled", "ata_gram_aat", "ata_unpack",
-                 "ata_tune_save", "ata_tune_load"):
+                 "ata_tune_save", "ata_tune_load", "ata_get_spread"):
         getattr(L, name).restype = st
     _LIB = L
     return L
@@ -187,6 +190,20 @@ def ata_get_report(h: int) -> dict:
     r = Report()
     _check(lib().ata_get_report(h, ctypes.byref(r)), "ata_get_report")
     return r.as_dict()
+
+
+def ata_get_spread(h: int, n: int):
+    """(nu, [(c0, w, flag), ...]) of the last ata_gram call's spread check:
+    nu as a list of n floats, then every AtA node in the recursion's pre-order."""
+    count = ctypes.c_int64()
+    _check(lib().ata_get_spread(h, None, 0, None, None, None, 0, ctypes.byref(count)), "ata_get_spread")
+    k = count.value
+    nu = (ctypes.c_double * max(n, 1))()
+    c0 = (ctypes.c_int64 * max(k, 1))()
+    w = (ctypes.c_int64 * max(k, 1))()
+    fl = (ctypes.c_uint8 * max(k, 1))()
+    _check(lib().ata_get_spread(h, nu, n, c0, w, fl, k, ctypes.byref(count)), "ata_get_spread")
+    return list(nu)[:n], [(c0[i], w[i], fl[i]) for i in range(k)]
 
 
 def ata_plan_query(m: int, n: int, dtype: int, leaf_cutoff: int = 0, max_depth: int = -1):
@@ -272,6 +289,10 @@ class Handle:
 
     def report(self) -> dict:
         return ata_get_report(self.h)
+
+    def spread(self, n: int):
+        """Column norms and per-node spread flags of the last ata_gram call."""
+        return ata_get_spread(self.h, n)
 
     def autotune(self, A, dtype=None) -> dict:
         """Tune the plan for A's shape bucket (A's contents are only read)."""

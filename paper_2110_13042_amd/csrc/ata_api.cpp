@@ -202,11 +202,29 @@ struct ata_ctx {
     size_t events_used = 0;
     int64_t profiled_calls = 0;
     double phase_ms[5] = {0, 0, 0, 0, 0};
+    // set once a call has been enqueued on a capturing stream: from then on
+    // superseded workspace buffers are retired, not freed (see ensure)
+    bool captured = false;
+    std::vector<void*> retired;
+    // column norms and spread flags of the last ata_gram call with the
+    // spread check (ata_get_spread); null plan when there is none
+    const DevicePlan* spread_plan = nullptr;
+    const double* spread_nu = nullptr;
+    const uint8_t* spread_flags = nullptr;
+    hipStream_t spread_stream = nullptr;
 };
 
 namespace {
 
 ata_status_t hip_status(hipError_t e) { return e == hipSuccess ? ATA_OK : ATA_ERR_HIP; }
+
+// Remember that work of this handle is being recorded into a graph.
+void note_capture(ata_ctx* h, void* stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cs) == hipSuccess &&
+        cs != hipStreamCaptureStatusNone)
+        h->captured = true;
+}
 
 constexpr int EVENTS_PER_CALL = 6;
 
@@ -233,11 +251,18 @@ void clear_events(ata_ctx* h) {
     h->events_used = 0;
 }
 
-ata_status_t ensure(void*& ptr, size_t& cap, size_t bytes) {
+// Grow one of the handle's device buffers.  A smaller buffer is freed
+// (hipFree waits for outstanding work on the device) unless a call on this
+// handle has been recorded into a caller's graph: that graph still holds the
+// old address, so the buffer is kept until ata_destroy.
+ata_status_t ensure(ata_ctx* h, void*& ptr, size_t& cap, size_t bytes) {
     if (bytes <= cap) return ATA_OK;
     if (ptr) {
-        // hipFree waits for outstanding work on the device
-        if (hipFree(ptr) != hipSuccess) return ATA_ERR_HIP;
+        if (h && h->captured) {
+            h->retired.push_back(ptr);
+        } else if (hipFree(ptr) != hipSuccess) {
+            return ATA_ERR_HIP;
+        }
         ptr = nullptr;
         cap = 0;
     }
@@ -441,6 +466,7 @@ ata_status_t ata_destroy(ata_handle_t h) {
     if (h->aux) (void)hipFree(h->aux);
     if (h->tmp) (void)hipFree(h->tmp);
     if (h->eq) (void)hipFree(h->eq);
+    for (void* p : h->retired) (void)hipFree(p);
     delete h;
     return ATA_OK;
 }
@@ -606,7 +632,7 @@ ata_status_t gram_equilibrated(ata_ctx* h, const void* A, int64_t m, int64_t n, 
     const size_t part_b = align256(sizeof(double) * (size_t)std::max<int64_t>(q.col_partial, 1));
     const size_t nu_b = align256(sizeof(double) * (size_t)n);
     const size_t e_b = align256(sizeof(int) * (size_t)n);
-    ata_status_t s = ensure(h->eq, h->eq_cap, ap_b + part_b + nu_b + e_b);
+    ata_status_t s = ensure(h, h->eq, h->eq_cap, ap_b + part_b + nu_b + e_b);
     if (s != ATA_OK) return s;
     unsigned char* base = static_cast<unsigned char*>(h->eq);
     float* Ap = reinterpret_cast<float*>(base);
@@ -655,6 +681,8 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
         return ATA_OK;
     }
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    note_capture(h, stream);
+    h->spread_plan = nullptr;
     const int32_t mode = (int32_t)dtype;
     if (h->equilibrate && mode != MODE_F64 && m > 0) return gram_equilibrated(h, A, m, n, lda, dtype, C_packed, stream);
     int64_t b;
@@ -700,10 +728,10 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     const size_t arena_bytes = (size_t)p.arena_elems * (size_t)p.elem_bytes();
     if (h->ws_limit > 0 && (int64_t)(arena_bytes + ax.total) > h->ws_limit) return ATA_ERR_OUT_OF_MEMORY;
     const size_t old_cap = h->arena_cap;
-    ata_status_t s = ensure(h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
+    ata_status_t s = ensure(h, h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
     if (s != ATA_OK) return s;
     if (h->arena_cap != old_cap) ++h->arena_gen;
-    s = ensure(h->aux, h->aux_cap, ax.total);
+    s = ensure(h, h->aux, h->aux_cap, ax.total);
     if (s != ATA_OK) return s;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -775,6 +803,12 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     h->last_flags = flags;
     h->last_residual = res;
     h->last_nodes = (int64_t)p.nodes.size();
+    if (p.fallback) {
+        h->spread_plan = &dp;
+        h->spread_nu = nu;
+        h->spread_flags = flags;
+        h->spread_stream = st;
+    }
     return ATA_OK;
 }
 
@@ -790,7 +824,7 @@ ata_status_t ata_residual(ata_handle_t h, const void* A, int64_t m, int64_t n, i
     const size_t bytes = align256(sizeof(double) * (size_t)residual_work_elems(m, n)) + 256;
     void* buf = nullptr;
     size_t cap = 0;
-    ata_status_t s = ensure(buf, cap, bytes);
+    ata_status_t s = ensure(nullptr, buf, cap, bytes);
     if (s != ATA_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     double* out = reinterpret_cast<double*>(static_cast<unsigned char*>(buf) + bytes - 256);
@@ -819,7 +853,7 @@ ata_status_t ata_check_columns(ata_handle_t h, const void* A, int64_t m, int64_t
     const size_t cols_b = align256(sizeof(int64_t) * (size_t)count);
     void* buf = nullptr;
     size_t cap = 0;
-    ata_status_t s = ensure(buf, cap, work_b + cols_b);
+    ata_status_t s = ensure(nullptr, buf, cap, work_b + cols_b);
     if (s != ATA_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     double* work = static_cast<double*>(buf);
@@ -863,8 +897,10 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     h->report.flagged_nodes = -1;
     h->report.residual = -1.0;
     h->pending_flags = h->pending_residual = false;
+    h->spread_plan = nullptr;
     if (n == 0 || k == 0) return ATA_OK;
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    note_capture(h, stream);
     const int32_t mode = (int32_t)dtype;
     int64_t b;
     int32_t depth, tile_cfg;
@@ -906,10 +942,10 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     const size_t arena_bytes = (size_t)p.arena_elems * (size_t)p.elem_bytes();
     if (h->ws_limit > 0 && (int64_t)arena_bytes > h->ws_limit) return ATA_ERR_OUT_OF_MEMORY;
     const size_t old_cap = h->arena_cap;
-    ata_status_t s = ensure(h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
+    ata_status_t s = ensure(h, h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
     if (s != ATA_OK) return s;
     if (h->arena_cap != old_cap) ++h->arena_gen;
-    s = ensure(h->aux, h->aux_cap, 512);
+    s = ensure(h, h->aux, h->aux_cap, 512);
     if (s != ATA_OK) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint8_t* flags = static_cast<const uint8_t*>(h->aux);     // no predicates in this plan
@@ -982,7 +1018,8 @@ ata_status_t ata_gram_scaled(ata_handle_t h, const void* A, int64_t m, int64_t n
         if (a0 < c1 && c0 < a1) return ATA_ERR_INVALID_VALUE;
     }
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
-    ata_status_t s = ensure(h->tmp, h->tmp_cap, (size_t)len * es);
+    note_capture(h, stream);
+    ata_status_t s = ensure(h, h->tmp, h->tmp_cap, (size_t)len * es);
     if (s != ATA_OK) return s;
     s = ata_gram(h, A, m, n, lda, dtype, h->tmp, stream);
     if (s != ATA_OK) return s;
@@ -1002,9 +1039,10 @@ ata_status_t ata_gram_aat(ata_handle_t h, const void* A, int64_t m, int64_t n, i
     }
     if (m == 0) return ATA_OK;                     // C is 0 x 0
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    note_capture(h, stream);
     // A A^T = (A^T)^T (A^T): transpose once (one HBM pass, O(m n) against the
     // O(m^2 n) product), then the AtA plan on the n x m transpose
-    ata_status_t s = ensure(h->tmp, h->tmp_cap, std::max<size_t>((size_t)(m * n) * es, 256));
+    ata_status_t s = ensure(h, h->tmp, h->tmp_cap, std::max<size_t>((size_t)(m * n) * es, 256));
     if (s != ATA_OK) return s;
     if (launch_transpose((int32_t)dtype, A, m, n, lda, h->tmp, static_cast<hipStream_t>(stream)) != hipSuccess)
         return ATA_ERR_HIP;
@@ -1112,6 +1150,8 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
         }
     }
     if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    note_capture(h, stream);
+    h->spread_plan = nullptr;
     const int32_t mode = (int32_t)dtype;
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0;
     // the batch runs one leaf kernel, so one tile shape: the handle's, or the
@@ -1221,7 +1261,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
     const size_t arena_bytes = (size_t)mp.arena_elems * (size_t)mp.elem_bytes();
     if (h->ws_limit > 0 && (int64_t)(arena_bytes + be.aux_bytes) > h->ws_limit) return ATA_ERR_OUT_OF_MEMORY;
     const size_t old_cap = h->arena_cap;
-    ata_status_t s = ensure(h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
+    ata_status_t s = ensure(h, h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
     if (s != ATA_OK) return s;
     if (h->arena_cap != old_cap) ++h->arena_gen;
     // stage the pointers; a previous replay may still be copying them
@@ -1489,6 +1529,29 @@ ata_status_t ata_tune_load(ata_handle_t h, const char* path) {
         h->tune[TuneKey{(int32_t)dt, (int32_t)mb, (int32_t)nb}] =
             ata_tune_entry_t{(int64_t)b, (int32_t)d, (int32_t)tl, ms};
     }
+    return ATA_OK;
+}
+
+ata_status_t ata_get_spread(ata_handle_t h, double* nu, int64_t n, int64_t* node_c0, int64_t* node_w,
+                            uint8_t* flags, int64_t cap, int64_t* count) {
+    if (!h || n < 0 || cap < 0) return ATA_ERR_INVALID_VALUE;
+    if (!h->spread_plan) return ATA_ERR_INVALID_VALUE;
+    const Plan& p = h->spread_plan->plan;
+    if (nu && n != p.n) return ATA_ERR_INVALID_VALUE;
+    const int64_t nodes = (int64_t)p.nodes.size();
+    if (count) *count = nodes;
+    const int64_t k = std::min(cap, nodes);
+    for (int64_t i = 0; i < k; ++i) {
+        if (node_c0) node_c0[i] = p.nodes[(size_t)i].c0;
+        if (node_w) node_w[i] = p.nodes[(size_t)i].w;
+    }
+    if (!nu && !(flags && k > 0)) return ATA_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    if (hipStreamSynchronize(h->spread_stream) != hipSuccess) return ATA_ERR_HIP;
+    if (nu && n > 0 && hipMemcpy(nu, h->spread_nu, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess)
+        return ATA_ERR_HIP;
+    if (flags && k > 0 && hipMemcpy(flags, h->spread_flags, (size_t)k, hipMemcpyDeviceToHost) != hipSuccess)
+        return ATA_ERR_HIP;
     return ATA_OK;
 }
 

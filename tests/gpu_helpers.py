@@ -12,9 +12,18 @@ def device():
 
 
 def run_gram(A_np, mode, handle=None, lda=None):
-    """Packed lower C from the HIP path (numpy FP64), A given on the host."""
+    """Packed lower C from the HIP path (numpy FP64), A given on the host.
+
+    For the FP32-family modes A must hold FP32 values (an FP32 array, or an
+    FP64 array whose values are exact in FP32): the oracle the result is
+    compared with then sees exactly the input the GPU sees.
+    """
     dev = device()
     dt = torch.float64 if mode == ata.F64 else torch.float32
+    if mode != ata.F64 and np.asarray(A_np).dtype != np.float32:
+        if not np.array_equal(np.asarray(A_np).astype(np.float32), A_np):
+            raise ValueError("FP32-family input holds values that FP32 cannot represent; round it "
+                             "to FP32 first so that the oracle sees the GPU's input")
     A = torch.from_numpy(np.ascontiguousarray(A_np)).to(dev, dt)
     if lda is not None and lda > A.shape[1]:
         big = torch.zeros((A.shape[0], lda), dtype=dt, device=dev)
@@ -24,6 +33,11 @@ def run_gram(A_np, mode, handle=None, lda=None):
     out = ata.gram(A, mode, handle=h)
     torch.cuda.synchronize()
     return out.double().cpu().numpy()
+
+
+def mode_input(A_np, mode):
+    """A rounded to the element type the mode takes (FP64 for ATA_F64, else FP32)."""
+    return np.asarray(A_np, dtype=np.float64 if mode == ata.F64 else np.float32)
 
 
 def full_error(Cp, ref):

@@ -62,7 +62,7 @@ def test_balanced_tail_integers_exact(h, ints, mode, tile, expect_cut):
 
 def test_balanced_tail_random_matches_uncut(h):
     rng = np.random.default_rng(112)
-    A = rng.uniform(-1, 1, (2048, 8192))
+    A = rng.uniform(-1, 1, (2048, 8192)).astype(np.float32)
     ref = plain.gram_packed(A)
     h.set("leaf_tile", 2)
     h.set("leaf_cutoff", 256)

@@ -10,7 +10,7 @@ import pytest
 
 from oracle import plain
 from paper_2110_13042_amd import ata
-from gpu_helpers import device, full_error, run_gram
+from gpu_helpers import device, full_error, mode_input, run_gram
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def test_fused_presums_reproduce_materialised(h, mode, tile):
     h.set("leaf_tile", tile)
     try:
         for (m, n, b, depth) in CASES:
-            A = rng.uniform(-1, 1, (m, n))
+            A = mode_input(rng.uniform(-1, 1, (m, n)), mode)
             h.set("leaf_cutoff", b)
             h.set("max_depth", depth)
             outs = []

@@ -7,7 +7,7 @@ import torch
 
 from oracle import emulate, plain, recursive
 from paper_2110_13042_amd import ata, workloads
-from gpu_helpers import device, full_error, packed_columns, run_gram
+from gpu_helpers import device, full_error, mode_input, packed_columns, run_gram
 
 pytestmark = pytest.mark.gpu
 
@@ -173,15 +173,30 @@ def test_fallback_flags_match_oracle(h):
     A = workloads.scaled_normal(m, n, seed=46, dtype=np.float32, span=1.0)
     h.set("leaf_cutoff", b)
     h.set("max_depth", 2)
-    tau = 30.0
+    # squared-norm spreads of this input's 15 nodes lie in [8150, 9528]:
+    # tau^2 = 9025 flags 9 of them, 0.66% or more away from the threshold
+    tau = 95.0
     h.set("spread_tau", tau)
     _say("case: fallback flags")
     Cp = run_gram(A, ata.F32, h)
     rep = h.report()
+    nu_gpu, nodes = h.spread(n)
     c = recursive.count(m, n, b, split_m=False, max_strassen_depth=2)
     nu = plain.colnorms(A)
-    want = sum(emulate.spread_flags(nu, c.ata_list, tau))
-    assert rep["flagged_nodes"] == want and want > 0
+    # nu: FP64 sums of exact products of the FP32 inputs, in another order
+    assert np.allclose(nu_gpu, nu, rtol=1e-13, atol=0)
+    # the same AtA nodes, in the recursion's order
+    assert [(c0, w) for c0, w, _f in nodes] == [(c0, w) for c0, w, _leaf in c.ata_list]
+    got = [bool(f) for _c0, _w, f in nodes]
+    # the decision rule on the GPU's own norms is exact ...
+    assert got == emulate.spread_flags(np.asarray(nu_gpu), c.ata_list, tau)
+    # ... and the oracle's norms give the same flags (no node sits within
+    # rounding of the threshold here)
+    spreads = [emulate.spread(nu[c0:c0 + w]) for c0, w, _leaf in c.ata_list]
+    assert min(abs(sp / tau ** 2 - 1) for sp in spreads) > 1e-9
+    want = emulate.spread_flags(nu, c.ata_list, tau)
+    assert got == want
+    assert rep["flagged_nodes"] == sum(want) and 0 < sum(want) < len(want)
     err = full_error(Cp, plain.gram_packed(A))
     _say("  e_F", err, "flagged", want)
     assert err <= 2e-5
@@ -247,7 +262,7 @@ def test_persistent_leaf_launch_matches_grid(h, mode, tile):
     try:
         for (m, n, b, depth) in [(3000, 1100, 256, 2), (40000, 300, 300, 0)]:
             _say("case: persistent vs grid", mode, "tile", tile, m, n, b, depth)
-            A = rng.uniform(-1, 1, (m, n))
+            A = mode_input(rng.uniform(-1, 1, (m, n)), mode)
             h.set("leaf_cutoff", b)
             h.set("max_depth", depth)
             outs = []

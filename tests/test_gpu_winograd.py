@@ -12,7 +12,7 @@ import torch
 
 from oracle import plain
 from paper_2110_13042_amd import ata
-from gpu_helpers import device, full_error, run_gram
+from gpu_helpers import device, full_error, mode_input, run_gram
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_winograd_random_within_tolerance(h, mode, tol):
     Strassen form on the same plan is printed beside it."""
     rng = np.random.default_rng(92)
     for (m, n, b, depth) in [(2047, 1500, 256, 3), (3000, 2048, 512, 2), (5000, 900, 256, 2)]:
-        A = rng.uniform(-1, 1, (m, n))
+        A = mode_input(rng.uniform(-1, 1, (m, n)), mode)
         ref = plain.gram_packed(A)
         h.set("leaf_cutoff", b)
         h.set("max_depth", depth)
