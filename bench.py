@@ -4,8 +4,14 @@ One step = one ata_gram call: every phase of the plan (column norms and
 spread flags, Strassen pre-sums, all leaf products, combines) on a
 synthetic input already resident in HBM.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode f32|f64|bf16x3|fp8]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode bf16x3,f32,fp8]
                     [--workload NAME] [--no-cpu-baseline] [--autotune]
+
+The default workload is the precision configuration: A 16384 x 16384 with
+i.i.d. N(0,1) entries, split-BF16 as the headline with FP32 and FP8 beside
+it, errors measured on the workload's 256 sampled columns against the plain
+FP64 oracle.  A headline mode that misses its error bound has its value
+withheld (null) and the script exits with status 3.
 
 With --workload batch_512_uneven_f32 one step is one ata_gram_batched call
 over all 512 problems (one captured graph replay); the same problems issued
@@ -35,8 +41,6 @@ if ROOT not in sys.path:
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0, "fp8": 5033.2}
 MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "fp8": 3}
 TUNE_TABLE = os.path.join(ROOT, "paper_2110_13042_amd", "tune_table.json")
-DEFAULT_WORKLOAD = {"f64": "square_f64_1024", "f32": "square_f32_8192",
-                    "bf16x3": "square_f32_8192", "fp8": "square_f32_8192"}
 LEAF_KERNEL_FILES = ["paper_2110_13042_amd/csrc/leaf.hip", "paper_2110_13042_amd/csrc/kernels_common.hpp"]
 
 
@@ -72,21 +76,45 @@ def traffic_from_profiles(mode: str, workload: str):
         return None
 
 
-def cpu_baseline(A: np.ndarray, samples: int):
-    """The plain FP64 oracle on a bounded sample: `samples` full columns of C."""
-    from oracle import plain
+def sample_columns(wl: str, n: int, samples: int):
+    """Column sample for the error measure: the precision workload's own 256
+    columns (drawn from its generator right after A), else `samples` columns
+    from a separate seed."""
     from paper_2110_13042_amd import workloads
+    w = workloads.WORKLOADS[wl]
+    if wl == "normal_f32_16384":
+        return workloads.sampled_columns(n, 256, seed=w.seed, after_rows=w.rows, after_cols=w.cols), \
+            "the workload's 256 columns (seed 4, drawn after A)"
+    return workloads.sampled_columns(n, min(samples, n), seed=1234), f"{min(samples, n)} columns (seed 1234)"
+
+
+def cpu_baseline(A: np.ndarray, S, what: str, single_cols: int):
+    """The plain FP64 oracle on a bounded sample: full columns C[:, S], timed on
+    all host cores, and on one thread over the first `single_cols` of them."""
+    from oracle import plain
     m, n = A.shape
-    S = workloads.sampled_columns(n, min(samples, n), seed=1234)
     threads = plain.threads_used(0)
     t0 = time.perf_counter()
     cols = plain.gram_cols(A, S)
     dt = time.perf_counter() - t0
     flops = 2.0 * m * n * len(S)
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(S)} of {n} full columns of C (plain FP64 oracle, same A), "
+    one = None
+    if single_cols > 0:
+        S1 = S[:single_cols]
+        t1 = time.perf_counter()
+        c1 = plain.gram_cols(A, S1, nthreads=1)
+        dt1 = time.perf_counter() - t1
+        assert np.array_equal(c1, cols[:, :len(S1)])      # thread count does not change the bits
+        one = {"value": 2.0 * m * n * len(S1) / dt1 / 1e12, "unit": "TFLOP/s", "cores": plain.threads_used(1),
+               "sample": f"the first {len(S1)} of those columns, {dt1:.2f} s; full-problem time "
+                         f"extrapolates to {dt1 * (n + 1) / (2 * len(S1)):.0f} s"}
+    base = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(S)} of {n} full columns of C, {what} (plain FP64 oracle, same A), "
                       f"{dt:.2f} s; full-problem time extrapolates to "
-                      f"{dt * (n + 1) / (2 * len(S)):.1f} s"}, S, cols
+                      f"{dt * (n + 1) / (2 * len(S)):.1f} s"}
+    if one is not None:
+        base["single_thread"] = one
+    return base, cols
 
 
 def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
@@ -137,6 +165,7 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
     res = {
         "value": round(eff, 3), "ms_per_step": round(ms_per_step, 4), "dtype": mode,
         "frac_of_dtype_peak_effective": round(eff / peak, 4),
+        "frac_of_dtype_peak_executed": round(leaf_flops / (ms_per_step * 1e-3) / 1e12 / peak, 4),
         "plan": {"leaf_cutoff": rep["leaf_cutoff"], "strassen_levels": rep["strassen_levels"],
                  "multiplications": rep["multiplications"],
                  "mult_ratio_vs_syrk": round(rep["multiplications"] / (m * n * (n + 1) / 2), 4),
@@ -324,6 +353,23 @@ def main_batch(args, torch, ata, workloads, dev, modes) -> int:
     return 0
 
 
+TOLERANCE = {"f64": 1e-12, "f32": 2e-5, "bf16x3": 2e-5, "fp8": None}
+
+
+def gpu_sampled_error(ata, torch, dev, A_np, C, mode: str, S) -> float:
+    """FP64 error of C on the sampled columns, computed on the GPU (the
+    library's column check), for runs without the CPU oracle."""
+    tdt = torch.float64 if mode == "f64" else torch.float32
+    A = torch.from_numpy(A_np).to(dev, tdt)
+    m, n = A_np.shape
+    h = ata.Handle()
+    try:
+        return ata.ata_check_columns(h.h, A.data_ptr(), m, n, n, MODES[mode], C.data_ptr(), S,
+                                     torch.cuda.current_stream(dev).cuda_stream)
+    finally:
+        h.close()
+
+
 def sampled_error(C, n: int, S, cols) -> float:
     Cp = C.double().cpu().numpy()
     ii = np.arange(n)[:, None]
@@ -338,9 +384,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="bf16x3,f32",
+    ap.add_argument("--mode", default="bf16x3,f32,fp8",
                     help="comma list; the first is the headline, the rest are reported beside it")
-    ap.add_argument("--workload", default="square_f32_8192")
+    ap.add_argument("--workload", default="normal_f32_16384")
     ap.add_argument("--leaf-cutoff", type=int, default=0)
     ap.add_argument("--max-depth", type=int, default=-1)
     ap.add_argument("--leaf-tile", type=int, default=-1,
@@ -351,7 +397,10 @@ def main() -> int:
                     help="FP32 family: column equilibration instead of the FP64 fallback")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=4096,
-                    help="full columns of C the CPU oracle computes for the baseline and the error sample")
+                    help="full columns of C the CPU oracle computes for the baseline and the error sample "
+                         "(the 16384^2 precision workload always takes its own 256 columns)")
+    ap.add_argument("--single-thread-cols", type=int, default=32,
+                    help="columns of that sample the oracle also computes on one thread (0: skip)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune leaf cutoff / depth / tile for the workload before the warmup (untimed)")
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table loaded into the handle")
@@ -375,8 +424,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the "
-              "multi-GPU sharding is described in DESIGN.md but not implemented", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library computes one "
+              "Gram product per GPU and does not shard rows or output tiles across GPUs", file=sys.stderr)
         return 2
 
     import torch
@@ -415,29 +464,48 @@ def main() -> int:
         torch.cuda.synchronize()
         print("[bench] copy calibration: 3 x copy of 1 GiB", file=sys.stderr, flush=True)
     base = None
+    S, what = sample_columns(wl, n, args.cpu_samples)
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline on a column sample", file=sys.stderr, flush=True)
-        base, S, cols = cpu_baseline(A_np, args.cpu_samples)
+        base, cols = cpu_baseline(A_np, S, what, args.single_thread_cols)
         for md in modes:
             results[md]["rel_error_sampled_columns"] = sampled_error(outs[md], n, S, cols)
+            results[md]["error_reference"] = "plain FP64 oracle (CPU)"
+    else:
+        for md in modes:
+            results[md]["rel_error_sampled_columns"] = gpu_sampled_error(ata, torch, dev, A_np, outs[md], md, S)
+            results[md]["error_reference"] = "FP64 column check on the GPU (ata_check_columns)"
+    for md in modes:
+        err, tol = results[md]["rel_error_sampled_columns"], TOLERANCE[md]
+        results[md]["error_sample"] = what
+        results[md]["tolerance"] = tol
+        results[md]["within_tolerance"] = None if tol is None else bool(err <= tol)
     head = results[modes[0]]
+    failing = head["within_tolerance"] is False
+    if failing:
+        print(f"[bench] the headline mode {modes[0]} misses its error bound "
+              f"({head['rel_error_sampled_columns']:.3e} > {TOLERANCE[modes[0]]}): value withheld",
+              file=sys.stderr, flush=True)
     out = {
         "metric": "effective TFLOP/s m*n*(n+1)/t of C = A^T A (AtA, packed lower); "
                   "split-BF16 x3 vs FP32, each at <= 2e-5 relative error",
-        "value": head["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "value": None if failing else head["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": modes[0], "data": "synthetic",
         "config": {"workload": wl, "m": m, "n": n, "description": w.description,
                    "plan": head["plan"], "phase_ms_per_step": head["phase_ms_per_step"],
                    "frac_of_dtype_peak_effective": head["frac_of_dtype_peak_effective"],
-                   "rel_error_sampled_columns": head.get("rel_error_sampled_columns")},
+                   "frac_of_dtype_peak_executed": head["frac_of_dtype_peak_executed"],
+                   "rel_error_sampled_columns": head["rel_error_sampled_columns"],
+                   "error_reference": head["error_reference"], "error_sample": head["error_sample"],
+                   "tolerance": head["tolerance"], "within_tolerance": head["within_tolerance"]},
         "roofline": head["roofline"],
         "side_by_side": {md: results[md] for md in modes[1:]},
     }
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
-    return 0
+    return 3 if failing else 0
 
 
 if __name__ == "__main__":

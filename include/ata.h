@@ -53,7 +53,7 @@ typedef struct ata_ctx* ata_handle_t;
 typedef enum {
     ATA_OK = 0,
     ATA_ERR_INVALID_VALUE = 1,   /* bad argument: nothing enqueued            */
-    ATA_ERR_NOT_SUPPORTED = 2,   /* valid request this build cannot serve     */
+    ATA_ERR_NOT_SUPPORTED = 2,   /* valid request the library cannot serve    */
     ATA_ERR_OUT_OF_MEMORY = 3,   /* workspace above the limit or hipMalloc failed */
     ATA_ERR_HIP = 4,             /* a HIP runtime call failed                 */
     ATA_ERR_INTERNAL = 5

@@ -7,7 +7,7 @@ and Sec. 3.2 in the paper's order and notation, with counters for the
 operations it performs.  Library matrix products stand in for the BLAS leaves
 (``?syrk`` for AtA leaves, ``?gemm`` for Strassen leaves), as in the paper.
 
-Readings of the paper used here (each one is also listed in the design doc):
+Readings of the paper used here:
 
 * Partition (Eq. "submatA"): m1 = floor(m/2), m2 = ceil(m/2), n1 = floor(n/2),
   n2 = ceil(n/2); the leading blocks are the floor-sized ones; the fourth
