@@ -234,8 +234,11 @@ typedef struct {
     int32_t pad_;
 } ata_leaf_t;
 
-/* Create a handle bound to the current HIP device.  Returns ATA_ERR_HIP when
-   no device is usable.  *out is set to NULL on failure. */
+/* Create a handle bound to the current HIP device.  The first handle on a
+   device also looks up that device's address of the static workspace of
+   ata_gram_noalloc (which loads the library's code object there).  Returns
+   ATA_ERR_HIP when no device is usable or the lookup fails.  *out is set to
+   NULL on failure. */
 ata_status_t ata_create(ata_handle_t* out);
 
 /* Destroy a handle and free its device memory.  No work that uses the handle
@@ -258,6 +261,39 @@ ata_status_t ata_destroy(ata_handle_t h);
 ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n,
                       int64_t lda, ata_dtype_t dtype, void* C_packed,
                       void* stream);
+
+/* Size in bytes of the static device workspace of ata_gram_noalloc: one
+   array per GPU in the library's code object, allocated when the code
+   object is loaded on that GPU (at the first ata_create there) and held until
+   the process ends. */
+#define ATA_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory (code under stream capture,
+   tight serving loops, harnesses that forbid hipMalloc): ata_gram with every
+   workspace buffer (plan descriptors, Strassen sums and products, packed
+   operands, split-K partials, column norms, spread flags, queue heads) in the
+   GPU's static ATA_NOALLOC_SCRATCH_BYTES array.  The call allocates no device
+   or pinned memory and calls no allocating library routine; it copies the
+   plan's descriptors into the array on `stream` (hipMemcpyAsync from host
+   memory the handle keeps) and then enqueues the same kernels as ata_gram.
+   Arguments, layout, output and argument errors are ata_gram's.  The plan is
+   ata_gram's for the same handle options, with the Strassen depth lowered
+   (then split-K and tail cuts dropped) until its workspace fits the array;
+   results equal ata_gram's whenever the plans agree.  Returns
+   ATA_ERR_OUT_OF_MEMORY, with nothing enqueued and C untouched, when even
+   that plan does not fit (for example split-BF16 needs 4 bytes per element
+   of A for its packed operands), or exceeds ATA_OPT_WORKSPACE_LIMIT; and
+   ATA_ERR_NOT_SUPPORTED when the handle has ATA_OPT_EQUILIBRATE or
+   ATA_OPT_RESIDUAL set.  ATA_OPT_PROFILE is ignored, and the report's
+   flagged-node count and residual are not available (-1).
+   Every call on one GPU shares that GPU's array and leaves its contents
+   there: calls that may overlap on one GPU (different streams, handles or
+   threads without ordering between them) race and must be serialised by the
+   caller; calls in order on one stream are safe.  The queue heads the leaf
+   launch needs at zero are cleared by a kernel on `stream` in every call. */
+ata_status_t ata_gram_noalloc(ata_handle_t h, const void* A, int64_t m, int64_t n,
+                              int64_t lda, ata_dtype_t dtype, void* C_packed,
+                              void* stream);
 
 /* batch independent Gram products, C_packed[i] = lower(A[i]^T A[i]), of
    uneven shapes.  Every problem's plan is merged into one: each phase is a

@@ -88,6 +88,7 @@ def lib() -> ctypes.CDLL:
     L.ata_create.argtypes = [ctypes.POINTER(vp)]
     L.ata_destroy.argtypes = [vp]
     L.ata_gram.argtypes = [vp, vp, i64, i64, i64, st, vp, vp]
+    L.ata_gram_noalloc.argtypes = [vp, vp, i64, i64, i64, st, vp, vp]
     L.ata_gram_batched.argtypes = [vp, i64, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                    ctypes.POINTER(i64), ctypes.POINTER(i64), st,
                                    ctypes.POINTER(vp), vp]
@@ -112,7 +113,7 @@ def lib() -> ctypes.CDLL:
                                  ctypes.POINTER(i64)]
     L.ata_status_string.argtypes = [st]
     L.ata_status_string.restype = ctypes.c_char_p
-    for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_batched", "ata_set_option",
+    for name in ("ata_create", "ata_destroy", "ata_gram", "ata_gram_noalloc", "ata_gram_batched", "ata_set_option",
                  "ata_get_report", "ata_plan_query", "ata_residual", "ata_check_columns", "ata_autotune",
                  "ata_autotune_batched",
                  "ata_gemm_tn", "ata_gram_scaled", "ata_gram_aat", "ata_unpack",
@@ -146,6 +147,13 @@ def ata_destroy(h: int) -> None:
 
 def ata_gram(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, stream: int = 0) -> None:
     _check(lib().ata_gram(h, A, m, n, lda, dtype, C, stream), "ata_gram")
+
+
+def ata_gram_noalloc(h: int, A: int, m: int, n: int, lda: int, dtype: int, C: int, stream: int = 0) -> None:
+    _check(lib().ata_gram_noalloc(h, A, m, n, lda, dtype, C, stream), "ata_gram_noalloc")
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20      # ATA_NOALLOC_SCRATCH_BYTES
 
 
 def batch_arrays(A_ptrs, ms, ns, ldas, C_ptrs):

@@ -13,6 +13,7 @@
 #include <string>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <tuple>
@@ -147,6 +148,39 @@ struct BatchEntry {
     }
 };
 
+// A plan of ata_gram_noalloc: descriptors, arena and auxiliary block laid
+// out in the device's static workspace, the descriptor blob on the host.
+struct StaticPlan {
+    DevicePlan dp;                     // d_buf stays null: nothing is owned
+    std::vector<unsigned char> blob;   // descriptor bytes, copied in by every call
+    size_t arena_off = 0, aux_off = 0, total = 0;
+};
+
+// The static workspace of ata_gram_noalloc.  Host code never uses this name
+// as an address (on the host it is only a stand-in for the symbol): each
+// device's address comes from hipGetSymbolAddress at the first ata_create on
+// that device and is kept in scratch_base.
+static __device__ __align__(256) unsigned char scratch[ATA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+unsigned char* scratch_base[kMaxDevices] = {};
+
+// This device's address of the static workspace (looked up once; the caller
+// has made the device current).
+ata_status_t scratch_address(int dev, unsigned char*& out) {
+    out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return ATA_ERR_NOT_SUPPORTED;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_base[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return ATA_ERR_HIP;
+        scratch_base[dev] = static_cast<unsigned char*>(ptr);
+    }
+    out = scratch_base[dev];
+    return ATA_OK;
+}
+
 }  // namespace
 
 struct ata_ctx {
@@ -212,6 +246,10 @@ struct ata_ctx {
     const double* spread_nu = nullptr;
     const uint8_t* spread_flags = nullptr;
     hipStream_t spread_stream = nullptr;
+    // ata_gram_noalloc: this device's static workspace and the plans laid out
+    // in it (descriptor blobs kept on the host, copied in by every call)
+    unsigned char* scratch = nullptr;
+    std::map<PlanKey, std::unique_ptr<StaticPlan>> static_plans;
 };
 
 namespace {
@@ -274,7 +312,10 @@ ata_status_t ensure(ata_ctx* h, void*& ptr, size_t& cap, size_t bytes) {
     return ATA_OK;
 }
 
-ata_status_t upload_plan(DevicePlan& dp) {
+// Lay the plan's descriptor arrays out in one blob (each array 256-byte
+// aligned) and point the DevicePlan's device arrays at `base` plus their
+// offsets.  The blob goes to `host`; returns its size in bytes.
+size_t layout_descriptors(DevicePlan& dp, unsigned char* base, std::vector<unsigned char>& host) {
     const Plan& p = dp.plan;
     size_t bytes = align256(p.leaves.size() * sizeof(LeafDesc));
     for (auto& l : p.presum) bytes += align256(l.size() * sizeof(PresumDesc));
@@ -286,16 +327,13 @@ ata_status_t upload_plan(DevicePlan& dp) {
     bytes += align256(p.col1.size() * sizeof(ColDesc));
     bytes += align256(p.col2.size() * sizeof(ColDesc));
     bytes += align256(p.reduce.size() * sizeof(ReduceDesc));
-    if (bytes == 0) return ATA_OK;
-    std::vector<unsigned char> host(bytes, 0);
-    if (hipMalloc(&dp.d_buf, bytes) != hipSuccess) {
-        dp.d_buf = nullptr;
-        return ATA_ERR_OUT_OF_MEMORY;
-    }
+    host.assign(bytes, 0);
+    dp.d_presum.clear();
+    dp.d_combine.clear();
     size_t off = 0;
     auto put = [&](const void* src, size_t n) {
-        std::memcpy(host.data() + off, src, n);
-        void* d = static_cast<unsigned char*>(dp.d_buf) + off;
+        if (n) std::memcpy(host.data() + off, src, n);
+        void* d = base + off;
         off += align256(n);
         return d;
     };
@@ -309,6 +347,18 @@ ata_status_t upload_plan(DevicePlan& dp) {
     dp.d_col1 = static_cast<ColDesc*>(put(p.col1.data(), p.col1.size() * sizeof(ColDesc)));
     dp.d_col2 = static_cast<ColDesc*>(put(p.col2.data(), p.col2.size() * sizeof(ColDesc)));
     dp.d_reduce = static_cast<ReduceDesc*>(put(p.reduce.data(), p.reduce.size() * sizeof(ReduceDesc)));
+    return bytes;
+}
+
+ata_status_t upload_plan(DevicePlan& dp) {
+    std::vector<unsigned char> host;
+    const size_t bytes = layout_descriptors(dp, nullptr, host);
+    if (bytes == 0) return ATA_OK;
+    if (hipMalloc(&dp.d_buf, bytes) != hipSuccess) {
+        dp.d_buf = nullptr;
+        return ATA_ERR_OUT_OF_MEMORY;
+    }
+    layout_descriptors(dp, static_cast<unsigned char*>(dp.d_buf), host);
     return hip_status(hipMemcpy(dp.d_buf, host.data(), bytes, hipMemcpyHostToDevice));
 }
 
@@ -393,6 +443,37 @@ bool fits_device(const ata_ctx* h, const Plan& p) {
     return need + (double)(1ull << 30) <= (double)free_b + (double)h->arena_cap;
 }
 
+// The plan of one Gram product for a plan-cache key, with the Strassen depth
+// lowered one level at a time until `fits` accepts the plan (a plan without
+// Strassen levels is returned whether it fits or not).
+template <class Fits>
+ata_status_t build_gram_plan(const ata_ctx* h, const PlanKey& k, Fits fits, Plan& out) {
+    PlanOptions o;
+    o.leaf_cutoff = k.b;
+    o.max_depth = k.depth;
+    o.spread_tau = k.fb ? h->popt.spread_tau : 0.0;
+    o.tile_cfg = k.tile_cfg;
+    o.split_target = k.split;
+    o.fuse_presum = k.fuse;
+    o.variant = k.variant;
+    o.slots = k.slots;
+    try {
+        out = make_plan(k.mode, k.m, k.n, k.lda, o);
+        while (out.stats.max_levels > 0 && !fits(out)) {
+            o.max_depth = out.stats.max_levels - 1;
+            out = make_plan(k.mode, k.m, k.n, k.lda, o);
+        }
+        if (out.fallback) fuse_pack_into_norms(out, out.col1);
+    } catch (const std::invalid_argument&) {
+        return ATA_ERR_INVALID_VALUE;
+    } catch (const std::length_error&) {
+        return ATA_ERR_NOT_SUPPORTED;
+    } catch (const std::exception&) {
+        return ATA_ERR_INTERNAL;
+    }
+    return ATA_OK;
+}
+
 // Resident leaf workgroups of the device (256 CUs) for the tail balancer,
 // or 0 when it is off.
 int64_t tail_slots(const ata_ctx* h, int32_t mode, int32_t tile_cfg) {
@@ -447,6 +528,10 @@ ata_status_t ata_create(ata_handle_t* out) {
     if (!h) return ATA_ERR_OUT_OF_MEMORY;
     h->device = dev;
     h->popt.tile_cfg = -1;                 // automatic: autotune table, else by shape
+    if (dev < kMaxDevices && scratch_address(dev, h->scratch) != ATA_OK) {
+        delete h;
+        return ATA_ERR_HIP;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) h->arch = prop.gcnArchName;
     *out = h;
@@ -605,6 +690,79 @@ ata_status_t take_events(ata_ctx* h, hipEvent_t*& ev) {
 
 namespace {
 
+// Enqueue every phase of a single-problem plan on `st`: column norms and
+// spread flags, pre-sums level by level, packing or quantisation, the leaf
+// launch, the FP64 fallback, the split-K reduce, the combines bottom-up, and
+// the optional residual probe.  `arena` and `aux` (laid out by aux_layout)
+// are the call's workspace; `ev` holds six profiling events or is null.
+hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, void* C_packed, void* arena,
+                        unsigned char* aux, const AuxLayout& ax, bool residual, hipStream_t st, hipEvent_t* ev,
+                        bool& persistent) {
+    const Plan& p = dp.plan;
+    const int32_t mode = p.mode;
+    BatchPtrs pq{nullptr, nullptr, reinterpret_cast<unsigned long long*>(aux + ax.counter_off), 0};
+    const BatchPtrs* lp = nullptr;
+    if (persistent_for(h->leaf_persistent, p)) {
+        pq.persistent_blocks = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
+        lp = &pq;
+    }
+    persistent = lp != nullptr;
+    uint8_t* flags = aux + ax.flags_off;
+    double* partial = reinterpret_cast<double*>(aux + ax.part_off);
+    double* nu = reinterpret_cast<double*>(aux + ax.nu_off);
+    double* res_work = reinterpret_cast<double*>(aux + ax.res_work_off);
+    double* res = reinterpret_cast<double*>(aux + ax.res_off);
+    hipError_t e = hipSuccess;
+    auto mark = [&](int i) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
+    };
+    mark(0);
+    if (p.fallback) {
+        e = launch_colnorms(dp.d_col1, (int)p.col1.size(), p.col1.back().elem_begin + p.col1.back().elems,
+                            dp.d_col2, (int)p.col2.size(), p.col2.back().elem_begin + p.col2.back().elems,
+                            static_cast<const float*>(A), nullptr, partial, nu, st, arena, has_pack(p.col1));
+        if (e == hipSuccess)
+            e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
+    }
+    mark(1);
+    for (size_t l = 0; e == hipSuccess && l < p.presum.size(); ++l) {
+        const auto& lv = p.presum[l];
+        e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
+                          A, arena, flags, st);
+    }
+    if (e == hipSuccess && !p.pack.empty())
+        e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
+                        A, arena, flags, st);
+    if (e == hipSuccess && !p.pack8.empty())
+        e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems,
+                          A, arena, flags, st);
+    mark(2);
+    if (e == hipSuccess)
+        e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, arena,
+                          flags, h->chunk, h->band, st, lp);
+    if (e == hipSuccess && !p.fb_leaves.empty())
+        e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
+                                   arena, flags, h->chunk, h->band, st);
+    if (e == hipSuccess && !p.reduce.empty())
+        e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
+                          C_packed, arena, flags, st);
+    mark(3);
+    for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
+        const auto& lv = p.combine[l];
+        e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
+                           C_packed, arena, flags, st);
+    }
+    mark(4);
+    if (e == hipSuccess && residual)
+        e = launch_residual(mode, A, p.m, p.n, p.lda, C_packed, h->seed, res_work, res, st);
+    mark(5);
+    return e;
+}
+
+}  // namespace
+
+namespace {
+
 // Column equilibration (an alternative to the FP64 fallback for ill-scaled
 // columns): scale column j by 2^-e_j so that every column norm lies in
 // [0.5, 1), run the plan on the scaled copy (no spread check needed: the
@@ -695,31 +853,10 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
-        PlanOptions o;
-        o.leaf_cutoff = b;
-        o.max_depth = depth;
-        o.spread_tau = fb ? h->popt.spread_tau : 0.0;
-        o.tile_cfg = tile_cfg;
-        o.split_target = h->split_target;
-        o.fuse_presum = h->popt.fuse_presum;
-        o.variant = h->popt.variant;
-        o.slots = slots;
-        try {
-            dp->plan = make_plan(mode, m, n, lda, o);
-            while (dp->plan.stats.max_levels > 0 && !fits_device(h, dp->plan)) {
-                o.max_depth = dp->plan.stats.max_levels - 1;
-                dp->plan = make_plan(mode, m, n, lda, o);
-            }
-            if (dp->plan.fallback) fuse_pack_into_norms(dp->plan, dp->plan.col1);
-        } catch (const std::invalid_argument&) {
-            return ATA_ERR_INVALID_VALUE;
-        } catch (const std::length_error&) {
-            return ATA_ERR_NOT_SUPPORTED;
-        } catch (const std::exception&) {
-            return ATA_ERR_INTERNAL;
-        }
-        const ata_status_t s = upload_plan(*dp);
+        const ata_status_t s = build_gram_plan(h, key, [h](const Plan& q) { return fits_device(h, q); }, dp->plan);
         if (s != ATA_OK) return s;
+        const ata_status_t su = upload_plan(*dp);
+        if (su != ATA_OK) return su;
         it = h->plans.emplace(key, std::move(dp)).first;
     }
     DevicePlan& dp = *it->second;
@@ -736,79 +873,112 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     unsigned char* aux = static_cast<unsigned char*>(h->aux);
-    BatchPtrs pq{nullptr, nullptr, reinterpret_cast<unsigned long long*>(aux + ax.counter_off), 0};
-    const BatchPtrs* lp = nullptr;
-    if (persistent_for(h->leaf_persistent, p)) {
-        pq.persistent_blocks = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
-        lp = &pq;
-    }
-    uint8_t* flags = aux + ax.flags_off;
-    double* partial = reinterpret_cast<double*>(aux + ax.part_off);
-    double* nu = reinterpret_cast<double*>(aux + ax.nu_off);
-    double* res_work = reinterpret_cast<double*>(aux + ax.res_work_off);
-    double* res = reinterpret_cast<double*>(aux + ax.res_off);
-    hipError_t e = hipSuccess;
     hipEvent_t* ev = nullptr;
     if (take_events(h, ev) != ATA_OK) return ATA_ERR_HIP;
-    auto mark = [&](int i) {
-        if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
-    };
-    mark(0);
-    if (p.fallback) {
-        e = launch_colnorms(dp.d_col1, (int)p.col1.size(), p.col1.back().elem_begin + p.col1.back().elems,
-                            dp.d_col2, (int)p.col2.size(), p.col2.back().elem_begin + p.col2.back().elems,
-                            static_cast<const float*>(A), nullptr, partial, nu, st, h->arena, has_pack(p.col1));
-        if (e == hipSuccess)
-            e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
-    }
-    mark(1);
-    for (size_t l = 0; e == hipSuccess && l < p.presum.size(); ++l) {
-        const auto& lv = p.presum[l];
-        e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
-                          A, h->arena, flags, st);
-    }
-    if (e == hipSuccess && !p.pack.empty())
-        e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
-                        A, h->arena, flags, st);
-    if (e == hipSuccess && !p.pack8.empty())
-        e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems,
-                          A, h->arena, flags, st);
-    mark(2);
-    if (e == hipSuccess)
-        e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, h->arena,
-                          flags, h->chunk, h->band, st, lp);
-    if (e == hipSuccess && !p.fb_leaves.empty())
-        e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
-                                   h->arena, flags, h->chunk, h->band, st);
-    if (e == hipSuccess && !p.reduce.empty())
-        e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
-                          C_packed, h->arena, flags, st);
-    mark(3);
-    for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
-        const auto& lv = p.combine[l];
-        e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
-                           C_packed, h->arena, flags, st);
-    }
-    mark(4);
-    if (e == hipSuccess && h->residual)
-        e = launch_residual(mode, A, m, n, lda, C_packed, h->seed, res_work, res, st);
-    mark(5);
-    if (e != hipSuccess) return ATA_ERR_HIP;
+    bool persistent = false;
+    if (enqueue_gram(h, dp, A, C_packed, h->arena, aux, ax, h->residual, st, ev, persistent) != hipSuccess)
+        return ATA_ERR_HIP;
 
     fill_report(h->report, p);
-    h->report.leaf_persistent = lp ? 1 : 0;
+    h->report.leaf_persistent = persistent ? 1 : 0;
     h->last_stream = st;
     h->pending_flags = p.fallback;
     h->pending_residual = h->residual;
-    h->last_flags = flags;
-    h->last_residual = res;
+    h->last_flags = aux + ax.flags_off;
+    h->last_residual = reinterpret_cast<double*>(aux + ax.res_off);
     h->last_nodes = (int64_t)p.nodes.size();
     if (p.fallback) {
         h->spread_plan = &dp;
-        h->spread_nu = nu;
-        h->spread_flags = flags;
+        h->spread_nu = reinterpret_cast<double*>(aux + ax.nu_off);
+        h->spread_flags = aux + ax.flags_off;
         h->spread_stream = st;
     }
+    return ATA_OK;
+}
+
+namespace {
+
+// Lay a plan out in the static workspace: descriptors, then the arena, then
+// the auxiliary block.  Returns the bytes it needs.
+size_t layout_static(StaticPlan& sp, unsigned char* base) {
+    const Plan& p = sp.dp.plan;
+    const size_t desc = align256(layout_descriptors(sp.dp, base, sp.blob));
+    sp.arena_off = desc;
+    sp.aux_off = sp.arena_off + align256((size_t)p.arena_elems * (size_t)p.elem_bytes());
+    sp.total = sp.aux_off + aux_layout(p, false).total;
+    return sp.total;
+}
+
+}  // namespace
+
+ata_status_t ata_gram_noalloc(ata_handle_t h, const void* A, int64_t m, int64_t n, int64_t lda,
+                              ata_dtype_t dtype, void* C_packed, void* stream) {
+    if (!h || !valid_dtype(dtype) || m < 0 || n < 0 || lda < std::max<int64_t>(1, n))
+        return ATA_ERR_INVALID_VALUE;
+    if (n > 0 && !C_packed) return ATA_ERR_INVALID_VALUE;
+    if (n > 0 && m > 0 && !A) return ATA_ERR_INVALID_VALUE;
+    const size_t es = dtype == ATA_F64 ? 8 : 4;
+    if (n > 0 && m > 0) {
+        const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (size_t)((m - 1) * lda + n) * es;
+        const uintptr_t c0 = (uintptr_t)C_packed, c1 = c0 + (size_t)(n * (n + 1) / 2) * es;
+        if (a0 < c1 && c0 < a1) return ATA_ERR_INVALID_VALUE;
+    }
+    const int32_t mode = (int32_t)dtype;
+    if (h->residual || (h->equilibrate && mode != MODE_F64)) return ATA_ERR_NOT_SUPPORTED;
+    h->report = ata_report_t{};
+    h->report.m = m;
+    h->report.lda = lda;
+    h->report.dtype = dtype;
+    h->report.flagged_nodes = -1;
+    h->report.residual = -1.0;
+    h->pending_flags = h->pending_residual = false;
+    h->spread_plan = nullptr;
+    if (n == 0) return ATA_OK;
+    if (!h->scratch) return ATA_ERR_NOT_SUPPORTED;
+    if (hipSetDevice(h->device) != hipSuccess) return ATA_ERR_HIP;
+    int64_t b;
+    int32_t depth, tile_cfg;
+    choose(h, mode, m, n, b, depth, tile_cfg);
+    const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
+    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
+                      h->popt.variant, tail_slots(h, mode, tile_cfg)};
+    const size_t limit = h->ws_limit > 0 ? std::min<size_t>((size_t)h->ws_limit, ATA_NOALLOC_SCRATCH_BYTES)
+                                         : (size_t)ATA_NOALLOC_SCRATCH_BYTES;
+    auto it = h->static_plans.find(key);
+    if (it == h->static_plans.end()) {
+        auto sp = std::make_unique<StaticPlan>();
+        auto fits = [&](const Plan& q) {
+            StaticPlan t;
+            t.dp.plan = q;
+            return layout_static(t, h->scratch) <= limit;
+        };
+        ata_status_t s = build_gram_plan(h, key, fits, sp->dp.plan);
+        if (s != ATA_OK) return s;
+        if (!fits(sp->dp.plan) && (key.split != 0 || key.slots != 0)) {
+            // without split-K partials and tail cuts
+            PlanKey k2 = key;
+            k2.split = 0;
+            k2.slots = 0;
+            s = build_gram_plan(h, k2, fits, sp->dp.plan);
+            if (s != ATA_OK) return s;
+        }
+        if (layout_static(*sp, h->scratch) > limit) return ATA_ERR_OUT_OF_MEMORY;
+        it = h->static_plans.emplace(key, std::move(sp)).first;
+    }
+    StaticPlan& sp = *it->second;
+    const Plan& p = sp.dp.plan;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned char* aux = h->scratch + sp.aux_off;
+    hipError_t e = hipSuccess;
+    if (!sp.blob.empty())
+        e = hipMemcpyAsync(h->scratch, sp.blob.data(), sp.blob.size(), hipMemcpyHostToDevice, st);
+    bool persistent = false;
+    if (e == hipSuccess)
+        e = enqueue_gram(h, sp.dp, A, C_packed, h->scratch + sp.arena_off, aux, aux_layout(p, false), false, st,
+                         nullptr, persistent);
+    if (e != hipSuccess) return ATA_ERR_HIP;
+    fill_report(h->report, p);
+    h->report.leaf_persistent = persistent ? 1 : 0;
     return ATA_OK;
 }
 
