@@ -52,29 +52,17 @@ constexpr int MODE_FP8_WIDE = 104;
 constexpr int MODE_F32_WIDE = 105;
 constexpr int MODE_F32_WIDE8 = 106;
 constexpr int MODE_BF16X3_WIDE8 = 107;
-#ifndef ATA_WIDE_STAGES
-#define ATA_WIDE_STAGES 4     // LDS ring depth of the 256 x 256 split-BF16 engine (32 KB each)
-#endif
-#ifndef ATA_F32W8_SK
-#define ATA_F32W8_SK 32       // rows per slab of the eight-wave FP32 engine
-#endif
-#ifndef ATA_F32W8_ST
-#define ATA_F32W8_ST 2        // its LDS stages (72 KB each)
-#endif
-#ifndef ATA_F32W_STAGES
-#define ATA_F32W_STAGES 3
-#endif
-#ifndef ATA_F32W_RS
-#define ATA_F32W_RS 288
-#endif
+constexpr int WIDE_STAGES = 4;  // LDS ring depth of the 256 x 256 split-BF16 engines (32 KB each)
+constexpr int F32W8_SK = 32;    // rows per slab of the eight-wave FP32 engine
+constexpr int F32W8_ST = 2;     // its LDS stages (72 KB each)
 // Geometry of the FP32 256 x 256 engine (tile_f32_wide).
 namespace wide32 {
 constexpr int TM = 256, TN = 256;
 constexpr int SK = 16;                        // rows per slab
-constexpr int RS = ATA_F32W_RS;               // LDS row stride in floats
+constexpr int RS = 288;                       // LDS row stride in floats
 constexpr int HALF = SK * RS * 4;             // one operand's slab: 18 KB
 constexpr int STAGE = 2 * HALF;
-constexpr int STAGES = ATA_F32W_STAGES;       // slabs kt .. kt + STAGES - 2 are in flight
+constexpr int STAGES = 3;                     // slabs kt .. kt + STAGES - 2 are in flight
 // s_waitcnt immediate: vmcnt(v) with lgkmcnt(l) (expcnt unconstrained)
 constexpr int waitcnt_imm(int v, int l) { return (v & 15) | ((v >> 4) << 14) | 0x70 | (l << 8); }
 // loads a wave may still have in flight once slab kt + 1 has landed
@@ -85,11 +73,11 @@ constexpr size_t lds_bytes(int mode) {
     return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 40 * 2
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
-           : mode == MODE_BF16X3_WIDE ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
+           : mode == MODE_BF16X3_WIDE ? (size_t)WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
            : mode == MODE_F32_WIDE ? (size_t)(wide32::STAGES * wide32::STAGE > 8 * wide32::HALF ? wide32::STAGES * wide32::STAGE : 8 * wide32::HALF)
-           : mode == MODE_F32_WIDE8 ? (size_t)ATA_F32W8_ST * 2 * ATA_F32W8_SK * wide32::RS * 4
-           : mode == MODE_BF16X3_WIDE8 ? (size_t)ATA_WIDE_STAGES * 4 * 2 * 256 * 16
+           : mode == MODE_F32_WIDE8 ? (size_t)F32W8_ST * 2 * F32W8_SK * wide32::RS * 4
+           : mode == MODE_BF16X3_WIDE8 ? (size_t)WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
 constexpr int threads_for(int mode) {
@@ -967,7 +955,7 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
 // past the packed arrays (and whole groups past K) return zero.
 namespace wide {
 constexpr int TM = 256, TN = 256;
-constexpr int STAGES = ATA_WIDE_STAGES;
+constexpr int STAGES = WIDE_STAGES;
 constexpr int ARR = 2 * 256 * 16;             // bytes of one operand half in a stage
 constexpr int STAGE = 4 * ARR;                // 32 KB
 constexpr size_t LDS = (size_t)STAGES * STAGE;
@@ -1624,7 +1612,7 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                           static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_F32_WIDE8) {
         if (flagged) return;
-        tile_f32_wide8<ATA_F32W8_SK, ATA_F32W8_ST>(d, view_ptr<float>(d.X, Aptr, args.B, args.arena),
+        tile_f32_wide8<F32W8_SK, F32W8_ST>(d, view_ptr<float>(d.X, Aptr, args.B, args.arena),
                                                   view_ptr<float>(d.Y, Aptr, args.B, args.arena), ti, tj,
                                                   static_cast<float*>(Cptr), static_cast<float*>(args.arena), smem,
                                                   kr);

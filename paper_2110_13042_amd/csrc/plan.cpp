@@ -29,8 +29,8 @@ int32_t default_leaf_tile(int32_t mode, int64_t m, int64_t n) {
 int32_t default_max_depth(int32_t mode, int64_t m) {
     // Strassen's rounding error adds to the contraction's own, which grows
     // with m: long contractions get no Strassen level in the FP32 family
-    // (measured: one level on 262144-row FP32 products with equilibrated
-    // columns reaches 2.1e-5 normwise, against 1.6e-7 without)
+    // (measured on 262144 x 4096 FP32 with equilibrated columns: one level
+    // reaches 2.1e-5 normwise on sampled columns, against 1.2e-5 without)
     const bool long_k = m >= 65536;
     switch (mode) {
         case MODE_F64: return 64;
