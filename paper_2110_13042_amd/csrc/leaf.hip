@@ -782,7 +782,6 @@ struct BfCfg {
 };
 using BfSmall = BfCfg<2, 2, 2, 2, 4>;   // 128 x 128, 4 waves, 80 KB LDS (two workgroups per CU)
 using BfLarge = BfCfg<2, 2, 4, 2, 4>;   // 256 x 128, 4 waves, 120 KB LDS
-using BfHuge = BfCfg<2, 4, 4, 2, 2>;    // 256 x 256, 8 waves, 16-row slabs, 96 KB LDS
 
 template <class CFG>
 __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, int tj,
@@ -939,6 +938,181 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
             for (int v = 0; v < 16; ++v) {
                 const int r = wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int cc = wn * BNB * 32 + b * 32 + (lane & 31);
+                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
+            }
+}
+
+// Split-BF16 x3 with a 256 x 256 tile on eight waves (2 x 4) of 128 x 64
+// (4 x 2 blocks of 32 x 32, 128 accumulators per lane), two waves per SIMD.
+// Each 16-row slab is one MFMA k step.  The K loop is software-pipelined so
+// that the matrix pipe never waits on LDS after the per-slab barrier:
+//   - the fragments of slab kt + 1 are read while slab kt's MFMAs run, each
+//     fragment register being refilled as soon as the pass that reads it has
+//     been issued (pass 1: lo(X) hi(Y); pass 2: hi(X) hi(Y); pass 3: hi(X)
+//     lo(Y)), so one set of fragment registers suffices;
+//   - global loads run two slabs ahead into two staging sets; slab kt + 2 is
+//     written to the LDS stage slab kt has left, in the middle of the
+//     iteration, and one barrier at its end publishes it;
+//   - loads go through buffer resources bounded to the K chunk's row groups,
+//     so groups past the chunk read as zeros and the loop needs no selects.
+namespace huge {
+constexpr int TM = 256, TN = 256;
+constexpr int LDR = 24;                       // bf16 per LDS column row: 16 k + 8 pad (48 bytes)
+constexpr int ARR = 256 * LDR;                // one operand half of a stage (bf16)
+constexpr int STAGE = 4 * ARR;                // Xh, Xl, Yh, Yl
+// s_waitcnt immediates: lgkmcnt(0) (vmcnt and expcnt unconstrained); vmcnt(4)
+// (lgkmcnt and expcnt unconstrained)
+constexpr int WAIT_LGKM0 = 0xC07F;
+constexpr int WAIT_VM4 = 0x0F74;
+}  // namespace huge
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const float* arena, const Packed& P, bool lo,
+                                                             int64_t gb, int64_t ngk) {
+    const float* b = arena + P.off + (lo ? P.lo_delta : 0) + gb * P.gstride;
+    const int64_t avail = (P.end - P.off - gb * P.gstride) * 4;
+    const int64_t want = ngk * P.gstride * 4;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(b), (short)0,
+                                             (int)(uint32_t)(want < avail ? want : avail), 0x00020000);
+}
+
+__device__ __forceinline__ void tile_bf16x3_huge(const LeafDesc& d, const float* arena_in, int ti, int tj,
+                                                 float* C, float* arena, unsigned char* smem, const KRange& kr) {
+    using namespace huge;
+    unsigned short* lds = reinterpret_cast<unsigned short*>(smem);
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = w >> 2, wn = w & 3;
+    const int64_t K = kr.ke - kr.kb;
+    const int64_t gb = kr.kb / 8;                 // first 8-row group of the K chunk
+    const int64_t ngk = (K + 7) / 8;              // row groups of the chunk
+    const int64_t nk = ((K + 15) / 16 + 1) & ~int64_t(1);   // slabs, rounded up to even (zeros past K)
+
+    // loader: thread t carries chunk (group g, column col) of X and of Y
+    const int g = w >> 2, col = t & 255;
+    const __amdgpu_buffer_rsrc_t rxh = chunk_rsrc(arena_in, d.PX, false, gb, ngk);
+    const __amdgpu_buffer_rsrc_t rxl = chunk_rsrc(arena_in, d.PX, true, gb, ngk);
+    const __amdgpu_buffer_rsrc_t ryh = chunk_rsrc(arena_in, d.PY, false, gb, ngk);
+    const __amdgpu_buffer_rsrc_t ryl = chunk_rsrc(arena_in, d.PY, true, gb, ngk);
+    const uint32_t xgs = (uint32_t)(d.PX.gstride * 4), ygs = (uint32_t)(d.PY.gstride * 4);
+    const uint32_t xo0 = (uint32_t)g * xgs + (uint32_t)((ti * TM + col) * 16);
+    const uint32_t yo0 = (uint32_t)g * ygs + (uint32_t)((tj * TN + col) * 16);
+    v4u sxh[2], sxl[2], syh[2], syl[2];
+    auto gload = [&](int set, int64_t s) {
+        const uint32_t ox = xo0 + (uint32_t)s * 2u * xgs, oy = yo0 + (uint32_t)s * 2u * ygs;
+        sxh[set] = __builtin_amdgcn_raw_buffer_load_b128(rxh, (int)ox, 0, 0);
+        sxl[set] = __builtin_amdgcn_raw_buffer_load_b128(rxl, (int)ox, 0, 0);
+        syh[set] = __builtin_amdgcn_raw_buffer_load_b128(ryh, (int)oy, 0, 0);
+        syl[set] = __builtin_amdgcn_raw_buffer_load_b128(ryl, (int)oy, 0, 0);
+    };
+    const int so = col * LDR + 8 * g;
+    auto sstore = [&](int set, int stage) {
+        unsigned short* st = lds + stage * STAGE + so;
+        *reinterpret_cast<v4u*>(st + 0 * ARR) = sxh[set];
+        *reinterpret_cast<v4u*>(st + 1 * ARR) = sxl[set];
+        *reinterpret_cast<v4u*>(st + 2 * ARR) = syh[set];
+        *reinterpret_cast<v4u*>(st + 3 * ARR) = syl[set];
+    };
+
+    // fragment of lane l: column (l % 32) of its block, k = 8 (l / 32) .. + 7
+    const int ao = (wm * 128 + (lane & 31)) * LDR + 8 * (lane >> 5);
+    const int bo = (wn * 64 + (lane & 31)) * LDR + 8 * (lane >> 5);
+    auto frag = [&](int stage, int half, int off) {
+        return *reinterpret_cast<const v8bf*>(lds + stage * STAGE + half * ARR + off);
+    };
+    v8bf ah[4], al[4], bh[2], bl[2];
+
+    v16f acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
+
+    auto barrier = [] {
+        __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+        __asm__ __volatile__("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        __asm__ __volatile__("" ::: "memory");
+    };
+
+    // iteration kt (par = kt & 1): the fragment registers hold slab kt; LDS
+    // stage par ^ 1 holds slab kt + 1; staging set par holds slab kt + 2 and
+    // set par ^ 1 slab kt + 3 (in flight)
+    auto iter = [&](int64_t kt, int par) {
+        const int nx = par ^ 1;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) al[a] = frag(nx, 1, ao + a * 32 * LDR);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bh[b] = frag(nx, 2, bo + b * 32 * LDR);
+        // slab kt + 2 into the stage slab kt has left: its loads are the
+        // older four of the eight this wave has in flight
+        __builtin_amdgcn_s_waitcnt(WAIT_VM4);
+        sstore(par, par);
+        gload(par, kt + 4);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            ah[a] = frag(nx, 0, ao + a * 32 * LDR);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bl[b] = frag(nx, 3, bo + b * 32 * LDR);
+        barrier();
+    };
+
+    // the two staging sets are issued one after the other (never
+    // interleaved), so that waiting for the older set leaves the newer in flight
+    gload(0, 0);
+    gload(1, 1);
+    sstore(0, 0);
+    sstore(1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    gload(0, 2);
+    __builtin_amdgcn_sched_barrier(0);
+    gload(1, 3);
+    __builtin_amdgcn_sched_barrier(0);
+    barrier();
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        ah[a] = frag(0, 0, ao + a * 32 * LDR);
+        al[a] = frag(0, 1, ao + a * 32 * LDR);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        bh[b] = frag(0, 2, bo + b * 32 * LDR);
+        bl[b] = frag(0, 3, bo + b * 32 * LDR);
+    }
+    barrier();                                     // stage 0 is free for slab 2
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+        iter(kt, 0);
+        iter(kt + 1, 1);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int cc = wn * 64 + b * 32 + (lane & 31);
                 store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
             }
 }
@@ -1634,8 +1808,8 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                          static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_HUGE) {
         if (flagged) return;
-        tile_bf16x3<BfHuge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                            static_cast<float*>(args.arena), smem, kr);
+        tile_bf16x3_huge(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                         static_cast<float*>(args.arena), smem, kr);
     } else {
         if (flagged) return;
         tile_f32(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
