@@ -40,8 +40,6 @@ constexpr int LD64 = TILE_M + PAD64;
 constexpr size_t LDS32_BYTES = 2 * 2 * BK * LD32 * sizeof(float);
 constexpr size_t LDS64_BYTES = 2 * 2 * BK * LD64 * sizeof(double);
 constexpr size_t LEAF_LDS_BYTES = LDS64_BYTES > LDS32_BYTES ? LDS64_BYTES : LDS32_BYTES;
-constexpr int BKB = 32;         // rows of A per K step, split-BF16 path
-constexpr int LDB = 40;         // bf16 per LDS row: 32 k values + 8 pad (80-byte stride)
 // Kernel variant of the FP64 fallback: FP32 inputs, FP64 MFMA, FP32 output.
 constexpr int MODE_FALLBACK = 100;
 // Split-BF16 with the 256 x 128 and 256 x 256 tiles.
@@ -70,8 +68,8 @@ constexpr int LATER = 32 * (STAGES - 2) < 63 ? 32 * (STAGES - 2) : 63;
 }  // namespace wide32
 
 constexpr size_t lds_bytes(int mode) {
-    return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 40 * 2
-           : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 40 * 2
+    return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 24 * 2
+           : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 24 * 2
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
            : mode == MODE_BF16X3_WIDE ? (size_t)WIDE_STAGES * 4 * 2 * 256 * 16
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
@@ -761,191 +759,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const float* arena
                                              (int)(uint32_t)((P.end - P.off) * 4), 0x00020000);
 }
 
-// Split-BF16 tile engine.  WAVES_M x WAVES_N waves; each wave owns BMB x BNB
-// blocks of 32 x 32, so the output tile is TM x TN with TM = WAVES_M * BMB * 32
-// and TN = WAVES_N * BNB * 32.  The K loop runs over slabs of 8 * GROUPS rows
-// (GROUPS / 2 MFMA steps of 16 k); LDS holds two slabs.  With two steps per
-// slab, operand fragments are double-buffered in registers (the second step's
-// fragments are read while the first step's MFMAs run).  Scheduling barriers
-// keep the compiler from merging these phases.
-template <int WAVES_M_, int WAVES_N_, int BMB_, int BNB_, int GROUPS_>
-struct BfCfg {
-    static constexpr int WAVES_M = WAVES_M_, WAVES_N = WAVES_N_, BMB = BMB_, BNB = BNB_;
-    static constexpr int GROUPS = GROUPS_;
-    static constexpr int THREADS = 64 * WAVES_M * WAVES_N;
-    static constexpr int TM = WAVES_M * BMB * 32;
-    static constexpr int TN = WAVES_N * BNB * 32;
-    static constexpr int LDR = 8 * GROUPS + 8;                  // bf16 per LDS row (k values + pad)
-    static constexpr int STAGE = (2 * TM + 2 * TN) * LDR;      // bf16 elements per slab
-    static constexpr size_t LDS = 2 * STAGE * 2;               // bytes, two slabs
-    static constexpr int PAIRS = GROUPS * (TM + TN) / THREADS;  // (hi, lo) chunk pairs per thread
-};
-using BfSmall = BfCfg<2, 2, 2, 2, 4>;   // 128 x 128, 4 waves, 80 KB LDS (two workgroups per CU)
-using BfLarge = BfCfg<2, 2, 4, 2, 4>;   // 256 x 128, 4 waves, 120 KB LDS
-
-template <class CFG>
-__device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, int tj,
-                            float* C, float* arena, unsigned char* smem, const KRange& kr) {
-    constexpr int TM = CFG::TM, TN = CFG::TN, STAGE = CFG::STAGE, LDR = CFG::LDR;
-    constexpr int BMB = CFG::BMB, BNB = CFG::BNB, G = CFG::GROUPS, NT = CFG::THREADS;
-    unsigned short* lds = reinterpret_cast<unsigned short*>(smem);
-    // slab s: Xh[TM][LDR], Xl[TM][LDR], Yh[TN][LDR], Yl[TN][LDR]
-    auto xh_ = [&](int s) { return lds + s * STAGE; };
-    auto xl_ = [&](int s) { return lds + s * STAGE + TM * LDR; };
-    auto yh_ = [&](int s) { return lds + s * STAGE + 2 * TM * LDR; };
-    auto yl_ = [&](int s) { return lds + s * STAGE + 2 * TM * LDR + TN * LDR; };
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w / CFG::WAVES_N, wn = w % CFG::WAVES_N;
-    const __amdgpu_buffer_rsrc_t rx[2] = {packed_rsrc(arena_in, d.PX, false), packed_rsrc(arena_in, d.PX, true)};
-    const __amdgpu_buffer_rsrc_t ry[2] = {packed_rsrc(arena_in, d.PY, false), packed_rsrc(arena_in, d.PY, true)};
-    const uint32_t xgs = (uint32_t)(d.PX.gstride * 4), ygs = (uint32_t)(d.PY.gstride * 4);
-    const int64_t K = kr.ke - kr.kb;
-    const int64_t gb = kr.kb / 8;                 // first 8-row group of the K chunk
-    const int64_t nk = (K + 8 * G - 1) / (8 * G);
-
-    v16f acc[BMB][BNB];
-#pragma unroll
-    for (int a = 0; a < BMB; ++a)
-#pragma unroll
-        for (int b = 0; b < BNB; ++b)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
-
-    // loader: pair index tr = t + NT i; X pairs [0, G TM) then Y pairs [0, G TN),
-    // pair (g, col) = row-group g of the slab, tile column col
-    v4u st_hi[CFG::PAIRS], st_lo[CFG::PAIRS];
-    const v4u zero = {0u, 0u, 0u, 0u};
-    // the operand and row-group of pair i are the same for the whole wave;
-    // derive them from the wave index so they are provably uniform (scalar
-    // buffer descriptors, no per-lane selection)
-    const int wave_base = __builtin_amdgcn_readfirstlane(t & ~63);
-    auto pair_of = [&](int i, bool& isx, int& g, int& col) {
-        const int trw = wave_base + NT * i;                 // first pair of this wave
-        isx = trw < G * TM;
-        const int trw2 = isx ? trw : trw - G * TM;
-        const int cols = isx ? TM : TN;
-        g = trw2 / cols;
-        col = trw2 - g * cols + lane;
-    };
-    auto gload = [&](int64_t kt) {
-#pragma unroll
-        for (int i = 0; i < CFG::PAIRS; ++i) {
-            bool isx;
-            int g, col;
-            pair_of(i, isx, g, col);
-            const int64_t lrow = kt * G + g;
-            const uint32_t off = (uint32_t)(gb + lrow) * (isx ? xgs : ygs) +
-                                 (uint32_t)(((isx ? ti * TM : tj * TN) + col) * 16);
-            if (lrow * 8 < K) {
-                st_hi[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx[0] : ry[0], (int)off, 0, 0);
-                st_lo[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx[1] : ry[1], (int)off, 0, 0);
-            } else {
-                st_hi[i] = zero;
-                st_lo[i] = zero;
-            }
-        }
-    };
-    auto sstore = [&](int s) {
-#pragma unroll
-        for (int i = 0; i < CFG::PAIRS; ++i) {
-            bool isx;
-            int g, col;
-            pair_of(i, isx, g, col);
-            unsigned short* h = (isx ? xh_(s) : yh_(s)) + col * LDR + 8 * g;
-            unsigned short* l = (isx ? xl_(s) : yl_(s)) + col * LDR + 8 * g;
-            *reinterpret_cast<v4u*>(h) = st_hi[i];
-            *reinterpret_cast<v4u*>(l) = st_lo[i];
-        }
-    };
-
-    const int io = lane & 31, ko = 8 * (lane >> 5);
-    constexpr int NB = G / 2 >= 2 ? 2 : 1;                 // fragment buffers
-    v8bf fah[NB][BMB], fal[NB][BMB], fbh[NB][BNB], fbl[NB][BNB];
-    auto read_frags = [&](int buf, int s, int ks) {
-        const unsigned short* ah = xh_(s) + (wm * BMB * 32 + io) * LDR + ko + ks * 16;
-        const unsigned short* al = xl_(s) + (wm * BMB * 32 + io) * LDR + ko + ks * 16;
-        const unsigned short* bh = yh_(s) + (wn * BNB * 32 + io) * LDR + ko + ks * 16;
-        const unsigned short* bl = yl_(s) + (wn * BNB * 32 + io) * LDR + ko + ks * 16;
-#pragma unroll
-        for (int a = 0; a < BMB; ++a) {
-            fah[buf][a] = *reinterpret_cast<const v8bf*>(ah + a * 32 * LDR);
-            fal[buf][a] = *reinterpret_cast<const v8bf*>(al + a * 32 * LDR);
-        }
-#pragma unroll
-        for (int b = 0; b < BNB; ++b) {
-            fbh[buf][b] = *reinterpret_cast<const v8bf*>(bh + b * 32 * LDR);
-            fbl[buf][b] = *reinterpret_cast<const v8bf*>(bl + b * 32 * LDR);
-        }
-    };
-    auto mfmas = [&](int buf) {
-#pragma unroll
-        for (int a = 0; a < BMB; ++a)
-#pragma unroll
-            for (int b = 0; b < BNB; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fal[buf][a], fbh[buf][b], acc[a][b], 0, 0, 0);
-#pragma unroll
-        for (int a = 0; a < BMB; ++a)
-#pragma unroll
-            for (int b = 0; b < BNB; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[buf][a], fbl[buf][b], acc[a][b], 0, 0, 0);
-#pragma unroll
-        for (int a = 0; a < BMB; ++a)
-#pragma unroll
-            for (int b = 0; b < BNB; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fah[buf][a], fbh[buf][b], acc[a][b], 0, 0, 0);
-    };
-
-    // Two slabs in flight: at the top of iteration kt the staging registers
-    // hold slab kt + 1 (loaded one iteration earlier) and go to the free LDS
-    // buffer, then the loads of slab kt + 2 are issued, so every global load
-    // has a whole iteration of MFMA work to arrive.
-    if (nk > 0) {
-        gload(0);
-        sstore(0);
-    }
-    if (nk > 1) gload(1);
-    __syncthreads();
-    if constexpr (NB == 2) {
-        if (nk > 0) read_frags(0, 0, 0);
-        for (int64_t kt = 0; kt < nk; ++kt) {
-            const int cur = (int)(kt & 1);
-            if (kt + 1 < nk) sstore(cur ^ 1);      // slab kt + 1 into the other LDS buffer
-            if (kt + 2 < nk) gload(kt + 2);
-            read_frags(1, cur, 1);                 // second 16-k step of this slab
-            __builtin_amdgcn_sched_barrier(0);
-            mfmas(0);                              // first step
-            __builtin_amdgcn_sched_barrier(0);
-            mfmas(1);
-            __builtin_amdgcn_sched_barrier(0);
-            __syncthreads();
-            if (kt + 1 < nk) read_frags(0, cur ^ 1, 0);
-        }
-    } else {
-        for (int64_t kt = 0; kt < nk; ++kt) {
-            const int cur = (int)(kt & 1);
-            if (kt + 1 < nk) sstore(cur ^ 1);
-            if (kt + 2 < nk) gload(kt + 2);
-            read_frags(0, cur, 0);
-            mfmas(0);
-            __syncthreads();
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < BMB; ++a)
-#pragma unroll
-        for (int b = 0; b < BNB; ++b)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int cc = wn * BNB * 32 + b * 32 + (lane & 31);
-                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
-            }
-}
-
-// Split-BF16 x3 with a 256 x 256 tile on eight waves (2 x 4) of 128 x 64
-// (4 x 2 blocks of 32 x 32, 128 accumulators per lane), two waves per SIMD.
-// Each 16-row slab is one MFMA k step.  The K loop is software-pipelined so
-// that the matrix pipe never waits on LDS after the per-slab barrier:
+// Split-BF16 x3 tile engine: WM x WN waves, each owning BMB x BNB blocks of
+// 32 x 32 (tile TM x TN = 32 WM BMB x 32 WN BNB).  Each 16-row slab is one
+// MFMA k step.  The K loop is software-pipelined so that the matrix pipe
+// never waits on LDS after the per-slab barrier:
 //   - the fragments of slab kt + 1 are read while slab kt's MFMAs run, each
 //     fragment register being refilled as soon as the pass that reads it has
 //     been issued (pass 1: lo(X) hi(Y); pass 2: hi(X) hi(Y); pass 3: hi(X)
@@ -955,16 +772,23 @@ __device__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, in
 //     iteration, and one barrier at its end publishes it;
 //   - loads go through buffer resources bounded to the K chunk's row groups,
 //     so groups past the chunk read as zeros and the loop needs no selects.
-namespace huge {
-constexpr int TM = 256, TN = 256;
+// Instances: 128 x 128 on four waves (tile 0), 256 x 128 on four waves
+// (tile 1), 256 x 256 on eight waves of 128 x 64 (tile 2).
+namespace pipe {
 constexpr int LDR = 24;                       // bf16 per LDS column row: 16 k + 8 pad (48 bytes)
-constexpr int ARR = 256 * LDR;                // one operand half of a stage (bf16)
-constexpr int STAGE = 4 * ARR;                // Xh, Xl, Yh, Yl
-// s_waitcnt immediates: lgkmcnt(0) (vmcnt and expcnt unconstrained); vmcnt(4)
+// s_waitcnt immediates: lgkmcnt(0) (vmcnt and expcnt unconstrained); vmcnt(n)
 // (lgkmcnt and expcnt unconstrained)
 constexpr int WAIT_LGKM0 = 0xC07F;
-constexpr int WAIT_VM4 = 0x0F74;
-}  // namespace huge
+constexpr int wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | 0x0F70; }
+template <int WM, int WN, int BMB, int BNB>
+struct Geo {
+    static constexpr int TM = 32 * WM * BMB, TN = 32 * WN * BNB, NT = 64 * WM * WN;
+    static constexpr int PX = 2 * TM / NT, PY = 2 * TN / NT;    // chunks per thread per slab
+    static constexpr int STAGE = (2 * TM + 2 * TN) * LDR;      // bf16 elements
+    static constexpr size_t LDS = (size_t)2 * STAGE * 2;       // two stages, bytes
+    static_assert(PX >= 1 && PY >= 1 && PX * NT == 2 * TM && PY * NT == 2 * TN, "loader layout");
+};
+}  // namespace pipe
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const float* arena, const Packed& P, bool lo,
                                                              int64_t gb, int64_t ngk) {
@@ -975,62 +799,89 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t chunk_rsrc(const float* arena,
                                              (int)(uint32_t)(want < avail ? want : avail), 0x00020000);
 }
 
-__device__ __forceinline__ void tile_bf16x3_huge(const LeafDesc& d, const float* arena_in, int ti, int tj,
-                                                 float* C, float* arena, unsigned char* smem, const KRange& kr) {
-    using namespace huge;
+template <int WM, int WN, int BMB, int BNB>
+__device__ __forceinline__ void tile_bf16x3(const LeafDesc& d, const float* arena_in, int ti, int tj,
+                                            float* C, float* arena, unsigned char* smem, const KRange& kr) {
+    using G = pipe::Geo<WM, WN, BMB, BNB>;
+    constexpr int TM = G::TM, TN = G::TN, NT = G::NT, PX = G::PX, PY = G::PY, LDR = pipe::LDR;
+    constexpr int STAGE = G::STAGE;
+    constexpr int XH = 0, XL = TM * LDR, YH = 2 * TM * LDR, YL = (2 * TM + TN) * LDR;
     unsigned short* lds = reinterpret_cast<unsigned short*>(smem);
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wm = w >> 2, wn = w & 3;
+    const int wm = w / WN, wn = w % WN;
     const int64_t K = kr.ke - kr.kb;
     const int64_t gb = kr.kb / 8;                 // first 8-row group of the K chunk
     const int64_t ngk = (K + 7) / 8;              // row groups of the chunk
     const int64_t nk = ((K + 15) / 16 + 1) & ~int64_t(1);   // slabs, rounded up to even (zeros past K)
 
-    // loader: thread t carries chunk (group g, column col) of X and of Y
-    const int g = w >> 2, col = t & 255;
+    // loader: chunk t + NT i of the slab's X (or Y) chunks = (group g, column col)
     const __amdgpu_buffer_rsrc_t rxh = chunk_rsrc(arena_in, d.PX, false, gb, ngk);
     const __amdgpu_buffer_rsrc_t rxl = chunk_rsrc(arena_in, d.PX, true, gb, ngk);
     const __amdgpu_buffer_rsrc_t ryh = chunk_rsrc(arena_in, d.PY, false, gb, ngk);
     const __amdgpu_buffer_rsrc_t ryl = chunk_rsrc(arena_in, d.PY, true, gb, ngk);
     const uint32_t xgs = (uint32_t)(d.PX.gstride * 4), ygs = (uint32_t)(d.PY.gstride * 4);
-    const uint32_t xo0 = (uint32_t)g * xgs + (uint32_t)((ti * TM + col) * 16);
-    const uint32_t yo0 = (uint32_t)g * ygs + (uint32_t)((tj * TN + col) * 16);
-    v4u sxh[2], sxl[2], syh[2], syl[2];
+    uint32_t xo0[PX], yo0[PY];
+    int xso[PX], yso[PY];
+#pragma unroll
+    for (int i = 0; i < PX; ++i) {
+        const int ci = t + NT * i, g = ci / TM, col = ci % TM;
+        xo0[i] = (uint32_t)g * xgs + (uint32_t)((ti * TM + col) * 16);
+        xso[i] = col * LDR + 8 * g;
+    }
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        const int ci = t + NT * i, g = ci / TN, col = ci % TN;
+        yo0[i] = (uint32_t)g * ygs + (uint32_t)((tj * TN + col) * 16);
+        yso[i] = col * LDR + 8 * g;
+    }
+    v4u sxh[2][PX], sxl[2][PX], syh[2][PY], syl[2][PY];
     auto gload = [&](int set, int64_t s) {
-        const uint32_t ox = xo0 + (uint32_t)s * 2u * xgs, oy = yo0 + (uint32_t)s * 2u * ygs;
-        sxh[set] = __builtin_amdgcn_raw_buffer_load_b128(rxh, (int)ox, 0, 0);
-        sxl[set] = __builtin_amdgcn_raw_buffer_load_b128(rxl, (int)ox, 0, 0);
-        syh[set] = __builtin_amdgcn_raw_buffer_load_b128(ryh, (int)oy, 0, 0);
-        syl[set] = __builtin_amdgcn_raw_buffer_load_b128(ryl, (int)oy, 0, 0);
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+            const uint32_t o = xo0[i] + (uint32_t)s * 2u * xgs;
+            sxh[set][i] = __builtin_amdgcn_raw_buffer_load_b128(rxh, (int)o, 0, 0);
+            sxl[set][i] = __builtin_amdgcn_raw_buffer_load_b128(rxl, (int)o, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            const uint32_t o = yo0[i] + (uint32_t)s * 2u * ygs;
+            syh[set][i] = __builtin_amdgcn_raw_buffer_load_b128(ryh, (int)o, 0, 0);
+            syl[set][i] = __builtin_amdgcn_raw_buffer_load_b128(ryl, (int)o, 0, 0);
+        }
     };
-    const int so = col * LDR + 8 * g;
     auto sstore = [&](int set, int stage) {
-        unsigned short* st = lds + stage * STAGE + so;
-        *reinterpret_cast<v4u*>(st + 0 * ARR) = sxh[set];
-        *reinterpret_cast<v4u*>(st + 1 * ARR) = sxl[set];
-        *reinterpret_cast<v4u*>(st + 2 * ARR) = syh[set];
-        *reinterpret_cast<v4u*>(st + 3 * ARR) = syl[set];
+        unsigned short* st = lds + stage * STAGE;
+#pragma unroll
+        for (int i = 0; i < PX; ++i) {
+            *reinterpret_cast<v4u*>(st + XH + xso[i]) = sxh[set][i];
+            *reinterpret_cast<v4u*>(st + XL + xso[i]) = sxl[set][i];
+        }
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            *reinterpret_cast<v4u*>(st + YH + yso[i]) = syh[set][i];
+            *reinterpret_cast<v4u*>(st + YL + yso[i]) = syl[set][i];
+        }
     };
 
     // fragment of lane l: column (l % 32) of its block, k = 8 (l / 32) .. + 7
-    const int ao = (wm * 128 + (lane & 31)) * LDR + 8 * (lane >> 5);
-    const int bo = (wn * 64 + (lane & 31)) * LDR + 8 * (lane >> 5);
+    const int ao = (wm * BMB * 32 + (lane & 31)) * LDR + 8 * (lane >> 5);
+    const int bo = (wn * BNB * 32 + (lane & 31)) * LDR + 8 * (lane >> 5);
     auto frag = [&](int stage, int half, int off) {
-        return *reinterpret_cast<const v8bf*>(lds + stage * STAGE + half * ARR + off);
+        return *reinterpret_cast<const v8bf*>(lds + stage * STAGE + half + off);
     };
-    v8bf ah[4], al[4], bh[2], bl[2];
+    v8bf ah[BMB], al[BMB], bh[BNB], bl[BNB];
 
-    v16f acc[4][2];
+    v16f acc[BMB][BNB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < BMB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < BNB; ++b)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
 
     auto barrier = [] {
-        __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+        __builtin_amdgcn_s_waitcnt(pipe::WAIT_LGKM0);
         __asm__ __volatile__("" ::: "memory");
         __builtin_amdgcn_s_barrier();
         __asm__ __volatile__("" ::: "memory");
@@ -1042,39 +893,39 @@ __device__ __forceinline__ void tile_bf16x3_huge(const LeafDesc& d, const float*
     auto iter = [&](int64_t kt, int par) {
         const int nx = par ^ 1;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < BMB; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < BNB; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) al[a] = frag(nx, 1, ao + a * 32 * LDR);
+        for (int a = 0; a < BMB; ++a) al[a] = frag(nx, XL, ao + a * 32 * LDR);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < BMB; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < BNB; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bh[b] = frag(nx, 2, bo + b * 32 * LDR);
+        for (int b = 0; b < BNB; ++b) bh[b] = frag(nx, YH, bo + b * 32 * LDR);
         // slab kt + 2 into the stage slab kt has left: its loads are the
-        // older four of the eight this wave has in flight
-        __builtin_amdgcn_s_waitcnt(WAIT_VM4);
+        // older half of those this thread has in flight
+        __builtin_amdgcn_s_waitcnt(pipe::wait_vm(2 * (PX + PY)));
         sstore(par, par);
         gload(par, kt + 4);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a < BMB; ++a) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < BNB; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
-            ah[a] = frag(nx, 0, ao + a * 32 * LDR);
+            ah[a] = frag(nx, XH, ao + a * 32 * LDR);
             __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bl[b] = frag(nx, 3, bo + b * 32 * LDR);
+        for (int b = 0; b < BNB; ++b) bl[b] = frag(nx, YL, bo + b * 32 * LDR);
         barrier();
     };
 
@@ -1091,14 +942,14 @@ __device__ __forceinline__ void tile_bf16x3_huge(const LeafDesc& d, const float*
     __builtin_amdgcn_sched_barrier(0);
     barrier();
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        ah[a] = frag(0, 0, ao + a * 32 * LDR);
-        al[a] = frag(0, 1, ao + a * 32 * LDR);
+    for (int a = 0; a < BMB; ++a) {
+        ah[a] = frag(0, XH, ao + a * 32 * LDR);
+        al[a] = frag(0, XL, ao + a * 32 * LDR);
     }
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        bh[b] = frag(0, 2, bo + b * 32 * LDR);
-        bl[b] = frag(0, 3, bo + b * 32 * LDR);
+    for (int b = 0; b < BNB; ++b) {
+        bh[b] = frag(0, YH, bo + b * 32 * LDR);
+        bl[b] = frag(0, YL, bo + b * 32 * LDR);
     }
     barrier();                                     // stage 0 is free for slab 2
     for (int64_t kt = 0; kt < nk; kt += 2) {
@@ -1106,13 +957,13 @@ __device__ __forceinline__ void tile_bf16x3_huge(const LeafDesc& d, const float*
         iter(kt + 1, 1);
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < BMB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < BNB; ++b)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int cc = wn * 64 + b * 32 + (lane & 31);
+                const int r = wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int cc = wn * BNB * 32 + b * 32 + (lane & 31);
                 store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
             }
 }
@@ -1723,6 +1574,13 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, const 
             }
 }
 
+static_assert(lds_bytes(MODE_BF16X3) == pipe::Geo<2, 2, 2, 2>::LDS, "tile 0 LDS");
+static_assert(lds_bytes(MODE_BF16X3_LARGE) == pipe::Geo<2, 2, 4, 2>::LDS, "tile 1 LDS");
+static_assert(lds_bytes(MODE_BF16X3_HUGE) == pipe::Geo<2, 4, 4, 2>::LDS, "tile 2 LDS");
+static_assert(threads_for(MODE_BF16X3) == pipe::Geo<2, 2, 2, 2>::NT && threads_for(MODE_BF16X3_LARGE) ==
+              pipe::Geo<2, 2, 4, 2>::NT && threads_for(MODE_BF16X3_HUGE) == pipe::Geo<2, 4, 4, 2>::NT,
+              "split-BF16 workgroup sizes");
+
 template <int MODE>
 __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsigned char* smem) {
     const LeafDesc& d = args.tasks[find_leaf(args.tasks, args.ntasks, bid)];
@@ -1757,12 +1615,12 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                                static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3) {
         if (flagged) return;
-        tile_bf16x3<BfSmall>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                             static_cast<float*>(args.arena), smem, kr);
+        tile_bf16x3<2, 2, 2, 2>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                                static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_LARGE) {
         if (flagged) return;
-        tile_bf16x3<BfLarge>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                             static_cast<float*>(args.arena), smem, kr);
+        tile_bf16x3<2, 2, 4, 2>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                                static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_F32_WIDE) {
         if (flagged) return;
         if (d.sx2 | d.sy2) {
@@ -1808,8 +1666,8 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                          static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_HUGE) {
         if (flagged) return;
-        tile_bf16x3_huge(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                         static_cast<float*>(args.arena), smem, kr);
+        tile_bf16x3<2, 4, 4, 2>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                                static_cast<float*>(args.arena), smem, kr);
     } else {
         if (flagged) return;
         tile_f32(d, view_ptr<float>(d.X, Aptr, args.B, args.arena), view_ptr<float>(d.Y, Aptr, args.B, args.arena),
