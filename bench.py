@@ -208,6 +208,8 @@ def make_handle(ata, args):
         h.set("strassen_form", 1)
     if args.no_balance_tail:
         h.set("balance_tail", 0)
+    if args.leaf_persistent >= 0:
+        h.set("leaf_persistent", args.leaf_persistent)
     if args.spread_tau >= 0:
         h.set("spread_tau", args.spread_tau)
     return h
@@ -419,6 +421,9 @@ def main() -> int:
                     help="column-norm spread threshold of the FP64 fallback (0: no spread check; default: the library's)")
     ap.add_argument("--no-balance-tail", action="store_true",
                     help="do not cut the leaves of an underfilled last round of the leaf launch into K chunks")
+    ap.add_argument("--leaf-persistent", type=int, default=-1,
+                    help="leaf launch: 1 = persistent grid with per-XCD queues, 0 = one workgroup per tile, "
+                         "-1 = the library's automatic choice")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

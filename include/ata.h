@@ -193,7 +193,28 @@ typedef enum {
        a cut leaf can differ from the uncut ones by rounding only.
        ata_report_t.tail_split_leaves tells whether a plan was cut.
        0 = never. */
-    ATA_OPT_BALANCE_TAIL = 18
+    ATA_OPT_BALANCE_TAIL = 18,
+    /* 1 = bounded workspace (Sec. 3.3 reuses one set of Strassen buffers per
+       level instead of holding every level at once): ata_gram runs each
+       Strassen root (the C21 block of an AtA node that gets Strassen levels)
+       product by product.  For each AtA level with roots and each product
+       i = 1..7, one stage forms product i's operand sums on their own, runs
+       the product's remaining Strassen levels (resident) into one buffer and
+       adds it into the root's quadrants in the combine's own order; every
+       stage reuses the workspace from its start.  The number of top levels
+       run this way is the smallest that keeps the workspace within
+       3/2 n max(m, n) elements (Sec. 3.3's 3/2 n^2 for square A; about n^2
+       for 30000 x 30000 FP64 at the default depth).  With split-K and tail
+       cuts off (ATA_OPT_SPLIT_TARGET 0, ATA_OPT_BALANCE_TAIL 0) results are
+       bit-identical to the default schedule's with the same leaf cutoff,
+       depth and tile (the same sums, leaves and additions, in the same
+       order); otherwise a stage's smaller launch may cut a contraction into
+       K chunks where the resident launch does not, which changes rounding
+       only.  Strassen's form
+       only (ATA_OPT_STRASSEN_FORM and ATA_OPT_FUSE_PRESUM are ignored).
+       Applies to ata_gram; ata_gram_noalloc, ata_gram_batched and
+       ata_gemm_tn ignore it.  0 = every level resident (default). */
+    ATA_OPT_BOUNDED_WORKSPACE = 19
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */

@@ -32,6 +32,7 @@ OPT_LEAF_PERSISTENT = 15
 OPT_FUSE_PRESUM = 16
 OPT_STRASSEN_FORM = 17
 OPT_BALANCE_TAIL = 18
+OPT_BOUNDED_WORKSPACE = 19
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -292,7 +293,7 @@ class Handle:
                "split_target": OPT_SPLIT_TARGET, "batch_use_table": OPT_BATCH_USE_TABLE,
                "equilibrate": OPT_EQUILIBRATE, "leaf_persistent": OPT_LEAF_PERSISTENT,
                "fuse_presum": OPT_FUSE_PRESUM, "strassen_form": OPT_STRASSEN_FORM,
-               "balance_tail": OPT_BALANCE_TAIL}[name]
+               "balance_tail": OPT_BALANCE_TAIL, "bounded_workspace": OPT_BOUNDED_WORKSPACE}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

@@ -36,10 +36,11 @@ struct PlanKey {
     bool fuse;
     int32_t variant;
     int64_t slots;
+    bool bounded;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant, slots) <
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant, slots, bounded) <
                std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant,
-                        o.slots);
+                        o.slots, o.bounded);
     }
 };
 
@@ -57,7 +58,14 @@ struct DevicePlan {
     ColDesc* d_col1 = nullptr;
     ColDesc* d_col2 = nullptr;
     ReduceDesc* d_reduce = nullptr;
+    std::vector<Sum2Desc*> d_sums;
+    std::vector<AccumDesc*> d_accum;
+    // bounded workspace: the stages after this one (this plan is stage 0),
+    // and the largest stage's arena
+    std::vector<std::unique_ptr<DevicePlan>> stages;
+    int64_t stage_arena_elems = 0;
     ~DevicePlan() { if (d_buf) (void)hipFree(d_buf); }
+    int64_t arena_elems() const { return stages.empty() ? plan.arena_elems : stage_arena_elems; }
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -229,6 +237,7 @@ struct ata_ctx {
     int batch_persistent = -1;         // 0 grid, 1 persistent, -1 automatic
     int leaf_persistent = -1;
     bool balance_tail = true;          // split the leaves of an underfilled last round
+    bool bounded = false;              // Strassen roots product by product (make_staged_plan)
     uint64_t arena_gen = 0;
     // phase profiling: six events per profiled call, summed at report time
     bool profile = false;
@@ -327,9 +336,13 @@ size_t layout_descriptors(DevicePlan& dp, unsigned char* base, std::vector<unsig
     bytes += align256(p.col1.size() * sizeof(ColDesc));
     bytes += align256(p.col2.size() * sizeof(ColDesc));
     bytes += align256(p.reduce.size() * sizeof(ReduceDesc));
+    for (auto& l : p.sums) bytes += align256(l.size() * sizeof(Sum2Desc));
+    for (auto& l : p.accum) bytes += align256(l.size() * sizeof(AccumDesc));
     host.assign(bytes, 0);
     dp.d_presum.clear();
     dp.d_combine.clear();
+    dp.d_sums.clear();
+    dp.d_accum.clear();
     size_t off = 0;
     auto put = [&](const void* src, size_t n) {
         if (n) std::memcpy(host.data() + off, src, n);
@@ -347,6 +360,9 @@ size_t layout_descriptors(DevicePlan& dp, unsigned char* base, std::vector<unsig
     dp.d_col1 = static_cast<ColDesc*>(put(p.col1.data(), p.col1.size() * sizeof(ColDesc)));
     dp.d_col2 = static_cast<ColDesc*>(put(p.col2.data(), p.col2.size() * sizeof(ColDesc)));
     dp.d_reduce = static_cast<ReduceDesc*>(put(p.reduce.data(), p.reduce.size() * sizeof(ReduceDesc)));
+    for (auto& l : p.sums) dp.d_sums.push_back(static_cast<Sum2Desc*>(put(l.data(), l.size() * sizeof(Sum2Desc))));
+    for (auto& l : p.accum)
+        dp.d_accum.push_back(static_cast<AccumDesc*>(put(l.data(), l.size() * sizeof(AccumDesc))));
     return bytes;
 }
 
@@ -436,12 +452,59 @@ bool persistent_for(int setting, const Plan& p) {
 // keeps every Strassen level's sums and products at once (a level's products
 // run concurrently), so the workspace grows about 7/4 per level: a plan for a
 // large matrix gets fewer levels rather than an allocation failure.
-bool fits_device(const ata_ctx* h, const Plan& p) {
+bool fits_device(const ata_ctx* h, int64_t arena_elems, int64_t elem_bytes) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return true;
-    const double need = (double)p.arena_elems * (double)p.elem_bytes();
+    const double need = (double)arena_elems * (double)elem_bytes;
     return need + (double)(1ull << 30) <= (double)free_b + (double)h->arena_cap;
 }
+bool fits_device(const ata_ctx* h, const Plan& p) { return fits_device(h, p.arena_elems, p.elem_bytes()); }
+
+int64_t max_arena(const std::vector<Plan>& st) {
+    int64_t a = 0;
+    for (const auto& q : st) a = std::max(a, q.arena_elems);
+    return a;
+}
+
+// The bounded-workspace (staged) plan of a key, with the Strassen depth
+// lowered until the largest stage fits the device; stage 0 goes into dp,
+// the others into dp.stages, each with its descriptors uploaded.
+ata_status_t build_staged(const ata_ctx* h, const PlanKey& k, DevicePlan& dp) {
+    PlanOptions o;
+    o.leaf_cutoff = k.b;
+    o.max_depth = k.depth;
+    o.spread_tau = k.fb ? h->popt.spread_tau : 0.0;
+    o.tile_cfg = k.tile_cfg;
+    o.split_target = k.split;
+    o.slots = k.slots;
+    o.bounded = true;
+    std::vector<Plan> st;
+    try {
+        st = make_staged_plan(k.mode, k.m, k.n, k.lda, o);
+        while (st[0].stats.max_levels > 0 && !fits_device(h, max_arena(st), st[0].elem_bytes())) {
+            o.max_depth = st[0].stats.max_levels - 1;
+            st = make_staged_plan(k.mode, k.m, k.n, k.lda, o);
+        }
+        if (st[0].fallback) fuse_pack_into_norms(st[0], st[0].col1);
+    } catch (const std::invalid_argument&) {
+        return ATA_ERR_INVALID_VALUE;
+    } catch (const std::length_error&) {
+        return ATA_ERR_NOT_SUPPORTED;
+    } catch (const std::exception&) {
+        return ATA_ERR_INTERNAL;
+    }
+    dp.stage_arena_elems = max_arena(st);
+    dp.plan = std::move(st[0]);
+    ata_status_t s = upload_plan(dp);
+    for (size_t i = 1; s == ATA_OK && i < st.size(); ++i) {
+        auto sp = std::make_unique<DevicePlan>();
+        sp->plan = std::move(st[i]);
+        s = upload_plan(*sp);
+        dp.stages.push_back(std::move(sp));
+    }
+    return s;
+}
+
 
 // The plan of one Gram product for a plan-cache key, with the Strassen depth
 // lowered one level at a time until `fits` accepts the plan (a plan without
@@ -624,6 +687,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             if (value < 0 || value > 1e9) return ATA_ERR_INVALID_VALUE;
             h->split_target = (int64_t)value;
             return ATA_OK;
+        case ATA_OPT_BOUNDED_WORKSPACE:
+            h->bounded = value != 0.0;
+            return ATA_OK;
         case ATA_OPT_PROFILE:
             if (h->events_used) (void)drain_events(h);
             h->profile = value != 0.0;
@@ -697,7 +763,7 @@ namespace {
 // are the call's workspace; `ev` holds six profiling events or is null.
 hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, void* C_packed, void* arena,
                         unsigned char* aux, const AuxLayout& ax, bool residual, hipStream_t st, hipEvent_t* ev,
-                        bool& persistent) {
+                        bool& persistent, bool mark_end = true) {
     const Plan& p = dp.plan;
     const int32_t mode = p.mode;
     BatchPtrs pq{nullptr, nullptr, reinterpret_cast<unsigned long long*>(aux + ax.counter_off), 0};
@@ -725,10 +791,19 @@ hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, v
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
     mark(1);
+    for (size_t l = 0; e == hipSuccess && l < p.sums.size(); ++l) {
+        const auto& lv = p.sums[l];
+        if (!lv.empty())
+            e = launch_sum2(mode, dp.d_sums[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems, A, arena,
+                            flags, st);
+    }
+    // (a bounded-workspace stage's resident subtree starts below the top,
+    // so its upper pre-sum levels are empty)
     for (size_t l = 0; e == hipSuccess && l < p.presum.size(); ++l) {
         const auto& lv = p.presum[l];
-        e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
-                          A, arena, flags, st);
+        if (!lv.empty())
+            e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
+                              A, arena, flags, st);
     }
     if (e == hipSuccess && !p.pack.empty())
         e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
@@ -749,13 +824,41 @@ hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, v
     mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
-        e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
-                           C_packed, arena, flags, st);
+        if (!lv.empty())
+            e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
+                               C_packed, arena, flags, st);
+    }
+    for (size_t l = 0; e == hipSuccess && l < p.accum.size(); ++l) {
+        const auto& lv = p.accum[l];
+        if (!lv.empty())
+            e = launch_accum(mode, dp.d_accum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems, C_packed,
+                             arena, flags, st);
     }
     mark(4);
     if (e == hipSuccess && residual)
         e = launch_residual(mode, A, p.m, p.n, p.lda, C_packed, h->seed, res_work, res, st);
-    mark(5);
+    if (mark_end) mark(5);
+    return e;
+}
+
+// A staged (bounded-workspace) plan: stage 0 with the column norms and
+// flags, then every later stage on the same arena and flags; the residual
+// probe after the last stage.  Profiling: phases 0-3 are stage 0's, phase 4
+// runs from stage 0's combines to the end.
+hipError_t enqueue_staged(const ata_ctx* h, const DevicePlan& dp, const void* A, void* C_packed, void* arena,
+                          unsigned char* aux, const AuxLayout& ax, bool residual, hipStream_t st, hipEvent_t* ev,
+                          bool& persistent) {
+    hipError_t e = enqueue_gram(h, dp, A, C_packed, arena, aux, ax, false, st, ev, persistent, false);
+    for (const auto& sp : dp.stages) {
+        bool pers = false;
+        if (e == hipSuccess) e = enqueue_gram(h, *sp, A, C_packed, arena, aux, ax, false, st, nullptr, pers);
+    }
+    const Plan& p = dp.plan;
+    if (e == hipSuccess && residual)
+        e = launch_residual(p.mode, A, p.m, p.n, p.lda, C_packed, h->seed,
+                            reinterpret_cast<double*>(aux + ax.res_work_off),
+                            reinterpret_cast<double*>(aux + ax.res_off), st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[5], st);
     return e;
 }
 
@@ -848,21 +951,28 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
     const int64_t slots = tail_slots(h, mode, tile_cfg);
-    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
-                       h->popt.variant, slots};
+    const bool bounded = h->bounded;
+    const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target,
+                      bounded ? false : h->popt.fuse_presum, bounded ? 0 : h->popt.variant, slots, bounded};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
-        const ata_status_t s = build_gram_plan(h, key, [h](const Plan& q) { return fits_device(h, q); }, dp->plan);
-        if (s != ATA_OK) return s;
-        const ata_status_t su = upload_plan(*dp);
-        if (su != ATA_OK) return su;
+        if (bounded) {
+            const ata_status_t s = build_staged(h, key, *dp);
+            if (s != ATA_OK) return s;
+        } else {
+            const ata_status_t s =
+                build_gram_plan(h, key, [h](const Plan& q) { return fits_device(h, q); }, dp->plan);
+            if (s != ATA_OK) return s;
+            const ata_status_t su = upload_plan(*dp);
+            if (su != ATA_OK) return su;
+        }
         it = h->plans.emplace(key, std::move(dp)).first;
     }
     DevicePlan& dp = *it->second;
     const Plan& p = dp.plan;
     const AuxLayout ax = aux_layout(p, h->residual);
-    const size_t arena_bytes = (size_t)p.arena_elems * (size_t)p.elem_bytes();
+    const size_t arena_bytes = (size_t)dp.arena_elems() * (size_t)p.elem_bytes();
     if (h->ws_limit > 0 && (int64_t)(arena_bytes + ax.total) > h->ws_limit) return ATA_ERR_OUT_OF_MEMORY;
     const size_t old_cap = h->arena_cap;
     ata_status_t s = ensure(h, h->arena, h->arena_cap, std::max<size_t>(arena_bytes, 256));
@@ -876,11 +986,17 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     hipEvent_t* ev = nullptr;
     if (take_events(h, ev) != ATA_OK) return ATA_ERR_HIP;
     bool persistent = false;
-    if (enqueue_gram(h, dp, A, C_packed, h->arena, aux, ax, h->residual, st, ev, persistent) != hipSuccess)
-        return ATA_ERR_HIP;
+    const hipError_t eq = dp.stages.empty()
+                              ? enqueue_gram(h, dp, A, C_packed, h->arena, aux, ax, h->residual, st, ev, persistent)
+                              : enqueue_staged(h, dp, A, C_packed, h->arena, aux, ax, h->residual, st, ev, persistent);
+    if (eq != hipSuccess) return ATA_ERR_HIP;
 
     fill_report(h->report, p);
     h->report.leaf_persistent = persistent ? 1 : 0;
+    if (!dp.stages.empty()) {
+        h->report.workspace_bytes = (int64_t)arena_bytes;
+        for (const auto& sp : dp.stages) h->report.kernel_launches += sp->plan.launches();
+    }
     h->last_stream = st;
     h->pending_flags = p.fallback;
     h->pending_residual = h->residual;
@@ -941,7 +1057,7 @@ ata_status_t ata_gram_noalloc(ata_handle_t h, const void* A, int64_t m, int64_t 
     choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
     const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
-                      h->popt.variant, tail_slots(h, mode, tile_cfg)};
+                      h->popt.variant, tail_slots(h, mode, tile_cfg), false};
     const size_t limit = h->ws_limit > 0 ? std::min<size_t>((size_t)h->ws_limit, ATA_NOALLOC_SCRATCH_BYTES)
                                          : (size_t)ATA_NOALLOC_SCRATCH_BYTES;
     auto it = h->static_plans.find(key);

@@ -1082,6 +1082,84 @@ hipError_t launch_eq_unscale(float* Cp, int64_t n, const int* e, hipStream_t str
     return hipGetLastError();
 }
 
+namespace {
+
+// Bounded workspace: one pre-sum on its own, one element per work item
+// (consecutive items are consecutive columns of a row).
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void sum2_kernel(const Sum2Desc* tasks, int ntasks, int64_t items,
+                                                          const T* A, T* arena, const uint8_t* flags) {
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < items; vb += gridDim.x) {
+        const int64_t x = vb * EW_THREADS + threadIdx.x;
+        if (x >= items) continue;
+        const Sum2Desc& d = tasks[block_task(tasks, ntasks, vb)];
+        const int64_t e = x - d.elem_begin;
+        if (e >= d.elems) continue;
+        if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) continue;
+        const int64_t r = udiv(e, d.cols), c = e - r * d.cols;
+        auto get = [&](const View& v) -> T {
+            const T* base = (v.base == BASE_A ? A : arena) + v.off;
+            return r < v.prows && c < v.pcols ? base[r * v.ld + c] : T(0);
+        };
+        const T a = get(d.a), b = get(d.b);
+        arena[d.out_off + e] = d.sign > 0 ? a + b : a - b;
+    }
+}
+
+// Bounded workspace: product i of a root into its one or two quadrants (the
+// first contribution overwrites), one product element per work item.
+template <class T>
+__global__ __launch_bounds__(EW_THREADS) void accum_kernel(const AccumDesc* tasks, int ntasks, int64_t items,
+                                                           T* C, T* arena, const uint8_t* flags) {
+    for (int64_t vb = blockIdx.x; vb * EW_THREADS < items; vb += gridDim.x) {
+        const int64_t x = vb * EW_THREADS + threadIdx.x;
+        if (x >= items) continue;
+        const AccumDesc& d = tasks[block_task(tasks, ntasks, vb)];
+        const int64_t e = x - d.elem_begin;
+        if (e >= d.elems) continue;
+        if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) continue;
+        const int64_t i = udiv(e, d.k2), j = e - i * d.k2;
+        const T m = arena[d.m_off + e];
+        for (int q = 0; q < d.nq; ++q) {
+            const int quad = d.quad[q];
+            const int64_t ro = quad >= 2 ? d.n1 : 0, co = (quad & 1) ? d.k1 : 0;
+            const int64_t rl = quad >= 2 ? d.n2 : d.n1, cl = (quad & 1) ? d.k2 : d.k1;
+            if (i >= rl || j >= cl) continue;
+            const int64_t ii = ro + i, jj = co + j;
+            T* p = d.out_kind == OUT_PACKED ? C + packed_index(d.out_row0 + ii, d.out_col0 + jj)
+                   : d.out_kind == OUT_CDENSE ? C + (d.out_row0 + ii) * d.out_ld + d.out_col0 + jj
+                                              : arena + d.out_off + ii * d.out_ld + jj;
+            *p = d.first[q] ? m : d.sign[q] > 0 ? *p + m : *p - m;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sum2(int32_t mode, const Sum2Desc* d_tasks, int ntasks, int64_t items, const void* A,
+                       void* arena, const uint8_t* flags, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(sum2_kernel<double>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream, d_tasks, ntasks,
+                           items, static_cast<const double*>(A), static_cast<double*>(arena), flags);
+    else
+        hipLaunchKernelGGL(sum2_kernel<float>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream, d_tasks, ntasks,
+                           items, static_cast<const float*>(A), static_cast<float*>(arena), flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_accum(int32_t mode, const AccumDesc* d_tasks, int ntasks, int64_t items, void* C, void* arena,
+                        const uint8_t* flags, hipStream_t stream) {
+    if (items <= 0) return hipSuccess;
+    if (mode == MODE_F64)
+        hipLaunchKernelGGL(accum_kernel<double>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream, d_tasks, ntasks,
+                           items, static_cast<double*>(C), static_cast<double*>(arena), flags);
+    else
+        hipLaunchKernelGGL(accum_kernel<float>, dim3(ew_grid(items)), dim3(EW_THREADS), 0, stream, d_tasks, ntasks,
+                           items, static_cast<float*>(C), static_cast<float*>(arena), flags);
+    return hipGetLastError();
+}
+
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
                           void* C, void* arena, const uint8_t* flags, hipStream_t stream,
                           const BatchPtrs* bp) {

@@ -73,6 +73,13 @@ hipError_t launch_eq_scale(const float* A, int64_t m, int64_t n, int64_t lda, co
                            int* e, hipStream_t stream);
 hipError_t launch_eq_unscale(float* Cp, int64_t n, const int* e, hipStream_t stream);
 
+// Bounded workspace: single pre-sums (Sum2Desc) and the adding of one
+// product into its quadrants (AccumDesc).
+hipError_t launch_sum2(int32_t mode, const Sum2Desc* d_tasks, int ntasks, int64_t items, const void* A,
+                       void* arena, const uint8_t* flags, hipStream_t stream);
+hipError_t launch_accum(int32_t mode, const AccumDesc* d_tasks, int ntasks, int64_t items, void* C, void* arena,
+                        const uint8_t* flags, hipStream_t stream);
+
 // One height of Strassen combines (seven products -> four quadrants).
 hipError_t launch_combine(int32_t mode, const CombineDesc* d_tasks, int ntasks, int64_t items,
                           void* C, void* arena, const uint8_t* flags, hipStream_t stream,

@@ -54,12 +54,16 @@ int64_t Plan::alloc(int64_t elems) {
 }
 
 int64_t Plan::launches() const {
-    int64_t l = (int64_t)presum.size() + (leaves.empty() ? 0 : 1) + (int64_t)combine.size();
+    int64_t l = leaves.empty() ? 0 : 1;
+    for (const auto& v : presum) l += v.empty() ? 0 : 1;
+    for (const auto& v : combine) l += v.empty() ? 0 : 1;
     if (!pack.empty()) l += 1;
     if (!pack8.empty()) l += 1;
     if (!fb_leaves.empty()) l += 1;
     if (!reduce.empty()) l += 1;
     if (fallback) l += 3;  // column norm passes + flags
+    for (const auto& v : sums) l += v.empty() ? 0 : 1;
+    for (const auto& v : accum) l += v.empty() ? 0 : 1;
     return l;
 }
 
@@ -110,6 +114,17 @@ struct Builder {
     int32_t maxd;
     bool fb;
     bool counting = true;   // false while planning a fallback alternative
+    // bounded workspace: C21 blocks with Strassen levels are collected here
+    // instead of being planned in place
+    struct Root {
+        View X, Y;
+        Target t;
+        int32_t pn, pv;
+        int level;            // AtA depth of the node
+    };
+    bool collect = false;
+    std::vector<Root> roots;
+    int ata_level = 0;
 
     explicit Builder(Plan& plan) : p(plan), b(plan.b), maxd(plan.max_depth), fb(plan.fallback) {}
 
@@ -198,16 +213,22 @@ struct Builder {
             return;
         }
         const int64_t n1 = w / 2, n2 = w - n1;
+        ++ata_level;
         ata(c0, n1);
         ata(c0 + n1, n2);
+        --ata_level;
         const View X = a_cols(c0 + n1, n2), Y = a_cols(c0, n1);
         const Target t{OUT_PACKED, 0, 0, c0 + n1, c0};
-        if (fb && levels(p.m, n2, n1, 0) > 0) {
+        const bool deep = levels(p.m, n2, n1, 0) > 0;
+        if (fb && deep) {
             // flagged node: plain product, no Strassen (predicated on the device)
             counting = false;
             add_leaf(LEAF_GEMM, X, Y, t, 0, node, 1, -1);
             counting = true;
-            strassen(X, Y, t, 0, node, 0);
+            if (collect) roots.push_back(Root{X, Y, t, node, 0, ata_level});
+            else strassen(X, Y, t, 0, node, 0);
+        } else if (collect && deep) {
+            roots.push_back(Root{X, Y, t, -1, 0, ata_level});
         } else {
             strassen(X, Y, t, 0, -1, 0);
         }
@@ -373,7 +394,8 @@ void assign_packed(Plan& p) {
         // (a whole-A packing past the 4 GiB reach of a buffer resource gives
         // way to packings of the views themselves)
         const bool a_fits = std::max<int64_t>(1, cdiv(p.m, 8)) * p.n * 16 <= (int64_t)0xFFFFFF00;
-        if (V.base == BASE_A && a_fits && r0 % 8 == 0 && V.pcols == V.cols && (K % 8 == 0 || r0 + K == p.m)) {
+        if (V.base == BASE_A && a_fits && !p.own_packings && r0 % 8 == 0 && V.pcols == V.cols &&
+            (K % 8 == 0 || r0 + K == p.m)) {
             const int64_t base = packed_a();
             P.off = base + (r0 / 8) * p.n * 4 + c0 * 4;
             P.lo_delta = a_groups * p.n * 4;
@@ -476,6 +498,216 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     if (opt.slots > 0) balance_tail(p, opt.slots);
     finalize_plan(p);
     return p;
+}
+
+std::vector<Plan> make_staged_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt) {
+    if (mode < MODE_F64 || mode > MODE_FP8) throw std::invalid_argument("mode");
+    if (m < 0 || n < 0 || lda < std::max<int64_t>(1, n)) throw std::invalid_argument("sizes");
+    std::vector<Plan> stages;
+    Plan p;
+    p.mode = mode;
+    p.m = m;
+    p.n = n;
+    p.lda = lda;
+    p.b = opt.leaf_cutoff > 0 ? opt.leaf_cutoff : default_leaf_cutoff(mode, m, n, opt.tile_cfg);
+    p.max_depth = opt.max_depth >= 0 ? opt.max_depth : default_max_depth(mode, m);
+    p.fallback = mode != MODE_F64 && opt.spread_tau > 0 && n > 0 && m > 0;
+    p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
+    if (n == 0) {
+        stages.push_back(std::move(p));
+        return stages;
+    }
+    Builder bld(p);
+    bld.collect = true;
+    bld.ata(0, n);
+    std::vector<Builder::Root> roots = bld.roots;
+    if (mode == MODE_BF16X3 && m > 0) assign_packed(p);
+    if (mode == MODE_FP8 && m > 0) assign_quant(p);
+    if (p.fallback) build_colnorm_tasks(&p.m, &p.n, &p.lda, 1, p.col1, p.col2, &p.col_partial);
+    if (opt.split_target > 0) split_leaves(p, opt.split_target);
+    if (opt.slots > 0) balance_tail(p, opt.slots);
+    finalize_plan(p);
+
+    // Strassen's seven products of a node C = X^T Y: which sums they take
+    // (sx / sy: 0 = a quadrant, 1..5 = S_i / T_i) and where they go
+    struct Prod { int sx, qx, sy, qy; int nq; int quad[2]; int sign[2]; };
+    // quadrant codes of an operand: 0 = 11, 1 = 12, 2 = 21, 3 = 22
+    static const Prod prods[7] = {
+        {1, -1, 1, -1, 2, {0, 3}, {1, 1}},      // M1 = S1^T T1 -> C11, C22
+        {2, -1, 0, 0, 2, {2, 3}, {1, -1}},      // M2 = S2^T Y11 -> C21, -C22
+        {0, 0, 2, -1, 2, {1, 3}, {1, 1}},       // M3 = X11^T T2 -> C12, C22
+        {0, 3, 3, -1, 2, {0, 2}, {1, 1}},       // M4 = X22^T T3 -> C11, C21
+        {3, -1, 0, 3, 2, {0, 1}, {-1, 1}},      // M5 = S3^T Y22 -> -C11, C12
+        {4, -1, 4, -1, 1, {3, 0}, {1, 0}},      // M6 = S4^T T4 -> C22
+        {5, -1, 5, -1, 1, {0, 0}, {1, 0}},      // M7 = S5^T T5 -> C11
+    };
+    // the first product to reach each quadrant overwrites it
+    static const int first_of[4] = {0, 2, 1, 0};   // C11: M1, C12: M3, C21: M2, C22: M1
+    // S_i = a + sign b over quadrants of X (T_i over Y)
+    static const int ssum[5][3] = {{0, 3, 1}, {1, 3, 1}, {0, 2, 1}, {1, 0, -1}, {2, 3, -1}};
+    static const int tsum[5][3] = {{0, 3, 1}, {1, 3, -1}, {2, 0, -1}, {0, 1, 1}, {2, 3, 1}};
+    struct Node { View X, Y; Target t; };
+    int max_level = 0, max_root_levels = 0;
+    for (const auto& r : roots) {
+        max_level = std::max(max_level, r.level);
+        max_root_levels = std::max(max_root_levels, bld.levels(r.X.rows, r.X.cols, r.Y.cols, 0));
+    }
+    // stages of the roots for D sequential levels; adds the sequential nodes
+    // to *nodes and returns the largest stage arena
+    auto make_stages = [&](int D, std::vector<Plan>& out, int64_t* nodes, int32_t* levels) {
+        int64_t amax = 0;
+        for (int lv = 0; lv <= max_level; ++lv) {
+            std::vector<const Builder::Root*> grp;
+            int dg = D;
+            for (const auto& r : roots)
+                if (r.level == lv) {
+                    grp.push_back(&r);
+                    dg = std::min(dg, bld.levels(r.X.rows, r.X.cols, r.Y.cols, 0));
+                }
+            if (grp.empty() || dg <= 0) continue;
+            int64_t nseq = 1;
+            for (int j = 0; j < dg; ++j) nseq *= 7;
+            for (const auto* r : grp) {
+                int64_t pw = 1;
+                for (int j = 0; j < dg; ++j) { *nodes += pw; pw *= 7; }
+                (void)r;
+            }
+            *levels = std::max(*levels, dg);
+            for (int64_t seq = 0; seq < nseq; ++seq) {
+                int dig[16];
+                int64_t q = seq;
+                for (int j = dg - 1; j >= 0; --j) { dig[j] = (int)(q % 7); q /= 7; }
+                auto all_after = [&](int j, int v) {   // digits after level j (0-based) all equal v
+                    for (int u = j + 1; u < dg; ++u)
+                        if (dig[u] != v) return false;
+                    return true;
+                };
+                Plan s;
+                s.mode = mode;
+                s.m = m;
+                s.n = n;
+                s.lda = lda;
+                s.b = p.b;
+                s.max_depth = p.max_depth;
+                s.tile_cfg = p.tile_cfg;
+                s.own_packings = true;
+                s.sums.resize(dg);
+                s.accum.resize(dg);
+                Builder sb(s);
+                // level buffers of every root first, at the same offsets in every stage
+                std::vector<std::vector<int64_t>> soff(grp.size()), toff(grp.size()), moff(grp.size());
+                for (size_t g = 0; g < grp.size(); ++g) {
+                    int64_t mm = grp[g]->X.rows, nn = grp[g]->X.cols, kk = grp[g]->Y.cols;
+                    for (int j = 0; j < dg; ++j) {
+                        mm -= mm / 2; nn -= nn / 2; kk -= kk / 2;
+                        soff[g].push_back(s.alloc(mm * nn));
+                        toff[g].push_back(s.alloc(mm * kk));
+                        moff[g].push_back(s.alloc(nn * kk));
+                    }
+                }
+                for (size_t g = 0; g < grp.size(); ++g) {
+                    const Builder::Root& r = *grp[g];
+                    Node nd{r.X, r.Y, r.t};
+                    for (int j = 0; j < dg; ++j) {
+                        const View& X = nd.X;
+                        const View& Y = nd.Y;
+                        const int64_t mm = X.rows, nx = X.cols, k = Y.cols;
+                        const int64_t m1 = mm / 2, m2 = mm - m1, n1 = nx / 2, n2 = nx - n1, k1 = k / 2, k2 = k - k1;
+                        const View Xq[4] = {sub(X, 0, m1, m2, 0, n1, n2), sub(X, 0, m1, m2, n1, n2, n2),
+                                            sub(X, m1, m2, m2, 0, n1, n2), sub(X, m1, m2, m2, n1, n2, n2)};
+                        const View Yq[4] = {sub(Y, 0, m1, m2, 0, k1, k2), sub(Y, 0, m1, m2, k1, k2, k2),
+                                            sub(Y, m1, m2, m2, 0, k1, k2), sub(Y, m1, m2, m2, k1, k2, k2)};
+                        const int i = dig[j];
+                        const Prod& pr = prods[i];
+                        const bool start = all_after(j, 0);   // this prefix begins: form its sums
+                        auto operand = [&](int sidx, int qd, const View* Vq, const int (*tab)[3], int64_t cols,
+                                           int64_t off) {
+                            if (sidx == 0) return Vq[qd];
+                            if (start) {
+                                Sum2Desc d{};
+                                d.a = Vq[tab[sidx - 1][0]];
+                                d.b = Vq[tab[sidx - 1][1]];
+                                d.sign = tab[sidx - 1][2];
+                                d.rows = m2;
+                                d.cols = cols;
+                                d.out_off = off;
+                                d.elems = m2 * cols;
+                                d.pred_node = r.pn;
+                                d.pred_value = r.pv;
+                                s.sums[j].push_back(d);
+                            }
+                            return arena_view(off, m2, cols);
+                        };
+                        const View Xo = operand(pr.sx, pr.qx, Xq, ssum, n2, soff[g][j]);
+                        const View Yo = operand(pr.sy, pr.qy, Yq, tsum, k2, toff[g][j]);
+                        if (all_after(j, 6)) {                // the product is finished in this stage
+                            AccumDesc a{};
+                            a.m_off = moff[g][j];
+                            a.n1 = n1; a.n2 = n2; a.k1 = k1; a.k2 = k2;
+                            a.out_kind = nd.t.kind;
+                            a.out_off = nd.t.off; a.out_ld = nd.t.ld; a.out_row0 = nd.t.row0; a.out_col0 = nd.t.col0;
+                            a.elems = n2 * k2;
+                            a.pred_node = r.pn;
+                            a.pred_value = r.pv;
+                            a.nq = pr.nq;
+                            for (int u = 0; u < pr.nq; ++u) {
+                                a.quad[u] = pr.quad[u];
+                                a.sign[u] = pr.sign[u];
+                                a.first[u] = first_of[pr.quad[u]] == i ? 1 : 0;
+                            }
+                            s.accum[dg - 1 - j].push_back(a);    // deepest level first
+                        }
+                        nd = Node{Xo, Yo, Target{OUT_DENSE, moff[g][j], k2, 0, 0}};
+                    }
+                    sb.strassen(nd.X, nd.Y, nd.t, dg, r.pn, r.pv);
+                }
+                if (mode == MODE_BF16X3 && m > 0) assign_packed(s);
+                if (mode == MODE_FP8 && m > 0) assign_quant(s);
+                if (opt.split_target > 0) split_leaves(s, opt.split_target);
+                if (opt.slots > 0) balance_tail(s, opt.slots);
+                finalize_plan(s);
+                for (auto& lvl : s.sums) {
+                    int64_t e = 0;
+                    for (auto& d : lvl) { d.elem_begin = e; e = item_align(e + d.elems); }
+                }
+                for (auto& lvl : s.accum) {
+                    int64_t e = 0;
+                    for (auto& d : lvl) { d.elem_begin = e; e = item_align(e + d.elems); }
+                }
+                while (!s.sums.empty() && s.sums.back().empty()) s.sums.pop_back();
+                amax = std::max(amax, s.arena_elems);
+                out.push_back(std::move(s));
+            }
+        }
+        return amax;
+    };
+    std::vector<Plan> rest;
+    if (!roots.empty()) {
+        const double target = 1.5 * (double)n * (double)std::max(m, n);
+        int D = opt.seq_levels > 0 ? std::min(opt.seq_levels, max_root_levels) : 1;
+        for (;;) {
+            rest.clear();
+            int64_t nodes = 0;
+            int32_t lv = 0;
+            const int64_t amax = std::max(p.arena_elems, make_stages(D, rest, &nodes, &lv));
+            if (opt.seq_levels > 0 || (double)amax <= target || D >= max_root_levels) {
+                p.stats.strassen_nodes += nodes;
+                p.stats.max_levels = std::max(p.stats.max_levels, lv);
+                break;
+            }
+            ++D;
+        }
+    }
+    for (auto& s : rest) {
+        p.stats.gemm_leaves += s.stats.gemm_leaves;
+        p.stats.strassen_nodes += s.stats.strassen_nodes;
+        p.stats.mults += s.stats.mults;
+        p.stats.max_levels = std::max(p.stats.max_levels, s.stats.max_levels);
+        stages.push_back(std::move(s));
+    }
+    if (!roots.empty()) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, 1);
+    stages.insert(stages.begin(), std::move(p));
+    return stages;
 }
 
 void fuse_pack_into_norms(Plan& p, std::vector<ColDesc>& col1) {

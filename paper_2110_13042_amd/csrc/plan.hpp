@@ -183,6 +183,40 @@ struct CombineDesc {
     int32_t unit;                 // columns per work item: 4 or 1 (k2 not a multiple of 4)
 };
 
+// Bounded workspace (PlanOptions::bounded): one sum of a Strassen root's
+// product operand, formed on its own into a dense buffer (row stride cols):
+// out = a + sign * b over rows x cols, each view read as zero outside its
+// physical extent (the same IEEE sum the pre-sum pass stores).
+struct Sum2Desc {
+    View a, b;
+    int64_t rows, cols;
+    int64_t out_off;               // arena element offset
+    int64_t elem_begin, elems;     // one work item per element
+    int32_t sign;                  // +1 or -1
+    int32_t pred_node, pred_value;
+    int32_t prob;
+};
+
+// Bounded workspace: product i (n2 x k2, row stride k2) of a Strassen root
+// added into its one or two quadrants of the root's target.  The products
+// run in order and the first contribution to a quadrant overwrites it, so
+// every quadrant receives the combine's own left-to-right sum (C11 =
+// ((M1 + M4) - M5) + M7, C12 = M3 + M5, C21 = M2 + M4, C22 = ((M1 - M2) + M3)
+// + M6).
+struct AccumDesc {
+    int64_t m_off;
+    int64_t n1, n2, k1, k2;
+    int64_t out_off, out_ld, out_row0, out_col0;
+    int64_t elem_begin, elems;     // one work item per product element
+    int32_t out_kind;
+    int32_t pred_node, pred_value;
+    int32_t nq;                    // targets: 1 or 2
+    int32_t quad[2];               // 0: C11, 1: C12, 2: C21, 3: C22
+    int32_t sign[2];               // +1 or -1
+    int32_t first[2];              // 1: the quadrant's first contribution (overwrite)
+    int32_t prob, pad_;
+};
+
 // Column-norm task of one problem.  Pass 1: a workgroup sums the squares of
 // 256 columns over one chunk of `rows` rows (elems = chunks x column blocks x
 // ITEM_BLOCK items); pass 2: one item per column sums the chunks in order.
@@ -211,6 +245,10 @@ struct PlanOptions {
     int32_t variant = 0;           // Strassen node: 0 = Strassen's form, 1 = Winograd's
     int64_t slots = 0;             // > 0: balance the leaf launch's last round over this
                                    // many resident workgroups (balance_tail)
+    bool bounded = false;          // make_staged_plan: Strassen roots product by product
+    int32_t seq_levels = 0;        // make_staged_plan: top levels run product by product
+                                   // (0: the fewest that keep the workspace within
+                                   // 3/2 n max(m, n) elements)
 };
 
 struct PlanStats {
@@ -239,6 +277,9 @@ struct Plan {
     std::vector<LeafDesc> fb_leaves;                // SYRK leaves under the spread check
     std::vector<ReduceDesc> reduce;                 // split leaves: partial sums
     std::vector<std::vector<CombineDesc>> combine;  // [height-1] bottom-up
+    std::vector<std::vector<Sum2Desc>> sums;        // bounded stages: single pre-sums, top-down (first)
+    std::vector<std::vector<AccumDesc>> accum;      // bounded stages: products into quadrants, bottom-up (last)
+    bool own_packings = false;                      // split-BF16: pack each leaf operand on its own
     std::vector<NodeDesc> nodes;                    // AtA nodes (flags)
     std::vector<ColDesc> col1, col2;                // column-norm passes (when fallback)
     int64_t col_partial = 0;                        // doubles of the pass-1 partial sums
@@ -260,6 +301,21 @@ int32_t default_max_depth(int32_t mode, int64_t m);
 
 // Builds the plan (host only).  Throws std::invalid_argument on bad sizes.
 Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);
+
+// Bounded-workspace form of make_plan (Sec. 3.3's buffer reuse): stage 0 is
+// the AtA plan with every Strassen root's C21 block taken out (SYRK leaves,
+// depth-0 blocks, column norms and flags).  The top D levels of every root
+// then run product by product: for each AtA level that has Strassen roots
+// and each sequence (i_1, .., i_D) of products, one stage forms the operand
+// sums that sequence needs on their own (Sum2Desc; a level's sums once per
+// prefix), runs the remaining Strassen levels of the sequence's product
+// resident into one buffer, and adds each finished product into its parent's
+// quadrants (AccumDesc), bottom-up.  Level j's buffers (one product's sums
+// and result) sit at the same arena offsets in every stage and persist while
+// their prefix is unchanged; everything below them is reused by every stage.
+// Stage 0's stats are the whole computation's (multiplications, leaves,
+// nodes, levels).  Strassen's form only (variant 0); no fused pre-sums.
+std::vector<Plan> make_staged_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOptions& opt);
 
 // Plan of the general product C = A^T B (A m x n, B m x k, C n x k dense):
 // one Strassen recursion (the paper's FastStrassen step on A^T B) writing

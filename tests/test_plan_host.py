@@ -2,7 +2,8 @@
 planner source is compiled with the host compiler into a small driver that
 prints the plans' structure.  Covers the tail balancer, the FP64 fallback's
 own K split, the K-chunk granule, the per-operand split-BF16 packing past the
-4 GiB buffer reach, the pre-sum work-item width and Winograd's workspace."""
+4 GiB buffer reach, the pre-sum work-item width, Winograd's workspace, and
+the bounded-workspace (staged) plans against the resident ones."""
 import os
 import shutil
 import subprocess
@@ -17,6 +18,7 @@ DRIVER = r"""
 #include <algorithm>
 #include <cstdio>
 #include <stdexcept>
+#include <vector>
 using namespace ata;
 
 static void show(const char* tag, int32_t mode, int64_t m, int64_t n, int64_t b, int32_t d, int32_t tile,
@@ -46,7 +48,39 @@ static void show(const char* tag, int32_t mode, int64_t m, int64_t n, int64_t b,
     }
 }
 
+// Bounded workspace: the staged plan against the resident one.
+static void show_staged(const char* tag, int32_t mode, int64_t m, int64_t n, int64_t b, int32_t d,
+                        double tau) {
+    PlanOptions o;
+    o.leaf_cutoff = b; o.max_depth = d; o.spread_tau = tau; o.split_target = 2048; o.slots = 0;
+    try {
+        Plan r = make_plan(mode, m, n, n, o);
+        o.bounded = true;
+        std::vector<Plan> st = make_staged_plan(mode, m, n, n, o);
+        int64_t maxa = 0, sums = 0, acc = 0, leaves = 0;
+        for (const auto& q : st) {
+            maxa = std::max<int64_t>(maxa, q.arena_elems);
+            for (const auto& v : q.sums) sums += (int64_t)v.size();
+            for (const auto& v : q.accum) acc += (int64_t)v.size();
+            leaves += (int64_t)q.leaves.size();
+        }
+        int64_t rleaves = (int64_t)r.leaves.size();
+        printf("%s stages=%zu arena=%lld resident_arena=%lld mults=%lld resident_mults=%lld levels=%d "
+               "resident_levels=%d nodes=%lld resident_nodes=%lld leaves=%lld resident_leaves=%lld sums=%lld "
+               "accum=%lld\n", tag, st.size(), (long long)maxa, (long long)r.arena_elems,
+               (long long)st[0].stats.mults, (long long)r.stats.mults, st[0].stats.max_levels, r.stats.max_levels,
+               (long long)st[0].stats.strassen_nodes, (long long)r.stats.strassen_nodes, (long long)leaves,
+               (long long)rleaves, (long long)sums, (long long)acc);
+    } catch (const std::exception& e) {
+        printf("%s error=%s\n", tag, e.what());
+    }
+}
+
 int main() {
+    show_staged("staged_f64_30k", MODE_F64, 30000, 30000, 0, -1, 0.0);
+    show_staged("staged_f64_odd", MODE_F64, 3001, 2999, 256, 3, 0.0);
+    show_staged("staged_f32_fb", MODE_F32, 4096, 4096, 512, 2, 4096.0);
+    show_staged("staged_bf16", MODE_BF16X3, 4096, 4096, 512, 2, 4096.0);
     show("bf16_tail", MODE_BF16X3, 8192, 8192, 256, 0, 2, 4096.0, 256);
     show("bf16_nobal", MODE_BF16X3, 8192, 8192, 256, 0, 2, 4096.0, 0);
     show("f32_balanced", MODE_F32, 8192, 8192, 2048, 1, 2, 4096.0, 256);
@@ -128,3 +162,26 @@ def test_winograd_needs_less_workspace(plans):
     """Four pre-sum buffers per operand instead of five."""
     assert plans["winograd"]["arena"] < plans["strassen"]["arena"]
     assert plans["winograd"]["levels"] == plans["strassen"]["levels"] == 1
+
+
+def test_staged_plan_performs_the_resident_plans_products(plans):
+    """The bounded-workspace plan runs exactly the resident plan's
+    multiplications, Strassen nodes and levels, as (for every root) seven
+    single-sum stages; its workspace is the largest stage's."""
+    for tag in ("staged_f64_30k", "staged_f64_odd", "staged_f32_fb", "staged_bf16"):
+        p = plans[tag]
+        assert "error" not in p, (tag, p)
+        assert p["mults"] == p["resident_mults"], tag
+        assert p["nodes"] == p["resident_nodes"] and p["levels"] == p["resident_levels"] >= 2, tag
+        assert p["stages"] > 7 and p["accum"] % 7 == 0, tag
+        assert p["arena"] < p["resident_arena"], tag
+
+
+def test_staged_workspace_within_sec33_bound(plans):
+    """FP64 30000^2 at the default leaf cutoff and depth: every level resident
+    needs about 28 n^2 elements (224 GB); the staged plan's largest stage stays
+    within Sec. 3.3's 3/2 n^2."""
+    p = plans["staged_f64_30k"]
+    n = 30000
+    assert p["resident_arena"] > 20 * n * n
+    assert p["arena"] <= 1.5 * n * n
