@@ -210,6 +210,10 @@ def make_handle(ata, args):
         h.set("balance_tail", 0)
     if args.leaf_persistent >= 0:
         h.set("leaf_persistent", args.leaf_persistent)
+    if args.overlap >= 0:
+        h.set("overlap", args.overlap)
+    if args.bounded:
+        h.set("bounded_workspace", 1)
     if args.spread_tau >= 0:
         h.set("spread_tau", args.spread_tau)
     return h
@@ -424,6 +428,11 @@ def main() -> int:
     ap.add_argument("--leaf-persistent", type=int, default=-1,
                     help="leaf launch: 1 = persistent grid with per-XCD queues, 0 = one workgroup per tile, "
                          "-1 = the library's automatic choice")
+    ap.add_argument("--overlap", type=int, default=-1,
+                    help="1: run the leaves that read only A beside the pre-sums on a second stream; 0: one "
+                         "leaf launch; -1: the library's default")
+    ap.add_argument("--bounded", action="store_true",
+                    help="bounded workspace: Strassen roots run product by product")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

@@ -214,7 +214,25 @@ typedef enum {
        only (ATA_OPT_STRASSEN_FORM and ATA_OPT_FUSE_PRESUM are ignored).
        Applies to ata_gram; ata_gram_noalloc, ata_gram_batched and
        ata_gemm_tn ignore it.  0 = every level resident (default). */
-    ATA_OPT_BOUNDED_WORKSPACE = 19
+    ATA_OPT_BOUNDED_WORKSPACE = 19,
+    /* Overlap of the Strassen pre-sums with leaf products.  The leaves whose
+       operands are views of A (SYRK leaves and depth-0 blocks, and with them
+       the FP64 fallback) need no pre-sum: they run in their own launch on a
+       second stream (created by the handle, default priority), forked from
+       `stream` after the column norms and joined back before the split-K
+       reduce, while `stream` runs the pre-sums and the other leaves.  Plans
+       without Strassen levels, FP8 plans and split-BF16 plans that pack A
+       outside the column-norm pass (spread check off) run as one launch.
+       Results are bit-identical either way (the same tiles, each computed
+       once).  Profiling: phase 1 (pre-sums) then includes the first leaf
+       launch's time, so the leaf time is phases 1 + 2.  Off by default: the
+       256 x 256 leaf engines fill every CU's register file, so the pre-sums
+       cannot run beside them and the split leaf launch loses its single
+       longest-first order (measured slower on the 16384 x 16384 FP32 and
+       split-BF16 plans).  1 = on, 0 = off (default), -1 = the default.
+       Ignored by ata_gram_noalloc, batches, ata_gemm_tn and bounded-workspace
+       plans. */
+    ATA_OPT_OVERLAP = 20
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */
@@ -243,6 +261,9 @@ typedef struct {
                                      grid, 0 = one workgroup per tile          */
     int32_t tail_split_leaves;    /* leaves cut by the tail balancer (0: none) */
     int32_t tail_split_chunks;    /* K chunks per cut leaf                     */
+    int32_t overlapped;           /* 1 = the leaves reading only A ran beside
+                                     the pre-sums (ATA_OPT_OVERLAP)            */
+    int32_t pad_;
 } ata_report_t;
 
 /* One leaf of a plan, as returned by ata_plan_query. */

@@ -33,6 +33,7 @@ OPT_FUSE_PRESUM = 16
 OPT_STRASSEN_FORM = 17
 OPT_BALANCE_TAIL = 18
 OPT_BOUNDED_WORKSPACE = 19
+OPT_OVERLAP = 20
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -54,7 +55,8 @@ class Report(ctypes.Structure):
                 ("flagged_nodes", ctypes.c_int64), ("residual", ctypes.c_double),
                 ("profiled_calls", ctypes.c_int64), ("phase_ms", ctypes.c_double * 5),
                 ("leaf_tile", ctypes.c_int32), ("leaf_persistent", ctypes.c_int32),
-                ("tail_split_leaves", ctypes.c_int32), ("tail_split_chunks", ctypes.c_int32)]
+                ("tail_split_leaves", ctypes.c_int32), ("tail_split_chunks", ctypes.c_int32),
+                ("overlapped", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -293,7 +295,8 @@ class Handle:
                "split_target": OPT_SPLIT_TARGET, "batch_use_table": OPT_BATCH_USE_TABLE,
                "equilibrate": OPT_EQUILIBRATE, "leaf_persistent": OPT_LEAF_PERSISTENT,
                "fuse_presum": OPT_FUSE_PRESUM, "strassen_form": OPT_STRASSEN_FORM,
-               "balance_tail": OPT_BALANCE_TAIL, "bounded_workspace": OPT_BOUNDED_WORKSPACE}[name]
+               "balance_tail": OPT_BALANCE_TAIL, "bounded_workspace": OPT_BOUNDED_WORKSPACE,
+               "overlap": OPT_OVERLAP}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

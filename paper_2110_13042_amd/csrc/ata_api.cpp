@@ -37,10 +37,11 @@ struct PlanKey {
     int32_t variant;
     int64_t slots;
     bool bounded;
+    bool overlap;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant, slots, bounded) <
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant, slots, bounded, overlap) <
                std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant,
-                        o.slots, o.bounded);
+                        o.slots, o.bounded, o.overlap);
     }
 };
 
@@ -238,6 +239,9 @@ struct ata_ctx {
     int leaf_persistent = -1;
     bool balance_tail = true;          // split the leaves of an underfilled last round
     bool bounded = false;              // Strassen roots product by product (make_staged_plan)
+    int overlap = 0;                   // pre-sums beside the A-only leaves: 1 on, 0 off, -1 automatic (off)
+    hipStream_t side = nullptr;        // second stream of an overlapped call (default priority)
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     uint64_t arena_gen = 0;
     // phase profiling: six events per profiled call, summed at report time
     bool profile = false;
@@ -520,6 +524,7 @@ ata_status_t build_gram_plan(const ata_ctx* h, const PlanKey& k, Fits fits, Plan
     o.fuse_presum = k.fuse;
     o.variant = k.variant;
     o.slots = k.slots;
+    o.overlap = k.overlap;
     try {
         out = make_plan(k.mode, k.m, k.n, k.lda, o);
         while (out.stats.max_levels > 0 && !fits(out)) {
@@ -609,6 +614,9 @@ ata_status_t ata_destroy(ata_handle_t h) {
     h->plans.clear();
     if (h->batch_stream) (void)hipStreamDestroy(h->batch_stream);
     if (h->batch_in) (void)hipEventDestroy(h->batch_in);
+    if (h->side) (void)hipStreamDestroy(h->side);
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    if (h->join_ev) (void)hipEventDestroy(h->join_ev);
     clear_events(h);
     if (h->arena) (void)hipFree(h->arena);
     if (h->aux) (void)hipFree(h->aux);
@@ -687,6 +695,10 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
             if (value < 0 || value > 1e9) return ATA_ERR_INVALID_VALUE;
             h->split_target = (int64_t)value;
             return ATA_OK;
+        case ATA_OPT_OVERLAP:
+            if (value != -1.0 && value != 0.0 && value != 1.0) return ATA_ERR_INVALID_VALUE;
+            h->overlap = (int)value;
+            return ATA_OK;
         case ATA_OPT_BOUNDED_WORKSPACE:
             h->bounded = value != 0.0;
             return ATA_OK;
@@ -763,16 +775,23 @@ namespace {
 // are the call's workspace; `ev` holds six profiling events or is null.
 hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, void* C_packed, void* arena,
                         unsigned char* aux, const AuxLayout& ax, bool residual, hipStream_t st, hipEvent_t* ev,
-                        bool& persistent, bool mark_end = true) {
+                        bool& persistent, bool mark_end = true, bool overlap = false) {
     const Plan& p = dp.plan;
     const int32_t mode = p.mode;
+    // two blocks of eight queue heads: the A-only leaves' launch on the side
+    // stream, and the caller stream's launch
     BatchPtrs pq{nullptr, nullptr, reinterpret_cast<unsigned long long*>(aux + ax.counter_off), 0};
+    BatchPtrs pq2 = pq;
+    pq2.counter += 8;
     const BatchPtrs* lp = nullptr;
+    const BatchPtrs* lp2 = nullptr;
     if (persistent_for(h->leaf_persistent, p)) {
-        pq.persistent_blocks = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
+        pq.persistent_blocks = pq2.persistent_blocks = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
         lp = &pq;
+        lp2 = &pq2;
     }
     persistent = lp != nullptr;
+    const bool ov = overlap && p.indep_tiles > 0 && h->side && h->fork_ev && h->join_ev;
     uint8_t* flags = aux + ax.flags_off;
     double* partial = reinterpret_cast<double*>(aux + ax.part_off);
     double* nu = reinterpret_cast<double*>(aux + ax.nu_off);
@@ -791,6 +810,24 @@ hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, v
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
     mark(1);
+    // packings and quantisations of views of A (the A-only leaves read them)
+    const int32_t ps = p.pack_split, qs = p.pack8_split;
+    if (e == hipSuccess && ps > 0)
+        e = launch_pack(dp.d_pack, ps, p.pack[ps - 1].elem_begin + p.pack[ps - 1].elems, A, arena, flags, st);
+    if (e == hipSuccess && qs > 0)
+        e = launch_quant8(dp.d_pack8, qs, p.pack8[qs - 1].elem_begin + p.pack8[qs - 1].elems, A, arena, flags, st);
+    if (ov && e == hipSuccess) {
+        // the leaves that read only A, and the FP64 fallback, beside the pre-sums
+        e = hipEventRecord(h->fork_ev, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->fork_ev, 0);
+        if (e == hipSuccess)
+            e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.indep_tiles, A, C_packed, arena,
+                              flags, h->chunk, h->band, h->side, lp);
+        if (e == hipSuccess && !p.fb_leaves.empty())
+            e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed, arena,
+                                       flags, h->chunk, h->band, h->side);
+        if (e == hipSuccess) e = hipEventRecord(h->join_ev, h->side);
+    }
     for (size_t l = 0; e == hipSuccess && l < p.sums.size(); ++l) {
         const auto& lv = p.sums[l];
         if (!lv.empty())
@@ -805,19 +842,26 @@ hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, v
             e = launch_presum(mode, dp.d_presum[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems,
                               A, arena, flags, st);
     }
-    if (e == hipSuccess && !p.pack.empty())
-        e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
+    if (e == hipSuccess && (int32_t)p.pack.size() > ps)
+        e = launch_pack(dp.d_pack + ps, (int)p.pack.size() - ps, p.pack.back().elem_begin + p.pack.back().elems,
                         A, arena, flags, st);
-    if (e == hipSuccess && !p.pack8.empty())
-        e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems,
-                          A, arena, flags, st);
+    if (e == hipSuccess && (int32_t)p.pack8.size() > qs)
+        e = launch_quant8(dp.d_pack8 + qs, (int)p.pack8.size() - qs,
+                          p.pack8.back().elem_begin + p.pack8.back().elems, A, arena, flags, st);
     mark(2);
-    if (e == hipSuccess)
-        e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed, arena,
-                          flags, h->chunk, h->band, st, lp);
-    if (e == hipSuccess && !p.fb_leaves.empty())
-        e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
-                                   arena, flags, h->chunk, h->band, st);
+    if (ov) {
+        if (e == hipSuccess)
+            e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles - p.indep_tiles, A,
+                              C_packed, arena, flags, h->chunk, h->band, st, lp2, nullptr, p.indep_tiles);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, h->join_ev, 0);
+    } else {
+        if (e == hipSuccess)
+            e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed,
+                              arena, flags, h->chunk, h->band, st, lp);
+        if (e == hipSuccess && !p.fb_leaves.empty())
+            e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
+                                       arena, flags, h->chunk, h->band, st);
+    }
     if (e == hipSuccess && !p.reduce.empty())
         e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
                           C_packed, arena, flags, st);
@@ -952,8 +996,10 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
     const int64_t slots = tail_slots(h, mode, tile_cfg);
     const bool bounded = h->bounded;
+    const bool overlap = !bounded && h->overlap == 1;
     const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target,
-                      bounded ? false : h->popt.fuse_presum, bounded ? 0 : h->popt.variant, slots, bounded};
+                      bounded ? false : h->popt.fuse_presum, bounded ? 0 : h->popt.variant, slots, bounded,
+                      overlap};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -985,14 +1031,26 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     unsigned char* aux = static_cast<unsigned char*>(h->aux);
     hipEvent_t* ev = nullptr;
     if (take_events(h, ev) != ATA_OK) return ATA_ERR_HIP;
+    if (overlap && p.indep_tiles > 0 && !h->side) {
+        if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+            h->side = nullptr;
+            return ATA_ERR_HIP;
+        }
+        if (hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess)
+            return ATA_ERR_HIP;
+    }
     bool persistent = false;
     const hipError_t eq = dp.stages.empty()
-                              ? enqueue_gram(h, dp, A, C_packed, h->arena, aux, ax, h->residual, st, ev, persistent)
+                              ? enqueue_gram(h, dp, A, C_packed, h->arena, aux, ax, h->residual, st, ev, persistent,
+                                             true, overlap)
                               : enqueue_staged(h, dp, A, C_packed, h->arena, aux, ax, h->residual, st, ev, persistent);
     if (eq != hipSuccess) return ATA_ERR_HIP;
 
     fill_report(h->report, p);
     h->report.leaf_persistent = persistent ? 1 : 0;
+    h->report.overlapped = overlap && p.indep_tiles > 0 && dp.stages.empty() ? 1 : 0;
+    if (h->report.overlapped) h->report.kernel_launches += 1;
     if (!dp.stages.empty()) {
         h->report.workspace_bytes = (int64_t)arena_bytes;
         for (const auto& sp : dp.stages) h->report.kernel_launches += sp->plan.launches();

@@ -26,10 +26,12 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg);
 // order: every window of 8 x chunk consecutive tiles gives each XCD chunk
 // consecutive tiles; GEMM leaves number their tiles in bands of `band` tile
 // rows, column by column.
+// tile_base: the launch covers tiles [tile_base, tile_base + ntiles) of the
+// plan's tile order (a plan's leaves may be split over two launches).
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
                          int chunk, int band, hipStream_t stream, const BatchPtrs* bp = nullptr,
-                         const void* B = nullptr);
+                         const void* B = nullptr, int64_t tile_base = 0);
 
 // FP64 fallback of flagged SYRK leaves (FP32 inputs and output); the tasks
 // are the plan's fallback-capable SYRK leaves, unflagged ones exit at once.

@@ -109,6 +109,7 @@ struct LeafArgs {
     void* const* Cptrs;
     unsigned long long* counter;  // persistent mode: eight tile queue heads (else null)
     const void* B;                // second input of a general product (else null)
+    int64_t tile_base;            // first tile of this launch in the plan's tile order
 };
 
 __device__ __forceinline__ int find_leaf(const LeafDesc* t, int n, int64_t x) {
@@ -1680,7 +1681,7 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
 template <int MODE>
 __global__ __launch_bounds__(threads_for(MODE), min_blocks_for(MODE)) void leaf_kernel(LeafArgs args) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[lds_bytes(MODE)];
-    run_tile<MODE>(args, xcd_remap(blockIdx.x, args.ntiles, args.chunk), smem);
+    run_tile<MODE>(args, args.tile_base + xcd_remap(blockIdx.x, args.ntiles, args.chunk), smem);
 }
 
 // Persistent form (its own kernel, so that the queue logic does not change
@@ -1715,7 +1716,7 @@ void leaf_kernel_persistent(LeafArgs args) {
             ++probe;
             continue;
         }
-        run_tile<MODE>(args, tile, smem);
+        run_tile<MODE>(args, args.tile_base + tile, smem);
     }
 }
 
@@ -1727,11 +1728,12 @@ __global__ void zero_counter(unsigned long long* c) { c[threadIdx.x] = 0ull; }
 
 hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks,
                          int64_t ntiles, const void* A, void* C, void* arena, const uint8_t* flags,
-                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp, const void* B) {
+                         int chunk, int band, hipStream_t stream, const BatchPtrs* bp, const void* B,
+                         int64_t tile_base) {
     if (ntiles <= 0) return hipSuccess;
     // a dispatch counts its work-items in 32 bits: refuse a grid that would wrap
     if (!(bp && bp->counter) && ntiles > (int64_t)(0xFFFFFFFFu / 512u)) return hipErrorInvalidConfiguration;
-    LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr, B};
+    LeafArgs a{d_tasks, ntasks, chunk, band, ntiles, A, C, arena, flags, nullptr, nullptr, nullptr, B, tile_base};
     dim3 grid((unsigned)ntiles);
     if (bp) {
         a.Aptrs = bp->A;

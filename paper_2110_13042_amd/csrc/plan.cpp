@@ -57,8 +57,10 @@ int64_t Plan::launches() const {
     int64_t l = leaves.empty() ? 0 : 1;
     for (const auto& v : presum) l += v.empty() ? 0 : 1;
     for (const auto& v : combine) l += v.empty() ? 0 : 1;
-    if (!pack.empty()) l += 1;
-    if (!pack8.empty()) l += 1;
+    if (pack_split > 0) l += 1;
+    if ((int64_t)pack.size() > pack_split) l += 1;
+    if (pack8_split > 0) l += 1;
+    if ((int64_t)pack8.size() > pack8_split) l += 1;
     if (!fb_leaves.empty()) l += 1;
     if (!reduce.empty()) l += 1;
     if (fallback) l += 3;  // column norm passes + flags
@@ -488,6 +490,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
     p.fuse = opt.fuse_presum;
     p.variant = opt.variant;
+    p.overlap = opt.overlap;
     if (n == 0) return p;
     Builder bld(p);
     bld.ata(0, n);
@@ -729,6 +732,8 @@ void fuse_pack_into_norms(Plan& p, std::vector<ColDesc>& col1) {
     }
     int64_t e = 0;
     for (auto& d : p.pack) { d.elem_begin = e; e = item_align(e + d.elems); }
+    // the leaves that read A's packing no longer wait for a pack launch
+    if (p.overlap) finalize_plan(p);
 }
 
 void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda, int64_t count,
@@ -1031,11 +1036,27 @@ void finalize_plan(Plan& p) {
     // LPT: longest per-tile contraction first (a split leaf's tiles cover one
     // K chunk; stable, so ties keep tree order)
     auto tile_k = [](const LeafDesc& L) { return L.ksplit > 1 ? L.kchunk : L.K; };
-    std::stable_sort(p.leaves.begin(), p.leaves.end(),
-                     [&](const LeafDesc& a, const LeafDesc& c) { return tile_k(a) > tile_k(c); });
+    // overlap: leaves that read only A (no pre-sum operand) first, each group
+    // longest first; the packings and quantisations of views of A run before
+    // the pre-sums
+    const bool ov = p.overlap && !p.presum.empty();
+    auto indep = [&](const LeafDesc& L) {
+        return L.X.base == BASE_A && L.Y.base == BASE_A && (L.sx2 == 0 || L.X2.base == BASE_A) &&
+               (L.sy2 == 0 || L.Y2.base == BASE_A);
+    };
+    std::stable_sort(p.leaves.begin(), p.leaves.end(), [&](const LeafDesc& a, const LeafDesc& c) {
+        if (ov && indep(a) != indep(c)) return indep(a);
+        return tile_k(a) > tile_k(c);
+    });
     int64_t t = 0;
-    for (auto& L : p.leaves) { L.tile_begin = t; t += L.tiles; }
+    p.indep_tiles = 0;
+    for (auto& L : p.leaves) {
+        L.tile_begin = t;
+        t += L.tiles;
+        if (ov && indep(L)) p.indep_tiles = t;
+    }
     p.total_tiles = t;
+    if (p.indep_tiles >= p.total_tiles) p.indep_tiles = 0;   // nothing to overlap with
     t = 0;
     p.fb_leaves.clear();
     for (const auto& L : p.leaves) {
@@ -1065,10 +1086,27 @@ void finalize_plan(Plan& p) {
         int64_t e = 0;
         for (auto& d : lvl) { d.elem_begin = e; e = item_align(e + d.elems); }
     }
+    p.pack_split = p.pack8_split = 0;
+    if (ov) {
+        auto pa = std::stable_partition(p.pack.begin(), p.pack.end(),
+                                        [](const PackDesc& d) { return d.src.base == BASE_A; });
+        p.pack_split = (int32_t)(pa - p.pack.begin());
+        auto qa = std::stable_partition(p.pack8.begin(), p.pack8.end(),
+                                        [](const Pack8Desc& d) { return d.src.base == BASE_A; });
+        p.pack8_split = (int32_t)(qa - p.pack8.begin());
+    }
     int64_t e = 0;
-    for (auto& d : p.pack) { d.elem_begin = e; e = item_align(e + d.elems); }
+    for (size_t i = 0; i < p.pack.size(); ++i) {
+        if ((int32_t)i == p.pack_split) e = 0;
+        p.pack[i].elem_begin = e;
+        e = item_align(e + p.pack[i].elems);
+    }
     e = 0;
-    for (auto& d : p.pack8) { d.elem_begin = e; e += d.elems; }
+    for (size_t i = 0; i < p.pack8.size(); ++i) {
+        if ((int32_t)i == p.pack8_split) e = 0;
+        p.pack8[i].elem_begin = e;
+        e += p.pack8[i].elems;
+    }
     e = 0;
     for (auto& d : p.reduce) { d.elem_begin = e; e = item_align(e + d.elems); }
 }

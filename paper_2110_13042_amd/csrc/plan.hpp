@@ -245,6 +245,7 @@ struct PlanOptions {
     int32_t variant = 0;           // Strassen node: 0 = Strassen's form, 1 = Winograd's
     int64_t slots = 0;             // > 0: balance the leaf launch's last round over this
                                    // many resident workgroups (balance_tail)
+    bool overlap = false;          // order the leaves that read only A first (indep_tiles)
     bool bounded = false;          // make_staged_plan: Strassen roots product by product
     int32_t seq_levels = 0;        // make_staged_plan: top levels run product by product
                                    // (0: the fewest that keep the workspace within
@@ -280,6 +281,18 @@ struct Plan {
     std::vector<std::vector<Sum2Desc>> sums;        // bounded stages: single pre-sums, top-down (first)
     std::vector<std::vector<AccumDesc>> accum;      // bounded stages: products into quadrants, bottom-up (last)
     bool own_packings = false;                      // split-BF16: pack each leaf operand on its own
+    // Overlap of the pre-sums with the leaf products: with `overlap` set, the
+    // leaves whose operands are ready before any pre-sum (views of A, read
+    // directly or, for split-BF16, through the column-norm pass's packing)
+    // come first in the leaf order, and indep_tiles counts their tiles; the
+    // executor runs them on a second stream while the pre-sums run.
+    bool overlap = false;
+    int64_t indep_tiles = 0;
+    // With overlap, the packings (split-BF16) and quantisations (FP8) of views
+    // of A come first in their lists and run before the pre-sums, in their
+    // own launch: pack_split / pack8_split descriptors, whose work items are
+    // numbered apart from the rest's (0: one launch after the pre-sums).
+    int32_t pack_split = 0, pack8_split = 0;
     std::vector<NodeDesc> nodes;                    // AtA nodes (flags)
     std::vector<ColDesc> col1, col2;                // column-norm passes (when fallback)
     int64_t col_partial = 0;                        // doubles of the pass-1 partial sums
