@@ -266,8 +266,10 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
         for i in range(len(As)):
             ata.ata_gram(h.h, As[i].data_ptr(), ms[i], ns[i], max(ns[i], 1), dt, Cs[i].data_ptr(), sp)
 
-    ms_sep = timed(separate, max(1, args.steps // 4))
-    print(f"[bench] {mode}: 512 separate calls {ms_sep:.3f} ms/step", file=sys.stderr, flush=True)
+    ms_sep = None
+    if not args.no_separate:
+        ms_sep = timed(separate, max(1, args.steps // 4))
+        print(f"[bench] {mode}: 512 separate calls {ms_sep:.3f} ms/step", file=sys.stderr, flush=True)
     h.close()
     calls = max(prof["profiled_calls"], 1)
     leaf_ms = prof["phase_ms"][2] / calls
@@ -279,8 +281,8 @@ def run_batched(ata, torch, dev, mats, mode: str, args):
         "dtype": mode,
         "eager_batched": {"ms_per_step": round(ms_eager, 4),
                           "value": round(work / (ms_eager * 1e-3) / 1e12, 3)},
-        "separate_calls": {"ms_per_step": round(ms_sep, 4),
-                           "value": round(work / (ms_sep * 1e-3) / 1e12, 3)},
+        "separate_calls": None if ms_sep is None else {"ms_per_step": round(ms_sep, 4),
+                                                       "value": round(work / (ms_sep * 1e-3) / 1e12, 3)},
         "plan": {"problems": len(As), "multiplications": rep["multiplications"],
                  "leaf_tile": rep["leaf_tile"],
                  "strassen_form": "winograd" if args.winograd else "strassen",
@@ -412,6 +414,8 @@ def main() -> int:
     ap.add_argument("--tune-table", default=TUNE_TABLE, help="tune table loaded into the handle")
     ap.add_argument("--no-tune-table", action="store_true")
     ap.add_argument("--tune-save", default="", help="with --autotune: merge the choices into this table")
+    ap.add_argument("--no-separate", action="store_true",
+                    help="batched workload: skip timing the same problems as separate calls")
     ap.add_argument("--no-batch-autotune", action="store_true",
                     help="batched workload: skip the (untimed) batch autotuner")
     ap.add_argument("--batch-persistent", type=int, default=-1,
