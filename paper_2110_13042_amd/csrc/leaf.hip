@@ -71,7 +71,7 @@ constexpr size_t lds_bytes(int mode) {
     return mode == MODE_BF16X3 ? 2 * (2 * 128 + 2 * 128) * 24 * 2
            : mode == MODE_BF16X3_LARGE ? 2 * (2 * 256 + 2 * 128) * 24 * 2
            : mode == MODE_BF16X3_HUGE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
-           : mode == MODE_BF16X3_WIDE ? (size_t)WIDE_STAGES * 4 * 2 * 256 * 16
+           : mode == MODE_BF16X3_WIDE ? 2 * (2 * 256 + 2 * 256) * 24 * 2
            : mode == MODE_FP8_WIDE ? (size_t)2 * 2 * 8 * 256 * 16
            : mode == MODE_F32_WIDE ? (size_t)(wide32::STAGES * wide32::STAGE > 8 * wide32::HALF ? wide32::STAGES * wide32::STAGE : 8 * wide32::HALF)
            : mode == MODE_F32_WIDE8 ? (size_t)F32W8_ST * 2 * F32W8_SK * wide32::RS * 4
@@ -774,7 +774,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t packed_rsrc(const float* arena
 //   - loads go through buffer resources bounded to the K chunk's row groups,
 //     so groups past the chunk read as zeros and the loop needs no selects.
 // Instances: 128 x 128 on four waves (tile 0), 256 x 128 on four waves
-// (tile 1), 256 x 256 on eight waves of 128 x 64 (tile 2).
+// (tile 1), 256 x 256 on eight waves of 128 x 64 (tile 2, two waves per SIMD)
+// and on four waves of 128 x 128 (tile 3, one wave per SIMD, a third fewer
+// LDS reads per MFMA).
 namespace pipe {
 constexpr int LDR = 24;                       // bf16 per LDS column row: 16 k + 8 pad (48 bytes)
 // s_waitcnt immediates: lgkmcnt(0) (vmcnt and expcnt unconstrained); vmcnt(n)
@@ -969,150 +971,23 @@ __device__ __forceinline__ void tile_bf16x3(const LeafDesc& d, const float* aren
             }
 }
 
-// Split-BF16 x3 with a 256 x 256 tile: four waves of 128 x 128 (4 x 4 blocks
-// of 32 x 32 each), one wave per SIMD.  A wave's 48 MFMAs per 16-k step
-// against 16 fragment reads keep LDS traffic at a third of the 128 x 128
-// engine's per MFMA.  Slabs of 16 k (two 8-k groups) stream into a ring of
-// four LDS stages through buffer loads that write LDS directly (no staging
-// registers, no LDS store instructions): stage s holds Xh, Xl, Yh, Yl, each
-// [group][256 columns] of 16-byte chunks, and lane l of a load lands at
-// 16 l bytes past the instruction's LDS base.  Three slabs are in flight;
-// the fragments of slab kt + 1 are read while slab kt's MFMAs run.  Reads
-// past the packed arrays (and whole groups past K) return zero.
+// LDS ring of the streamed split-BF16 engine (tile 4): slabs of 16 k (two
+// 8-k groups) stream into four LDS stages through buffer loads that write LDS
+// directly; stage s holds Xh, Xl, Yh, Yl, each [group][256 columns] of
+// 16-byte chunks, and lane l of a load lands at 16 l bytes past the
+// instruction's LDS base.
 namespace wide {
 constexpr int TM = 256, TN = 256;
 constexpr int STAGES = WIDE_STAGES;
 constexpr int ARR = 2 * 256 * 16;             // bytes of one operand half in a stage
 constexpr int STAGE = 4 * ARR;                // 32 KB
 constexpr size_t LDS = (size_t)STAGES * STAGE;
-constexpr int LOADS = 8;                      // buffer->LDS loads per wave per slab
 }  // namespace wide
 
-
-// s_waitcnt until at most 8 n loads of this wave are outstanding (n in 0..3).
-__device__ __forceinline__ void wait_slabs(int64_t n) {
-    if (n <= 0) __builtin_amdgcn_s_waitcnt(0x0F70);        // vmcnt(0)
-    else if (n == 1) __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8)
-    else if (n == 2) __builtin_amdgcn_s_waitcnt(0x4F70);   // vmcnt(16)
-    else __builtin_amdgcn_s_waitcnt(0x4F78);               // vmcnt(24)
-}
-
-__device__ __forceinline__ void tile_bf16x3_wide(const LeafDesc& d, const float* arena_in, int ti, int tj, float* C,
-                                 float* arena, unsigned char* smem, const KRange& kr) {
-    using namespace wide;
-    const int t = threadIdx.x, lane = t & 63;
-    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wm = w >> 1, wn = w & 1;
-    const int64_t K = kr.ke - kr.kb;
-    const int64_t gb = kr.kb / 8;                 // first 8-row group of the K chunk
-    // an even number of 16-k slabs (a trailing slab past K loads zeros), so
-    // the K loop is a plain loop over pairs of steps
-    const int64_t nk = ((K + 15) / 16 + 1) & ~int64_t(1);
-
-    // wave w streams operand half w (0 Xh, 1 Xl, 2 Yh, 3 Yl) of every slab
-    const bool isx = w < 2;
-    const __amdgpu_buffer_rsrc_t src = packed_rsrc(arena_in, isx ? d.PX : d.PY, (w & 1) != 0);
-    const uint32_t gs = (uint32_t)((isx ? d.PX.gstride : d.PY.gstride) * 4);
-    const uint32_t col0 = (uint32_t)((isx ? ti * TM : tj * TN) + lane) * 16u;
-    // offset of a zero load: the array's byte size (the first offset past it)
-    const uint32_t past = (uint32_t)(((isx ? d.PX.end - d.PX.off : d.PY.end - d.PY.off)) * 4);
-    auto issue = [&](int64_t kt) {
-        unsigned char* base = smem + (kt % STAGES) * STAGE + w * ARR;
-#pragma unroll
-        for (int i = 0; i < LOADS; ++i) {
-            const int g = i >> 2, seg = i & 3;
-            const int64_t lrow = kt * 2 + g;
-            const uint32_t off = lrow * 8 < K ? (uint32_t)(gb + lrow) * gs + col0 + (uint32_t)(seg * 64 * 16)
-                                              : past;               // past the array: zeros
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + g * 4096 + seg * 1024), 16,
-                                                     (int)off, 0, 0, 0);
-        }
-    };
-
-    v16f acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
-
-    // fragment of lane l: column (l % 32) of its block, k = 8 (l / 32) .. + 7
-    const int fo = (lane >> 5) * 4096 + (lane & 31) * 16;
-    v8bf xh[2][4], xl[2][4], yh[2][4], yl[2][4];
-    auto frags = [&](int buf, int64_t kt) {
-        const unsigned char* st = smem + (kt % STAGES) * STAGE + fo;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int xo = (wm * 128 + a * 32) * 16, yo = (wn * 128 + a * 32) * 16;
-            xh[buf][a] = *reinterpret_cast<const v8bf*>(st + 0 * ARR + xo);
-            xl[buf][a] = *reinterpret_cast<const v8bf*>(st + 1 * ARR + xo);
-            yh[buf][a] = *reinterpret_cast<const v8bf*>(st + 2 * ARR + yo);
-            yl[buf][a] = *reinterpret_cast<const v8bf*>(st + 3 * ARR + yo);
-        }
-    };
-    // the three products in separate passes over the 16 blocks, so that
-    // consecutive MFMAs never depend on each other
-    auto mfmas = [&](int buf) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[buf][a], yh[buf][b], acc[a][b], 0, 0, 0);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[buf][a], yl[buf][b], acc[a][b], 0, 0, 0);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[buf][a], yh[buf][b], acc[a][b], 0, 0, 0);
-    };
-    // one K step: make slab kt + 1 visible, refill the stage freed by slab
-    // kt - 1 with slab kt + 3, then slab kt's MFMAs with slab kt + 1's
-    // fragment reads in their shadow
-    constexpr int AHEAD = STAGES - 1;             // slabs in flight
-    auto step = [&](int64_t kt, int cur) {
-        if (kt + 1 < nk) wait_slabs((kt + AHEAD - 1 < nk ? kt + AHEAD - 1 : nk - 1) - kt - 1);
-        __builtin_amdgcn_s_barrier();
-        if (kt + AHEAD < nk) issue(kt + AHEAD);
-        if (kt + 1 < nk) frags(cur ^ 1, kt + 1);
-        mfmas(cur);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
-            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);   // three MFMAs
-        }
-    };
-
-    for (int64_t j = 0; j < AHEAD && j < nk; ++j) issue(j);
-    if (nk > 0) {
-        wait_slabs((nk < AHEAD ? nk : AHEAD) - 1);
-        __builtin_amdgcn_s_barrier();
-        frags(0, 0);
-    }
-    for (int64_t kt = 0; kt < nk; kt += 2) {
-        step(kt, 0);
-        step(kt + 1, 1);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int cc = wn * 128 + b * 32 + (lane & 31);
-                store_elem<float, TM, TN>(d, ti, tj, r, cc, acc[a][b][v], C, arena, kr.split);
-            }
-}
-
-// The same split-BF16 256 x 256 tile on eight waves of 128 x 64 (4 x 2 blocks,
-// 128 accumulators per lane), two waves per SIMD, so that one wave's MFMAs
-// cover the other's loads and LDS reads.  Same packed slabs and LDS ring;
-// each operand half is streamed by two waves, one 8-row group each.
+// Split-BF16 256 x 256 tile on eight waves of 128 x 64 (4 x 2 blocks, 128
+// accumulators per lane), two waves per SIMD, operands streamed through the
+// LDS ring above; each operand half is streamed by two waves, one 8-row group
+// each, and the fragments of slab kt + 1 are read under slab kt's MFMAs.
 __device__ __forceinline__ void tile_bf16x3_wide8(const LeafDesc& d, const float* arena_in, int ti, int tj, float* C,
                                                   float* arena, unsigned char* smem, const KRange& kr) {
     using namespace wide;
@@ -1578,6 +1453,7 @@ __device__ void tile_f64(const LeafDesc& d, const InT* Xp, const InT* Yp, const 
 static_assert(lds_bytes(MODE_BF16X3) == pipe::Geo<2, 2, 2, 2>::LDS, "tile 0 LDS");
 static_assert(lds_bytes(MODE_BF16X3_LARGE) == pipe::Geo<2, 2, 4, 2>::LDS, "tile 1 LDS");
 static_assert(lds_bytes(MODE_BF16X3_HUGE) == pipe::Geo<2, 4, 4, 2>::LDS, "tile 2 LDS");
+static_assert(lds_bytes(MODE_BF16X3_WIDE) == pipe::Geo<2, 2, 4, 4>::LDS, "tile 3 LDS");
 static_assert(threads_for(MODE_BF16X3) == pipe::Geo<2, 2, 2, 2>::NT && threads_for(MODE_BF16X3_LARGE) ==
               pipe::Geo<2, 2, 4, 2>::NT && threads_for(MODE_BF16X3_HUGE) == pipe::Geo<2, 4, 4, 2>::NT,
               "split-BF16 workgroup sizes");
@@ -1663,8 +1539,8 @@ __device__ __forceinline__ void run_tile(const LeafArgs& args, int64_t bid, unsi
                           static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_WIDE) {
         if (flagged) return;
-        tile_bf16x3_wide(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
-                         static_cast<float*>(args.arena), smem, kr);
+        tile_bf16x3<2, 2, 4, 4>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
+                                static_cast<float*>(args.arena), smem, kr);
     } else if constexpr (MODE == MODE_BF16X3_HUGE) {
         if (flagged) return;
         tile_bf16x3<2, 4, 4, 2>(d, static_cast<const float*>(args.arena), ti, tj, static_cast<float*>(Cptr),
