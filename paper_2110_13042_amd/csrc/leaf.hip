@@ -184,6 +184,34 @@ __device__ __forceinline__ double2 load2d(const double* p, int64_t ld, int64_t r
 template <int RHO>
 __device__ __forceinline__ void leaf_tile(const LeafDesc& d, int64_t q, int64_t B, int& ti, int& tj) {
     const int64_t tn = d.tiles_n;
+    if (d.kind == LEAF_SYRK && RHO == 1) {
+        // the lower triangle in bands of B tile rows, each band column by
+        // column (as the general leaves), so consecutive tiles share row and
+        // column panels; band k (rows r0 = k B .. r0 + h - 1, h = min(B,
+        // tn - r0)) holds r0 h rectangle tiles, then h (h + 1) / 2 triangle
+        // tiles (column r0 + c has h - c of them)
+        int64_t k = 0, start = 0;
+        for (;;) {
+            const int64_t r0 = k * B, h = tn - r0 < B ? tn - r0 : B;
+            const int64_t cnt = r0 * h + h * (h + 1) / 2;
+            if (q < start + cnt || r0 + h >= tn) {
+                int64_t u = q - start;
+                if (u < r0 * h) {
+                    tj = (int)(u / h);
+                    ti = (int)(r0 + u % h);
+                } else {
+                    u -= r0 * h;
+                    int64_t c = 0;
+                    while (u >= h - c) { u -= h - c; ++c; }
+                    tj = (int)(r0 + c);
+                    ti = (int)(r0 + c + u);
+                }
+                return;
+            }
+            start += cnt;
+            ++k;
+        }
+    }
     if (d.kind == LEAF_SYRK) {
         const int64_t L = tn / RHO;
         const int64_t full = RHO * L * (L + 1) / 2;
