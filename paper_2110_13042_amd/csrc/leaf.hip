@@ -79,7 +79,8 @@ constexpr size_t lds_bytes(int mode) {
            : mode == MODE_F32 ? LDS32_BYTES : mode == MODE_FP8 ? 2 * 2 * 128 * 144 : LDS64_BYTES;
 }
 constexpr int threads_for(int mode) {
-    return mode == MODE_BF16X3_HUGE || mode == MODE_F32_WIDE8 || mode == MODE_BF16X3_WIDE8 ? 512 : LEAF_THREADS;
+    return mode == MODE_BF16X3_HUGE || mode == MODE_F32_WIDE8 || mode == MODE_BF16X3_WIDE8 || mode == MODE_FP8_WIDE
+               ? 512 : LEAF_THREADS;
 }
 // Resident workgroups per CU the one-tile-per-workgroup kernel is compiled
 // for: the 128 x 128 FP32 engine keeps four (64 VGPRs + 64 accumulators per
@@ -1260,26 +1261,34 @@ constexpr int HALF = 8 * 256 * 16;            // one operand's slab: 32 KB
 constexpr int STAGE = 2 * HALF;
 }  // namespace wide8
 
+// FP8 256 x 256 tile on eight waves (2 x 4) of 128 x 64 (8 x 4 blocks of
+// 16 x 16 on the scaled 16 x 16 x 128 MFMA, 128 accumulators per lane), two
+// waves per SIMD, so that one wave's MFMAs cover the other's load waits,
+// barrier and fragment reads.  A slab is 128 rows, one scale block of each
+// operand: waves 0-3 stream X's eight 16-row groups (two each), waves 4-7
+// Y's, through buffer loads that write LDS directly ([group][256 columns] of
+// 16-byte chunks; lane l of a load lands at 16 l bytes past its base).  Two
+// stages: slab kt + 1 streams in while slab kt is multiplied.
 __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* arena_in, int ti, int tj, float* C,
                                               float* arena, unsigned char* smem, const KRange& kr) {
     using namespace wide8;
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wm = w >> 1, wn = w & 1;
+    const int wm = w >> 2, wn = w & 3;
     const int64_t K = kr.ke - kr.kb;
     const int64_t nk = (K + 127) / 128;
     const int64_t sb0 = kr.kb / 128;              // first 128-row slab of the K chunk
-    const bool isx = w < 2;
+    const bool isx = w < 4;
     const Packed8& Q = isx ? d.QX : d.QY;
     const __amdgpu_buffer_rsrc_t src = q8_rsrc(arena_in, Q);
     const uint32_t past = (uint32_t)((Q.end - Q.off) * 4);
     const int64_t cp = Q.cols_p;
     const int64_t col0 = (isx ? (int64_t)ti * TM : (int64_t)tj * TN) + lane;
-    const int gbase = (w & 1) * 4;                // this wave's four row-groups of the slab
+    const int gbase = (w & 3) * 2;                // this wave's two row-groups of the slab
     auto issue = [&](int64_t kt, int stage) {
         unsigned char* base = smem + stage * STAGE + (isx ? 0 : HALF);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < 8; ++i) {
             const int g = gbase + (i >> 2), seg = i & 3;
             const int64_t col = col0 + seg * 64;
             const uint32_t off = col < cp ? (uint32_t)((((sb0 + kt) * 8 + g) * cp + col) * 16) : past;
@@ -1293,46 +1302,41 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
     const int* sy = reinterpret_cast<const int*>(arena_in + d.QY.scales);
     const int64_t sxs = d.QX.cols_p / 128, sys = d.QY.cols_p / 128;
     const int64_t bx = (int64_t)ti * 2 + wm < sxs ? (int64_t)ti * 2 + wm : sxs - 1;
-    const int64_t by = (int64_t)tj * 2 + wn < sys ? (int64_t)tj * 2 + wn : sys - 1;
+    const int64_t by = (int64_t)tj * 2 + (wn >> 1) < sys ? (int64_t)tj * 2 + (wn >> 1) : sys - 1;
 
-    v4f acc[8][8];
+    v4f acc[8][4];
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.f;
 
     // fragment of lane l: column (l % 16) of its block, rows 32 (l / 16) ..
     // + 31 of the slab = groups 2 (l / 16) and 2 (l / 16) + 1
     const int fo = (2 * (lane >> 4)) * 256 * 16 + (lane & 15) * 16;
+    auto frag = [](const unsigned char* p) {
+        const v4u lo = *reinterpret_cast<const v4u*>(p);
+        const v4u hi = *reinterpret_cast<const v4u*>(p + 256 * 16);
+        return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+    };
     auto step = [&](int64_t kt) {
         const int cur = (int)(kt & 1);
-        if (kt + 1 < nk) {
-            __builtin_amdgcn_s_waitcnt(0x0F70);   // this wave's loads of slab kt are done
-        } else {
-            __builtin_amdgcn_s_waitcnt(0x0F70);
-        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);       // this wave's loads of slab kt are done
         __builtin_amdgcn_s_barrier();             // every wave's loads of slab kt are visible,
                                                   // and slab kt - 1's stage is free
         if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
         const int sa = 127 + sx[(sb0 + kt) * sxs + bx], sb = 127 + sy[(sb0 + kt) * sys + by];
         const unsigned char* xs = smem + cur * STAGE + fo + (wm * 128) * 16;
-        const unsigned char* ys = smem + cur * STAGE + HALF + fo + (wn * 128) * 16;
-        v8i fb[8];
+        const unsigned char* ys = smem + cur * STAGE + HALF + fo + (wn * 64) * 16;
+        v8i fb[4];
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const v4u lo = *reinterpret_cast<const v4u*>(ys + b * 16 * 16);
-            const v4u hi = *reinterpret_cast<const v4u*>(ys + b * 16 * 16 + 256 * 16);
-            fb[b] = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-        }
+        for (int b = 0; b < 4; ++b) fb[b] = frag(ys + b * 16 * 16);
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
-            const v4u lo = *reinterpret_cast<const v4u*>(xs + a * 16 * 16);
-            const v4u hi = *reinterpret_cast<const v4u*>(xs + a * 16 * 16 + 256 * 16);
-            const v8i fa = v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            const v8i fa = frag(xs + a * 16 * 16);
 #pragma unroll
-            for (int b = 0; b < 8; ++b)
+            for (int b = 0; b < 4; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(fa, fb[b], acc[a][b], 0, 0, 0, sa, 0, sb);
         }
     };
@@ -1341,11 +1345,11 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
+        for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = wm * 128 + a * 16 + 4 * (lane >> 4) + v;
-                const int c = wn * 128 + b * 16 + (lane & 15);
+                const int c = wn * 64 + b * 16 + (lane & 15);
                 store_elem<float, TM, TN>(d, ti, tj, r, c, acc[a][b][v], C, arena, kr.split);
             }
 }
@@ -1673,7 +1677,7 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
         return hipGetLastError();
     }
     if (mode == MODE_FP8 && tile_cfg == 3) {
-        ATA_LAUNCH_LEAF(MODE_FP8_WIDE, LEAF_THREADS);
+        ATA_LAUNCH_LEAF(MODE_FP8_WIDE, 512);
         return hipGetLastError();
     }
     if (mode == MODE_F32 && tile_cfg == 3) {
@@ -1734,7 +1738,7 @@ int leaf_blocks_per_cu(int32_t mode, int32_t tile_cfg) {
     else if (mode == MODE_F32 && tile_cfg == 2)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_F32_WIDE8>, 512, 0);
     else if (mode == MODE_FP8 && tile_cfg == 3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8_WIDE>, LEAF_THREADS, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8_WIDE>, 512, 0);
     else if (mode == MODE_FP8)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, leaf_kernel_persistent<MODE_FP8>, LEAF_THREADS, 0);
     else if (mode == MODE_F32)
