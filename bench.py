@@ -41,7 +41,7 @@ if ROOT not in sys.path:
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6 / 3.0, "fp8": 5033.2}
 MODES = {"f64": 0, "f32": 1, "bf16x3": 2, "fp8": 3}
 TUNE_TABLE = os.path.join(ROOT, "paper_2110_13042_amd", "tune_table.json")
-LEAF_KERNEL_FILES = ["paper_2110_13042_amd/csrc/leaf.hip", "paper_2110_13042_amd/csrc/kernels_common.hpp"]
+LEAF_KERNEL_FILES = ["paper_2110_13042_amd/csrc/leaf_kernels.hpp", "paper_2110_13042_amd/csrc/kernels_common.hpp"]
 
 
 def leaf_source_hash() -> str:
@@ -173,7 +173,8 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
                  "leaf_tile": rep["leaf_tile"],
                  "strassen_form": "winograd" if args.winograd else "strassen",
                  "tail_split": [rep["tail_split_leaves"], rep["tail_split_chunks"]],
-                 "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile"},
+                 "leaf_launch": "persistent" if rep["leaf_persistent"] else "one workgroup per tile",
+                 "leaf_rounds": rep["leaf_rounds"]},
         "phase_ms_per_step": {k: round(v / calls, 4) for k, v in zip(
             ["norms_flags", "presum_pack", "leaves", "combine", "residual"], rep["phase_ms"])},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1),
@@ -214,6 +215,8 @@ def make_handle(ata, args):
         h.set("overlap", args.overlap)
     if args.bounded:
         h.set("bounded_workspace", 1)
+    if args.fuse_combine:
+        h.set("fuse_combine", 1)
     if args.spread_tau >= 0:
         h.set("spread_tau", args.spread_tau)
     return h
@@ -437,6 +440,8 @@ def main() -> int:
                          "leaf launch; -1: the library's default")
     ap.add_argument("--bounded", action="store_true",
                     help="bounded workspace: Strassen roots run product by product")
+    ap.add_argument("--fuse-combine", action="store_true",
+                    help="Strassen combines of the last level in the leaf epilogues (five leaf launch rounds)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()

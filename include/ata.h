@@ -232,7 +232,27 @@ typedef enum {
        split-BF16 plans).  1 = on, 0 = off (default), -1 = the default.
        Ignored by ata_gram_noalloc, batches, ata_gemm_tn and bounded-workspace
        plans. */
-    ATA_OPT_OVERLAP = 20
+    ATA_OPT_OVERLAP = 20,
+    /* Strassen combine in the leaf epilogues (Sec. 3.2's post-additions moved
+       into the products).  A Strassen node whose seven products are all
+       leaves gets no product buffers and no combine pass: each product's
+       leaf adds its tiles straight into its one or two quadrants of the
+       node's target.  The products run in five dependent leaf launches,
+       {M1}, {M2}, {M3, M4}, {M5, M6}, {M7}, so that every quadrant element
+       has one writer per launch and receives the combine's own left-to-right
+       sum (C11 = ((M1 + M4) - M5) + M7, C12 = M3 + M5, C21 = M2 + M4, C22 =
+       ((M1 - M2) + M3) + M6); the other leaves are spread over the five
+       launches.  Results are bit-identical to the default schedule's when no
+       leaf is cut into K chunks (ATA_OPT_SPLIT_TARGET 0, ATA_OPT_BALANCE_TAIL
+       0): the leaves with epilogue combines are never cut, so other cuts can
+       differ.  Strassen's form only; not with the 256 x 256 four-wave FP32
+       and split-BF16 tiles (ATA_OPT_LEAF_TILE 3 runs without it).  Applies to
+       ata_gram, ata_gram_noalloc and ata_gemm_tn; batches and
+       bounded-workspace plans ignore it.  Off by default (measured slower:
+       the product's read-modify-write of its quadrants moves as many bytes
+       as the combine pass, and five launches leave five tails).
+       1 = on, 0 = off (default). */
+    ATA_OPT_FUSE_COMBINE = 21
 } ata_option_t;
 
 /* Plan and run summary of the last ata_gram call on a handle. */
@@ -263,7 +283,9 @@ typedef struct {
     int32_t tail_split_chunks;    /* K chunks per cut leaf                     */
     int32_t overlapped;           /* 1 = the leaves reading only A ran beside
                                      the pre-sums (ATA_OPT_OVERLAP)            */
-    int32_t pad_;
+    int32_t leaf_rounds;          /* leaf launches in sequence: 1, or the
+                                     launch rounds of the combines in the leaf
+                                     epilogues (ATA_OPT_FUSE_COMBINE)          */
 } ata_report_t;
 
 /* One leaf of a plan, as returned by ata_plan_query. */

@@ -34,6 +34,7 @@ OPT_STRASSEN_FORM = 17
 OPT_BALANCE_TAIL = 18
 OPT_BOUNDED_WORKSPACE = 19
 OPT_OVERLAP = 20
+OPT_FUSE_COMBINE = 21
 
 STATUS = {0: "ATA_OK", 1: "ATA_ERR_INVALID_VALUE", 2: "ATA_ERR_NOT_SUPPORTED",
           3: "ATA_ERR_OUT_OF_MEMORY", 4: "ATA_ERR_HIP", 5: "ATA_ERR_INTERNAL"}
@@ -56,7 +57,7 @@ class Report(ctypes.Structure):
                 ("profiled_calls", ctypes.c_int64), ("phase_ms", ctypes.c_double * 5),
                 ("leaf_tile", ctypes.c_int32), ("leaf_persistent", ctypes.c_int32),
                 ("tail_split_leaves", ctypes.c_int32), ("tail_split_chunks", ctypes.c_int32),
-                ("overlapped", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("overlapped", ctypes.c_int32), ("leaf_rounds", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -296,7 +297,7 @@ class Handle:
                "equilibrate": OPT_EQUILIBRATE, "leaf_persistent": OPT_LEAF_PERSISTENT,
                "fuse_presum": OPT_FUSE_PRESUM, "strassen_form": OPT_STRASSEN_FORM,
                "balance_tail": OPT_BALANCE_TAIL, "bounded_workspace": OPT_BOUNDED_WORKSPACE,
-               "overlap": OPT_OVERLAP}[name]
+               "overlap": OPT_OVERLAP, "fuse_combine": OPT_FUSE_COMBINE}[name]
         ata_set_option(self.h, key, value)
 
     def report(self) -> dict:

@@ -16,7 +16,7 @@ OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libata.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plan.cpp", "ata_api.cpp", "leaf.hip", "elementwise.hip"]
+SOURCES = ["plan.cpp", "ata_api.cpp", "leaf.hip", "leaf_epi.hip", "elementwise.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]

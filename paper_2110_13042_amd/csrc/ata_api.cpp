@@ -38,10 +38,12 @@ struct PlanKey {
     int64_t slots;
     bool bounded;
     bool overlap;
+    bool fuse_combine = false;
     bool operator<(const PlanKey& o) const {
-        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant, slots, bounded, overlap) <
+        return std::tie(mode, m, n, lda, b, depth, fb, tile_cfg, split, fuse, variant, slots, bounded, overlap,
+                        fuse_combine) <
                std::tie(o.mode, o.m, o.n, o.lda, o.b, o.depth, o.fb, o.tile_cfg, o.split, o.fuse, o.variant,
-                        o.slots, o.bounded, o.overlap);
+                        o.slots, o.bounded, o.overlap, o.fuse_combine);
     }
 };
 
@@ -106,10 +108,11 @@ struct GemmKey {
     bool fuse;
     int32_t variant;
     int64_t slots;
+    bool fuse_combine = false;
     bool operator<(const GemmKey& o) const {
-        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split, fuse, variant, slots) <
+        return std::tie(mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, split, fuse, variant, slots, fuse_combine) <
                std::tie(o.mode, o.m, o.n, o.k, o.lda, o.ldb, o.ldc, o.b, o.depth, o.tile_cfg, o.split, o.fuse,
-                        o.variant, o.slots);
+                        o.variant, o.slots, o.fuse_combine);
     }
 };
 
@@ -525,6 +528,7 @@ ata_status_t build_gram_plan(const ata_ctx* h, const PlanKey& k, Fits fits, Plan
     o.variant = k.variant;
     o.slots = k.slots;
     o.overlap = k.overlap;
+    o.fuse_combine = k.fuse_combine;
     try {
         out = make_plan(k.mode, k.m, k.n, k.lda, o);
         while (out.stats.max_levels > 0 && !fits(out)) {
@@ -548,6 +552,14 @@ int64_t tail_slots(const ata_ctx* h, int32_t mode, int32_t tile_cfg) {
     return h->balance_tail ? (int64_t)leaf_blocks_per_cu(mode, tile_cfg) * 256 : 0;
 }
 
+// Whether a plan combines its last Strassen level in the leaf epilogues:
+// asked for, Strassen's form, and a leaf tile built for it (the 256 x 256
+// four-wave FP32 and split-BF16 tiles are not).
+bool combine_in_epilogue(const ata_ctx* h, int32_t mode, int32_t tile_cfg) {
+    return h->popt.fuse_combine && h->popt.variant == 0 &&
+           !((mode == MODE_F32 || mode == MODE_BF16X3) && tile_cfg == 3);
+}
+
 void fill_report(ata_report_t& r, const Plan& p) {
     r.m = p.m;
     r.n = p.n;
@@ -568,6 +580,12 @@ void fill_report(ata_report_t& r, const Plan& p) {
     r.leaf_persistent = 0;
     r.tail_split_leaves = p.tail_leaves;
     r.tail_split_chunks = p.tail_chunks;
+    r.leaf_rounds = p.leaves.empty() ? 0 : 1;
+    if (!p.round_tiles.empty()) {
+        r.leaf_rounds = 0;
+        for (size_t i = 0; i + 1 < p.round_tiles.size(); ++i)
+            r.leaf_rounds += p.round_tiles[i + 1] > p.round_tiles[i] ? 1 : 0;
+    }
 }
 
 }  // namespace
@@ -702,6 +720,9 @@ ata_status_t ata_set_option(ata_handle_t h, ata_option_t key, double value) {
         case ATA_OPT_BOUNDED_WORKSPACE:
             h->bounded = value != 0.0;
             return ATA_OK;
+        case ATA_OPT_FUSE_COMBINE:
+            h->popt.fuse_combine = value != 0.0;
+            return ATA_OK;
         case ATA_OPT_PROFILE:
             if (h->events_used) (void)drain_events(h);
             h->profile = value != 0.0;
@@ -767,6 +788,23 @@ ata_status_t take_events(ata_ctx* h, hipEvent_t*& ev) {
 }  // namespace
 
 namespace {
+
+// The leaf products of a plan: one launch, or one per launch round when the
+// plan combines its last Strassen level in the leaf epilogues (the rounds
+// run in order on `st`).
+hipError_t launch_plan_leaves(const ata_ctx* h, const DevicePlan& dp, const void* A, void* C, void* arena,
+                              const uint8_t* flags, hipStream_t st, const BatchPtrs* lp, const void* B = nullptr) {
+    const Plan& p = dp.plan;
+    if (p.round_tiles.empty())
+        return launch_leaves(p.mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C, arena,
+                             flags, h->chunk, h->band, st, lp, B);
+    hipError_t e = hipSuccess;
+    for (size_t r = 0; e == hipSuccess && r + 1 < p.round_tiles.size(); ++r)
+        e = launch_leaves_epi(p.mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(),
+                              p.round_tiles[r + 1] - p.round_tiles[r], A, C, arena, flags, h->chunk, h->band, st,
+                              lp, B, p.round_tiles[r]);
+    return e;
+}
 
 // Enqueue every phase of a single-problem plan on `st`: column norms and
 // spread flags, pre-sums level by level, packing or quantisation, the leaf
@@ -855,9 +893,7 @@ hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, v
                               C_packed, arena, flags, h->chunk, h->band, st, lp2, nullptr, p.indep_tiles);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, h->join_ev, 0);
     } else {
-        if (e == hipSuccess)
-            e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C_packed,
-                              arena, flags, h->chunk, h->band, st, lp);
+        if (e == hipSuccess) e = launch_plan_leaves(h, dp, A, C_packed, arena, flags, st, lp);
         if (e == hipSuccess && !p.fb_leaves.empty())
             e = launch_fallback_leaves(dp.d_fb_leaves, (int)p.fb_leaves.size(), p.fb_tiles, A, C_packed,
                                        arena, flags, h->chunk, h->band, st);
@@ -999,7 +1035,7 @@ ata_status_t ata_gram(ata_handle_t h, const void* A, int64_t m, int64_t n, int64
     const bool overlap = !bounded && h->overlap == 1;
     const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target,
                       bounded ? false : h->popt.fuse_presum, bounded ? 0 : h->popt.variant, slots, bounded,
-                      overlap};
+                      overlap, !bounded && combine_in_epilogue(h, mode, tile_cfg)};
     auto it = h->plans.find(key);
     if (it == h->plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -1115,7 +1151,8 @@ ata_status_t ata_gram_noalloc(ata_handle_t h, const void* A, int64_t m, int64_t 
     choose(h, mode, m, n, b, depth, tile_cfg);
     const bool fb = mode != MODE_F64 && h->popt.spread_tau > 0 && m > 0;
     const PlanKey key{mode, m, n, lda, b, depth, fb, tile_cfg, h->split_target, h->popt.fuse_presum,
-                      h->popt.variant, tail_slots(h, mode, tile_cfg), false};
+                      h->popt.variant, tail_slots(h, mode, tile_cfg), false, false,
+                      combine_in_epilogue(h, mode, tile_cfg)};
     const size_t limit = h->ws_limit > 0 ? std::min<size_t>((size_t)h->ws_limit, ATA_NOALLOC_SCRATCH_BYTES)
                                          : (size_t)ATA_NOALLOC_SCRATCH_BYTES;
     auto it = h->static_plans.find(key);
@@ -1251,7 +1288,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
     choose(h, mode, m, std::max(n, k), b, depth, tile_cfg);
     const int64_t slots = tail_slots(h, mode, tile_cfg);
     const GemmKey key{mode, m, n, k, lda, ldb, ldc, b, depth, tile_cfg, h->split_target, h->popt.fuse_presum,
-                       h->popt.variant, slots};
+                       h->popt.variant, slots, combine_in_epilogue(h, mode, tile_cfg)};
     auto it = h->gemm_plans.find(key);
     if (it == h->gemm_plans.end()) {
         auto dp = std::make_unique<DevicePlan>();
@@ -1264,6 +1301,7 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
         o.fuse_presum = h->popt.fuse_presum;
         o.variant = h->popt.variant;
         o.slots = slots;
+        o.fuse_combine = key.fuse_combine;
         try {
             dp->plan = make_gemm_plan(mode, m, n, k, lda, ldb, ldc, o);
             while (dp->plan.stats.max_levels > 0 && !fits_device(h, dp->plan)) {
@@ -1319,17 +1357,16 @@ ata_status_t ata_gemm_tn(ata_handle_t h, const void* A, const void* B, int64_t m
         e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems, A,
                           h->arena, flags, st, nullptr, B);
     mark(2);
-    if (e == hipSuccess)
-        e = launch_leaves(mode, p.tile_cfg, dp.d_leaves, (int)p.leaves.size(), p.total_tiles, A, C, h->arena,
-                          flags, h->chunk, h->band, st, lp, B);
+    if (e == hipSuccess) e = launch_plan_leaves(h, dp, A, C, h->arena, flags, st, lp, B);
     if (e == hipSuccess && !p.reduce.empty())
         e = launch_reduce(mode, dp.d_reduce, (int)p.reduce.size(), p.reduce.back().elem_begin + p.reduce.back().elems,
                           C, h->arena, flags, st);
     mark(3);
     for (size_t l = 0; e == hipSuccess && l < p.combine.size(); ++l) {
         const auto& lv = p.combine[l];
-        e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems, C,
-                           h->arena, flags, st);
+        if (!lv.empty())
+            e = launch_combine(mode, dp.d_combine[l], (int)lv.size(), lv.back().elem_begin + lv.back().elems, C,
+                               h->arena, flags, st);
     }
     mark(4);
     mark(5);

@@ -33,6 +33,15 @@ hipError_t launch_leaves(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks
                          int chunk, int band, hipStream_t stream, const BatchPtrs* bp = nullptr,
                          const void* B = nullptr, int64_t tile_base = 0);
 
+// The leaf launch of a plan with Strassen combines in the leaf epilogues
+// (Plan::fuse_combine): the same kernels, built to add a leaf's product into
+// its one or two node quadrants (LeafDesc::nq); leaves with nq = 0 store as
+// usual.  One call per launch round.
+hipError_t launch_leaves_epi(int32_t mode, int32_t tile_cfg, const LeafDesc* d_tasks, int ntasks, int64_t ntiles,
+                             const void* A, void* C, void* arena, const uint8_t* flags, int chunk, int band,
+                             hipStream_t stream, const BatchPtrs* bp = nullptr, const void* B = nullptr,
+                             int64_t tile_base = 0);
+
 // FP64 fallback of flagged SYRK leaves (FP32 inputs and output); the tasks
 // are the plan's fallback-capable SYRK leaves, unflagged ones exit at once.
 hipError_t launch_fallback_leaves(const LeafDesc* d_tasks, int ntasks, int64_t ntiles, const void* A,

@@ -55,6 +55,10 @@ int64_t Plan::alloc(int64_t elems) {
 
 int64_t Plan::launches() const {
     int64_t l = leaves.empty() ? 0 : 1;
+    if (!round_tiles.empty()) {
+        l = 0;
+        for (size_t r = 0; r + 1 < round_tiles.size(); ++r) l += round_tiles[r + 1] > round_tiles[r] ? 1 : 0;
+    }
     for (const auto& v : presum) l += v.empty() ? 0 : 1;
     for (const auto& v : combine) l += v.empty() ? 0 : 1;
     if (pack_split > 0) l += 1;
@@ -127,6 +131,13 @@ struct Builder {
     bool collect = false;
     std::vector<Root> roots;
     int ata_level = 0;
+    // combine in the epilogue: the target quadrants of the next leaf added
+    // (null: the leaf stores its product)
+    struct Epi {
+        int32_t round, nq, quad[2], sign[2], first[2];
+    };
+    const Epi* epi = nullptr;
+    int64_t epi_n1 = 0, epi_k1 = 0;
 
     explicit Builder(Plan& plan) : p(plan), b(plan.b), maxd(plan.max_depth), fb(plan.fallback) {}
 
@@ -186,6 +197,17 @@ struct Builder {
         L.pred_value = pred_value;
         L.fb_node = fb_node;
         L.depth = depth;
+        if (epi) {
+            L.round = epi->round;
+            L.nq = epi->nq;
+            for (int q = 0; q < 2; ++q) {
+                L.quad[q] = epi->quad[q];
+                L.qsign[q] = epi->sign[q];
+                L.qfirst[q] = epi->first[q];
+            }
+            L.qn1 = epi_n1;
+            L.qk1 = epi_k1;
+        }
         if (counting) {
             if (kind == LEAF_SYRK) {
                 ++p.stats.syrk_leaves;
@@ -255,30 +277,57 @@ struct Builder {
         const View Y11 = sub(Y, 0, m1, m2, 0, k1, k2), Y12 = sub(Y, 0, m1, m2, k1, k2, k2);
         const View Y21 = sub(Y, m1, m2, m2, 0, k1, k2), Y22 = sub(Y, m1, m2, m2, k1, k2, k2);
         auto Mt = [&](int i, int64_t M) { return Target{OUT_DENSE, M + (i - 1) * n2 * k2, k2, 0, 0}; };
+        // combine in the epilogue: the seven products are leaves that add
+        // themselves into the quadrants of t in five launch rounds.  Each
+        // quadrant gets its contributions in the combine's order (C11 =
+        // ((M1 + M4) - M5) + M7, C12 = M3 + M5, C21 = M2 + M4, C22 = ((M1 -
+        // M2) + M3) + M6), one writer per element per round.
+        static const Epi kEpi[7] = {
+            {0, 2, {0, 3}, {1, 1}, {1, 1}},      // M1 -> C11, C22
+            {1, 2, {2, 3}, {1, -1}, {1, 0}},     // M2 -> C21, -C22
+            {2, 2, {1, 3}, {1, 1}, {1, 0}},      // M3 -> C12, C22
+            {2, 2, {0, 2}, {1, 1}, {0, 0}},      // M4 -> C11, C21
+            {3, 2, {0, 1}, {-1, 1}, {0, 0}},     // M5 -> -C11, C12
+            {3, 1, {3, 0}, {1, 0}, {0, 0}},      // M6 -> C22
+            {4, 1, {0, 0}, {1, 0}, {0, 0}},      // M7 -> C11
+        };
+        const bool in_epilogue = p.fuse_combine && p.variant == 0 && children_leaf;
+        auto product_leaf = [&](int i, const Operand& OX, const Operand& OY, int64_t M) {
+            if (in_epilogue) {
+                epi = &kEpi[i - 1];
+                epi_n1 = n1;
+                epi_k1 = k1;
+            }
+            add_leaf(LEAF_GEMM, OX, OY, in_epilogue ? t : Mt(i, M), depth + 1, pn, pv, -1);
+            epi = nullptr;
+        };
+        auto push_combine = [&](int64_t M, int level) {
+            if ((int)p.combine.size() < level + 1) p.combine.resize(level + 1);
+            CombineDesc c{};
+            c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
+            c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
+            c.unit = k2 % 4 == 0 ? 4 : 1;
+            c.elems = n2 * cdiv(k2, c.unit); c.pred_node = pn; c.pred_value = pv; c.variant = p.variant;
+            p.combine[level].push_back(c);
+        };
         if (p.fuse && p.variant == 0 && children_leaf &&
             ((p.mode == MODE_F32 && p.tile_cfg != 2) || p.mode == MODE_F64)) {
             // the seven products are leaves: each forms its pre-sums while
             // loading its operands (same IEEE sums as the pre-sum pass)
-            const int64_t M = alloc(7 * n2 * k2);
+            const int64_t M = in_epilogue ? 0 : alloc(7 * n2 * k2);
             auto op = [](const View& a, const View& b, int32_t sg) { return Operand{a, b, sg}; };
             const Operand S1 = op(X11, X22, 1), S2 = op(X12, X22, 1), S3 = op(X11, X21, 1);
             const Operand S4 = op(X12, X11, -1), S5 = op(X21, X22, -1);
             const Operand T1 = op(Y11, Y22, 1), T2 = op(Y12, Y22, -1), T3 = op(Y21, Y11, -1);
             const Operand T4 = op(Y11, Y12, 1), T5 = op(Y21, Y22, 1);
-            add_leaf(LEAF_GEMM, S1, T1, Mt(1, M), depth + 1, pn, pv, -1);            // M1 = S1^T T1
-            add_leaf(LEAF_GEMM, S2, Operand{Y11}, Mt(2, M), depth + 1, pn, pv, -1);  // M2 = S2^T Y11
-            add_leaf(LEAF_GEMM, Operand{X11}, T2, Mt(3, M), depth + 1, pn, pv, -1);  // M3 = X11^T T2
-            add_leaf(LEAF_GEMM, Operand{X22}, T3, Mt(4, M), depth + 1, pn, pv, -1);  // M4 = X22^T T3
-            add_leaf(LEAF_GEMM, S3, Operand{Y22}, Mt(5, M), depth + 1, pn, pv, -1);  // M5 = S3^T Y22
-            add_leaf(LEAF_GEMM, S4, T4, Mt(6, M), depth + 1, pn, pv, -1);            // M6 = S4^T T4
-            add_leaf(LEAF_GEMM, S5, T5, Mt(7, M), depth + 1, pn, pv, -1);            // M7 = S5^T T5
-            if ((int)p.combine.size() < 1) p.combine.resize(1);
-            CombineDesc c{};
-            c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
-            c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
-            c.unit = k2 % 4 == 0 ? 4 : 1;
-            c.elems = n2 * cdiv(k2, c.unit); c.pred_node = pn; c.pred_value = pv;
-            p.combine[0].push_back(c);
+            product_leaf(1, S1, T1, M);                       // M1 = S1^T T1
+            product_leaf(2, S2, Operand{Y11}, M);             // M2 = S2^T Y11
+            product_leaf(3, Operand{X11}, T2, M);             // M3 = X11^T T2
+            product_leaf(4, Operand{X22}, T3, M);             // M4 = X22^T T3
+            product_leaf(5, S3, Operand{Y22}, M);             // M5 = S3^T Y22
+            product_leaf(6, S4, T4, M);                       // M6 = S4^T T4
+            product_leaf(7, S5, T5, M);                       // M7 = S5^T T5
+            if (!in_epilogue) push_combine(M, 0);
             if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
             return 1;
         }
@@ -287,7 +336,8 @@ struct Builder {
         const int64_t groups = cdiv(m2, 8);
         const int64_t s_each = packed ? groups * n2 * 8 : m2 * n2;
         const int64_t t_each = packed ? groups * k2 * 8 : m2 * k2;
-        const int64_t S = alloc(nsums * s_each), T = alloc(nsums * t_each), M = alloc(7 * n2 * k2);
+        const int64_t S = alloc(nsums * s_each), T = alloc(nsums * t_each);
+        const int64_t M = in_epilogue ? 0 : alloc(7 * n2 * k2);
         if ((int)p.presum.size() <= depth) p.presum.resize(depth + 1);
         PresumDesc ps{};
         ps.V = X; ps.m1 = m1; ps.m2 = m2; ps.n1 = n1; ps.n2 = n2; ps.out_off = S;
@@ -331,6 +381,16 @@ struct Builder {
             h = std::max(h, strassen(Sv(1), Tv(1), Mt(5, M), depth + 1, pn, pv));  // M5 = S1^T T1
             h = std::max(h, strassen(Sv(2), Tv(2), Mt(6, M), depth + 1, pn, pv));  // M6 = S2^T T2
             h = std::max(h, strassen(Sv(3), Tv(3), Mt(7, M), depth + 1, pn, pv));  // M7 = S3^T T3
+        } else if (in_epilogue) {
+            product_leaf(1, Operand{Sv(1)}, Operand{Tv(1)}, M);   // M1 = S1^T T1
+            product_leaf(2, Operand{Sv(2)}, Operand{Y11}, M);     // M2 = S2^T Y11
+            product_leaf(3, Operand{X11}, Operand{Tv(2)}, M);     // M3 = X11^T T2
+            product_leaf(4, Operand{X22}, Operand{Tv(3)}, M);     // M4 = X22^T T3
+            product_leaf(5, Operand{Sv(3)}, Operand{Y22}, M);     // M5 = S3^T Y22
+            product_leaf(6, Operand{Sv(4)}, Operand{Tv(4)}, M);   // M6 = S4^T T4
+            product_leaf(7, Operand{Sv(5)}, Operand{Tv(5)}, M);   // M7 = S5^T T5
+            if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
+            return 1;
         } else {
             h = std::max(h, strassen(Sv(1), Tv(1), Mt(1, M), depth + 1, pn, pv));  // M1 = S1^T T1
             h = std::max(h, strassen(Sv(2), Y11, Mt(2, M), depth + 1, pn, pv));    // M2 = S2^T Y11
@@ -341,13 +401,7 @@ struct Builder {
             h = std::max(h, strassen(Sv(5), Tv(5), Mt(7, M), depth + 1, pn, pv));  // M7 = S5^T T5
         }
         const int height = h + 1;
-        if ((int)p.combine.size() < height) p.combine.resize(height);
-        CombineDesc c{};
-        c.m_off = M; c.n1 = n1; c.n2 = n2; c.k1 = k1; c.k2 = k2;
-        c.out_kind = t.kind; c.out_off = t.off; c.out_ld = t.ld; c.out_row0 = t.row0; c.out_col0 = t.col0;
-        c.unit = k2 % 4 == 0 ? 4 : 1;
-        c.elems = n2 * cdiv(k2, c.unit); c.pred_node = pn; c.pred_value = pv; c.variant = p.variant;
-        p.combine[height - 1].push_back(c);
+        push_combine(M, height - 1);
         if (counting) p.stats.max_levels = std::max<int32_t>(p.stats.max_levels, depth + 1);
         return height;
     }
@@ -491,6 +545,7 @@ Plan make_plan(int32_t mode, int64_t m, int64_t n, int64_t lda, const PlanOption
     p.fuse = opt.fuse_presum;
     p.variant = opt.variant;
     p.overlap = opt.overlap;
+    p.fuse_combine = opt.fuse_combine;
     if (n == 0) return p;
     Builder bld(p);
     bld.ata(0, n);
@@ -803,6 +858,7 @@ Plan make_gemm_plan(int32_t mode, int64_t m, int64_t n, int64_t k, int64_t lda, 
     p.fallback = false;
     p.tile_cfg = mode == MODE_BF16X3 ? opt.tile_cfg : (mode == MODE_FP8 || mode == MODE_F32) && opt.tile_cfg == 3 ? 3 : mode == MODE_F32 && opt.tile_cfg == 2 ? 2 : 0;
     p.fuse = opt.fuse_presum;
+    p.fuse_combine = opt.fuse_combine;
     p.variant = opt.variant;
     if (n == 0 || k == 0) return p;
     Builder bld(p);
@@ -906,7 +962,7 @@ void split_leaves(Plan& p, int64_t target, int64_t min_chunk) {
         const int64_t most_fb = L.K / chunk_min(t_fb, 128);
         const int64_t s_fb = L.fb_node >= 0 && t_fb > 0 && t_fb < target && most_fb >= 2
                                  ? std::min(target / t_fb, most_fb) : 1;
-        if (s < 2 && s_fb < 2) continue;
+        if ((s < 2 && s_fb < 2) || L.nq > 0) continue;   // (an epilogue combine needs the whole K)
         split_leaf(p, L, s, s_fb);
     }
 }
@@ -961,6 +1017,7 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
     int64_t total_tiles = 0;
     for (const auto& L : p.leaves) {
         if (L.ksplit > 1) return;                  // split_leaves has cut this launch
+        if (L.nq > 0) return;                      // launch rounds: no single last round
         total_tiles += L.tiles;
     }
     if (total_tiles > 64 * slots) return;         // the tail is a small part of the launch
@@ -1039,7 +1096,8 @@ void finalize_plan(Plan& p) {
     // overlap: leaves that read only A (no pre-sum operand) first, each group
     // longest first; the packings and quantisations of views of A run before
     // the pre-sums
-    const bool ov = p.overlap && !p.presum.empty();
+    const bool rounds = std::any_of(p.leaves.begin(), p.leaves.end(), [](const LeafDesc& L) { return L.nq > 0; });
+    const bool ov = p.overlap && !p.presum.empty() && !rounds;
     auto indep = [&](const LeafDesc& L) {
         return L.X.base == BASE_A && L.Y.base == BASE_A && (L.sx2 == 0 || L.X2.base == BASE_A) &&
                (L.sy2 == 0 || L.Y2.base == BASE_A);
@@ -1048,6 +1106,24 @@ void finalize_plan(Plan& p) {
         if (ov && indep(a) != indep(c)) return indep(a);
         return tile_k(a) > tile_k(c);
     });
+    constexpr int kRounds = 5;
+    if (rounds) {
+        // the epilogue combines fix their products' rounds; every other leaf
+        // (longest first) joins the round with the least work so far
+        double load[kRounds] = {0, 0, 0, 0, 0};
+        for (const auto& L : p.leaves)
+            if (L.nq > 0) load[L.round] += (double)L.tiles * (double)tile_cost(L);
+        for (auto& L : p.leaves) {
+            if (L.nq > 0) continue;
+            const int r = (int)(std::min_element(load, load + kRounds) - load);
+            L.round = r;
+            load[r] += (double)L.tiles * (double)tile_cost(L);
+        }
+        std::stable_sort(p.leaves.begin(), p.leaves.end(),
+                         [](const LeafDesc& a, const LeafDesc& c) { return a.round < c.round; });
+    } else {
+        for (auto& L : p.leaves) L.round = 0;
+    }
     int64_t t = 0;
     p.indep_tiles = 0;
     for (auto& L : p.leaves) {
@@ -1056,6 +1132,12 @@ void finalize_plan(Plan& p) {
         if (ov && indep(L)) p.indep_tiles = t;
     }
     p.total_tiles = t;
+    p.round_tiles.clear();
+    if (rounds) {
+        p.round_tiles.assign(kRounds + 1, t);
+        for (auto it = p.leaves.rbegin(); it != p.leaves.rend(); ++it) p.round_tiles[it->round] = it->tile_begin;
+        for (int r = kRounds - 1; r >= 0; --r) p.round_tiles[r] = std::min(p.round_tiles[r], p.round_tiles[r + 1]);
+    }
     if (p.indep_tiles >= p.total_tiles) p.indep_tiles = 0;   // nothing to overlap with
     t = 0;
     p.fb_leaves.clear();

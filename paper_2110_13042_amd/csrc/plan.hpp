@@ -107,8 +107,21 @@ struct LeafDesc {
     // launch is small, so it may cut where the mode's launch need not):
     // fb_ksplit chunks of fb_kchunk rows (<= 1: none), partials at part64_off.
     int32_t fb_ksplit;
-    int32_t pad2_;
+    int32_t round;            // launch round of a plan with combines in the epilogue (0 otherwise)
     int64_t fb_kchunk;
+    // Strassen combine in the epilogue (PlanOptions::fuse_combine): product
+    // M_i of a node whose seven products are all leaves goes straight into
+    // its one or two quadrants of the node's target (out_*).  Quadrant q
+    // (0: C11, 1: C12, 2: C21, 3: C22) starts at row (q >= 2 ? qn1 : 0) and
+    // column (q odd ? qk1 : 0) of the target and takes the product's
+    // elements that fall inside it (C11 and C12 have qn1 rows, C11 and C21
+    // qk1 columns); the first contribution to a quadrant overwrites it, the
+    // later ones add qsign times the product to what the earlier launch
+    // rounds left there.
+    int32_t nq;               // 0: plain store; 1 or 2 quadrants
+    int32_t quad[2], qsign[2], qfirst[2];
+    int32_t qpad_;
+    int64_t qn1, qk1;
 };
 
 // Sum of the K-chunk partials of a split leaf (one work item per output
@@ -246,6 +259,7 @@ struct PlanOptions {
     int64_t slots = 0;             // > 0: balance the leaf launch's last round over this
                                    // many resident workgroups (balance_tail)
     bool overlap = false;          // order the leaves that read only A first (indep_tiles)
+    bool fuse_combine = false;     // last-level combines in the leaf epilogues (Strassen form)
     bool bounded = false;          // make_staged_plan: Strassen roots product by product
     int32_t seq_levels = 0;        // make_staged_plan: top levels run product by product
                                    // (0: the fewest that keep the workspace within
@@ -281,6 +295,14 @@ struct Plan {
     std::vector<std::vector<Sum2Desc>> sums;        // bounded stages: single pre-sums, top-down (first)
     std::vector<std::vector<AccumDesc>> accum;      // bounded stages: products into quadrants, bottom-up (last)
     bool own_packings = false;                      // split-BF16: pack each leaf operand on its own
+    // Combines in the leaf epilogues: a node whose seven products are all
+    // leaves gets no product buffers and no combine; its products run in five
+    // dependent launch rounds, {M1}, {M2}, {M3, M4}, {M5, M6}, {M7}, so that
+    // every quadrant element has one writer per round and receives the
+    // combine's own left-to-right sum.  Round r is the tiles [round_tiles[r],
+    // round_tiles[r + 1]) of the leaf order (empty: one leaf launch).
+    bool fuse_combine = false;
+    std::vector<int64_t> round_tiles;
     // Overlap of the pre-sums with the leaf products: with `overlap` set, the
     // leaves whose operands are ready before any pre-sum (views of A, read
     // directly or, for split-BF16, through the column-norm pass's packing)

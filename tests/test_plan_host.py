@@ -3,7 +3,8 @@ planner source is compiled with the host compiler into a small driver that
 prints the plans' structure.  Covers the tail balancer, the FP64 fallback's
 own K split, the K-chunk granule, the per-operand split-BF16 packing past the
 4 GiB buffer reach, the pre-sum work-item width, Winograd's workspace, and
-the bounded-workspace (staged) plans against the resident ones."""
+the bounded-workspace (staged) plans against the resident ones, and the
+plans that combine their last Strassen level in the leaf epilogues."""
 import os
 import shutil
 import subprocess
@@ -17,6 +18,8 @@ DRIVER = r"""
 #include "plan.hpp"
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <tuple>
 #include <stdexcept>
 #include <vector>
 using namespace ata;
@@ -76,7 +79,66 @@ static void show_staged(const char* tag, int32_t mode, int64_t m, int64_t n, int
     }
 }
 
+// Combines in the leaf epilogues against the materialised plan: same
+// multiplications; per fused node, every quadrant's writers in increasing
+// launch rounds with the combine's order of signs, the first one overwriting.
+static void show_epi(const char* tag, int32_t mode, int64_t m, int64_t n, int64_t b, int32_t d, double tau,
+                     bool gemm = false, int64_t k = 0) {
+    PlanOptions o;
+    o.leaf_cutoff = b; o.max_depth = d; o.spread_tau = tau; o.split_target = 2048; o.slots = 256;
+    try {
+        Plan r = gemm ? make_gemm_plan(mode, m, n, k, n, k, k, o) : make_plan(mode, m, n, n, o);
+        o.fuse_combine = true;
+        Plan f = gemm ? make_gemm_plan(mode, m, n, k, n, k, k, o) : make_plan(mode, m, n, n, o);
+        int64_t rc = 0, fc = 0, fused = 0, split_fused = 0, bad_round = 0;
+        for (const auto& v : r.combine) rc += (int64_t)v.size();
+        for (const auto& v : f.combine) fc += (int64_t)v.size();
+        struct W { int round, sign, first; };
+        std::map<std::tuple<int32_t, int64_t, int64_t, int64_t, int32_t, int32_t, int>, std::vector<W>> q;
+        for (const auto& L : f.leaves) {
+            const int rr = L.round;
+            if (!f.round_tiles.empty() &&
+                (L.tile_begin < f.round_tiles.at(rr) || L.tile_begin + L.tiles > f.round_tiles.at(rr + 1)))
+                ++bad_round;
+            if (L.nq == 0) continue;
+            ++fused;
+            if (L.ksplit > 1) ++split_fused;
+            for (int i = 0; i < L.nq; ++i)
+                q[std::make_tuple(L.out_kind, L.out_off, L.out_row0, L.out_col0, L.pred_node, L.pred_value, L.quad[i])]
+                    .push_back(W{L.round, L.qsign[i], L.qfirst[i]});
+        }
+        static const int want_n[4] = {4, 2, 2, 4};
+        static const int want_sign[4][4] = {{1, 1, -1, 1}, {1, 1, 0, 0}, {1, 1, 0, 0}, {1, -1, 1, 1}};
+        int64_t bad_quad = 0;
+        for (auto& kv : q) {
+            auto& w = kv.second;
+            const int quad = std::get<6>(kv.first);
+            std::stable_sort(w.begin(), w.end(), [](const W& a, const W& c) { return a.round < c.round; });
+            bool ok = (int)w.size() == want_n[quad];
+            for (size_t i = 0; ok && i < w.size(); ++i) {
+                ok = w[i].sign == want_sign[quad][i] && w[i].first == (i == 0 ? 1 : 0) &&
+                     (i == 0 || w[i].round > w[i - 1].round);
+            }
+            if (!ok) ++bad_quad;
+        }
+        printf("%s mults=%lld resident_mults=%lld levels=%d resident_levels=%d arena=%lld resident_arena=%lld "
+               "combines=%lld resident_combines=%lld fused=%lld quads=%zu bad_quad=%lld split_fused=%lld "
+               "bad_round=%lld rounds=%zu launches=%lld resident_launches=%lld\n", tag, (long long)f.stats.mults,
+               (long long)r.stats.mults, f.stats.max_levels, r.stats.max_levels, (long long)f.arena_elems,
+               (long long)r.arena_elems, (long long)fc, (long long)rc, (long long)fused, q.size(),
+               (long long)bad_quad, (long long)split_fused, (long long)bad_round, f.round_tiles.size(),
+               (long long)f.launches(), (long long)r.launches());
+    } catch (const std::exception& e) {
+        printf("%s error=%s\n", tag, e.what());
+    }
+}
+
 int main() {
+    show_epi("epi_f32_2lv", MODE_F32, 16384, 16384, 2048, 2, 4096.0);
+    show_epi("epi_f64_odd", MODE_F64, 3001, 2999, 256, 3, 0.0);
+    show_epi("epi_bf16_fb", MODE_BF16X3, 4095, 4097, 512, 2, 20.0);
+    show_epi("epi_gemm", MODE_F32, 3000, 2500, 512, 2, 0.0, true, 2100);
+    show_epi("epi_none", MODE_F32, 2048, 2048, 4096, 2, 0.0);
     show_staged("staged_f64_30k", MODE_F64, 30000, 30000, 0, -1, 0.0);
     show_staged("staged_f64_odd", MODE_F64, 3001, 2999, 256, 3, 0.0);
     show_staged("staged_f32_fb", MODE_F32, 4096, 4096, 512, 2, 4096.0);
@@ -185,3 +247,26 @@ def test_staged_workspace_within_sec33_bound(plans):
     n = 30000
     assert p["resident_arena"] > 20 * n * n
     assert p["arena"] <= 1.5 * n * n
+
+
+def test_epilogue_combine_plans(plans):
+    """Combines in the leaf epilogues: the same multiplications and levels as
+    the materialised plan, one combine fewer per fused node (seven product
+    buffers less workspace), no fused leaf cut into K chunks, every leaf inside
+    its launch round, and every quadrant of every fused node written in the
+    combine's order (C11: +M1 +M4 -M5 +M7, C12: +M3 +M5, C21: +M2 +M4, C22:
+    +M1 -M2 +M3 +M6) in strictly increasing rounds, the first write
+    overwriting.  Flagged-node alternatives and general products included."""
+    for tag in ("epi_f32_2lv", "epi_f64_odd", "epi_bf16_fb", "epi_gemm"):
+        p = plans[tag]
+        assert "error" not in p, (tag, p)
+        assert p["mults"] == p["resident_mults"] and p["levels"] == p["resident_levels"] >= 1, tag
+        assert p["fused"] > 0 and p["fused"] % 7 == 0, tag
+        nodes = p["fused"] // 7
+        assert p["combines"] == p["resident_combines"] - nodes, tag
+        assert p["quads"] == 4 * nodes and p["bad_quad"] == 0, tag
+        assert p["split_fused"] == 0 and p["bad_round"] == 0 and p["rounds"] == 6, tag
+        assert p["arena"] < p["resident_arena"], tag
+    # no Strassen level: nothing to fuse, one leaf launch
+    p = plans["epi_none"]
+    assert p["fused"] == 0 and p["rounds"] == 0 and p["launches"] == p["resident_launches"]
