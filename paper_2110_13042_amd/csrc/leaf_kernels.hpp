@@ -1313,16 +1313,20 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
     if (nk > 1) gload(1);
     __syncthreads();
     const int io = lane & 15, ko = 32 * (lane >> 4);
-    int sa_next = nk > 0 ? 127 + sx[sb0 * sxs + ti] : 127, sb_next = nk > 0 ? 127 + sy[sb0 * sys + tj] : 127;
+    // block scales: the exponents of slab kt + 1 are loaded in iteration kt
+    // ahead of the slab loads and biased in iteration kt + 1 (vector memory
+    // counts complete in order: a use right after them would also wait for
+    // slab kt + 2's loads)
+    int ex = nk > 0 ? sx[sb0 * sxs + ti] : 0, ey = nk > 0 ? sy[sb0 * sys + tj] : 0;
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
         if (kt + 1 < nk) sstore(cur ^ 1);
-        if (kt + 2 < nk) gload(kt + 2);
-        const int sa = sa_next, sb = sb_next;
+        const int sa = 127 + ex, sb = 127 + ey;
         if (kt + 1 < nk) {
-            sa_next = 127 + sx[(sb0 + kt + 1) * sxs + ti];
-            sb_next = 127 + sy[(sb0 + kt + 1) * sys + tj];
+            ex = sx[(sb0 + kt + 1) * sxs + ti];
+            ey = sy[(sb0 + kt + 1) * sys + tj];
         }
+        if (kt + 2 < nk) gload(kt + 2);
         v8i fa[4], fb[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
@@ -1397,13 +1401,24 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
     const int64_t cp = Q.cols_p;
     const int64_t col0 = (isx ? (int64_t)ti * TM : (int64_t)tj * TN) + lane;
     const int gbase = (w & 3) * 2;                // this wave's two row-groups of the slab
+    // byte offsets of this lane's four column segments in row-group gbase of
+    // the K chunk's first slab; a lane past the padded width keeps the offset
+    // past the end of the array (keep = 0), where the range check reads zeros
+    uint32_t o0[4], keep[4];
+#pragma unroll
+    for (int seg = 0; seg < 4; ++seg) {
+        const int64_t col = col0 + seg * 64;
+        o0[seg] = col < cp ? (uint32_t)(((sb0 * 8 + gbase) * cp + col) * 16) : past;
+        keep[seg] = col < cp ? 0xFFFFFFFFu : 0u;
+    }
+    const uint32_t group_bytes = (uint32_t)(cp * 16), slab_bytes = 8 * group_bytes;
     auto issue = [&](int64_t kt, int stage) {
         unsigned char* base = smem + stage * STAGE + (isx ? 0 : HALF);
+        const uint32_t step = (uint32_t)kt * slab_bytes;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int g = gbase + (i >> 2), seg = i & 3;
-            const int64_t col = col0 + seg * 64;
-            const uint32_t off = col < cp ? (uint32_t)((((sb0 + kt) * 8 + g) * cp + col) * 16) : past;
+            const uint32_t off = o0[seg] + ((step + (uint32_t)(i >> 2) * group_bytes) & keep[seg]);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(src, ATA_LDS_PTR(base + (g * 256 + seg * 64) * 16), 16,
                                                      (int)off, 0, 0, 0);
         }
@@ -1432,13 +1447,22 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
         const v4u hi = *reinterpret_cast<const v4u*>(p + 256 * 16);
         return v8i{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     };
+    // block scales: the exponents of slab kt + 1 are loaded at the start of
+    // step kt, ahead of that step's slab loads, and biased at step kt + 1
+    // (vector memory counts complete in order, so a use in step kt would also
+    // wait for the slab loads issued before it)
+    int ex = nk > 0 ? sx[sb0 * sxs + bx] : 0, ey = nk > 0 ? sy[sb0 * sys + by] : 0;
     auto step = [&](int64_t kt) {
         const int cur = (int)(kt & 1);
         __builtin_amdgcn_s_waitcnt(0x0F70);       // this wave's loads of slab kt are done
         __builtin_amdgcn_s_barrier();             // every wave's loads of slab kt are visible,
                                                   // and slab kt - 1's stage is free
-        if (kt + 1 < nk) issue(kt + 1, cur ^ 1);
-        const int sa = 127 + sx[(sb0 + kt) * sxs + bx], sb = 127 + sy[(sb0 + kt) * sys + by];
+        const int sa = 127 + ex, sb = 127 + ey;
+        if (kt + 1 < nk) {
+            ex = sx[(sb0 + kt + 1) * sxs + bx];
+            ey = sy[(sb0 + kt + 1) * sys + by];
+            issue(kt + 1, cur ^ 1);
+        }
         const unsigned char* xs = smem + cur * STAGE + fo + (wm * 128) * 16;
         const unsigned char* ys = smem + cur * STAGE + HALF + fo + (wn * 64) * 16;
         v8i fb[4];
