@@ -90,8 +90,10 @@ def test_precision_forms_16384_sampled(h):
 def test_fp8_small_integers_bit_exact(h, tile):
     rng = np.random.default_rng(61)
     h.set("leaf_tile", tile)
+    # (the last two: long contractions with an odd number of 128-row slabs,
+    # cut into K chunks because their launches have few tiles)
     for (m, n, b, depth) in [(300, 513, 128, 1), (1000, 777, 256, 0), (64, 700, 128, 1), (5, 3, 64, 0),
-                             (2000, 900, 1024, 0)]:
+                             (2000, 900, 1024, 0), (4000, 700, 1024, 0), (9000, 300, 512, 0)]:
         _say("case: fp8 int", m, n, b, depth, "tile", tile)
         A = rng.integers(-2, 3, (m, n)).astype(np.float32)
         h.set("leaf_cutoff", b)
