@@ -1,8 +1,12 @@
 // Leaf products of the AtA plan on MFMA: SYRK leaves (lower(X^T X), the
 // paper's ?syrk base case, Sec. 3.1) and GEMM leaves (X^T Y, the ?gemm base
-// case of Strassen), all leaves of a plan in one grouped launch.
+// case of Strassen), all leaves of a plan in one grouped launch (or in the
+// five launch rounds of a plan that combines its last Strassen level in the
+// leaf epilogues).  The kernels are templates on EPI: leaf.hip builds them
+// with plain stores, leaf_epi.hip with the epilogue that adds a product into
+// its one or two node quadrants (TileStore).
 //
-// Each workgroup (4 waves) computes one 128 x 128 output tile.  The
+// The 128 x 128 engines: each workgroup (4 waves) computes one output tile.  The
 // contraction runs over rows of A (the K loop): a 16-row slab of X's and Y's
 // tile columns is staged through LDS (double-buffered, one barrier per slab),
 // each wave owns a 64 x 64 sub-tile.  Rows of A are contiguous along the
