@@ -29,7 +29,11 @@ import argparse
 import hashlib
 import json
 import os
+import shutil
+import statistics
+import subprocess
 import sys
+import threading
 import time
 
 import numpy as np
@@ -50,6 +54,56 @@ def leaf_source_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+class PowerSampler:
+    """Socket power and graphics clock sampled with amd-smi while a timed region
+    runs (every 0.25 s, in a thread of this process; off unless asked for).
+    Reports the medians of the samples taken under load (power above half the
+    busiest sample), which leave out the idle moments at the region's ends."""
+
+    def __init__(self, enabled: bool):
+        self.enabled = enabled and shutil.which("amd-smi") is not None
+        self.samples = []
+        self._stop = threading.Event()
+        self._thread = None
+
+    def _poll(self):
+        while not self._stop.is_set():
+            try:
+                r = subprocess.run(["amd-smi", "metric", "-p", "-c", "--json"], capture_output=True, text=True,
+                                   timeout=5)
+                j = json.loads(r.stdout)
+                g = j["gpu_data"][0] if isinstance(j, dict) else j[0]
+                watts = float(g["power"]["socket_power"]["value"])
+                clks = [float(v["clk"]["value"]) for k, v in g["clock"].items()
+                        if k.startswith("gfx_") and isinstance(v, dict)
+                        and isinstance(v.get("clk", {}).get("value"), (int, float))]
+                if clks:
+                    self.samples.append((watts, sum(clks) / len(clks)))
+            except (OSError, ValueError, KeyError, IndexError, TypeError, subprocess.SubprocessError):
+                pass
+            self._stop.wait(0.25)
+
+    def __enter__(self):
+        if self.enabled:
+            self._thread = threading.Thread(target=self._poll, daemon=True)
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        if self._thread is not None:
+            self._stop.set()
+            self._thread.join()
+
+    def summary(self):
+        if not self.samples:
+            return None
+        top = max(w for w, _ in self.samples)
+        busy = [(w, c) for w, c in self.samples if w >= 0.5 * top]
+        return {"socket_w_median": statistics.median(w for w, _ in busy),
+                "gfx_mhz_median": round(statistics.median(c for _, c in busy), 1),
+                "samples": len(busy), "tool": "amd-smi metric -p -c (0.25 s period)"}
 
 
 def traffic_from_profiles(mode: str, workload: str):
@@ -145,11 +199,12 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
     # timed region: K steps; the library records phase events on the same stream
     h.set("profile", 1)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with PowerSampler(args.sample_power) as power:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     rep = h.report()
     h.set("profile", 0)
     h.close()
@@ -184,6 +239,8 @@ def run_mode(ata, torch, dev, A_np, mode: str, args, wl: str):
                      "algorithmic_flops_per_launch": leaf_flops,
                      "avg_launch_ms": round(leaf_ms, 4)},
     }
+    if args.sample_power:
+        res["power"] = power.summary()
     return res, C
 
 
@@ -440,6 +497,8 @@ def main() -> int:
                          "leaf launch; -1: the library's default")
     ap.add_argument("--bounded", action="store_true",
                     help="bounded workspace: Strassen roots run product by product")
+    ap.add_argument("--sample-power", action="store_true",
+                    help="sample socket power and graphics clock with amd-smi during each mode's timed steps")
     ap.add_argument("--fuse-combine", action="store_true",
                     help="Strassen combines of the last level in the leaf epilogues (five leaf launch rounds)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -525,6 +584,8 @@ def main() -> int:
         "roofline": head["roofline"],
         "side_by_side": {md: results[md] for md in modes[1:]},
     }
+    if "power" in head:
+        out["config"]["power"] = head["power"]
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
