@@ -492,7 +492,10 @@ ata_status_t build_staged(const ata_ctx* h, const PlanKey& k, DevicePlan& dp) {
             o.max_depth = st[0].stats.max_levels - 1;
             st = make_staged_plan(k.mode, k.m, k.n, k.lda, o);
         }
-        if (st[0].fallback) fuse_pack_into_norms(st[0], st[0].col1);
+        if (st[0].fallback) {
+            fuse_pack_into_norms(st[0], st[0].col1);
+            fuse_norms_into_quant(st[0], st[0].col1, st[0].col2, st[0].col_partial);
+        }
     } catch (const std::invalid_argument&) {
         return ATA_ERR_INVALID_VALUE;
     } catch (const std::length_error&) {
@@ -535,7 +538,10 @@ ata_status_t build_gram_plan(const ata_ctx* h, const PlanKey& k, Fits fits, Plan
             o.max_depth = out.stats.max_levels - 1;
             out = make_plan(k.mode, k.m, k.n, k.lda, o);
         }
-        if (out.fallback) fuse_pack_into_norms(out, out.col1);
+        if (out.fallback) {
+            fuse_pack_into_norms(out, out.col1);
+            fuse_norms_into_quant(out, out.col1, out.col2, out.col_partial);
+        }
     } catch (const std::invalid_argument&) {
         return ATA_ERR_INVALID_VALUE;
     } catch (const std::length_error&) {
@@ -840,20 +846,26 @@ hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, v
         if (ev && e == hipSuccess) e = hipEventRecord(ev[i], st);
     };
     mark(0);
+    const int32_t ps = p.pack_split, q0 = p.pack8_norm, qs = std::max(p.pack8_split, q0);
     if (p.fallback) {
-        e = launch_colnorms(dp.d_col1, (int)p.col1.size(), p.col1.back().elem_begin + p.col1.back().elems,
-                            dp.d_col2, (int)p.col2.size(), p.col2.back().elem_begin + p.col2.back().elems,
-                            static_cast<const float*>(A), nullptr, partial, nu, st, arena, has_pack(p.col1));
+        // FP8: the quantisation of the whole of A writes the norm partials
+        if (q0 > 0)
+            e = launch_quant8(dp.d_pack8, q0, p.pack8[q0 - 1].elem_begin + p.pack8[q0 - 1].elems, A, arena, flags,
+                              st, nullptr, nullptr, partial);
+        if (e == hipSuccess)
+            e = launch_colnorms(dp.d_col1, (int)p.col1.size(), p.col1.back().elem_begin + p.col1.back().elems,
+                                dp.d_col2, (int)p.col2.size(), p.col2.back().elem_begin + p.col2.back().elems,
+                                static_cast<const float*>(A), nullptr, partial, nu, st, arena, has_pack(p.col1));
         if (e == hipSuccess)
             e = launch_flags(nu, dp.d_nodes, (int)p.nodes.size(), h->popt.spread_tau * h->popt.spread_tau, flags, st);
     }
     mark(1);
     // packings and quantisations of views of A (the A-only leaves read them)
-    const int32_t ps = p.pack_split, qs = p.pack8_split;
     if (e == hipSuccess && ps > 0)
         e = launch_pack(dp.d_pack, ps, p.pack[ps - 1].elem_begin + p.pack[ps - 1].elems, A, arena, flags, st);
-    if (e == hipSuccess && qs > 0)
-        e = launch_quant8(dp.d_pack8, qs, p.pack8[qs - 1].elem_begin + p.pack8[qs - 1].elems, A, arena, flags, st);
+    if (e == hipSuccess && qs > q0)
+        e = launch_quant8(dp.d_pack8 + q0, qs - q0, p.pack8[qs - 1].elem_begin + p.pack8[qs - 1].elems, A, arena,
+                          flags, st);
     if (ov && e == hipSuccess) {
         // the leaves that read only A, and the FP64 fallback, beside the pre-sums
         e = hipEventRecord(h->fork_ev, st);
@@ -1461,10 +1473,15 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
     const int64_t slots = (int64_t)leaf_blocks_per_cu(mode, p.tile_cfg) * 256;
     BatchPtrs bp{be.d_A, be.d_C, persistent_for(h->batch_persistent, p) ? be.d_counter : nullptr, slots};
     BatchPtrs bq{be.d_A, be.d_C, nullptr, 0};
+    const int32_t q0 = p.pack8_norm;
     if (e == hipSuccess && p.fallback) {
         const ColDesc& l1 = be.col1.back();
         const ColDesc& l2 = be.col2.back();
-        e = launch_colnorms(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
+        if (q0 > 0)
+            e = launch_quant8(dp.d_pack8, q0, p.pack8[q0 - 1].elem_begin + p.pack8[q0 - 1].elems, nullptr, h->arena,
+                              be.d_flags, st, &bq, nullptr, be.d_partial);
+        if (e == hipSuccess)
+            e = launch_colnorms(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
                             (int)be.col2.size(), l2.elem_begin + l2.elems, nullptr, be.d_A, be.d_partial,
                             be.d_nu, st, h->arena, has_pack(be.col1));
         if (e == hipSuccess)
@@ -1481,8 +1498,8 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
     if (e == hipSuccess && !p.pack.empty())
         e = launch_pack(dp.d_pack, (int)p.pack.size(), p.pack.back().elem_begin + p.pack.back().elems,
                         nullptr, h->arena, be.d_flags, st, &bq);
-    if (e == hipSuccess && !p.pack8.empty())
-        e = launch_quant8(dp.d_pack8, (int)p.pack8.size(), p.pack8.back().elem_begin + p.pack8.back().elems,
+    if (e == hipSuccess && (int32_t)p.pack8.size() > q0)
+        e = launch_quant8(dp.d_pack8 + q0, (int)p.pack8.size() - q0, p.pack8.back().elem_begin + p.pack8.back().elems,
                           nullptr, h->arena, be.d_flags, st, &bq);
     mark(2);
     if (e == hipSuccess)
@@ -1599,6 +1616,7 @@ ata_status_t ata_gram_batched(ata_handle_t h, int64_t batch, const void* const* 
         if (mp.fallback) {
             build_colnorm_tasks(m, n, lda, batch, be->col1, be->col2, &part_off);
             fuse_pack_into_norms(be->dp->plan, be->col1);
+            fuse_norms_into_quant(be->dp->plan, be->col1, be->col2, part_off);
             for (int64_t i = 0; i < batch; ++i) nu_off += n[i];
         }
         ata_status_t st0 = upload_plan(*be->dp);

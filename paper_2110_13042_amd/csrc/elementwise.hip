@@ -296,12 +296,17 @@ __global__ __launch_bounds__(EW_THREADS) void pack_kernel(const PackDesc* tasks,
 // One workgroup per 128 x 128 block of an operand view: block amax, the
 // power-of-two exponent e (smallest e with amax <= 448 * 2^e; 448 = 0.875 * 2^9,
 // so with amax = f 2^E, f in [0.5, 1): e = E - 9 if f <= 0.875 else E - 8,
-// exact), then q = e4m3_RNE(a * 2^-e) packed in 16-row chunks.
+// exact), then q = e4m3_RNE(a * 2^-e) packed in 16-row chunks.  A task with
+// `norm` set (a full-height column slice of A) also writes, per column, the
+// FP64 sum of squares of the block's 128 rows in row order:
+// partial[part_off + bi * part_ld + col].
 __global__ __launch_bounds__(EW_THREADS) void quant8_kernel(const Pack8Desc* tasks, int ntasks,
                                                             const float* A0, float* arena,
                                                             const uint8_t* flags,
-                                                            const void* const* Aptrs, const float* B) {
+                                                            const void* const* Aptrs, const float* B,
+                                                            double* partial) {
     __shared__ float wmax[EW_THREADS / 64];
+    __shared__ double lower[128];
     const int64_t x = blockIdx.x;
     const Pack8Desc& d = tasks[find_task(tasks, ntasks, x)];
     if (d.pred_node >= 0 && (int32_t)flags[d.pred_node] != d.pred_value) return;
@@ -320,10 +325,17 @@ __global__ __launch_bounds__(EW_THREADS) void quant8_kernel(const Pack8Desc* tas
         v[q] = (r < d.src.prows && col < d.src.pcols) ? src[r * d.src.ld + col] : 0.f;
         amax = fmaxf(amax, fabsf(v[q]));
     }
+    double ss = 0.0;
+    if (d.norm) {
+#pragma unroll
+        for (int q = 0; q < 64; ++q) ss += (double)v[q] * (double)v[q];
+        if (h == 1) lower[c] = ss;
+    }
     for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
     if ((t & 63) == 0) wmax[t >> 6] = amax;
     __syncthreads();
     amax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    if (d.norm && h == 0 && col < d.src.pcols) partial[d.part_off + bi * d.part_ld + col] = ss + lower[c];
     int e = 0;
     if (amax > 0.f) {
         int E;
@@ -1011,11 +1023,11 @@ hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const
 
 hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, const void* A,
                          void* arena, const uint8_t* flags, hipStream_t stream, const BatchPtrs* bp,
-                         const void* B) {
+                         const void* B, double* partial) {
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(quant8_kernel, dim3((unsigned)blocks), dim3(EW_THREADS), 0, stream, d_tasks,
                        ntasks, static_cast<const float*>(A), static_cast<float*>(arena), flags,
-                       bp ? bp->A : nullptr, static_cast<const float*>(B));
+                       bp ? bp->A : nullptr, static_cast<const float*>(B), partial);
     return hipGetLastError();
 }
 

@@ -61,7 +61,7 @@ hipError_t launch_pack(const PackDesc* d_tasks, int ntasks, int64_t items, const
 // FP8 quantisation of the leaf operands (one workgroup per 128 x 128 block).
 hipError_t launch_quant8(const Pack8Desc* d_tasks, int ntasks, int64_t blocks, const void* A,
                          void* arena, const uint8_t* flags, hipStream_t stream,
-                         const BatchPtrs* bp = nullptr, const void* B = nullptr);
+                         const BatchPtrs* bp = nullptr, const void* B = nullptr, double* partial = nullptr);
 
 // Partial sums of the split-K leaves (after both leaf launches).
 hipError_t launch_reduce(int32_t mode, const ReduceDesc* d_tasks, int ntasks, int64_t items, void* C,

@@ -63,11 +63,13 @@ int64_t Plan::launches() const {
     for (const auto& v : combine) l += v.empty() ? 0 : 1;
     if (pack_split > 0) l += 1;
     if ((int64_t)pack.size() > pack_split) l += 1;
-    if (pack8_split > 0) l += 1;
-    if ((int64_t)pack8.size() > pack8_split) l += 1;
+    const int32_t q8 = std::max(pack8_split, pack8_norm);
+    if (pack8_norm > 0) l += 1;
+    if (q8 > pack8_norm) l += 1;
+    if ((int64_t)pack8.size() > q8) l += 1;
     if (!fb_leaves.empty()) l += 1;
     if (!reduce.empty()) l += 1;
-    if (fallback) l += 3;  // column norm passes + flags
+    if (fallback) l += norm_pass1 ? 3 : 2;  // column norm passes + flags
     for (const auto& v : sums) l += v.empty() ? 0 : 1;
     for (const auto& v : accum) l += v.empty() ? 0 : 1;
     return l;
@@ -791,6 +793,70 @@ void fuse_pack_into_norms(Plan& p, std::vector<ColDesc>& col1) {
     if (p.overlap) finalize_plan(p);
 }
 
+void number_pack8(Plan& p);
+
+void fuse_norms_into_quant(Plan& p, std::vector<ColDesc>& col1, std::vector<ColDesc>& col2,
+                           int64_t& partial_total) {
+    if (p.mode != MODE_FP8 || p.pack8.empty()) return;
+    std::vector<ColDesc> keep;
+    std::vector<int32_t> fused_probs;
+    for (const auto& c : col1) {
+        if (c.n <= 0 || c.m <= 0) continue;              // nothing for pass 1 (placeholder)
+        // unpredicated quantisations of full-height column slices of A that
+        // cover its columns exactly once, widest first at each column
+        std::vector<size_t> chain;
+        int64_t pos = 0;
+        while (pos < c.n) {
+            size_t best = p.pack8.size();
+            for (size_t i = 0; i < p.pack8.size(); ++i) {
+                const Pack8Desc& d = p.pack8[i];
+                if (d.norm || d.prob != c.prob || d.pred_node >= 0 || d.src.base != BASE_A || d.src.off != pos ||
+                    d.src.ld != c.lda || d.src.prows != c.m || d.src.pcols <= 0 || pos + d.src.pcols > c.n)
+                    continue;
+                if (best == p.pack8.size() || d.src.pcols > p.pack8[best].src.pcols) best = i;
+            }
+            if (best == p.pack8.size()) break;
+            chain.push_back(best);
+            pos += p.pack8[best].src.pcols;
+        }
+        if (pos != c.n) {
+            keep.push_back(c);
+            continue;
+        }
+        for (size_t i : chain) p.pack8[i].norm = 1;
+        fused_probs.push_back(c.prob);
+    }
+    if (fused_probs.empty()) return;
+    // partial layout: each problem's pass 2 sums nchunks rows of n doubles,
+    // from its pass 1 task or from its quantisations' 128-row block rows
+    int64_t off = 0;
+    for (auto& c2 : col2) {
+        if (c2.n <= 0) continue;
+        if (std::find(fused_probs.begin(), fused_probs.end(), c2.prob) != fused_probs.end())
+            c2.nchunks = cdiv(c2.m, 128);
+        c2.part_off = off;
+        for (auto& c1 : keep)
+            if (c1.prob == c2.prob) c1.part_off = off;
+        for (auto& d : p.pack8)
+            if (d.norm && d.prob == c2.prob) {
+                d.part_off = off + d.src.off;
+                d.part_ld = c2.n;
+            }
+        off += c2.nchunks * c2.n;
+    }
+    partial_total = off;
+    int64_t e = 0;
+    for (auto& c : keep) { c.elem_begin = e; e = item_align(e + c.elems); }
+    p.norm_pass1 = !keep.empty();
+    if (keep.empty()) keep.push_back(ColDesc{});
+    col1 = std::move(keep);
+    std::stable_partition(p.pack8.begin(), p.pack8.end(), [](const Pack8Desc& d) { return d.norm != 0; });
+    p.pack8_norm = 0;
+    for (const auto& d : p.pack8) p.pack8_norm += d.norm;
+    if (p.overlap) finalize_plan(p);
+    else number_pack8(p);
+}
+
 void build_colnorm_tasks(const int64_t* m, const int64_t* n, const int64_t* lda, int64_t count,
                          std::vector<ColDesc>& col1, std::vector<ColDesc>& col2,
                          int64_t* partial_total) {
@@ -1089,6 +1155,19 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split) {
     p.tail_chunks = (int32_t)best_s;
 }
 
+// Work items of the quantisations, numbered from 0 in each of their launches:
+// [0, pack8_norm) with the column norms, [pack8_norm, q) before the pre-sums
+// and [q, end) after them, q = max(pack8_split, pack8_norm).
+void number_pack8(Plan& p) {
+    const int32_t q = std::max(p.pack8_split, p.pack8_norm);
+    int64_t e = 0;
+    for (size_t i = 0; i < p.pack8.size(); ++i) {
+        if ((int32_t)i == p.pack8_norm || (int32_t)i == q) e = 0;
+        p.pack8[i].elem_begin = e;
+        e += p.pack8[i].elems;
+    }
+}
+
 void finalize_plan(Plan& p) {
     // LPT: longest per-tile contraction first (a split leaf's tiles cover one
     // K chunk; stable, so ties keep tree order)
@@ -1183,12 +1262,7 @@ void finalize_plan(Plan& p) {
         p.pack[i].elem_begin = e;
         e = item_align(e + p.pack[i].elems);
     }
-    e = 0;
-    for (size_t i = 0; i < p.pack8.size(); ++i) {
-        if ((int32_t)i == p.pack8_split) e = 0;
-        p.pack8[i].elem_begin = e;
-        e += p.pack8[i].elems;
-    }
+    number_pack8(p);
     e = 0;
     for (auto& d : p.reduce) { d.elem_begin = e; e = item_align(e + d.elems); }
 }

@@ -147,7 +147,10 @@ struct Pack8Desc {
     int64_t rows_p, cols_p;
     int64_t elem_begin, elems;
     int32_t pred_node, pred_value;
-    int32_t prob, pad_;
+    int32_t prob;
+    int32_t norm;             // also writes column-norm partials (one per 128-row block row)
+    int64_t part_off;         // those partials: partial[part_off + block_row * part_ld + column of the view]
+    int64_t part_ld;
 };
 
 // Split one FP32 operand view into the packed hi/lo layout (one work item per
@@ -315,6 +318,12 @@ struct Plan {
     // own launch: pack_split / pack8_split descriptors, whose work items are
     // numbered apart from the rest's (0: one launch after the pre-sums).
     int32_t pack_split = 0, pack8_split = 0;
+    // FP8 with column norms: the first pack8_norm quantisations (column
+    // slices of A that cover each such problem's columns once) also write
+    // its column-norm partials and run in their own launch before norm
+    // pass 2; norm_pass1 is false when no problem is left for pass 1.
+    int32_t pack8_norm = 0;
+    bool norm_pass1 = true;
     std::vector<NodeDesc> nodes;                    // AtA nodes (flags)
     std::vector<ColDesc> col1, col2;                // column-norm passes (when fallback)
     int64_t col_partial = 0;                        // doubles of the pass-1 partial sums
@@ -392,6 +401,17 @@ void balance_tail(Plan& p, int64_t slots, int32_t max_split = 16);
 // plan, or a batch's merged plan with its own pass 1 tasks), never to the
 // parts of a batch.
 void fuse_pack_into_norms(Plan& p, std::vector<ColDesc>& col1);
+
+// FP8 plans with column norms, the other way round: for each problem whose
+// quantisations include unpredicated full-height column slices of A that
+// cover its columns once (the whole of A, or the diagonal leaves' slices),
+// those quantisations also sum their column squares (per 128-row block row;
+// pass 2 then sums the block rows in order) and the problem drops out of
+// norm pass 1.  They move to the front of the list (pack8_norm); the pass 1 /
+// pass 2 partial layout is rebuilt and its size returned in `partial_total`.
+// Applied like fuse_pack_into_norms.
+void fuse_norms_into_quant(Plan& p, std::vector<ColDesc>& col1, std::vector<ColDesc>& col2,
+                           int64_t& partial_total);
 
 // Orders the leaves (longest contraction first) and fills the tile and
 // work-item prefix sums of every phase.

@@ -134,6 +134,29 @@ def test_batch_fallback_flags(h):
         assert full_error(G, plain.gram_packed(M)) <= 2e-5, i
 
 
+def test_batch_fp8_fallback_matches_single_calls(h):
+    """FP8 batch with ill-scaled members: the column norms come from the
+    quantisations of each member's column slices, so every member must take
+    the same flags as its own ata_gram call (a flag taken differently would
+    put FP64 against FP8 results, about 1e-2 apart)."""
+    mats = [workloads.scaled_normal(600, 300, seed=s, dtype=np.float32, span=1.0) for s in range(4)]
+    mats += _batch(76, 6, (100, 800), (50, 400))
+    h.set("leaf_cutoff", 64)
+    h.set("max_depth", 1)
+    h.set("spread_tau", 20.0)
+    _say("case: fp8 batch fallback")
+    got, _, _ = _run(h, mats, ata.F32_FP8E4M3)
+    dev = device()
+    flagged = 0
+    for i, (G, M) in enumerate(zip(got, mats)):
+        one = ata.gram(torch.from_numpy(M).to(dev), ata.F32_FP8E4M3, handle=h).double().cpu().numpy()
+        flagged += h.report()["flagged_nodes"]
+        assert full_error(G, one) <= 1e-6, i
+        assert full_error(G, plain.gram_packed(M)) < 0.1, i
+    h.set("spread_tau", 4096)
+    assert flagged > 0
+
+
 @pytest.mark.parametrize("mode", [ata.F32, ata.F32_BF16X3, ata.F32_FP8E4M3])
 def test_persistent_and_grid_launch_agree(h, mode):
     """The persistent leaf launch (per-XCD queues) and the one-workgroup-per-tile

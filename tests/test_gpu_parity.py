@@ -203,6 +203,41 @@ def test_fallback_flags_match_oracle(h):
     h.set("spread_tau", 4096)
 
 
+@pytest.mark.parametrize("b,depth", [(2048, 0), (150, 1)])
+def test_fp8_norms_from_quantisation_match_oracle(h, b, depth):
+    """FP8: the quantisations of A's column slices also sum the column
+    squares (no separate norm pass over A).  The norms must match the oracle's
+    and the flags must follow from them, for one leaf over all columns and
+    for the recursion's diagonal slices."""
+    m, n = 3000, 1200
+    A = workloads.scaled_normal(m, n, seed=46, dtype=np.float32, span=1.0)
+    h.set("leaf_cutoff", b)
+    h.set("max_depth", depth)
+    tau = 95.0              # the spreads of this input: see test_fallback_flags_match_oracle
+    h.set("spread_tau", tau)
+    _say("case: fp8 norms from the quantisation", b, depth)
+    Cp = run_gram(A, ata.F32_FP8E4M3, h)
+    rep = h.report()
+    nu_gpu, nodes = h.spread(n)
+    nu = plain.colnorms(A)
+    assert np.allclose(nu_gpu, nu, rtol=1e-13, atol=0)
+    c = recursive.count(m, n, b, split_m=False, max_strassen_depth=depth)
+    assert [(c0, w) for c0, w, _f in nodes] == [(c0, w) for c0, w, _leaf in c.ata_list]
+    got = [bool(f) for _c0, _w, f in nodes]
+    spreads = [emulate.spread(nu[c0:c0 + w]) for c0, w, _leaf in c.ata_list]
+    assert min(abs(sp / tau ** 2 - 1) for sp in spreads) > 1e-9
+    want = emulate.spread_flags(nu, c.ata_list, tau)
+    assert got == want and rep["flagged_nodes"] == sum(want) > 0
+    err = full_error(Cp, plain.gram_packed(A))
+    _say("  flagged", sum(want), "of", len(want), "e_F", err, "launches", rep["kernel_launches"])
+    assert err < 0.1
+    if depth == 0:
+        # the one node is flagged: the whole product in FP64, rounded once to
+        # the FP32 output
+        assert err <= 2.0 ** -24
+    h.set("spread_tau", 4096)
+
+
 def test_full_size_square_f32_8192_sampled(h):
     """The benchmark's workload at full size, default plan, 64 sampled columns."""
     _say("case: square_f32_8192 full size")

@@ -3,8 +3,9 @@ planner source is compiled with the host compiler into a small driver that
 prints the plans' structure.  Covers the tail balancer, the FP64 fallback's
 own K split, the K-chunk granule, the per-operand split-BF16 packing past the
 4 GiB buffer reach, the pre-sum work-item width, Winograd's workspace, and
-the bounded-workspace (staged) plans against the resident ones, and the
-plans that combine their last Strassen level in the leaf epilogues."""
+the bounded-workspace (staged) plans against the resident ones, the plans
+that combine their last Strassen level in the leaf epilogues, and the FP8
+quantisation that also sums the column squares."""
 import os
 import shutil
 import subprocess
@@ -133,7 +134,61 @@ static void show_epi(const char* tag, int32_t mode, int64_t m, int64_t n, int64_
     }
 }
 
+// FP8 with column norms: quantisations of column slices of A take over norm
+// pass 1.  Prints the fused tasks (whether they tile the columns once, full
+// height and unpredicated, with their partial offsets), the rebuilt partial
+// layout, whether every quantisation launch numbers its work items from 0
+// contiguously, and the launch counts before and after.
+static void show_q8(const char* tag, int64_t m, int64_t n, int64_t b, int32_t d, bool overlap) {
+    PlanOptions o;
+    o.leaf_cutoff = b; o.max_depth = d; o.spread_tau = 4096.0; o.split_target = 2048; o.slots = 0;
+    o.overlap = overlap;
+    try {
+        Plan p = make_plan(MODE_FP8, m, n, n, o);
+        const int64_t before = p.launches(), partial_before = p.col_partial;
+        const size_t tasks = p.pack8.size();
+        fuse_norms_into_quant(p, p.col1, p.col2, p.col_partial);
+        const int32_t pn = p.pack8_norm, q = std::max(p.pack8_split, pn);
+        int numbering_ok = 1;
+        int64_t e = 0;
+        for (size_t i = 0; i < p.pack8.size(); ++i) {
+            if ((int32_t)i == pn || (int32_t)i == q) e = 0;
+            if (p.pack8[i].elem_begin != e) numbering_ok = 0;
+            e += p.pack8[i].elems;
+        }
+        int fused_flags = 0, front = 1, tiles_once = 1, offsets_ok = 1;
+        std::vector<std::pair<int64_t, int64_t>> cols;
+        for (size_t i = 0; i < p.pack8.size(); ++i) {
+            const Pack8Desc& t = p.pack8[i];
+            fused_flags += t.norm;
+            if (t.norm && (int32_t)i >= pn) front = 0;
+            if (!t.norm) continue;
+            if (t.src.base != BASE_A || t.src.prows != m || t.pred_node >= 0) tiles_once = 0;
+            if (t.part_off != p.col2.at(0).part_off + t.src.off || t.part_ld != n) offsets_ok = 0;
+            cols.push_back({t.src.off, t.src.pcols});
+        }
+        std::sort(cols.begin(), cols.end());
+        int64_t pos = 0;
+        for (auto& cw : cols) {
+            if (cw.first != pos) tiles_once = 0;
+            pos = cw.first + cw.second;
+        }
+        if (pos != n) tiles_once = 0;
+        printf("%s pn=%d fused_flags=%d front=%d tiles_once=%d offsets_ok=%d nchunks=%lld partial=%lld "
+               "partial_before=%lld pass1=%d col1=%zu col1_items=%lld numbering_ok=%d tasks=%zu tasks_before=%zu "
+               "split=%d launches=%lld launches_before=%lld\n", tag, pn, fused_flags, front, tiles_once, offsets_ok,
+               (long long)p.col2.at(0).nchunks, (long long)p.col_partial, (long long)partial_before,
+               p.norm_pass1 ? 1 : 0, p.col1.size(), (long long)(p.col1.back().elem_begin + p.col1.back().elems),
+               numbering_ok, p.pack8.size(), tasks, p.pack8_split, (long long)p.launches(), (long long)before);
+    } catch (const std::exception& e) {
+        printf("%s error=%s\n", tag, e.what());
+    }
+}
+
 int main() {
+    show_q8("q8_leaf", 16384, 16384, 16384, 0, false);
+    show_q8("q8_odd", 1999, 1501, 256, 1, false);
+    show_q8("q8_overlap", 1536, 1100, 256, 1, true);
     show_epi("epi_f32_2lv", MODE_F32, 16384, 16384, 2048, 2, 4096.0);
     show_epi("epi_f64_odd", MODE_F64, 3001, 2999, 256, 3, 0.0);
     show_epi("epi_bf16_fb", MODE_BF16X3, 4095, 4097, 512, 2, 20.0);
@@ -270,3 +325,31 @@ def test_epilogue_combine_plans(plans):
     # no Strassen level: nothing to fuse, one leaf launch
     p = plans["epi_none"]
     assert p["fused"] == 0 and p["rounds"] == 0 and p["launches"] == p["resident_launches"]
+
+
+def test_fp8_quantisation_takes_over_norm_pass1(plans):
+    """FP8 with the spread check: the quantisations of full-height column
+    slices of A that tile its columns once (the whole of A for a single leaf,
+    the diagonal leaves' slices under the recursion), unpredicated and moved
+    to the front, also write the column-norm partials, one row of n doubles
+    per 128-row block row, and norm pass 1 has nothing left; every
+    quantisation launch numbers its work items from 0.  The norm launch of
+    the quantisations replaces pass 1, so the launch count does not grow."""
+    dims = {"q8_leaf": (16384, 16384), "q8_odd": (1999, 1501), "q8_overlap": (1536, 1100)}
+    for tag, (m, n) in dims.items():
+        p = plans[tag]
+        assert "error" not in p, (tag, p)
+        assert p["pn"] >= 1 and p["fused_flags"] == p["pn"] and p["front"] == 1, tag
+        assert p["tiles_once"] == 1 and p["offsets_ok"] == 1, tag
+        assert p["nchunks"] == -(-m // 128) and p["partial"] == p["nchunks"] * n, tag
+        assert p["pass1"] == 0 and p["col1"] == 1 and p["col1_items"] == 0, tag
+        assert p["numbering_ok"] == 1 and p["tasks"] == p["tasks_before"], tag
+    # a single SYRK leaf: its quantisation takes the norms, pass 1 goes
+    assert plans["q8_leaf"]["tasks"] == 1 and plans["q8_leaf"]["pn"] == 1
+    assert plans["q8_leaf"]["launches"] == plans["q8_leaf"]["launches_before"] - 1
+    # the recursion: eight diagonal leaves; the pre-sum quantisations keep
+    # their own launch
+    assert plans["q8_odd"]["pn"] == 8 and plans["q8_odd"]["tasks"] > 8
+    assert plans["q8_odd"]["launches"] == plans["q8_odd"]["launches_before"]
+    # overlap: the other views of A still go before the pre-sums
+    assert plans["q8_overlap"]["split"] > plans["q8_overlap"]["pn"] == 8
