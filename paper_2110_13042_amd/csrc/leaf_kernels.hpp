@@ -331,47 +331,76 @@ __device__ __forceinline__ void store_at(const Dest<OutT>& o, int64_t gi, int64_
     *p = o.accum ? *p + x : x;
 }
 
-// The epilogue stores of one tile: put() takes accumulator element (r, c)
-// of tile (ti, tj).  Kernels built without combines in the epilogue (EPI
-// false) store it into the leaf's target or its K chunk's partial sums; the
-// others send it to one or two destinations (make_dest).
+// The epilogue stores of one tile, a row at a time: row(ti, r) takes tile
+// row r of tile (ti, .) once, put(row, tj, c, v) stores its accumulator
+// element in column c of tile (., tj).  Kernels built without combines in the
+// epilogue (EPI false) store into the leaf's target or its K chunk's partial
+// sums: the destination's base, row stride and form (packed or strided) are
+// fixed per tile, so a row costs one address and one column limit and an
+// element a compare and a store.  The others send each element to one or two
+// destinations (make_dest).
 template <bool EPI, class OutT, int TM, int TN>
 struct TileStore;
 
 template <class OutT, int TM, int TN>
 struct TileStore<false, OutT, TM, TN> {
-    const LeafDesc& d;
-    OutT* C;
-    OutT* arena;
-    int split;
-    __device__ __forceinline__ TileStore(const LeafDesc& d_, int split_, OutT* C_, OutT* arena_)
-        : d(d_), C(C_), arena(arena_), split(split_) {}
-    __device__ __forceinline__ void put(int ti, int tj, int r, int c, OutT v) const {
-        const int64_t gi = (int64_t)ti * TM + r, gj = (int64_t)tj * TN + c;
-        if (gi >= d.rows || gj >= d.cols) return;
-        if (d.kind == LEAF_SYRK && gj > gi) return;
-        if (d.ksplit > 1)
-            arena[d.part_off + ((int64_t)split * d.rows + gi) * d.cols + gj] = v;
-        else if (d.out_kind == OUT_CDENSE)
-            C[(d.out_row0 + gi) * d.out_ld + d.out_col0 + gj] = v;
-        else if (d.out_kind == OUT_PACKED)
-            C[packed_index(d.out_row0 + gi, d.out_col0 + gj)] = v;
-        else
-            arena[d.out_off + gi * d.out_ld + gj] = v;
+    struct Row {
+        OutT* p;          // element (gi, 0) of the leaf's output
+        int64_t lim;      // columns gj < lim are stored (0 past the leaf's rows)
+    };
+    OutT* base;
+    int64_t ld, row0, rows, cols;
+    bool packed, syrk;
+    __device__ __forceinline__ TileStore(const LeafDesc& d, int split, OutT* C, OutT* arena) {
+        rows = d.rows;
+        cols = d.cols;
+        syrk = d.kind == LEAF_SYRK;
+        packed = false;
+        row0 = 0;
+        if (d.ksplit > 1) {
+            base = arena + d.part_off + (int64_t)split * d.rows * d.cols;
+            ld = d.cols;
+        } else if (d.out_kind == OUT_CDENSE) {
+            base = C + d.out_row0 * d.out_ld + d.out_col0;
+            ld = d.out_ld;
+        } else if (d.out_kind == OUT_PACKED) {
+            base = C + d.out_col0;        // row i of C starts at packed_index(i, 0)
+            ld = 0;
+            row0 = d.out_row0;
+            packed = true;
+        } else {
+            base = arena + d.out_off;
+            ld = d.out_ld;
+        }
+    }
+    __device__ __forceinline__ Row row(int ti, int r) const {
+        const int64_t gi = (int64_t)ti * TM + r;
+        const int64_t lim = gi >= rows ? 0 : syrk && gi + 1 < cols ? gi + 1 : cols;
+        const int64_t off = packed ? packed_index(row0 + gi, 0) : gi * ld;
+        return Row{base + off, lim};
+    }
+    __device__ __forceinline__ void put(const Row& w, int tj, int c, OutT v) const {
+        const int64_t gj = (int64_t)tj * TN + c;
+        // C and the arena are device memory: a global store, not a flat one
+        if (gj < w.lim) *(__attribute__((address_space(1))) OutT*)(w.p + gj) = v;
     }
 };
 
 template <class OutT, int TM, int TN>
 struct TileStore<true, OutT, TM, TN> {
+    struct Row {
+        int64_t gi;
+    };
     Dest<OutT> d0, d1;
     bool second;
     __device__ __forceinline__ TileStore(const LeafDesc& d, int split, OutT* C, OutT* arena)
         : d0(make_dest<OutT>(d, 0, split, C, arena)), d1(make_dest<OutT>(d, store_passes(d) - 1, split, C, arena)),
           second(store_passes(d) > 1) {}
-    __device__ __forceinline__ void put(int ti, int tj, int r, int c, OutT v) const {
-        const int64_t gi = (int64_t)ti * TM + r, gj = (int64_t)tj * TN + c;
-        store_at(d0, gi, gj, v);
-        if (second) store_at(d1, gi, gj, v);
+    __device__ __forceinline__ Row row(int ti, int r) const { return Row{(int64_t)ti * TM + r}; }
+    __device__ __forceinline__ void put(const Row& w, int tj, int c, OutT v) const {
+        const int64_t gj = (int64_t)tj * TN + c;
+        store_at(d0, w.gi, gj, v);
+        if (second) store_at(d1, w.gi, gj, v);
     }
 };
 
@@ -471,13 +500,15 @@ __device__ void tile_f32(const LeafDesc& d, const float* Xp, const float* Yp, co
         __syncthreads();
     }
     const TileStore<EPI, float, TILE_M, TILE_N> sink(d, kr.split, C, arena);
+#pragma unroll
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int c = wn * 64 + b * 32 + (lane & 31);
-                sink.put(ti, tj, r, c, acc[a][b][v]);
-            }
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const auto row = sink.row(ti, wm * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3));
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                sink.put(row, tj, wn * 64 + b * 32 + (lane & 31), acc[a][b][v]);
+        }
 }
 
 // FP32 with a 256 x 256 tile: four waves of 128 x 128 (4 x 4 blocks of
@@ -606,13 +637,12 @@ __device__ __forceinline__ void tile_f32_wide(const LeafDesc& d, const float* Xp
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int v = 0; v < 16; ++v) {
+            const auto row = sink.row(ti, wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3));
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int c = wn * 128 + b * 32 + (lane & 31);
-                sink.put(ti, tj, r, c, acc[a][b][v]);
-            }
+            for (int b = 0; b < 4; ++b)
+                sink.put(row, tj, wn * 128 + b * 32 + (lane & 31), acc[a][b][v]);
+        }
 }
 
 // The 256 x 256 FP32 tile on eight waves of 128 x 64 (4 x 2 blocks of 32 x 32,
@@ -735,13 +765,12 @@ __device__ __forceinline__ void tile_f32_wide8(const LeafDesc& d, const float* X
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int v = 0; v < 16; ++v) {
+            const auto row = sink.row(ti, wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3));
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int c = wn * 64 + b * 32 + (lane & 31);
-                sink.put(ti, tj, r, c, acc[a][b][v]);
-            }
+            for (int b = 0; b < 2; ++b)
+                sink.put(row, tj, wn * 64 + b * 32 + (lane & 31), acc[a][b][v]);
+        }
 }
 
 // The same engine for leaves with fused pre-sums: a side whose operand is
@@ -876,13 +905,12 @@ __device__ __forceinline__ void tile_f32_wide_sum(const LeafDesc& d, const float
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int v = 0; v < 16; ++v) {
+            const auto row = sink.row(ti, wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3));
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int c = wn * 128 + b * 32 + (lane & 31);
-                sink.put(ti, tj, r, c, acc[a][b][v]);
-            }
+            for (int b = 0; b < 4; ++b)
+                sink.put(row, tj, wn * 128 + b * 32 + (lane & 31), acc[a][b][v]);
+        }
 }
 
 // ------------------------------------------------------------ split-BF16 x3
@@ -1102,13 +1130,12 @@ __device__ __forceinline__ void tile_bf16x3(const LeafDesc& d, const float* aren
 #pragma unroll
     for (int a = 0; a < BMB; ++a)
 #pragma unroll
-        for (int b = 0; b < BNB; ++b)
+        for (int v = 0; v < 16; ++v) {
+            const auto row = sink.row(ti, wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3));
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * BMB * 32 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int cc = wn * BNB * 32 + b * 32 + (lane & 31);
-                sink.put(ti, tj, r, cc, acc[a][b][v]);
-            }
+            for (int b = 0; b < BNB; ++b)
+                sink.put(row, tj, wn * BNB * 32 + b * 32 + (lane & 31), acc[a][b][v]);
+        }
 }
 
 // LDS ring of the streamed split-BF16 engine (tile 4): slabs of 16 k (two
@@ -1235,13 +1262,12 @@ __device__ __forceinline__ void tile_bf16x3_wide8(const LeafDesc& d, const float
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int v = 0; v < 16; ++v) {
+            const auto row = sink.row(ti, wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3));
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int r = wm * 128 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int cc = wn * 64 + b * 32 + (lane & 31);
-                sink.put(ti, tj, r, cc, acc[a][b][v]);
-            }
+            for (int b = 0; b < 2; ++b)
+                sink.put(row, tj, wn * 64 + b * 32 + (lane & 31), acc[a][b][v]);
+        }
 }
 
 // ------------------------------------------------------------ FP8 e4m3
@@ -1356,13 +1382,12 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int v = 0; v < 4; ++v) {
+            const auto row = sink.row(ti, wm * 64 + a * 16 + 4 * (lane >> 4) + v);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = wm * 64 + a * 16 + 4 * (lane >> 4) + v;
-                const int c = wn * 64 + b * 16 + (lane & 15);
-                sink.put(ti, tj, r, c, acc[a][b][v]);
-            }
+            for (int b = 0; b < 4; ++b)
+                sink.put(row, tj, wn * 64 + b * 16 + (lane & 15), acc[a][b][v]);
+        }
 }
 
 // FP8 e4m3 with a 256 x 256 tile: four waves of 128 x 128 (8 x 8 blocks of
@@ -1486,13 +1511,12 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int v = 0; v < 4; ++v) {
+            const auto row = sink.row(ti, wm * 128 + a * 16 + 4 * (lane >> 4) + v);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = wm * 128 + a * 16 + 4 * (lane >> 4) + v;
-                const int c = wn * 64 + b * 16 + (lane & 15);
-                sink.put(ti, tj, r, c, acc[a][b][v]);
-            }
+            for (int b = 0; b < 4; ++b)
+                sink.put(row, tj, wn * 64 + b * 16 + (lane & 15), acc[a][b][v]);
+        }
 }
 
 // ---------------------------------------------------------------- FP64 MFMA
@@ -1613,15 +1637,19 @@ __device__ __forceinline__ void tile_f64(const LeafDesc& d, const InT* Xp, const
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int v = 0; v < 4; ++v) {
+                const auto row = sink.row(ti, wm * 64 + a * 16 + 4 * v + (lane >> 4));
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    sink.put(ti, tj, wm * 64 + a * 16 + 4 * v + (lane >> 4), wn * 64 + b * 16 + (lane & 15),
-                             (OutT)acc[a][b][v]);
+                for (int b = 0; b < 4; ++b)
+                    sink.put(row, tj, wn * 64 + b * 16 + (lane & 15), (OutT)acc[a][b][v]);
+            }
         return;
     }
+#pragma unroll
     for (int a = 0; a < 4; ++a)
+#pragma unroll
         for (int b = 0; b < 4; ++b)
+#pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = wm * 64 + a * 16 + 4 * v + (lane >> 4);
                 const int c = wn * 64 + b * 16 + (lane & 15);
@@ -1632,7 +1660,7 @@ __device__ __forceinline__ void tile_f64(const LeafDesc& d, const InT* Xp, const
                         reinterpret_cast<double*>(arena + d.part64_off)[((int64_t)kr.split * d.rows + gi) * d.cols + gj] =
                             acc[a][b][v];
                 } else {
-                    sink.put(ti, tj, r, c, (OutT)acc[a][b][v]);
+                    sink.put(sink.row(ti, r), tj, c, (OutT)acc[a][b][v]);
                 }
             }
 }
