@@ -801,7 +801,11 @@ void fuse_norms_into_quant(Plan& p, std::vector<ColDesc>& col1, std::vector<ColD
     std::vector<ColDesc> keep;
     std::vector<int32_t> fused_probs;
     for (const auto& c : col1) {
-        if (c.n <= 0 || c.m <= 0) continue;              // nothing for pass 1 (placeholder)
+        if (c.n <= 0) continue;                          // the placeholder of an empty list
+        if (c.m <= 0) {                                  // pass 1 writes its zero norms
+            keep.push_back(c);
+            continue;
+        }
         // unpredicated quantisations of full-height column slices of A that
         // cover its columns exactly once, widest first at each column
         std::vector<size_t> chain;

@@ -185,7 +185,56 @@ static void show_q8(const char* tag, int64_t m, int64_t n, int64_t b, int32_t d,
     }
 }
 
+// The same for a batch: one member with no rows (its pass 1 task stays and
+// writes zero norms), one whose quantisations take over, one SYRK leaf each.
+static void show_q8_batch(const char* tag) {
+    PlanOptions o;
+    o.leaf_cutoff = 512; o.max_depth = 0; o.spread_tau = 4096.0; o.split_target = 0; o.slots = 0;
+    try {
+        const int64_t m[3] = {0, 700, 300}, n[3] = {300, 400, 200}, lda[3] = {300, 400, 256};
+        std::vector<Plan> parts;
+        for (int i = 0; i < 3; ++i) parts.push_back(make_plan(MODE_FP8, m[i], n[i], lda[i], o));
+        Plan p = merge_plans(parts);
+        std::vector<ColDesc> col1, col2;
+        int64_t part = 0;
+        build_colnorm_tasks(m, n, lda, 3, col1, col2, &part);
+        const int64_t before = part;
+        fuse_norms_into_quant(p, col1, col2, part);
+        // the partial regions of pass 2 tile [0, part) in problem order
+        int64_t off = 0, regions_ok = 1, chunks[3] = {0, 0, 0};
+        for (const auto& c2 : col2) {
+            if (c2.part_off != off) regions_ok = 0;
+            chunks[c2.prob] = c2.nchunks;
+            off += c2.nchunks * c2.n;
+        }
+        if (off != part) regions_ok = 0;
+        int64_t kept_prob = -1, kept_items = 0, fused_ok = 1;
+        for (const auto& c1 : col1) {
+            if (c1.elems > 0) { kept_prob = c1.prob; kept_items = c1.elems; }
+            if (c1.part_off != col2.at(0).part_off) fused_ok = 0;    // the m = 0 member's region
+        }
+        int64_t fused_probs = 0;
+        for (size_t i = 0; i < p.pack8.size(); ++i) {
+            const Pack8Desc& t = p.pack8[i];
+            if (!t.norm) continue;
+            fused_probs |= 1 << t.prob;
+            const ColDesc* c2 = nullptr;
+            for (const auto& c : col2) if (c.prob == t.prob) c2 = &c;
+            if (!c2 || t.part_off != c2->part_off + t.src.off || t.part_ld != c2->n || (int32_t)i >= p.pack8_norm)
+                fused_ok = 0;
+        }
+        printf("%s col1=%zu kept_prob=%lld kept_items=%lld fused_probs=%lld fused_ok=%d regions_ok=%lld "
+               "chunks0=%lld chunks1=%lld chunks2=%lld pass1=%d part=%lld before=%lld\n", tag, col1.size(),
+               (long long)kept_prob, (long long)kept_items, (long long)fused_probs, (int)fused_ok,
+               (long long)regions_ok, (long long)chunks[0], (long long)chunks[1], (long long)chunks[2],
+               p.norm_pass1 ? 1 : 0, (long long)part, (long long)before);
+    } catch (const std::exception& e) {
+        printf("%s error=%s\n", tag, e.what());
+    }
+}
+
 int main() {
+    show_q8_batch("q8_batch");
     show_q8("q8_leaf", 16384, 16384, 16384, 0, false);
     show_q8("q8_odd", 1999, 1501, 256, 1, false);
     show_q8("q8_overlap", 1536, 1100, 256, 1, true);
@@ -353,3 +402,16 @@ def test_fp8_quantisation_takes_over_norm_pass1(plans):
     assert plans["q8_odd"]["launches"] == plans["q8_odd"]["launches_before"]
     # overlap: the other views of A still go before the pre-sums
     assert plans["q8_overlap"]["split"] > plans["q8_overlap"]["pn"] == 8
+
+
+def test_fp8_batch_norms_partial_layout(plans):
+    """A batch: the member without rows keeps its pass 1 task (zero norms,
+    its own partial region), the members whose quantisations tile their
+    columns drop out of pass 1 and sum ceil(m / 128) block rows in pass 2,
+    and the regions of all members lie end to end."""
+    p = plans["q8_batch"]
+    assert "error" not in p, p
+    assert p["col1"] == 1 and p["kept_prob"] == 0 and p["kept_items"] > 0 and p["pass1"] == 1
+    assert p["fused_probs"] == 0b110 and p["fused_ok"] == 1 and p["regions_ok"] == 1
+    assert p["chunks1"] == -(-700 // 128) and p["chunks2"] == -(-300 // 128)
+    assert p["part"] == p["chunks0"] * 300 + p["chunks1"] * 400 + p["chunks2"] * 200
