@@ -848,7 +848,7 @@ hipError_t enqueue_gram(const ata_ctx* h, const DevicePlan& dp, const void* A, v
     mark(0);
     const int32_t ps = p.pack_split, q0 = p.pack8_norm, qs = std::max(p.pack8_split, q0);
     if (p.fallback) {
-        // FP8: the quantisation of the whole of A writes the norm partials
+        // FP8: the quantisations of A's column slices write the norm partials
         if (q0 > 0)
             e = launch_quant8(dp.d_pack8, q0, p.pack8[q0 - 1].elem_begin + p.pack8[q0 - 1].elems, A, arena, flags,
                               st, nullptr, nullptr, partial);
@@ -1482,8 +1482,8 @@ hipError_t enqueue_batch(ata_ctx* h, BatchEntry& be, hipStream_t st, hipEvent_t*
                               be.d_flags, st, &bq, nullptr, be.d_partial);
         if (e == hipSuccess)
             e = launch_colnorms(be.d_col1, (int)be.col1.size(), l1.elem_begin + l1.elems, be.d_col2,
-                            (int)be.col2.size(), l2.elem_begin + l2.elems, nullptr, be.d_A, be.d_partial,
-                            be.d_nu, st, h->arena, has_pack(be.col1));
+                                (int)be.col2.size(), l2.elem_begin + l2.elems, nullptr, be.d_A, be.d_partial,
+                                be.d_nu, st, h->arena, has_pack(be.col1));
         if (e == hipSuccess)
             e = launch_flags(be.d_nu, dp.d_nodes, (int)p.nodes.size(),
                              h->popt.spread_tau * h->popt.spread_tau, be.d_flags, st);
