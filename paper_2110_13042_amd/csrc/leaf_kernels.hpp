@@ -1295,7 +1295,7 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
     const __amdgpu_buffer_rsrc_t rx = q8_rsrc(arena_in, d.QX), ry = q8_rsrc(arena_in, d.QY);
     const int* sx = reinterpret_cast<const int*>(arena_in + d.QX.scales);
     const int* sy = reinterpret_cast<const int*>(arena_in + d.QY.scales);
-    const int64_t sxs = d.QX.cols_p / 128, sys = d.QY.cols_p / 128;
+    const int64_t sxs = d.QX.ld / 128, sys = d.QY.ld / 128;     // scale rows
     const int64_t K = kr.ke - kr.kb;
     const int64_t sb0 = kr.kb / 128;              // first 128-row slab of the K chunk
     const int64_t nk = (K + 127) / 128;
@@ -1318,8 +1318,8 @@ __device__ void tile_fp8(const LeafDesc& d, const float* arena_in, int ti, int t
             const bool isx = trw < 1024;
             const int trw2 = isx ? trw : trw - 1024;
             const int g = trw2 >> 7, col = (trw2 & 127) + lane;
-            const int64_t cp = isx ? d.QX.cols_p : d.QY.cols_p;
-            const uint32_t off = (uint32_t)((((sb0 + kt) * 8 + g) * cp + (isx ? ti : tj) * 128 + col) * 16);
+            const int64_t ld = isx ? d.QX.ld : d.QY.ld;
+            const uint32_t off = (uint32_t)((((sb0 + kt) * 8 + g) * ld + (isx ? ti : tj) * 128 + col) * 16);
             st[i] = __builtin_amdgcn_raw_buffer_load_b128(isx ? rx : ry, (int)off, 0, 0);
         }
     };
@@ -1427,7 +1427,7 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
     const Packed8& Q = isx ? d.QX : d.QY;
     const __amdgpu_buffer_rsrc_t src = q8_rsrc(arena_in, Q);
     const uint32_t past = (uint32_t)((Q.end - Q.off) * 4);
-    const int64_t cp = Q.cols_p;
+    const int64_t cp = Q.cols_p, ld = Q.ld;
     const int64_t col0 = (isx ? (int64_t)ti * TM : (int64_t)tj * TN) + lane;
     const int gbase = (w & 3) * 2;                // this wave's two row-groups of the slab
     // byte offsets of this lane's four column segments in row-group gbase of
@@ -1437,10 +1437,10 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
 #pragma unroll
     for (int seg = 0; seg < 4; ++seg) {
         const int64_t col = col0 + seg * 64;
-        o0[seg] = col < cp ? (uint32_t)(((sb0 * 8 + gbase) * cp + col) * 16) : past;
+        o0[seg] = col < cp ? (uint32_t)(((sb0 * 8 + gbase) * ld + col) * 16) : past;
         keep[seg] = col < cp ? 0xFFFFFFFFu : 0u;
     }
-    const uint32_t group_bytes = (uint32_t)(cp * 16), slab_bytes = 8 * group_bytes;
+    const uint32_t group_bytes = (uint32_t)(ld * 16), slab_bytes = 8 * group_bytes;
     auto issue = [&](int64_t kt, int stage) {
         unsigned char* base = smem + stage * STAGE + (isx ? 0 : HALF);
         const uint32_t step = (uint32_t)kt * slab_bytes;
@@ -1456,9 +1456,10 @@ __device__ __forceinline__ void tile_fp8_wide(const LeafDesc& d, const float* ar
     // the padded width only feeds outputs that are never stored)
     const int* sx = reinterpret_cast<const int*>(arena_in + d.QX.scales);
     const int* sy = reinterpret_cast<const int*>(arena_in + d.QY.scales);
-    const int64_t sxs = d.QX.cols_p / 128, sys = d.QY.cols_p / 128;
-    const int64_t bx = (int64_t)ti * 2 + wm < sxs ? (int64_t)ti * 2 + wm : sxs - 1;
-    const int64_t by = (int64_t)tj * 2 + (wn >> 1) < sys ? (int64_t)tj * 2 + (wn >> 1) : sys - 1;
+    const int64_t sxs = d.QX.ld / 128, sys = d.QY.ld / 128;     // scale rows
+    const int64_t nbx = d.QX.cols_p / 128, nby = d.QY.cols_p / 128;
+    const int64_t bx = (int64_t)ti * 2 + wm < nbx ? (int64_t)ti * 2 + wm : nbx - 1;
+    const int64_t by = (int64_t)tj * 2 + (wn >> 1) < nby ? (int64_t)tj * 2 + (wn >> 1) : nby - 1;
 
     v4f acc[8][4];
 #pragma unroll

@@ -494,7 +494,12 @@ void assign_packed(Plan& p) {
 }
 
 // FP8: every distinct leaf operand view is quantised on its own (blocks
-// aligned to the view's first row and column).
+// aligned to the view's first row and column), except the full-height column
+// slices of A: when each of those is a run of whole 128-column blocks of A
+// (its first column a multiple of 128, its width too unless it ends at A's
+// last column), A is quantised once and they read its blocks (the same
+// blocks, exponents and codes as quantising each slice on its own), so a
+// plan whose leaves cover A in several slices reads and quantises A once.
 void assign_quant(Plan& p) {
     std::map<std::tuple<int32_t, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t>, Packed8> memo;
     auto ref = [&](const View& V, int32_t pn, int32_t pv) {
@@ -517,14 +522,44 @@ void assign_quant(Plan& p) {
         Q.off = d.dst;
         Q.scales = d.scales;
         Q.cols_p = cols_p;
+        Q.ld = cols_p;
         Q.end = d.dst + rows_p * cols_p / 4;
         check_buffer_bytes(Q.end - Q.off);
         memo.emplace(key, Q);
         return Q;
     };
+    auto a_slice = [&](const View& V) {
+        return V.base == BASE_A && V.off >= 0 && V.off < p.lda && V.ld == p.lda && V.rows == p.m &&
+               V.prows == p.m && V.pcols == V.cols && V.off + V.cols <= p.n;
+    };
+    bool slices = false, aligned = true;
+    for (const auto& L : p.leaves)
+        for (const View* V : {&L.X, &L.Y})
+            if (a_slice(*V)) {
+                slices = true;
+                aligned = aligned && V->off % 128 == 0 && (V->cols % 128 == 0 || V->off + V->cols == p.n);
+            }
+    Packed8 W{};
+    const bool shared = slices && aligned;
+    if (shared) {
+        View A{};
+        A.base = BASE_A;
+        A.ld = p.lda;
+        A.rows = A.prows = p.m;
+        A.cols = A.pcols = p.n;
+        W = ref(A, -1, 0);
+    }
+    auto quant = [&](const View& V, int32_t pn, int32_t pv) {
+        if (!shared || !a_slice(V)) return ref(V, pn, pv);
+        Packed8 Q = W;                       // column c of A is chunk column c
+        Q.off = W.off + V.off * 4;           // 16 bytes (4 floats) per chunk column
+        Q.scales = W.scales + V.off / 128;
+        Q.cols_p = std::max<int64_t>(128, cdiv(V.cols, 128) * 128);
+        return Q;
+    };
     for (auto& L : p.leaves) {
-        L.QX = ref(L.X, L.pred_node, L.pred_value);
-        L.QY = L.kind == LEAF_SYRK ? L.QX : ref(L.Y, L.pred_node, L.pred_value);
+        L.QX = quant(L.X, L.pred_node, L.pred_value);
+        L.QY = L.kind == LEAF_SYRK ? L.QX : quant(L.Y, L.pred_node, L.pred_value);
     }
     int64_t e = 0;
     for (auto& d : p.pack8) { d.elem_begin = e; e += d.elems; }

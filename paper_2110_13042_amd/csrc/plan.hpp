@@ -60,10 +60,13 @@ struct Packed {
 // 128 x 128 elements has the scale 2^e, e = scales[bi * (cols_p / 128) + bj]
 // (int32).  Offsets in floats of the arena.
 struct Packed8 {
-    int64_t off;        // data array
-    int64_t scales;     // int32 exponents
-    int64_t cols_p;     // padded columns
+    int64_t off;        // data array (at the view's first column)
+    int64_t scales;     // int32 exponents (at the view's first block column)
+    int64_t cols_p;     // padded columns of the view
     int64_t end;        // end of the data array (bounds every load)
+    int64_t ld;         // padded columns of the quantised array: the stride of a
+                        // 16-row group and, / 128, of a row of block scales
+                        // (above cols_p for a column slice of a wider array)
 };
 
 enum LeafKind : int32_t { LEAF_SYRK = 0, LEAF_GEMM = 1 };

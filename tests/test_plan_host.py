@@ -233,7 +233,51 @@ static void show_q8_batch(const char* tag) {
     }
 }
 
+// FP8 leaf operands that are column slices of A: quantised once as the whole
+// of A when every slice is a run of whole 128-column blocks.  Prints the
+// quantisation count and whether every leaf operand that is such a slice
+// reads the whole's blocks at its own first column.
+static void show_q8_shared(const char* tag, int64_t m, int64_t n, int64_t b) {
+    PlanOptions o;
+    o.leaf_cutoff = b; o.max_depth = 0; o.spread_tau = 4096.0; o.split_target = 2048; o.slots = 256;
+    try {
+        Plan p = make_plan(MODE_FP8, m, n, n, o);
+        int whole = -1;
+        for (size_t i = 0; i < p.pack8.size(); ++i) {
+            const View& v = p.pack8[i].src;
+            if (v.base == BASE_A && v.off == 0 && v.prows == m && v.pcols == n) whole = (int)i;
+        }
+        int64_t slice_ops = 0, slices_ok = 1, own_ok = 1;
+        for (const auto& L : p.leaves)
+            for (int side = 0; side < 2; ++side) {
+                const View& v = side ? L.Y : L.X;
+                const Packed8& q = side ? L.QY : L.QX;
+                const bool slice = v.base == BASE_A && v.prows == m && v.off < n;
+                if (!slice) continue;
+                ++slice_ops;
+                if (whole >= 0) {
+                    const Pack8Desc& w = p.pack8[whole];
+                    const int64_t wcols = w.cols_p;
+                    if (q.ld != wcols || q.off != w.dst + v.off * 4 || q.scales != w.scales + v.off / 128 ||
+                        q.cols_p != std::max<int64_t>(128, (v.cols + 127) / 128 * 128) ||
+                        q.end != w.dst + w.rows_p * w.cols_p / 4)
+                        slices_ok = 0;
+                } else if (q.ld != q.cols_p) {
+                    own_ok = 0;
+                }
+            }
+        printf("%s tasks=%zu whole=%d slice_ops=%lld slices_ok=%lld own_ok=%lld leaves=%zu\n", tag, p.pack8.size(),
+               whole >= 0 ? 1 : 0, (long long)slice_ops, (long long)slices_ok, (long long)own_ok, p.leaves.size());
+    } catch (const std::exception& e) {
+        printf("%s error=%s\n", tag, e.what());
+    }
+}
+
 int main() {
+    show_q8_shared("q8s_aligned", 4096, 16384, 2048);
+    show_q8_shared("q8s_aligned_2560", 600, 2560, 1024);
+    show_q8_shared("q8s_unaligned_2944", 600, 2944, 1024);
+    show_q8_shared("q8s_unaligned", 3000, 3000, 512);
     show_q8_batch("q8_batch");
     show_q8("q8_leaf", 16384, 16384, 16384, 0, false);
     show_q8("q8_odd", 1999, 1501, 256, 1, false);
@@ -415,3 +459,22 @@ def test_fp8_batch_norms_partial_layout(plans):
     assert p["fused_probs"] == 0b110 and p["fused_ok"] == 1 and p["regions_ok"] == 1
     assert p["chunks1"] == -(-700 // 128) and p["chunks2"] == -(-300 // 128)
     assert p["part"] == p["chunks0"] * 300 + p["chunks1"] * 400 + p["chunks2"] * 200
+
+
+def test_fp8_slices_of_a_share_one_quantisation(plans):
+    """FP8 leaves whose operands are column slices of A, each a run of whole
+    128-column blocks (or ending at A's last column), read one quantisation
+    of the whole of A at their own first column (data, block scales, the
+    whole's group stride); unaligned slices keep one quantisation each."""
+    p = plans["q8s_aligned"]
+    assert "error" not in p, p
+    assert p["tasks"] == 1 and p["whole"] == 1 and p["slices_ok"] == 1 and p["leaves"] > 8
+    # 2560 = 20 x 128 halves into 1280 and 640 column slices, all aligned
+    p = plans["q8s_aligned_2560"]
+    assert "error" not in p, p
+    assert p["tasks"] == 1 and p["whole"] == 1 and p["slices_ok"] == 1 and p["leaves"] > 4
+    # 2944 = 23 x 128 halves into 1472 = 11.5 x 128: unaligned, as is 3000
+    for tag in ("q8s_unaligned", "q8s_unaligned_2944"):
+        p = plans[tag]
+        assert "error" not in p, (tag, p)
+        assert p["whole"] == 0 and p["tasks"] > 1 and p["own_ok"] == 1, tag
