@@ -92,8 +92,11 @@ def test_fp8_small_integers_bit_exact(h, tile):
     h.set("leaf_tile", tile)
     # (the last two: long contractions with an odd number of 128-row slabs,
     # cut into K chunks because their launches have few tiles)
+    # (1024 and 2048 columns: the leaves' column slices of A are whole 128-column
+    # blocks and read one shared quantisation of A)
     for (m, n, b, depth) in [(300, 513, 128, 1), (1000, 777, 256, 0), (64, 700, 128, 1), (5, 3, 64, 0),
-                             (2000, 900, 1024, 0), (4000, 700, 1024, 0), (9000, 300, 512, 0)]:
+                             (2000, 900, 1024, 0), (4000, 700, 1024, 0), (9000, 300, 512, 0),
+                             (700, 1024, 256, 0), (1000, 2048, 512, 1)]:
         _say("case: fp8 int", m, n, b, depth, "tile", tile)
         A = rng.integers(-2, 3, (m, n)).astype(np.float32)
         h.set("leaf_cutoff", b)
@@ -102,11 +105,15 @@ def test_fp8_small_integers_bit_exact(h, tile):
         assert np.array_equal(Cp, plain.gram_packed(A)), (m, n, b, depth)
 
 
+@pytest.mark.parametrize("n", [1100, 1024])
 @pytest.mark.parametrize("depth,tile", [(0, 0), (1, 0), (0, 3), (1, 3)])
-def test_fp8_matches_emulation(h, depth, tile):
-    """Block-scaled e4m3 leaves against the CPU emulation of the same quantisation."""
+def test_fp8_matches_emulation(h, depth, tile, n):
+    """Block-scaled e4m3 leaves against the CPU emulation of the same
+    quantisation (each leaf operand quantised on its own).  With 1024 columns
+    the leaves' column slices of A are whole 128-column blocks and read one
+    shared quantisation of A, which must give the same blocks."""
     rng = np.random.default_rng(62 + depth)
-    m, n, b = 1536, 1100, 256
+    m, b = 1536, 256
     A = (rng.standard_normal((m, n)) * np.exp(rng.uniform(-2, 2, n))).astype(np.float32)
     h.set("leaf_cutoff", b)
     h.set("max_depth", depth)
