@@ -161,6 +161,26 @@ def test_batch_fp8_fallback_matches_single_calls(h):
     assert flagged > 0
 
 
+def test_batch_fp8_shared_quantisation_matches_single_calls():
+    """FP8 members whose leaves are column slices of A made of whole
+    128-column blocks (1024 and 2048 columns) read one quantisation of their
+    A; merged into a batch, their offsets move with the arena.  With split-K
+    and tail cuts off the batch runs each member's own plan, so every member
+    must equal its own ata_gram call bit for bit."""
+    rng = np.random.default_rng(77)
+    shapes = [(700, 1024), (900, 2048), (300, 1100), (1200, 1024), (64, 2048)]
+    mats = [(rng.standard_normal((m, n)) * np.exp(rng.uniform(-1, 1, n))).astype(np.float32) for m, n in shapes]
+    dev = device()
+    with ata.Handle(leaf_cutoff=256, max_depth=0, split_target=0, balance_tail=0) as h2:
+        _say("case: fp8 batch, shared quantisations")
+        As = [torch.from_numpy(M).to(dev) for M in mats]
+        got = [C.double().cpu().numpy() for C in ata.gram_batched(As, ata.F32_FP8E4M3, handle=h2)]
+        for i, (A, G) in enumerate(zip(As, got)):
+            one = ata.gram(A, ata.F32_FP8E4M3, handle=h2).double().cpu().numpy()
+            assert np.array_equal(G, one), (i, shapes[i])
+            assert full_error(G, plain.gram_packed(mats[i])) < 0.1, i
+
+
 @pytest.mark.parametrize("mode", [ata.F32, ata.F32_BF16X3, ata.F32_FP8E4M3])
 def test_persistent_and_grid_launch_agree(h, mode):
     """The persistent leaf launch (per-XCD queues) and the one-workgroup-per-tile
