@@ -1611,6 +1611,13 @@ __device__ __forceinline__ void tile_f64(const LeafDesc& d, const InT* Xp, const
     }
     __syncthreads();
     const int ko = lane >> 4, io = lane & 15;
+    // a wave whose 64 x 64 block of a SYRK tile lies wholly above the
+    // diagonal (nothing it computes is stored) skips its MFMAs, leaving the
+    // matrix pipe to the other workgroup's wave on its SIMD; it still loads,
+    // stores and waits
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const bool idle = d.kind == LEAF_SYRK &&
+                      (int64_t)tj * TILE_N + (wu & 1) * 64 >= (int64_t)ti * TILE_M + ((wu >> 1) + 1) * 64;
     for (int64_t kt = 0; kt < nk; ++kt) {
         const int cur = (int)(kt & 1);
         if (kt + 1 < nk) gload((kt + 1) * BK);
@@ -1618,6 +1625,7 @@ __device__ __forceinline__ void tile_f64(const LeafDesc& d, const InT* Xp, const
         const double* ys = Ys + cur * BK * LD64 + wn * 64 + io;
 #pragma unroll
         for (int kq = 0; kq < BK / 4; ++kq) {
+            if (idle) break;
             const int row = (4 * kq + ko) * LD64;
             double a[4], b[4];
 #pragma unroll
